@@ -1,0 +1,247 @@
+"""FP64 CPU oracle for the D3Q19 BGK + immersed-boundary step (ctypes binding).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only users.  The product path never imports
+this package.  The arithmetic lives in ``oracle.c`` (plain C, FP64, no fast
+math); this module only marshals numpy arrays.  It shares nothing with the
+GPU library.
+
+Array conventions: populations ``f`` float64 [19, N]; vector fields [3, N];
+IB points [nv, 3] absolute (unwrapped) positions; N = nx*ny*nz with node
+``x + nx*(y + ny*z)``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP, no contraction)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-shared", "-fPIC", "-o", _SO + ".tmp", _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _Lat(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("periodic", C.c_int * 3),
+                ("tau", C.c_double), ("g", C.c_double * 3),
+                ("solid", C.POINTER(C.c_uint8)), ("G", _dp)]
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("ncells", C.c_int), ("nverts", C.c_int), ("ntris", C.c_int), ("nedges", C.c_int),
+                ("vert_off", _ip), ("tri_off", _ip), ("edge_off", _ip), ("tri", _ip), ("hinge", _ip),
+                ("moduli", _dp), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
+                ("l0", _dp), ("A0", _dp), ("th0", _dp), ("A0c", _dp), ("V0c", _dp)]
+
+
+class _Trace(C.Structure):
+    _fields_ = [("uk", _dp), ("Fel", _dp), ("Fc", _dp), ("F", _dp)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_SO)
+        L.orc_membrane_energy.restype = C.c_double
+        L.orc_step.restype = C.c_int
+        L.orc_run.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a: np.ndarray):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(_ip)
+
+
+# ---------------------------------------------------------------------------
+
+def d3q19():
+    c = np.zeros((19, 3), np.int32)
+    w = np.zeros(19)
+    o = np.zeros(19, np.int32)
+    lib().orc_d3q19(_i(c), _d(w), _i(o))
+    return c, w, o
+
+
+def equilibrium(rho: float, u) -> np.ndarray:
+    out = np.zeros(19)
+    lib().orc_equilibrium(C.c_double(rho), _d(np.ascontiguousarray(u, dtype=np.float64)), _d(out))
+    return out
+
+
+def forcing(tau: float, u, F) -> np.ndarray:
+    out = np.zeros(19)
+    lib().orc_forcing(C.c_double(tau), _d(np.ascontiguousarray(u, dtype=np.float64)),
+                      _d(np.ascontiguousarray(F, dtype=np.float64)), _d(out))
+    return out
+
+
+def collide_node(tau: float, f, F) -> np.ndarray:
+    out = np.zeros(19)
+    lib().orc_collide_node(C.c_double(tau), _d(np.ascontiguousarray(f, dtype=np.float64)),
+                           _d(np.ascontiguousarray(F, dtype=np.float64)), _d(out))
+    return out
+
+
+class Lattice:
+    """Lattice description: size, periodicity, tau, body force g, solid mask,
+    optional forcing field G [3, nz, ny, nx]."""
+
+    def __init__(self, nx, ny, nz, tau, g=(0.0, 0.0, 0.0), solid=None, periodic=(1, 1, 1), G=None):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.N = self.nx * self.ny * self.nz
+        self.solid = np.ascontiguousarray(
+            np.zeros(self.N, np.uint8) if solid is None else np.asarray(solid, np.uint8).reshape(-1))
+        assert self.solid.size == self.N
+        self.G = None if G is None else np.ascontiguousarray(np.asarray(G, np.float64).reshape(3, self.N))
+        self.s = _Lat(self.nx, self.ny, self.nz, (C.c_int * 3)(*periodic), float(tau),
+                      (C.c_double * 3)(*g), self.solid.ctypes.data_as(C.POINTER(C.c_uint8)),
+                      _d(self.G) if self.G is not None else _dp())
+        self.tau = float(tau)
+        self.g = tuple(float(v) for v in g)
+
+    @classmethod
+    def from_scenario(cls, s, G=None):
+        return cls(s.nx, s.ny, s.nz, s.tau, s.g, s.solid, s.periodic,
+                   G if G is not None else s.gfield)
+
+    def rest(self) -> np.ndarray:
+        """f = w_i on every node (rho = 1, u = 0)."""
+        _, w, _ = d3q19()
+        return np.repeat(w[:, None], self.N, axis=1).copy()
+
+
+class Mesh:
+    """Membrane population; holds its own FP64 rest-shape arrays."""
+
+    def __init__(self, cells, moduli=None):
+        self.cells = cells
+        self.vert_off = np.ascontiguousarray(cells.vert_off, np.int32)
+        self.tri_off = np.ascontiguousarray(cells.tri_off, np.int32)
+        self.edge_off = np.ascontiguousarray(cells.edge_off, np.int32)
+        self.tri = np.ascontiguousarray(cells.tri, np.int32)
+        self.hinge = np.ascontiguousarray(cells.hinge, np.int32)
+        self.moduli = np.ascontiguousarray(cells.moduli if moduli is None else moduli, np.float64)
+        nc, nv, nt, ne = cells.ncells, cells.nverts, cells.ntris, cells.nedges
+        self.l0 = np.zeros(ne)
+        self.A0 = np.zeros(nt)
+        self.th0 = np.zeros(ne)
+        self.A0c = np.zeros(nc)
+        self.V0c = np.zeros(nc)
+        self.s = _Mesh(nc, nv, nt, ne, _i(self.vert_off), _i(self.tri_off), _i(self.edge_off),
+                       _i(self.tri), _i(self.hinge), _d(self.moduli), float(cells.xi),
+                       float(cells.mass), float(cells.dt),
+                       _d(self.l0), _d(self.A0), _d(self.th0), _d(self.A0c), _d(self.V0c))
+        self.nverts = nv
+
+    def rest_shape(self, X: np.ndarray) -> None:
+        lib().orc_rest_shape(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)))
+
+    def energy(self, X) -> float:
+        return lib().orc_membrane_energy(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)))
+
+    def forces(self, X) -> np.ndarray:
+        F = np.zeros((self.nverts, 3))
+        lib().orc_membrane_forces(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)), _d(F))
+        return F
+
+    def area_volume(self, X):
+        nc = len(self.vert_off) - 1
+        A, V = np.zeros(nc), np.zeros(nc)
+        lib().orc_cell_area_volume(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)), _d(A), _d(V))
+        return A, V
+
+    def geometry(self, X):
+        l = np.zeros(len(self.hinge))
+        th = np.zeros(len(self.hinge))
+        A = np.zeros(len(self.tri))
+        lib().orc_mesh_geometry(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)), _d(l), _d(A), _d(th))
+        return l, A, th
+
+
+def fluid_velocity(L: Lattice, f: np.ndarray):
+    rho = np.zeros(L.N)
+    u = np.zeros((3, L.N))
+    lib().orc_fluid_velocity(C.byref(L.s), _d(f), _d(rho), _d(u))
+    return rho, u
+
+
+def mass_momentum(L: Lattice, f: np.ndarray) -> np.ndarray:
+    out = np.zeros(4)
+    lib().orc_mass_momentum(C.byref(L.s), _d(f), _d(out))
+    return out
+
+
+def collide_stream(L: Lattice, f: np.ndarray, F: np.ndarray, fnew: Optional[np.ndarray] = None):
+    out = f.copy() if fnew is None else fnew
+    lib().orc_collide_stream(C.byref(L.s), _d(f), _d(np.ascontiguousarray(F, np.float64)), _d(out))
+    return out
+
+
+def interpolate(L: Lattice, field: np.ndarray, X: np.ndarray) -> np.ndarray:
+    X = np.ascontiguousarray(X, np.float64)
+    out = np.zeros((len(X), 3))
+    lib().orc_interpolate(C.byref(L.s), _d(np.ascontiguousarray(field, np.float64)), C.c_int(len(X)),
+                          _d(X), _d(out))
+    return out
+
+
+def spread(L: Lattice, X: np.ndarray, Fk: np.ndarray, field: Optional[np.ndarray] = None) -> np.ndarray:
+    X = np.ascontiguousarray(X, np.float64)
+    out = np.zeros((3, L.N)) if field is None else field
+    lib().orc_spread(C.byref(L.s), C.c_int(len(X)), _d(X), _d(np.ascontiguousarray(Fk, np.float64)), _d(out))
+    return out
+
+
+def step(L: Lattice, M: Optional[Mesh], f: np.ndarray, X=None, V=None, trace: bool = False):
+    """One coupled step.  Returns fnew; X and V (float64 [nv,3]) advance in place.
+    With trace=True also returns dict(uk, Fel, Fc, F) of that step."""
+    fnew = np.empty_like(f)
+    nv = M.nverts if M is not None else 0
+    tr = None
+    arrs = {}
+    if trace:
+        arrs = dict(uk=np.zeros((nv, 3)), Fel=np.zeros((nv, 3)), Fc=np.zeros((nv, 3)), F=np.zeros((3, L.N)))
+        tr = _Trace(_d(arrs["uk"]), _d(arrs["Fel"]), _d(arrs["Fc"]), _d(arrs["F"]))
+    Xp = _d(X) if X is not None else _dp()
+    Vp = _d(V) if V is not None else _dp()
+    rc = lib().orc_step(C.byref(L.s), C.byref(M.s) if M is not None else None, _d(f), _d(fnew), Xp, Vp,
+                        C.byref(tr) if tr is not None else None)
+    if rc:
+        raise MemoryError("orc_step failed")
+    return (fnew, arrs) if trace else fnew
+
+
+def run(L: Lattice, M: Optional[Mesh], f: np.ndarray, X=None, V=None, nsteps: int = 1) -> np.ndarray:
+    """nsteps coupled steps; f, X, V are advanced in place and f is returned."""
+    rc = lib().orc_run(C.byref(L.s), C.byref(M.s) if M is not None else None, _d(f),
+                       _d(X) if X is not None else _dp(), _d(V) if V is not None else _dp(), C.c_int(nsteps))
+    if rc:
+        raise MemoryError("orc_run failed")
+    return f

@@ -1,0 +1,583 @@
+/*
+ * FP64 CPU oracle for the D3Q19 BGK + immersed-boundary cell-flow step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code,
+ * header, table or helper with the GPU library (which has its own D3Q19
+ * table, kernels and host code); the two meet only in the seeded input
+ * arrays.
+ *
+ * What it computes, step n -> n+1 (one call of orc_step), following the
+ * paper's four-step immersed-boundary procedure (Sec. 2.2) around the
+ * forced LBM update (Sec. 2.1, eq. for f_i):
+ *   1. rho = sum_i f_i, j = sum_i f_i c_i on fluid nodes; F_ext = g + G(x);
+ *      u_ext = (j + F_ext/2)/rho (fluid), 0 on solid nodes.
+ *   2. IB points: u_k = sum over the 2x2x2 stencil of W(x - X_k) u_ext(x)
+ *      (trilinear discrete delta, periodic wrap)        [Sec. 2.2 step 1]
+ *   3. per cell: total area A_c and enclosed volume V_c, then the elastic
+ *      force F_el = -grad(E_s + E_b + E_al + E_ag + E_v)  [Sec. 2.3.1, 2.3.3]
+ *      and the coupling force F_c = xi (u_k - V_k)        [Sec. 2.2 step 2]
+ *   4. F(x) = F_ext(x) + sum_k W(x - X_k) (-F_c,k)         [Sec. 2.2 step 3]
+ *   5. BGK collision with the Guo source on fluid nodes, u = (j + F/2)/rho,
+ *      then streaming to x + c_i, or halfway bounce-back into the opposite
+ *      slot when x + c_i is a solid node                   [Sec. 2.1, 2.4]
+ *   6. V_k += dt/m (F_el + F_c), X_k += dt V_k              [Sec. 2.2 step 4]
+ * The points where the paper is silent (form of f_eq, of the source term, of
+ * the delta function, of the membrane energies, the ordering above) are the
+ * readings listed in the design notes; each is marked "reading" below.
+ *
+ * Layouts: lattice node n = x + nx*(y + ny*z); populations f[i*N + n];
+ * vector fields v[d*N + n]; IB points X[k*3 + d] (absolute, unwrapped).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define Q 19
+
+/* D3Q19 velocities: rest, 6 faces, 12 edges; the opposite of odd i is i+1. */
+static const int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+static const int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+static const int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+static double weight(int i) {
+    if (i == 0) return 1.0 / 3.0;
+    if (i <= 6) return 1.0 / 18.0;
+    return 1.0 / 36.0;
+}
+
+static int opposite(int i) {
+    if (i == 0) return 0;
+    return (i % 2 == 1) ? i + 1 : i - 1;
+}
+
+typedef struct {
+    int nx, ny, nz;
+    int periodic[3];
+    double tau;
+    double g[3];
+    const uint8_t *solid; /* [N], 1 = solid */
+    const double *G;      /* [3][N] external forcing field, or NULL */
+} orc_lattice;
+
+typedef struct {
+    int ncells, nverts, ntris, nedges;
+    const int *vert_off; /* [ncells+1] */
+    const int *tri_off;  /* [ncells+1] */
+    const int *edge_off; /* [ncells+1] */
+    const int *tri;      /* [ntris][3], outward counter-clockwise */
+    const int *hinge;    /* [nedges][4] = (p1, p2, qa, qb) */
+    const double *moduli;/* [ncells][5] = (k_s, k_b, k_al, k_ag, k_v) */
+    double xi, mass, dt;
+    /* rest shape, filled by orc_rest_shape */
+    double *l0;  /* [nedges] */
+    double *A0;  /* [ntris]  */
+    double *th0; /* [nedges] */
+    double *A0c; /* [ncells] */
+    double *V0c; /* [ncells] */
+} orc_mesh;
+
+/* ------------------------------------------------------------------------ */
+/* tables (exported so the tests can check the lattice identities)          */
+/* ------------------------------------------------------------------------ */
+
+void orc_d3q19(int *c /* [19][3] */, double *w /* [19] */, int *opp /* [19] */) {
+    for (int i = 0; i < Q; i++) {
+        c[3 * i + 0] = CX[i];
+        c[3 * i + 1] = CY[i];
+        c[3 * i + 2] = CZ[i];
+        w[i] = weight(i);
+        opp[i] = opposite(i);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* local collision pieces (Sec. 2.1)                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Reading: the second-order polynomial equilibrium of D3Q19,
+ * f_eq_i = w_i rho (1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u). */
+void orc_equilibrium(double rho, const double u[3], double feq[Q]) {
+    double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; i++) {
+        double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
+        feq[i] = weight(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    }
+}
+
+/* Reading: the forcing term F_i of the LBM equation is Guo's source,
+ * F_i = (1 - 1/(2 tau)) w_i [3 (c_i - u) + 9 (c_i.u) c_i] . F,
+ * used together with the half-force velocity u = (j + F/2)/rho. */
+void orc_forcing(double tau, const double u[3], const double F[3], double S[Q]) {
+    for (int i = 0; i < Q; i++) {
+        double c[3] = {CX[i], CY[i], CZ[i]};
+        double cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2];
+        double s = 0.0;
+        for (int d = 0; d < 3; d++) s += (3.0 * (c[d] - u[d]) + 9.0 * cu * c[d]) * F[d];
+        S[i] = (1.0 - 0.5 / tau) * weight(i) * s;
+    }
+}
+
+/* One BGK relaxation with source, for a single node. */
+void orc_collide_node(double tau, const double f[Q], const double F[3], double fout[Q]) {
+    double rho = 0.0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; i++) {
+        rho += f[i];
+        j[0] += f[i] * CX[i];
+        j[1] += f[i] * CY[i];
+        j[2] += f[i] * CZ[i];
+    }
+    double u[3];
+    for (int d = 0; d < 3; d++) u[d] = (j[d] + 0.5 * F[d]) / rho;
+    double feq[Q], S[Q];
+    orc_equilibrium(rho, u, feq);
+    orc_forcing(tau, u, F, S);
+    for (int i = 0; i < Q; i++) fout[i] = f[i] - (f[i] - feq[i]) / tau + S[i];
+}
+
+/* ------------------------------------------------------------------------ */
+/* lattice helpers                                                           */
+/* ------------------------------------------------------------------------ */
+
+static long nnodes(const orc_lattice *L) { return (long)L->nx * L->ny * L->nz; }
+
+static int wrap(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+/* Neighbour of (x,y,z) along c_i; -1 if it leaves a non-periodic axis. */
+static long neighbour(const orc_lattice *L, int x, int y, int z, int i) {
+    int p[3] = {x + CX[i], y + CY[i], z + CZ[i]};
+    int n[3] = {L->nx, L->ny, L->nz};
+    for (int d = 0; d < 3; d++) {
+        if (p[d] < 0 || p[d] >= n[d]) {
+            if (!L->periodic[d]) return -1;
+            p[d] = wrap(p[d], n[d]);
+        }
+    }
+    return p[0] + (long)L->nx * (p[1] + (long)L->ny * p[2]);
+}
+
+/* rho and u_ext = (j + F_ext/2)/rho per node; solid nodes get rho = 0, u = 0
+ * (reading: the interpolated velocity excludes the not-yet-known IB force). */
+void orc_fluid_velocity(const orc_lattice *L, const double *f, double *rho, double *uext) {
+    long N = nnodes(L);
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; n++) {
+        if (L->solid[n]) {
+            if (rho) rho[n] = 0.0;
+            for (int d = 0; d < 3; d++) uext[d * N + n] = 0.0;
+            continue;
+        }
+        double r = 0.0, j[3] = {0, 0, 0};
+        for (int i = 0; i < Q; i++) {
+            double v = f[i * N + n];
+            r += v;
+            j[0] += v * CX[i];
+            j[1] += v * CY[i];
+            j[2] += v * CZ[i];
+        }
+        for (int d = 0; d < 3; d++) {
+            double Fe = L->g[d] + (L->G ? L->G[d * N + n] : 0.0);
+            uext[d * N + n] = (j[d] + 0.5 * Fe) / r;
+        }
+        if (rho) rho[n] = r;
+    }
+}
+
+/* Compensated (Neumaier) running sum, so that the global sums below do not
+ * lose the conservation signal to the rounding of large partial sums. */
+typedef struct { double s, c; } ksum;
+static void kadd(ksum *k, double v) {
+    double t = k->s + v;
+    if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+    else k->c += (v - t) + k->s;
+    k->s = t;
+}
+
+/* Sum of rho and j over fluid nodes: out = (M, Px, Py, Pz). */
+void orc_mass_momentum(const orc_lattice *L, const double *f, double out[4]) {
+    long N = nnodes(L);
+    ksum acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    for (long n = 0; n < N; n++) {
+        if (L->solid[n]) continue;
+        double r = 0, jx = 0, jy = 0, jz = 0;
+        for (int i = 0; i < Q; i++) {
+            double v = f[i * N + n];
+            r += v;
+            jx += v * CX[i];
+            jy += v * CY[i];
+            jz += v * CZ[i];
+        }
+        kadd(&acc[0], r);
+        kadd(&acc[1], jx);
+        kadd(&acc[2], jy);
+        kadd(&acc[3], jz);
+    }
+    for (int d = 0; d < 4; d++) out[d] = acc[d].s + acc[d].c;
+}
+
+/* Collide every fluid node with total force F[3][N] and stream into fnew.
+ * A population heading into a solid node (or out through a non-periodic
+ * face) is reflected into the opposite slot of its own node (halfway
+ * bounce-back).  Solid-node slots of fnew are left untouched. */
+void orc_collide_stream(const orc_lattice *L, const double *f, const double *F, double *fnew) {
+    long N = nnodes(L);
+#pragma omp parallel for schedule(static)
+    for (int z = 0; z < L->nz; z++) {
+        for (int y = 0; y < L->ny; y++) {
+            for (int x = 0; x < L->nx; x++) {
+                long n = x + (long)L->nx * (y + (long)L->ny * z);
+                if (L->solid[n]) continue;
+                double fl[Q], fo[Q], Fn[3];
+                for (int i = 0; i < Q; i++) fl[i] = f[i * N + n];
+                for (int d = 0; d < 3; d++) Fn[d] = F[d * N + n];
+                orc_collide_node(L->tau, fl, Fn, fo);
+                for (int i = 0; i < Q; i++) {
+                    long m = neighbour(L, x, y, z, i);
+                    if (m < 0 || L->solid[m])
+                        fnew[opposite(i) * N + n] = fo[i];
+                    else
+                        fnew[i * N + m] = fo[i];
+                }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* discrete delta (Sec. 2.2 steps 1 and 3)                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Reading: the discrete delta is the trilinear kernel over the 8 nodes
+ * around X; node indices wrap periodically on every axis. */
+static void stencil(const orc_lattice *L, const double X[3], long idx[8], double w[8]) {
+    int i0[3];
+    double fr[3];
+    int n[3] = {L->nx, L->ny, L->nz};
+    for (int d = 0; d < 3; d++) {
+        double fl = floor(X[d]);
+        i0[d] = (int)fl;
+        fr[d] = X[d] - fl;
+    }
+    int k = 0;
+    for (int bz = 0; bz < 2; bz++)
+        for (int by = 0; by < 2; by++)
+            for (int bx = 0; bx < 2; bx++) {
+                int x = wrap(i0[0] + bx, n[0]);
+                int y = wrap(i0[1] + by, n[1]);
+                int z = wrap(i0[2] + bz, n[2]);
+                idx[k] = x + (long)n[0] * (y + (long)n[1] * z);
+                w[k] = (bx ? fr[0] : 1.0 - fr[0]) * (by ? fr[1] : 1.0 - fr[1]) * (bz ? fr[2] : 1.0 - fr[2]);
+                k++;
+            }
+}
+
+/* out[k] = sum_x W(x - X_k) field(x) for a vector field [3][N]. */
+void orc_interpolate(const orc_lattice *L, const double *field, int nv, const double *X, double *out) {
+    long N = nnodes(L);
+    for (int k = 0; k < nv; k++) {
+        long idx[8];
+        double w[8];
+        stencil(L, X + 3 * k, idx, w);
+        for (int d = 0; d < 3; d++) {
+            double s = 0.0;
+            for (int c = 0; c < 8; c++) s += w[c] * field[d * N + idx[c]];
+            out[3 * k + d] = s;
+        }
+    }
+}
+
+/* field(x) += sum_k W(x - X_k) Fk[k] */
+void orc_spread(const orc_lattice *L, int nv, const double *X, const double *Fk, double *field) {
+    long N = nnodes(L);
+    for (int k = 0; k < nv; k++) {
+        long idx[8];
+        double w[8];
+        stencil(L, X + 3 * k, idx, w);
+        for (int c = 0; c < 8; c++)
+            for (int d = 0; d < 3; d++) field[d * N + idx[c]] += w[c] * Fk[3 * k + d];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* membrane geometry and elastic forces (Sec. 2.3.1, Table 1)                */
+/* ------------------------------------------------------------------------ */
+
+static void sub3(const double *a, const double *b, double *r) {
+    r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2];
+}
+static void cross3(const double *a, const double *b, double *r) {
+    r[0] = a[1] * b[2] - a[2] * b[1];
+    r[1] = a[2] * b[0] - a[0] * b[2];
+    r[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static double norm3(const double *a) { return sqrt(dot3(a, a)); }
+
+/* Triangle area, half the norm of (b-a) x (c-a). */
+static double tri_area(const double *a, const double *b, const double *c) {
+    double e1[3], e2[3], n[3];
+    sub3(b, a, e1);
+    sub3(c, a, e2);
+    cross3(e1, e2, n);
+    return 0.5 * norm3(n);
+}
+
+/* Signed volume of the tetrahedron (origin, a, b, c): a.(b x c)/6. */
+static double tri_volume(const double *a, const double *b, const double *c) {
+    double n[3];
+    cross3(b, c, n);
+    return dot3(a, n) / 6.0;
+}
+
+/* Angle between the outward normals of triangles (p1,p2,qa) and (p2,p1,qb),
+ * signed so that a convex fold is positive and a flat hinge is zero. */
+static double dihedral(const double *p1, const double *p2, const double *qa, const double *qb) {
+    double e[3], t1[3], t2[3], na[3], nb[3], m[3];
+    sub3(p2, p1, e);
+    sub3(qa, p1, t1);
+    cross3(e, t1, na);           /* (p2-p1) x (qa-p1) */
+    double me[3] = {-e[0], -e[1], -e[2]};
+    sub3(qb, p2, t2);
+    cross3(me, t2, nb);          /* (p1-p2) x (qb-p2) */
+    cross3(na, nb, m);
+    double s = dot3(m, e) / norm3(e);
+    double c = dot3(na, nb);
+    return atan2(s, c);
+}
+
+static const double *vtx(const double *X, int k) { return X + 3 * k; }
+
+/* Per-cell total area and volume (divergence theorem on absolute positions). */
+void orc_cell_area_volume(const orc_mesh *M, const double *X, double *A, double *V) {
+    for (int c = 0; c < M->ncells; c++) {
+        double a = 0.0, v = 0.0;
+        for (int t = M->tri_off[c]; t < M->tri_off[c + 1]; t++) {
+            const int *T = M->tri + 3 * t;
+            a += tri_area(vtx(X, T[0]), vtx(X, T[1]), vtx(X, T[2]));
+            v += tri_volume(vtx(X, T[0]), vtx(X, T[1]), vtx(X, T[2]));
+        }
+        A[c] = a;
+        V[c] = v;
+    }
+}
+
+/* Edge lengths, triangle areas and dihedral angles of the mesh at X. */
+void orc_mesh_geometry(const orc_mesh *M, const double *X, double *l, double *A, double *th) {
+    for (int e = 0; e < M->nedges; e++) {
+        const int *h = M->hinge + 4 * e;
+        double d[3];
+        sub3(vtx(X, h[1]), vtx(X, h[0]), d);
+        if (l) l[e] = norm3(d);
+        if (th) th[e] = dihedral(vtx(X, h[0]), vtx(X, h[1]), vtx(X, h[2]), vtx(X, h[3]));
+    }
+    if (A)
+        for (int t = 0; t < M->ntris; t++) {
+            const int *T = M->tri + 3 * t;
+            A[t] = tri_area(vtx(X, T[0]), vtx(X, T[1]), vtx(X, T[2]));
+        }
+}
+
+/* Reading: the rest shape is the mesh as given (the initial icosphere), so
+ * the elastic forces vanish initially. */
+void orc_rest_shape(orc_mesh *M, const double *X) {
+    orc_mesh_geometry(M, X, M->l0, M->A0, M->th0);
+    orc_cell_area_volume(M, X, M->A0c, M->V0c);
+}
+
+/* Reading of the four moduli as energies (all values from Table 1):
+ *   E_s  = sum_edges (k_s/2) (l - l0)^2 / l0          (linear stretching)
+ *   E_b  = sum_hinges (k_b/2) (theta - theta0)^2      (preferred angle)
+ *   E_al = sum_tris (k_al/2) (A - A0)^2 / A0          (local area)
+ *   E_ag = (k_ag/2) (A_c - A0_c)^2 / A0_c             (global area)
+ *   E_v  = (k_v/2) (V_c - V0_c)^2 / V0_c              (volume)            */
+double orc_membrane_energy(const orc_mesh *M, const double *X) {
+    double E = 0.0;
+    for (int c = 0; c < M->ncells; c++) {
+        const double *k = M->moduli + 5 * c;
+        double Ac = 0.0, Vc = 0.0;
+        for (int t = M->tri_off[c]; t < M->tri_off[c + 1]; t++) {
+            const int *T = M->tri + 3 * t;
+            double A = tri_area(vtx(X, T[0]), vtx(X, T[1]), vtx(X, T[2]));
+            Ac += A;
+            Vc += tri_volume(vtx(X, T[0]), vtx(X, T[1]), vtx(X, T[2]));
+            E += 0.5 * k[2] * (A - M->A0[t]) * (A - M->A0[t]) / M->A0[t];
+        }
+        E += 0.5 * k[3] * (Ac - M->A0c[c]) * (Ac - M->A0c[c]) / M->A0c[c];
+        E += 0.5 * k[4] * (Vc - M->V0c[c]) * (Vc - M->V0c[c]) / M->V0c[c];
+        for (int e = M->edge_off[c]; e < M->edge_off[c + 1]; e++) {
+            const int *h = M->hinge + 4 * e;
+            double d[3];
+            sub3(vtx(X, h[1]), vtx(X, h[0]), d);
+            double l = norm3(d);
+            E += 0.5 * k[0] * (l - M->l0[e]) * (l - M->l0[e]) / M->l0[e];
+            double th = dihedral(vtx(X, h[0]), vtx(X, h[1]), vtx(X, h[2]), vtx(X, h[3]));
+            E += 0.5 * k[1] * (th - M->th0[e]) * (th - M->th0[e]);
+        }
+    }
+    return E;
+}
+
+static void addv(double *F, int k, double s, const double *v) {
+    F[3 * k + 0] += s * v[0];
+    F[3 * k + 1] += s * v[1];
+    F[3 * k + 2] += s * v[2];
+}
+
+/* F = -grad E (membrane_energy), written out term by term.
+ *   grad_a A   = (b - c) x n_hat / 2 (cyclic in a, b, c)
+ *   grad_a V_t = (b x c) / 6        (cyclic)
+ *   grad l     = +-(p2 - p1)/l
+ *   grad theta: wings qa, qb get -|e| n_a/|n_a|^2, -|e| n_b/|n_b|^2; the edge
+ *   ends get the combinations that keep the sum and the torque zero,
+ *   grad_p1 = -(1-s_a) g_qa - (1-s_b) g_qb, grad_p2 = -s_a g_qa - s_b g_qb,
+ *   with s_q = (q - p1).e/|e|^2.                                           */
+void orc_membrane_forces(const orc_mesh *M, const double *X, double *F) {
+    memset(F, 0, sizeof(double) * 3 * M->nverts);
+    for (int c = 0; c < M->ncells; c++) {
+        const double *k = M->moduli + 5 * c;
+        /* global constraints first: they need the whole cell (Sec. 2.3.3) */
+        double Ac = 0.0, Vc = 0.0;
+        for (int t = M->tri_off[c]; t < M->tri_off[c + 1]; t++) {
+            const int *T = M->tri + 3 * t;
+            Ac += tri_area(vtx(X, T[0]), vtx(X, T[1]), vtx(X, T[2]));
+            Vc += tri_volume(vtx(X, T[0]), vtx(X, T[1]), vtx(X, T[2]));
+        }
+        double cag = k[3] * (Ac - M->A0c[c]) / M->A0c[c];
+        double cv = k[4] * (Vc - M->V0c[c]) / M->V0c[c];
+        for (int t = M->tri_off[c]; t < M->tri_off[c + 1]; t++) {
+            const int *T = M->tri + 3 * t;
+            const double *a = vtx(X, T[0]), *b = vtx(X, T[1]), *cc = vtx(X, T[2]);
+            double e1[3], e2[3], n[3];
+            sub3(b, a, e1);
+            sub3(cc, a, e2);
+            cross3(e1, e2, n);
+            double nn = norm3(n);
+            double A = 0.5 * nn;
+            double nh[3] = {n[0] / nn, n[1] / nn, n[2] / nn};
+            double cal = k[2] * (A - M->A0[t]) / M->A0[t];
+            double ca = cal + cag; /* both area terms share grad A_t */
+            double d[3], gA[3];
+            sub3(b, cc, d); cross3(d, nh, gA); addv(F, T[0], -0.5 * ca, gA);
+            sub3(cc, a, d); cross3(d, nh, gA); addv(F, T[1], -0.5 * ca, gA);
+            sub3(a, b, d); cross3(d, nh, gA); addv(F, T[2], -0.5 * ca, gA);
+            double gV[3];
+            cross3(b, cc, gV); addv(F, T[0], -cv / 6.0, gV);
+            cross3(cc, a, gV); addv(F, T[1], -cv / 6.0, gV);
+            cross3(a, b, gV); addv(F, T[2], -cv / 6.0, gV);
+        }
+        for (int e = M->edge_off[c]; e < M->edge_off[c + 1]; e++) {
+            const int *h = M->hinge + 4 * e;
+            const double *p1 = vtx(X, h[0]), *p2 = vtx(X, h[1]), *qa = vtx(X, h[2]), *qb = vtx(X, h[3]);
+            /* stretching */
+            double ev[3];
+            sub3(p2, p1, ev);
+            double l = norm3(ev);
+            double cs = k[0] * (l - M->l0[e]) / M->l0[e];
+            addv(F, h[0], cs / l, ev);  /* -dE/dp1 = +cs (p2-p1)/l */
+            addv(F, h[1], -cs / l, ev);
+            /* bending */
+            double th = dihedral(p1, p2, qa, qb);
+            double cb = k[1] * (th - M->th0[e]);
+            double t1[3], t2[3], na[3], nb[3], me[3] = {-ev[0], -ev[1], -ev[2]};
+            sub3(qa, p1, t1);
+            cross3(ev, t1, na);
+            sub3(qb, p2, t2);
+            cross3(me, t2, nb);
+            double na2 = dot3(na, na), nb2 = dot3(nb, nb);
+            double ga[3] = {-l * na[0] / na2, -l * na[1] / na2, -l * na[2] / na2};
+            double gb[3] = {-l * nb[0] / nb2, -l * nb[1] / nb2, -l * nb[2] / nb2};
+            double sa = dot3(t1, ev) / (l * l);
+            double qb1[3];
+            sub3(qb, p1, qb1);
+            double sb = dot3(qb1, ev) / (l * l);
+            addv(F, h[2], -cb, ga);
+            addv(F, h[3], -cb, gb);
+            double g1[3], g2[3];
+            for (int d = 0; d < 3; d++) {
+                g1[d] = -(1.0 - sa) * ga[d] - (1.0 - sb) * gb[d];
+                g2[d] = -sa * ga[d] - sb * gb[d];
+            }
+            addv(F, h[0], -cb, g1);
+            addv(F, h[1], -cb, g2);
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* the coupled step                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Optional per-step diagnostics written by orc_step (NULL to skip). */
+typedef struct {
+    double *uk;   /* [nv][3] interpolated velocity */
+    double *Fel;  /* [nv][3] elastic force */
+    double *Fc;   /* [nv][3] coupling force */
+    double *F;    /* [3][N]  total force seen by the collision */
+} orc_trace;
+
+/* One step n -> n+1.  f (in) and fnew (out) are distinct [19][N] arrays;
+ * solid-node slots of fnew are copied from f.  M may be NULL (no cells);
+ * otherwise X, V [nv][3] are advanced in place. */
+int orc_step(const orc_lattice *L, const orc_mesh *M, const double *f, double *fnew, double *X, double *V,
+             const orc_trace *tr) {
+    long N = nnodes(L);
+    double *uext = malloc(sizeof(double) * 3 * N);
+    double *F = malloc(sizeof(double) * 3 * N);
+    if (!uext || !F) { free(uext); free(F); return -1; }
+    orc_fluid_velocity(L, f, NULL, uext);
+    for (int d = 0; d < 3; d++)
+        for (long n = 0; n < N; n++) F[d * N + n] = L->g[d] + (L->G ? L->G[d * N + n] : 0.0);
+    double *uk = NULL, *Fel = NULL, *Fc = NULL;
+    int nv = M ? M->nverts : 0;
+    if (nv) {
+        uk = malloc(sizeof(double) * 3 * nv);
+        Fel = malloc(sizeof(double) * 3 * nv);
+        Fc = malloc(sizeof(double) * 3 * nv);
+        double *mFc = malloc(sizeof(double) * 3 * nv);
+        orc_interpolate(L, uext, nv, X, uk);                 /* step 1 */
+        orc_membrane_forces(M, X, Fel);                      /* step 2 */
+        for (int i = 0; i < 3 * nv; i++) {
+            Fc[i] = M->xi * (uk[i] - V[i]);
+            mFc[i] = -Fc[i];
+        }
+        orc_spread(L, nv, X, mFc, F);                        /* step 3 */
+        free(mFc);
+    }
+    for (int i = 0; i < Q; i++)
+        for (long n = 0; n < N; n++)
+            if (L->solid[n]) fnew[i * N + n] = f[i * N + n];
+    orc_collide_stream(L, f, F, fnew);                      /* step 4, fluid */
+    for (int i = 0; i < 3 * nv; i++) {                      /* step 4, points */
+        V[i] += M->dt / M->mass * (Fel[i] + Fc[i]);
+        X[i] += M->dt * V[i];
+    }
+    if (tr) {
+        if (tr->uk && nv) memcpy(tr->uk, uk, sizeof(double) * 3 * nv);
+        if (tr->Fel && nv) memcpy(tr->Fel, Fel, sizeof(double) * 3 * nv);
+        if (tr->Fc && nv) memcpy(tr->Fc, Fc, sizeof(double) * 3 * nv);
+        if (tr->F) memcpy(tr->F, F, sizeof(double) * 3 * N);
+    }
+    free(uk); free(Fel); free(Fc);
+    free(uext); free(F);
+    return 0;
+}
+
+/* nsteps steps; the result is left in f (two-buffer swap internally). */
+int orc_run(const orc_lattice *L, const orc_mesh *M, double *f, double *X, double *V, int nsteps) {
+    long N = nnodes(L);
+    double *g = malloc(sizeof(double) * Q * N);
+    if (!g) return -1;
+    double *a = f, *b = g;
+    for (int s = 0; s < nsteps; s++) {
+        if (orc_step(L, M, a, b, X, V, NULL)) { free(g); return -1; }
+        double *t = a; a = b; b = t;
+    }
+    if (a != f) memcpy(f, a, sizeof(double) * Q * N);
+    free(g);
+    return 0;
+}

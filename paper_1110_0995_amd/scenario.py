@@ -1,0 +1,406 @@
+"""Seeded synthetic inputs for the D3Q19 + immersed-boundary cell-flow step.
+
+Geometry and bookkeeping only: solid masks (channel walls, cylindrical
+microposts), icosphere membrane meshes with their edge/hinge connectivity,
+seeded random sequential placement of cells, and the parameter records of the
+workloads.  Nothing in this module evaluates lattice-Boltzmann or
+immersed-boundary arithmetic (no equilibria, no forces, no reference lengths,
+areas, angles or volumes): the GPU library and the CPU oracle both take these
+arrays as plain inputs and derive everything else themselves.
+
+Conventions shared by every consumer of these arrays
+----------------------------------------------------
+* Lattice arrays are indexed ``[z, y, x]`` with x fastest; node id
+  ``n = x + nx*(y + ny*z)``.
+* ``solid`` is uint8, 1 = solid (bounce-back) node, 0 = fluid node.  The
+  paper distinguishes boundary and fluid nodes and places the wall between
+  them (Sec. 2.4).
+* A cell membrane is a closed triangle mesh.  ``tri[t] = (a, b, c)`` is
+  ordered counter-clockwise seen from outside, so ``(b-a) x (c-a)`` points
+  outward.  Every undirected edge appears once in ``hinge[e] = (p1, p2, qa,
+  qb)``: triangle ``(p1, p2, qa)`` and triangle ``(p2, p1, qb)`` (both in the
+  cyclic order of ``tri``) share it.  Indices are global vertex ids.
+* IB-point positions are stored as an int32 anchor per cell plus a float32
+  offset per vertex; the position is ``anchor + offset`` (evaluated exactly
+  in float64 by anyone who wants absolute coordinates).
+* ``moduli[c] = (k_s, k_b, k_al, k_ag, k_v)`` for cell c (Table 1 names:
+  K^S, K^B, K^A_l, K^A_g, K^V).
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# Table 1 of the paper: elastic constants of the two cell models, in the
+# order (k_s, k_b, k_al, k_ag, k_v).  The table gives no units; they are used
+# as lattice-unit values.
+MODULI_CTC = (0.0023, 0.000464, 0.0029, 0.29, 2.9)
+MODULI_RBC = (0.008, 0.0016, 0.01, 1.0, 10.0)
+
+
+# ---------------------------------------------------------------------------
+# meshes
+# ---------------------------------------------------------------------------
+
+def _icosahedron() -> Tuple[np.ndarray, np.ndarray]:
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = np.array([
+        (-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
+        (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+        (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)], dtype=np.float64)
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    f = np.array([
+        (0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+        (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+        (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+        (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)], dtype=np.int64)
+    return v, f
+
+
+def _orient_outward(v: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Flip triangles of a star-shaped mesh (about the origin) to face outward."""
+    a, b, c = v[f[:, 0]], v[f[:, 1]], v[f[:, 2]]
+    out = np.einsum("ij,ij->i", np.cross(b - a, c - a), a + b + c) > 0
+    g = f.copy()
+    g[~out] = g[~out][:, [0, 2, 1]]
+    return g
+
+
+def icosphere(level: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Unit icosphere: the icosahedron with each triangle split into four
+    ``level`` times, new vertices pushed onto the sphere.  Returns (verts
+    [V,3] float64, tris [T,3] int64), V = 10*4^level + 2, T = 20*4^level."""
+    v, f = _icosahedron()
+    verts: List[np.ndarray] = list(v)
+    for _ in range(level):
+        cache = {}
+
+        def mid(i, j):
+            key = (i, j) if i < j else (j, i)
+            if key not in cache:
+                p = verts[i] + verts[j]
+                verts.append(p / np.linalg.norm(p))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in f:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        f = np.array(nf, dtype=np.int64)
+    v = np.array(verts, dtype=np.float64)
+    return v, _orient_outward(v, f)
+
+
+def hinges(tris: np.ndarray) -> np.ndarray:
+    """Edge/hinge table of a closed oriented triangle mesh.
+
+    Returns int64 [E,4] rows (p1, p2, qa, qb), p1 < p2, where (p1, p2, qa) is
+    the cyclic order of one triangle and (p2, p1, qb) that of the other."""
+    opp = {}
+    for a, b, c in tris:
+        for p, q, r in ((a, b, c), (b, c, a), (c, a, b)):
+            key = (int(p), int(q))
+            if key in opp:
+                raise ValueError("mesh is not consistently oriented")
+            opp[key] = int(r)
+    rows = []
+    for (p, q), r in opp.items():
+        if p < q:
+            if (q, p) not in opp:
+                raise ValueError("mesh is not closed")
+            rows.append((p, q, r, opp[(q, p)]))
+    rows.sort()
+    return np.array(rows, dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# solid masks
+# ---------------------------------------------------------------------------
+
+def channel_mask(nx: int, ny: int, nz: int, walls_z: bool = True) -> np.ndarray:
+    """uint8 [nz, ny, nx]; the planes z = 0 and z = nz-1 are solid walls."""
+    m = np.zeros((nz, ny, nx), dtype=np.uint8)
+    if walls_z:
+        m[0] = 1
+        m[nz - 1] = 1
+    return m
+
+
+def add_posts(mask: np.ndarray, centres: Sequence[Tuple[float, float]], radius: float) -> None:
+    """Cylinders with axis along z over the full height: node (x, y) is solid
+    iff (x-xc)^2 + (y-yc)^2 <= r^2 (no periodic images)."""
+    nz, ny, nx = mask.shape
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    for xc, yc in centres:
+        inside = (xx - xc) ** 2 + (yy - yc) ** 2 <= radius * radius
+        mask[:, inside] = 1
+
+
+def post_array_centres(nx: int, ny: int, gaps_x: Sequence[int], gaps_y: Sequence[int],
+                       radius: int) -> List[Tuple[float, float]]:
+    """Rectangular post array, centred in the (x, y) plane.  Neighbouring
+    centres are 2*radius + gap apart (gap = surface-to-surface distance);
+    the array is shifted by an integer so every centre stays on a node."""
+    xs = np.concatenate([[0], np.cumsum(2 * radius + np.asarray(gaps_x, dtype=np.int64))])
+    ys = np.concatenate([[0], np.cumsum(2 * radius + np.asarray(gaps_y, dtype=np.int64))])
+    xs = xs + (nx // 2 - int(round(xs.mean())))
+    ys = ys + (ny // 2 - int(round(ys.mean())))
+    return [(float(x), float(y)) for y in ys for x in xs]
+
+
+# ---------------------------------------------------------------------------
+# cell placement
+# ---------------------------------------------------------------------------
+
+def place_cells(rng: np.random.Generator, n: int, radius: float, dims: Tuple[int, int, int],
+                posts: Sequence[Tuple[float, float]] = (), post_radius: float = 0.0,
+                clearance: float = 1.0, walls_z: bool = True, max_tries: int = 200000) -> np.ndarray:
+    """Random sequential addition of n spheres (centres float64 [n,3]).
+
+    Centres are uniform over the fluid box; a candidate is kept if it stays
+    ``clearance`` away from every kept sphere (periodic minimum image in x
+    and y), from the wall planes z = 0.5 and z = nz-1.5, and from every
+    post surface."""
+    nx, ny, nz = dims
+    zlo, zhi = (0.5, nz - 1.5) if walls_z else (0.0, float(nz))
+    cen: List[np.ndarray] = []
+    tries = 0
+    while len(cen) < n:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError(f"could only place {len(cen)} of {n} cells")
+        lo = zlo + radius + clearance if walls_z else 0.0
+        hi = zhi - radius - clearance if walls_z else float(nz)
+        p = np.array([rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(lo, hi)])
+        ok = True
+        for xc, yc in posts:
+            dx = (p[0] - xc + nx / 2) % nx - nx / 2
+            dy = (p[1] - yc + ny / 2) % ny - ny / 2
+            if math.hypot(dx, dy) < post_radius + 0.5 + radius + clearance:
+                ok = False
+                break
+        if ok:
+            for q in cen:
+                d = p - q
+                d[0] = (d[0] + nx / 2) % nx - nx / 2
+                d[1] = (d[1] + ny / 2) % ny - ny / 2
+                if not walls_z:
+                    d[2] = (d[2] + nz / 2) % nz - nz / 2
+                if np.linalg.norm(d) < 2 * radius + clearance:
+                    ok = False
+                    break
+        if ok:
+            cen.append(p)
+    return np.array(cen, dtype=np.float64).reshape(n, 3)
+
+
+# ---------------------------------------------------------------------------
+# scenario record
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Cells:
+    """A population of closed membranes in one lattice."""
+    vert_off: np.ndarray   # int32 [ncells+1]
+    tri_off: np.ndarray    # int32 [ncells+1]
+    edge_off: np.ndarray   # int32 [ncells+1]
+    tri: np.ndarray        # int32 [ntris, 3]   global vertex ids
+    hinge: np.ndarray      # int32 [nedges, 4]  global vertex ids
+    anchor: np.ndarray     # int32 [ncells, 3]
+    offset: np.ndarray     # float32 [nverts, 3]
+    moduli: np.ndarray     # float64 [ncells, 5]  (k_s, k_b, k_al, k_ag, k_v)
+    xi: float = 1.0        # friction of the fluid-object coupling
+    mass: float = 1.0      # IB-point mass
+    dt: float = 1.0        # IB time step (one per lattice step)
+
+    @property
+    def ncells(self) -> int:
+        return len(self.vert_off) - 1
+
+    @property
+    def nverts(self) -> int:
+        return int(self.vert_off[-1])
+
+    @property
+    def ntris(self) -> int:
+        return int(self.tri_off[-1])
+
+    @property
+    def nedges(self) -> int:
+        return int(self.edge_off[-1])
+
+    def vertex_cell(self) -> np.ndarray:
+        return np.repeat(np.arange(self.ncells, dtype=np.int32), np.diff(self.vert_off))
+
+    def positions(self) -> np.ndarray:
+        """Absolute (unwrapped) IB-point positions, float64 [nverts, 3]."""
+        return self.anchor[self.vertex_cell()].astype(np.float64) + self.offset.astype(np.float64)
+
+
+def make_cells(centres: np.ndarray, radius: float, level: int,
+               moduli: Sequence[float] = MODULI_CTC, xi: float = 1.0) -> Cells:
+    """Icosphere cells of the given radius around ``centres`` [n,3]."""
+    unit, tris = icosphere(level)
+    hin = hinges(tris)
+    nv, nt, ne = len(unit), len(tris), len(hin)
+    n = len(centres)
+    anchor = np.floor(centres).astype(np.int32)
+    off = (radius * unit[None, :, :] + (centres - anchor)[:, None, :]).astype(np.float32)
+    base = (np.arange(n) * nv)[:, None, None]
+    return Cells(
+        vert_off=(np.arange(n + 1) * nv).astype(np.int32),
+        tri_off=(np.arange(n + 1) * nt).astype(np.int32),
+        edge_off=(np.arange(n + 1) * ne).astype(np.int32),
+        tri=(tris[None] + base).reshape(-1, 3).astype(np.int32),
+        hinge=(hin[None] + base).reshape(-1, 4).astype(np.int32),
+        anchor=anchor,
+        offset=off.reshape(-1, 3),
+        moduli=np.tile(np.asarray(moduli, dtype=np.float64), (n, 1)),
+        xi=xi)
+
+
+@dataclasses.dataclass
+class Scenario:
+    """One lattice workload: geometry, fluid parameters and (optionally) cells."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    tau: float
+    g: Tuple[float, float, float]
+    solid: np.ndarray                 # uint8 [nz, ny, nx]
+    steps: int
+    periodic: Tuple[int, int, int] = (1, 1, 1)
+    cells: Optional[Cells] = None
+    gfield: Optional[np.ndarray] = None   # float64 [3, nz, ny, nx] external forcing field G
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def fluid_fraction(self) -> float:
+        return float(1.0 - self.solid.mean())
+
+
+# ---------------------------------------------------------------------------
+# the workloads
+# ---------------------------------------------------------------------------
+
+def poiseuille(nx: int = 64, ny: int = 16, nz: int = 16, tau: float = 1.0, gx: float = 1e-6,
+               steps: int = 1000) -> Scenario:
+    """Plain D3Q19 channel, solid planes z = 0 and z = nz-1, body force along x.
+
+    Defaults: 64x16x16, tau = 1, g_x = 1e-6, 1000 steps."""
+    return Scenario("poiseuille", nx, ny, nz, tau, (gx, 0.0, 0.0), channel_mask(nx, ny, nz), steps)
+
+
+def posts_and_cells(nx: int = 256, ny: int = 128, nz: int = 64, *, posts_x: int = 4, posts_y: int = 2,
+                    post_radius: int = 8, gap: int = 12, ncells: int = 20, cell_radius: float = 4.0,
+                    level: int = 3, tau: float = 0.8, gx: float = 1e-5, steps: int = 2000,
+                    seed: int = 2, moduli=MODULI_CTC) -> Scenario:
+    """Channel with a regular post array and seeded cells.
+
+    Defaults: 256x128x64, 4x2 posts of radius 8 with gap 12, 20 cells of
+    radius 4 (icosphere level 3, 642 vertices), tau = 0.8, g_x = 1e-5."""
+    rng = np.random.default_rng(seed)
+    mask = channel_mask(nx, ny, nz)
+    centres = post_array_centres(nx, ny, [gap] * (posts_x - 1), [gap] * (posts_y - 1), post_radius) \
+        if posts_x * posts_y else []
+    add_posts(mask, centres, post_radius)
+    cells = None
+    if ncells:
+        cen = place_cells(rng, ncells, cell_radius, (nx, ny, nz), centres, post_radius)
+        cells = make_cells(cen, cell_radius, level, moduli)
+    return Scenario("posts_cells", nx, ny, nz, tau, (gx, 0.0, 0.0), mask, steps, cells=cells,
+                    meta=dict(post_centres=centres, post_radius=post_radius, seed=seed))
+
+
+def throughput(nx: int = 512, ny: int = 256, nz: int = 128, *, posts_x: int = 8, posts_y: int = 4,
+               post_radius: int = 8, gap_range=(6, 14), ncells: int = 400, cell_radius: float = 10.0,
+               level: int = 3, tau: float = 0.7, gx: float = 1e-5, steps: int = 1000,
+               seed: int = 3) -> Scenario:
+    """Large channel: 8x4 posts with integer gaps drawn from U{6..14}, 400
+    cells of 642 vertices (radius 10 gives about 10 % volume fraction)."""
+    rng = np.random.default_rng(seed)
+    mask = channel_mask(nx, ny, nz)
+    gx_ = rng.integers(gap_range[0], gap_range[1] + 1, size=posts_x - 1)
+    gy_ = rng.integers(gap_range[0], gap_range[1] + 1, size=posts_y - 1)
+    centres = post_array_centres(nx, ny, gx_, gy_, post_radius)
+    add_posts(mask, centres, post_radius)
+    cen = place_cells(rng, ncells, cell_radius, (nx, ny, nz), centres, post_radius)
+    cells = make_cells(cen, cell_radius, level)
+    vol = ncells * 4.0 / 3.0 * math.pi * cell_radius ** 3 / (nx * ny * nz)
+    return Scenario("throughput", nx, ny, nz, tau, (gx, 0.0, 0.0), mask, steps, cells=cells,
+                    meta=dict(post_centres=centres, post_radius=post_radius, seed=seed,
+                              gaps_x=gx_.tolist(), gaps_y=gy_.tolist(), volume_fraction=vol))
+
+
+def gap_sweep(nch: int = 64, *, lengths=(64, 128, 192, 256), ny: int = 64, nz: int = 32,
+              gap_range=(4, 16), post_radius: int = 8, ncells: int = 5, cell_radius: float = 4.0,
+              level: int = 3, tau: float = 0.8, gx: float = 1e-5, steps: int = 2000,
+              seed: int = 4) -> List[Scenario]:
+    """Independent channels of uneven length, each with one post pair across
+    the channel (gap drawn from U{4..16}) in front of which cells are seeded."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(nch):
+        L = int(rng.choice(lengths))
+        gap = int(rng.integers(gap_range[0], gap_range[1] + 1))
+        mask = channel_mask(L, ny, nz)
+        centres = [(L / 2.0, ny / 2.0 - (post_radius + gap / 2.0)),
+                   (L / 2.0, ny / 2.0 + (post_radius + gap / 2.0))]
+        add_posts(mask, centres, post_radius)
+        cells = None
+        if ncells:
+            cen = place_cells(rng, ncells, cell_radius, (L, ny, nz), centres, post_radius)
+            cells = make_cells(cen, cell_radius, level)
+        out.append(Scenario(f"channel{c}", L, ny, nz, tau, (gx, 0.0, 0.0), mask, steps, cells=cells,
+                            meta=dict(gap=gap, post_centres=centres, post_radius=post_radius)))
+    return out
+
+
+def adjoint_channel(nx: int = 128, ny: int = 64, nz: int = 32, *, ncells: int = 3,
+                    cell_radius: float = 4.0, level: int = 2, tau: float = 0.8, gx: float = 1e-5,
+                    steps: int = 300, seed: int = 5, design_x=(32, 96)) -> Scenario:
+    """Channel without posts, 3 cells of 162 vertices; the forcing field G
+    lives on the design slab design_x[0] <= x < design_x[1] (all y, z)."""
+    rng = np.random.default_rng(seed)
+    mask = channel_mask(nx, ny, nz)
+    cen = place_cells(rng, ncells, cell_radius, (nx, ny, nz))
+    cells = make_cells(cen, cell_radius, level)
+    return Scenario("adjoint", nx, ny, nz, tau, (gx, 0.0, 0.0), mask, steps, cells=cells,
+                    gfield=np.zeros((3, nz, ny, nx)),
+                    meta=dict(design_x=list(design_x), checkpoint_every=20, seed=seed))
+
+
+def design_region_size(s: Scenario) -> int:
+    x0, x1 = s.meta["design_x"]
+    return (x1 - x0) * s.ny * s.nz
+
+
+def random_directions(s: Scenario, count: int = 16, seed0: int = 0) -> np.ndarray:
+    """Seeded unit directions over the design region, [count, 3, nz, ny, x1-x0]."""
+    x0, x1 = s.meta["design_x"]
+    out = np.empty((count, 3, s.nz, s.ny, x1 - x0))
+    for k in range(count):
+        v = np.random.default_rng(seed0 + k).standard_normal((3, s.nz, s.ny, x1 - x0))
+        out[k] = v / np.linalg.norm(v)
+    return out
+
+
+def random_field(rng: np.random.Generator, shape, amp: float) -> np.ndarray:
+    """Seeded uniform noise in [-amp, amp] (float64), e.g. a forcing field G."""
+    return amp * rng.uniform(-1.0, 1.0, size=shape)
+
+
+def to_json(s: Scenario) -> str:
+    d = dict(name=s.name, nx=s.nx, ny=s.ny, nz=s.nz, tau=s.tau, g=list(s.g), steps=s.steps,
+             periodic=list(s.periodic), ncells=(s.cells.ncells if s.cells else 0),
+             nverts=(s.cells.nverts if s.cells else 0), meta=s.meta)
+    return json.dumps(d, default=float)
