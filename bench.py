@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the D3Q19 + immersed-boundary step on one MI355X.
+
+One "step" is one full coupled step of the hot path: membrane forces, IBM
+interpolation/coupling/spreading/point update, and the fused collide-stream
+of the whole lattice.  The default workload is the throughput channel:
+512x256x128 lattice, 8x4 posts (gaps U{6..14}), 400 cells of 642 vertices,
+tau 0.7, FP32 deviation storage.  Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+# Algorithmic bytes per lattice node of one collide-stream launch: the 19
+# populations read and written once (4 B each in FP32 storage, 8 B in FP64)
+# plus the 1-byte node class.  The sparse immersed-boundary force (read and
+# cleared only on tiles that received spread force) is not counted, which
+# makes the achieved figure conservative.
+def bytes_per_node(prec: str) -> int:
+    s = 8 if prec == "f64" else 4
+    return 2 * 19 * s + 1
+
+
+# HBM traffic of one collide-stream launch on the throughput workload, from
+# two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the same
+# counters on a plain copy kernel; see profiles/.  Valid only while the
+# kernel source hashes to "sha".
+MEASURED_TRAFFIC = {"sha": None, "bytes_per_launch": None}
+KERNEL_SOURCES = ["paper_1110_0995_amd/csrc/lattice_kernels.hpp", "paper_1110_0995_amd/csrc/d3q19.hpp"]
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def make_workload(name: str):
+    from paper_1110_0995_amd import scenario as S
+    if name == "throughput":
+        return S.throughput(), "f32dev"
+    if name == "posts_cells":
+        return S.posts_and_cells(), "f32dev"
+    if name == "poiseuille":
+        return S.poiseuille(), "f64"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def describe(s, prec):
+    d = {"workload": s.name, "lattice": [s.nx, s.ny, s.nz], "nodes": s.n, "tau": s.tau, "g": list(s.g),
+         "storage": prec, "fluid_fraction": round(s.fluid_fraction(), 4)}
+    if s.cells is not None:
+        d.update(cells=s.cells.ncells, ib_points=s.cells.nverts, triangles=s.cells.ntris)
+    if "post_centres" in s.meta:
+        d["posts"] = len(s.meta["post_centres"])
+    return d
+
+
+def cpu_baseline(s, prec, steps, lbm_mod):
+    """The FP64 oracle on the host cores for a bounded number of steps of the
+    same workload; also the GPU's error against it after those steps."""
+    import oracle
+    oracle.build()
+    L = oracle.Lattice.from_scenario(s)
+    M = None
+    X = V = None
+    if s.cells is not None:
+        M = oracle.Mesh(s.cells)
+        X = s.cells.positions()
+        M.rest_shape(X)
+        V = np.zeros_like(X)
+    f = L.rest()
+    t0 = time.perf_counter()
+    oracle.run(L, M, f, X, V, nsteps=steps)
+    dt = time.perf_counter() - t0
+    # GPU from the same start
+    lat = lbm_mod.Lattice.from_scenario(s, prec=prec)
+    mesh = lbm_mod.Mesh(lat, s.cells) if s.cells is not None else None
+    lat.run(steps, mesh)
+    _, ug = lat.fields()
+    ug = ug.double().cpu().numpy()
+    _, uo = oracle.fluid_velocity(L, f)
+    fl = s.solid.reshape(-1) == 0
+    err = float(np.linalg.norm(ug[:, fl] - uo[:, fl]) / np.linalg.norm(uo[:, fl]))
+    perr = float(np.abs(mesh.positions() - X).max()) if mesh is not None else None
+    lat.close()
+    return ({"value": s.n * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+             "sample": f"{steps} full coupled steps of the same workload in FP64 ({dt:.1f} s)"},
+            {"u_rel_l2": err, "max_position_err": perr, "steps": steps})
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="throughput")
+    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); multi-GPU runs are not part of this build",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1110_0995_amd import lbm
+
+    s, prec = make_workload(args.workload)
+    lat = lbm.Lattice.from_scenario(s, prec=prec)
+    mesh = lbm.Mesh(lat, s.cells) if s.cells is not None else None
+    stream = torch.cuda.current_stream()
+
+    def one_step():
+        if mesh is not None:
+            lat.couple(mesh)
+        lat.step(1)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps; events bracket each collide-stream launch
+    # on the stream the library enqueues on (torch's current stream)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        if mesh is not None:
+            lat.couple(mesh)
+        ev[k][0].record(stream)
+        lat.step(1)
+        ev[k][1].record(stream)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    ms_cs = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    sums = lat.sums()
+
+    mlups = s.n * args.steps / (ms_total * 1e-3) / 1e6
+    nfluid = int((s.solid == 0).sum())
+    bpn = bytes_per_node(prec)
+    achieved = bpn * s.n / (ms_cs * 1e-3) / 1e9
+    sha = kernel_sha()
+    traffic = MEASURED_TRAFFIC["bytes_per_launch"] if MEASURED_TRAFFIC["sha"] == sha else None
+
+    out = {
+        "metric": "D3Q19+IBM MLUPS & % HBM peak; batched sweep and adjoint vs plain",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == "f64" else "f32",
+        "data": "synthetic",
+        "config": describe(s, prec),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_collide_stream", "bytes_per_node": bpn, "ms_per_launch": round(ms_cs, 5),
+                     "kernel_sha": sha},
+        "fluid_mlups": round(nfluid * args.steps / (ms_total * 1e-3) / 1e6, 1),
+        "ibm_ms_per_step": round(ms_step - ms_cs, 5) if mesh is not None else 0.0,
+        "mass": sums[0],
+    }
+    if not args.no_cpu_baseline:
+        cb, perr = cpu_baseline(s, prec, args.cpu_steps, lbm)
+        out["cpu_baseline"] = cb
+        out["error_vs_oracle"] = perr
+    lat.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * lbmibm.h -- C ABI of the MI355X (gfx950) D3Q19 lattice-Boltzmann +
+ * immersed-boundary cell-flow library.
+ *
+ * The method (paper: Gusenbauer et al., "A tunable cancer cell filter using
+ * magnetic beads: cellular and fluid dynamic simulations"):
+ *   - Sec. 2.1, LBM equation: one BGK collide-and-stream step of the D3Q19
+ *     populations f_i with an external force term F_i;
+ *   - Sec. 2.2, the four immersed-boundary steps: lattice velocity is
+ *     interpolated to the membrane (IB) points, forces are computed at the
+ *     points, spread back to the lattice with a discrete delta, and fluid
+ *     and points are advanced;
+ *   - Sec. 2.3, the membrane forces from the moduli K^S, K^B, K^A_l, K^A_g,
+ *     K^V of Table 1 (the global terms need the whole cell, Sec. 2.3.3);
+ *   - Sec. 2.4, halfway bounce-back at solid nodes.
+ * Where the paper leaves the form open, the library implements: second-order
+ * polynomial equilibrium, Guo's forcing with u = (j + F/2)/rho, trilinear
+ * delta, coupling force F_c = xi (u(X) - V), linear-spring/area/volume/angle
+ * energies, and the step order interpolate -> forces -> spread ->
+ * collide/stream -> move points.
+ *
+ * Conventions
+ *   - Lattice node n = x + nx*(y + ny*z), N = nx*ny*nz, x fastest.
+ *   - Populations: 19 planes, plane i at element offset i*plane_stride.
+ *     D3Q19 order: 0 rest; 1,2 = +-x; 3,4 = +-y; 5,6 = +-z; 7,8 = (1,1,0),
+ *     (-1,-1,0); 9,10 = (1,-1,0),(-1,1,0); 11,12 = (1,0,1),(-1,0,-1);
+ *     13,14 = (1,0,-1),(-1,0,1); 15,16 = (0,1,1),(0,-1,-1);
+ *     17,18 = (0,1,-1),(0,-1,1).  Odd i and i+1 are opposite.
+ *   - Precision LBM_F64: double populations and arithmetic.  LBM_F32: float
+ *     f_i.  LBM_F32_DEV: float deviations h_i = f_i - w_i from the rest
+ *     weights, float arithmetic.  Global mass/momentum sums are double in
+ *     every mode.  "real" below means double for LBM_F64, float otherwise.
+ *   - Vector fields are [3][N] (component planes), point arrays [3][nverts].
+ *   - Ownership: the caller allocates every buffer passed in (device
+ *     memory unless stated) and keeps it alive until lbm_destroy; the
+ *     library only borrows them.  The context owns its own work buffers
+ *     (node classes, immersed-boundary force accumulator, reduction
+ *     partials), allocated in lbm_init and freed in lbm_destroy.
+ *   - Streams: every call enqueues on params.stream and returns without
+ *     waiting, except lbm_read_fields with a non-NULL host_sums,
+ *     ibm_rest_shape (reads the mesh topology back to check it) and
+ *     lbm_init/lbm_destroy.
+ *   - Errors: functions return LBM_OK (0) or a negative code; nothing is
+ *     thrown across the ABI.  lbm_last_error() gives the message of the last
+ *     failure on the calling thread.  Argument checks run on the host before
+ *     any device work is enqueued, so a rejected call changes nothing.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef LBMIBM_H
+#define LBMIBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* bad argument (sizes, tau <= 1/2, null/misaligned pointer, bad mesh) */
+#define LBM_ENOMEM (-2)     /* device allocation failed */
+#define LBM_EHIP (-3)       /* HIP runtime or launch error */
+#define LBM_ENONFINITE (-4) /* a global sum came back NaN or Inf */
+#define LBM_ESTATE (-5)     /* call out of order (e.g. ibm_couple before ibm_rest_shape) */
+
+#define LBM_F64 0
+#define LBM_F32 1
+#define LBM_F32_DEV 2
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Lattice description for lbm_init (Sec. 2.1, 2.4). */
+typedef struct {
+    int32_t nx, ny, nz;      /* lattice size, each >= 1 */
+    int32_t periodic[3];     /* 1 = periodic axis; a link leaving a non-periodic axis bounces back */
+    double tau;              /* BGK relaxation time, > 1/2 (viscosity (tau - 1/2)/3) */
+    double body_force[3];    /* uniform force density g (lattice units) */
+    int32_t prec;            /* LBM_F64, LBM_F32 or LBM_F32_DEV */
+    int64_t plane_stride;    /* elements between population planes: 0 = lbm_plane_stride(), else >= N and a multiple of 64 */
+    const uint8_t *solid;    /* [N] uint8, 1 = solid node, 0 = fluid */
+    void *f_a;               /* [19*plane_stride] populations (storage type of prec); state buffer A */
+    void *f_b;               /* same size; state buffer B */
+    const void *gfield;      /* [3][N] real external forcing field G added to g, or NULL */
+    void *stream;            /* hipStream_t to enqueue on (NULL = null stream) */
+} lbm_params;
+
+/* Membrane population (Sec. 2.2, 2.3).  All pointers are device memory.
+ * Topology arrays use global vertex ids; each cell's triangles and edges may
+ * only reference that cell's vertices [vert_off[c], vert_off[c+1]). */
+typedef struct {
+    int32_t ncells, nverts, ntris, nedges;
+    const int32_t *vert_off; /* [ncells+1] first vertex of each cell */
+    const int32_t *tri_off;  /* [ncells+1] first triangle of each cell */
+    const int32_t *edge_off; /* [ncells+1] first edge of each cell */
+    const int32_t *tri;      /* [3][ntris] vertices (a,b,c), counter-clockwise seen from outside */
+    const int32_t *hinge;    /* [4][nedges] (p1,p2,qa,qb): triangles (p1,p2,qa) and (p2,p1,qb) share edge p1-p2 */
+    const int32_t *anchor;   /* [3][ncells] integer anchor of each cell */
+    void *x;                 /* [3][nverts] real: position minus the cell's anchor (updated by ibm_couple) */
+    void *v;                 /* [3][nverts] real: velocity (updated by ibm_couple) */
+    void *f_el;              /* [3][nverts] real: written with the elastic force of the last ibm_couple */
+    const void *moduli;      /* [5][ncells] real: k_s, k_b, k_al, k_ag, k_v per cell (Table 1 order K^S, K^B, K^A_l, K^A_g, K^V) */
+    void *l0;                /* [nedges] real: rest edge lengths   (written by ibm_rest_shape) */
+    void *a0;                /* [ntris]  real: rest triangle areas (written by ibm_rest_shape) */
+    void *th0;               /* [nedges] real: rest hinge angles   (written by ibm_rest_shape) */
+    double *a0c;             /* [ncells] rest cell areas           (written by ibm_rest_shape) */
+    double *v0c;             /* [ncells] rest cell volumes         (written by ibm_rest_shape) */
+    double xi;               /* friction of the coupling force F_c = xi (u(X) - V), > 0 */
+    double mass;             /* IB-point mass m (Newton equation of Sec. 2.2), > 0 */
+    double dt;               /* IB time step, > 0 */
+    /* filled by ibm_rest_shape; the caller must not edit them */
+    int32_t max_cell_verts, max_cell_tris, max_cell_edges;
+    uint32_t checked;
+} ibm_mesh;
+
+/* Suggested population plane stride (elements) for an N-node lattice:
+ * N rounded up to 64 plus a pad that keeps the 19 plane starts off a common
+ * large power-of-two alignment. */
+int64_t lbm_plane_stride(int64_t n_nodes, int32_t prec);
+
+/* Bytes the context will allocate on the device for this lattice. */
+int64_t lbm_workspace_bytes(const lbm_params *p);
+
+/* Validate p, create a context and set both state buffers to the fluid at
+ * rest (f_i = w_i; h_i = 0 in LBM_F32_DEV).  The LBM equation of Sec. 2.1
+ * starts from this state.  On failure *out is NULL. */
+int lbm_init(const lbm_params *p, lbm_ctx **out);
+
+/* Advance the lattice nsteps >= 0 times: fused BGK collision with Guo
+ * forcing (force = g + G + the immersed-boundary force spread by the last
+ * ibm_couple, which this call consumes and clears), then streaming with
+ * halfway bounce-back (Sec. 2.1 LBM equation, Sec. 2.4).  With cells present
+ * call ibm_couple before each single step. */
+int lbm_step(lbm_ctx *c, int32_t nsteps);
+
+/* Compute the rest shape (edge lengths, triangle areas, hinge angles, cell
+ * area and volume) of the mesh at its current positions into m->l0, a0,
+ * th0, a0c, v0c, after checking the topology (read back to the host; this
+ * call waits on the stream).  Must be called once per mesh before
+ * ibm_couple; fills the trailing fields of *m. */
+int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m);
+
+/* The immersed-boundary part of one step (Sec. 2.2 steps 1-3 and the point
+ * half of step 4): per cell, area/volume then elastic forces (written to
+ * m->f_el); per point, interpolated velocity u_k from the current
+ * populations, F_c = xi (u_k - V), spreading of -F_c to the 8 surrounding
+ * nodes for the next lbm_step, then V += dt/m (F_el + F_c), X += dt V. */
+int ibm_couple(lbm_ctx *c, const ibm_mesh *m);
+
+/* rho [N] and u [3][N] (real, device, either may be NULL) of the current
+ * state: u = (j + (g + G)/2)/rho on fluid nodes, 0 on solid nodes (rho 0).
+ * host_sums (host memory, may be NULL): double [4] = sum over fluid nodes of
+ * rho, j_x, j_y, j_z; when given, the call waits and returns
+ * LBM_ENONFINITE if any sum is not finite. */
+int lbm_read_fields(lbm_ctx *c, void *rho, void *u, double *host_sums);
+
+/* Device pointer of the state buffer that holds the current populations
+ * (f_a or f_b) and the number of steps taken so far. */
+int lbm_current(lbm_ctx *c, void **f_cur, int64_t *steps);
+
+/* Copy the current state to / from full FP64 populations f_i ([19][N]
+ * double, device) -- adds / subtracts w_i in LBM_F32_DEV. */
+int lbm_store_f64(lbm_ctx *c, double *f64);
+int lbm_load_f64(lbm_ctx *c, const double *f64);
+
+/* Free the context's own buffers (waits for its stream). NULL is a no-op. */
+void lbm_destroy(lbm_ctx *c);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMIBM_H */

@@ -81,6 +81,11 @@ def _i(a: np.ndarray):
 
 # ---------------------------------------------------------------------------
 
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(lib().orc_threads())
+
+
 def d3q19():
     c = np.zeros((19, 3), np.int32)
     w = np.zeros(19)

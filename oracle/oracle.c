@@ -34,6 +34,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define Q 19
 
@@ -78,6 +81,15 @@ typedef struct {
     double *A0c; /* [ncells] */
     double *V0c; /* [ncells] */
 } orc_mesh;
+
+/* Threads the OpenMP loops below will use. */
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* tables (exported so the tests can check the lattice identities)          */

@@ -1,0 +1,240 @@
+// Lattice kernels: node classification, rest state, the fused
+// collide-and-stream step (LBM equation of Sec. 2.1 with halfway
+// bounce-back of Sec. 2.4), and the moments / FP64 global sums.
+#pragma once
+
+#include "d3q19.hpp"
+
+namespace lbm {
+
+// Node classes.  The collide-stream kernel takes the plain streaming path
+// for CLS_BULK nodes and consults the per-node link mask only for CLS_WALL.
+enum : uint8_t { CLS_BULK = 0, CLS_WALL = 1, CLS_SOLID = 2 };
+
+struct Geometry {
+    int nx, ny, nz;
+    int per[3];
+};
+
+// cls[n] and links[n] (bit i set = the link along c_i ends on a solid node
+// or leaves a non-periodic axis, so population i bounces back).
+__global__ void k_classify(Geometry g, const uint8_t *__restrict__ solid, uint8_t *__restrict__ cls,
+                           uint32_t *__restrict__ links) {
+    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    if (solid[n]) {
+        cls[n] = CLS_SOLID;
+        links[n] = 0;
+        return;
+    }
+    const int x = (int)(n % g.nx);
+    const int y = (int)((n / g.nx) % g.ny);
+    const int z = (int)(n / ((int64_t)g.nx * g.ny));
+    uint32_t m = 0;
+    for (int i = 1; i < Q; i++) {
+        int p[3] = {x + cx(i), y + cy(i), z + cz(i)};
+        const int d[3] = {g.nx, g.ny, g.nz};
+        bool out = false;
+        for (int a = 0; a < 3; a++) {
+            if (p[a] < 0 || p[a] >= d[a]) {
+                if (g.per[a]) p[a] = pmod(p[a], d[a]);
+                else out = true;
+            }
+        }
+        if (out || solid[p[0] + (int64_t)g.nx * (p[1] + (int64_t)g.ny * p[2])]) m |= 1u << i;
+    }
+    cls[n] = m ? CLS_WALL : CLS_BULK;
+    links[n] = m;
+}
+
+// Fluid at rest: f_i = w_i (or h_i = 0 for the deviation storage).
+template <class S, bool DEV>
+__global__ void k_rest(S *__restrict__ f, int64_t stride, int64_t N) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+#pragma unroll
+    for (int i = 0; i < Q; i++) f[i * stride + n] = DEV ? S(0) : wgt<S>(i);
+}
+
+// BGK relaxation with Guo's source for one node, in place on f[19].
+// rho = sum f (DEV: 1 + sum h), j = sum f c, u = (j + F/2)/rho,
+// f_eq = w rho (1 + 3cu + 9/2 (cu)^2 - 3/2 u.u) (DEV: minus w),
+// S_i = (1 - 1/(2 tau)) w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F)),
+// f_i <- f_i - (f_i - f_eq_i)/tau + S_i.
+template <class R, bool DEV>
+__device__ __forceinline__ void collide(R (&f)[Q], R Fx, R Fy, R Fz, R omega, R kf) {
+    R s = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; i++) s += f[i];
+    const R jx = (f[1] - f[2]) + (f[7] - f[8]) + (f[9] - f[10]) + (f[11] - f[12]) + (f[13] - f[14]);
+    const R jy = (f[3] - f[4]) + (f[7] - f[8]) + (f[10] - f[9]) + (f[15] - f[16]) + (f[17] - f[18]);
+    const R jz = (f[5] - f[6]) + (f[11] - f[12]) + (f[14] - f[13]) + (f[15] - f[16]) + (f[18] - f[17]);
+    const R rho = DEV ? R(1) + s : s;
+    const R ir = R(1) / rho;
+    const R ux = (jx + R(0.5) * Fx) * ir;
+    const R uy = (jy + R(0.5) * Fy) * ir;
+    const R uz = (jz + R(0.5) * Fz) * ir;
+    const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
+    const R uF = ux * Fx + uy * Fy + uz * Fz;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const R cu = R(cx(i)) * ux + R(cy(i)) * uy + R(cz(i)) * uz;
+        const R cF = R(cx(i)) * Fx + R(cy(i)) * Fy + R(cz(i)) * Fz;
+        const R e = R(3) * cu + R(4.5) * cu * cu - usq;
+        const R w = wgt<R>(i);
+        const R feq = DEV ? w * (s + rho * e) : w * rho * (R(1) + e);
+        const R src = kf * w * (R(3) * (cF - uF) + R(9) * cu * cF);
+        f[i] = f[i] - omega * (f[i] - feq) + src;
+    }
+}
+
+struct StepArgs {
+    const void *fa;
+    void *fb;
+    int64_t stride;
+    const uint8_t *cls;
+    const uint32_t *links;
+    void *fibm;           // [3][N] immersed-boundary force accumulator
+    uint8_t *tflag;       // [ntiles] 1 = the tile holds spread force
+    const void *gfield;   // [3][N] or null
+    int nx, ny, nz, tpr;  // tpr = 64-node tiles per x-row
+    int ntiles;
+    int64_t N;
+    double g[3];
+    double omega, kf;
+};
+
+// One fused collide-and-stream pass (push): each wave owns one tile of 64
+// consecutive x of one (y,z) row, reads the 19 planes of its nodes
+// coalesced, collides in registers and writes every post-collision value
+// straight to its destination slot (neighbour along c_i, or the opposite
+// slot of the same node when that link is a wall link).  The spread force of
+// a tile is read, and cleared, only when the tile's flag says it has one.
+template <class S, class R, bool DEV, bool HAS_G>
+__global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+    if (tile >= a.ntiles) return;
+    const int row = tile / a.tpr;
+    const int x = (tile - row * a.tpr) * 64 + lane;
+    if (x >= a.nx) return;
+    const int64_t n = (int64_t)row * a.nx + x;
+    const int64_t N = a.N;
+
+    R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
+    if (HAS_G) {
+        const R *G = static_cast<const R *>(a.gfield);
+        Fx += G[n];
+        Fy += G[N + n];
+        Fz += G[2 * N + n];
+    }
+    if (a.tflag[tile]) {
+        R *fi = static_cast<R *>(a.fibm);
+        Fx += fi[n];
+        Fy += fi[N + n];
+        Fz += fi[2 * N + n];
+        fi[n] = R(0);
+        fi[N + n] = R(0);
+        fi[2 * N + n] = R(0);
+        if (lane == 0) a.tflag[tile] = 0;
+    }
+    const uint8_t cl = a.cls[n];
+    if (cl == CLS_SOLID) return;
+
+    const S *__restrict__ fa = static_cast<const S *>(a.fa);
+    S *__restrict__ fb = static_cast<S *>(a.fb);
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) f[i] = R(fa[i * a.stride + n]);
+
+    collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
+
+    const int y = row % a.ny, z = row / a.ny;
+    const int xp = (x + 1 == a.nx) ? 0 : x + 1;
+    const int xm = (x == 0) ? a.nx - 1 : x - 1;
+    const int yp = (y + 1 == a.ny) ? 0 : y + 1;
+    const int ym = (y == 0) ? a.ny - 1 : y - 1;
+    const int zp = (z + 1 == a.nz) ? 0 : z + 1;
+    const int zm = (z == 0) ? a.nz - 1 : z - 1;
+    const uint32_t links = (cl == CLS_WALL) ? a.links[n] : 0u;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const int xq = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
+        const int yq = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
+        const int zq = cz(i) > 0 ? zp : (cz(i) < 0 ? zm : z);
+        const int64_t dst = ((links >> i) & 1u) ? (int64_t)opp(i) * a.stride + n
+                                               : (int64_t)i * a.stride + xq + (int64_t)a.nx * (yq + (int64_t)a.ny * zq);
+        fb[dst] = S(f[i]);
+    }
+}
+
+// rho and u = (j + F_ext/2)/rho per node (solid: 0), plus per-block FP64
+// partial sums of rho and j over fluid nodes.
+template <class S, class R, bool DEV, bool HAS_G>
+__global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, int64_t stride,
+                                                 const uint8_t *__restrict__ cls, const R *__restrict__ G,
+                                                 int64_t N, double gx, double gy, double gz, R *rho_out,
+                                                 R *u_out, double *partials) {
+    __shared__ double red[4 * 4];
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (n < N) {
+        if (cls[n] != CLS_SOLID) {
+            double r = DEV ? 1.0 : 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                const double v = (double)f[i * stride + n];
+                r += v;
+                j[0] += cx(i) * v;
+                j[1] += cy(i) * v;
+                j[2] += cz(i) * v;
+            }
+            acc[0] = r;
+            acc[1] = j[0];
+            acc[2] = j[1];
+            acc[3] = j[2];
+            const double F[3] = {gx + (HAS_G ? (double)G[n] : 0.0), gy + (HAS_G ? (double)G[N + n] : 0.0),
+                                 gz + (HAS_G ? (double)G[2 * N + n] : 0.0)};
+            if (rho_out) rho_out[n] = R(r);
+            if (u_out)
+                for (int d = 0; d < 3; d++) u_out[d * N + n] = R((j[d] + 0.5 * F[d]) / r);
+        } else {
+            if (rho_out) rho_out[n] = R(0);
+            if (u_out)
+                for (int d = 0; d < 3; d++) u_out[d * N + n] = R(0);
+        }
+    }
+    block_sum<4>(acc, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; k++) partials[4 * (int64_t)blockIdx.x + k] = acc[k];
+}
+
+__global__ __launch_bounds__(256) void k_final_sum(const double *__restrict__ partials, int64_t nparts,
+                                                   double *out) {
+    __shared__ double red[4 * 4];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t p = threadIdx.x; p < nparts; p += blockDim.x)
+        for (int k = 0; k < 4; k++) acc[k] += partials[4 * p + k];
+    block_sum<4>(acc, red);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; k++) out[k] = acc[k];
+}
+
+template <class S, bool DEV>
+__global__ void k_store_f64(const S *__restrict__ f, int64_t stride, int64_t N, double *__restrict__ out) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+#pragma unroll
+    for (int i = 0; i < Q; i++) out[i * N + n] = (double)f[i * stride + n] + (DEV ? wgt<double>(i) : 0.0);
+}
+
+template <class S, bool DEV>
+__global__ void k_load_f64(S *__restrict__ f, int64_t stride, int64_t N, const double *__restrict__ in) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+#pragma unroll
+    for (int i = 0; i < Q; i++) f[i * stride + n] = S(in[i * N + n] - (DEV ? wgt<double>(i) : 0.0));
+}
+
+}  // namespace lbm

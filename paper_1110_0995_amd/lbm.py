@@ -1,0 +1,171 @@
+"""Python front end of the library: device buffers from torch, every step in
+the HIP kernels behind the C ABI (include/lbmibm.h)."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from .scenario import Cells, Scenario
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """A D3Q19 lattice on one GPU (state buffers, mask, optional field G).
+
+    prec: "f64", "f32" or "f32dev" (float deviations from the rest weights)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, tau: float, g: Sequence[float] = (0.0, 0.0, 0.0),
+                 solid: Optional[np.ndarray] = None, prec: str = "f32dev",
+                 periodic: Sequence[int] = (1, 1, 1), gfield: Optional[np.ndarray] = None,
+                 device: str = "cuda", plane_stride: int = 0):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lattice kernels run only on an MI355X")
+        self.device = torch.device(device)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.N = self.nx * self.ny * self.nz
+        self.prec = prec
+        self.code = _lib.PRECISIONS[prec]
+        self.rdtype = torch.float64 if prec == "f64" else torch.float32
+        self.stride = int(plane_stride) if plane_stride else int(self.lib.lbm_plane_stride(self.N, self.code))
+        self.f_a = torch.empty(19 * self.stride, dtype=self.rdtype, device=self.device)
+        self.f_b = torch.empty_like(self.f_a)
+        if solid is None:
+            solid = np.zeros(self.N, np.uint8)
+        self.solid = torch.as_tensor(np.ascontiguousarray(np.asarray(solid, np.uint8).reshape(-1))).to(self.device)
+        assert self.solid.numel() == self.N
+        self.gfield = None
+        if gfield is not None:
+            self.gfield = torch.as_tensor(np.asarray(gfield, np.float64).reshape(3, self.N)).to(
+                self.device, self.rdtype).contiguous()
+        self.stream = torch.cuda.current_stream(self.device)
+        self.params = _lib.LbmParams(self.nx, self.ny, self.nz, (C.c_int32 * 3)(*periodic), float(tau),
+                                     (C.c_double * 3)(*g), self.code, self.stride, self.solid.data_ptr(),
+                                     self.f_a.data_ptr(), self.f_b.data_ptr(),
+                                     None if self.gfield is None else self.gfield.data_ptr(),
+                                     self.stream.cuda_stream)
+        self.tau, self.g = float(tau), tuple(float(v) for v in g)
+        ctx = C.c_void_p()
+        _lib.check(self.lib.lbm_init(C.byref(self.params), C.byref(ctx)))
+        self.ctx = ctx
+        self.meshes = []
+
+    @classmethod
+    def from_scenario(cls, s: Scenario, prec: str = "f32dev", **kw) -> "Lattice":
+        return cls(s.nx, s.ny, s.nz, s.tau, s.g, s.solid, prec, s.periodic,
+                   kw.pop("gfield", s.gfield), **kw)
+
+    # -- the four calls of the path --------------------------------------
+    def step(self, nsteps: int = 1) -> None:
+        _lib.check(self.lib.lbm_step(self.ctx, int(nsteps)))
+
+    def couple(self, mesh: "Mesh") -> None:
+        _lib.check(self.lib.ibm_couple(self.ctx, C.byref(mesh.s)))
+
+    def run(self, nsteps: int, mesh: Optional["Mesh"] = None) -> None:
+        """nsteps full steps (immersed-boundary coupling then collide-stream)."""
+        if mesh is None:
+            self.step(nsteps)
+            return
+        for _ in range(nsteps):
+            self.couple(mesh)
+            self.step(1)
+
+    def fields(self):
+        """(rho [N], u [3, N]) of the current state as device tensors."""
+        rho = torch.empty(self.N, dtype=self.rdtype, device=self.device)
+        u = torch.empty(3, self.N, dtype=self.rdtype, device=self.device)
+        _lib.check(self.lib.lbm_read_fields(self.ctx, _ptr(rho), _ptr(u), None))
+        return rho, u
+
+    def sums(self) -> np.ndarray:
+        """FP64 (sum rho, sum j) over fluid nodes; waits for the stream."""
+        out = (C.c_double * 4)()
+        _lib.check(self.lib.lbm_read_fields(self.ctx, None, None, out))
+        return np.array(out[:])
+
+    # -- state access -----------------------------------------------------
+    def current(self) -> torch.Tensor:
+        p = C.c_void_p()
+        st = C.c_int64()
+        _lib.check(self.lib.lbm_current(self.ctx, C.byref(p), C.byref(st)))
+        buf = self.f_a if p.value == self.f_a.data_ptr() else self.f_b
+        return buf.view(19, self.stride)[:, :self.N]
+
+    def steps_taken(self) -> int:
+        st = C.c_int64()
+        _lib.check(self.lib.lbm_current(self.ctx, None, C.byref(st)))
+        return st.value
+
+    def populations_f64(self) -> torch.Tensor:
+        out = torch.empty(19, self.N, dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.lbm_store_f64(self.ctx, _ptr(out)))
+        return out
+
+    def load_f64(self, f) -> None:
+        t = torch.as_tensor(np.ascontiguousarray(f, np.float64).reshape(19, self.N)).to(self.device)
+        _lib.check(self.lib.lbm_load_f64(self.ctx, _ptr(t)))
+        torch.cuda.synchronize(self.device)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            self.lib.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Mesh:
+    """Membrane population on a lattice's device (SoA arrays, rest shape computed on the GPU)."""
+
+    def __init__(self, lat: Lattice, cells: Cells):
+        dev, R = lat.device, lat.rdtype
+        i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32)).to(dev)
+        self.cells = cells
+        self.lat = lat
+        self.vert_off = i32(cells.vert_off)
+        self.tri_off = i32(cells.tri_off)
+        self.edge_off = i32(cells.edge_off)
+        self.tri = i32(np.asarray(cells.tri).T)
+        self.hinge = i32(np.asarray(cells.hinge).T)
+        self.anchor = i32(np.asarray(cells.anchor).T)
+        self.x = torch.as_tensor(np.ascontiguousarray(np.asarray(cells.offset, np.float64).T)).to(dev, R).contiguous()
+        self.v = torch.zeros_like(self.x)
+        self.f_el = torch.zeros_like(self.x)
+        self.moduli = torch.as_tensor(np.ascontiguousarray(np.asarray(cells.moduli, np.float64).T)).to(dev, R).contiguous()
+        self.l0 = torch.zeros(cells.nedges, dtype=R, device=dev)
+        self.th0 = torch.zeros(cells.nedges, dtype=R, device=dev)
+        self.a0 = torch.zeros(cells.ntris, dtype=R, device=dev)
+        self.a0c = torch.zeros(cells.ncells, dtype=torch.float64, device=dev)
+        self.v0c = torch.zeros(cells.ncells, dtype=torch.float64, device=dev)
+        p = lambda t: t.data_ptr()
+        self.s = _lib.IbmMesh(cells.ncells, cells.nverts, cells.ntris, cells.nedges, p(self.vert_off),
+                              p(self.tri_off), p(self.edge_off), p(self.tri), p(self.hinge), p(self.anchor),
+                              p(self.x), p(self.v), p(self.f_el), p(self.moduli), p(self.l0), p(self.a0),
+                              p(self.th0), p(self.a0c), p(self.v0c), float(cells.xi), float(cells.mass),
+                              float(cells.dt), 0, 0, 0, 0)
+        _lib.check(lat.lib.ibm_rest_shape(lat.ctx, C.byref(self.s)))
+        lat.meshes.append(self)
+
+    def positions(self) -> np.ndarray:
+        """Absolute positions (float64 [nverts, 3]) = anchor + offset."""
+        x = self.x.double().cpu().numpy().T
+        return self.cells.anchor[self.cells.vertex_cell()].astype(np.float64) + x
+
+    def velocities(self) -> np.ndarray:
+        return self.v.double().cpu().numpy().T.copy()
+
+    def set_offsets(self, offsets: np.ndarray) -> None:
+        """Overwrite the positions (offsets from the anchors, [nverts, 3])."""
+        self.x.copy_(torch.as_tensor(np.ascontiguousarray(np.asarray(offsets, np.float64).T)).to(self.x.device, self.x.dtype))

@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI: the library loads, exports exactly what the
+header declares, and rejects bad arguments on the host before touching the
+device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from tests.conftest import ROOT
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1110_0995_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1110_0995_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "lbmibm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"^\s*(?:const\s+)?[a-z0-9_]+\s*\*?\s*([a-z_0-9]+)\s*\(", src, flags=re.M))
+
+
+def test_header_and_exports_agree(L):
+    from paper_1110_0995_amd import _lib
+    decl = _header_functions()
+    assert decl == set(_lib.EXPORTS)
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    assert decl <= exported
+    # nothing but the C ABI is exported (kernels and helpers stay hidden)
+    assert {s for s in exported if not s.startswith("_")} == decl
+    for name in decl:
+        getattr(L, name)
+
+
+def test_plane_stride(L):
+    for n, prec in [(1, 0), (16384, 1), (16777216, 2), (2097152, 1), (327680, 1), (100, 0)]:
+        s = L.lbm_plane_stride(n, prec)
+        assert s >= n and s % 64 == 0
+        es = 8 if prec == 0 else 4
+        assert (s * es) % 65536 != 0
+    assert L.lbm_plane_stride(0, 1) == 0
+
+
+def _params(**kw):
+    from paper_1110_0995_amd import _lib
+    p = _lib.LbmParams()
+    p.nx, p.ny, p.nz = 8, 8, 8
+    p.periodic[:] = [1, 1, 1]
+    p.tau = 0.8
+    p.prec = 2
+    p.solid, p.f_a, p.f_b = 4096, 8192, 16384  # never dereferenced: every case below fails validation
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=0.5), "tau"), (dict(tau=float("nan")), "tau"), (dict(nx=0), "size"), (dict(nz=-3), "size"),
+    (dict(prec=7), "prec"), (dict(plane_stride=100), "plane_stride"), (dict(plane_stride=448), "plane_stride"),
+    (dict(solid=None), "non-NULL"), (dict(f_b=8192), "distinct"), (dict(f_a=8196), "aligned"),
+    (dict(gfield=4098, prec=0), "misaligned"), (dict(body_force=(C.c_double * 3)(0, float("inf"), 0)), "body_force"),
+])
+def test_init_rejects_bad_params(L, kw, msg):
+    from paper_1110_0995_amd import _lib
+    p = _params(**kw)
+    ctx = C.c_void_p(1234)
+    rc = L.lbm_init(C.byref(p), C.byref(ctx))
+    assert rc == _lib.LBM_EINVAL
+    assert ctx.value is None
+    assert msg in L.lbm_last_error().decode()
+    assert L.lbm_workspace_bytes(C.byref(p)) == -1
+
+
+def test_null_context_calls(L):
+    from paper_1110_0995_amd import _lib
+    assert L.lbm_step(None, 1) == _lib.LBM_EINVAL
+    assert L.ibm_couple(None, None) == _lib.LBM_EINVAL
+    assert L.ibm_rest_shape(None, None) == _lib.LBM_EINVAL
+    assert L.lbm_read_fields(None, None, None, None) == _lib.LBM_EINVAL
+    assert L.lbm_current(None, None, None) == _lib.LBM_EINVAL
+    assert L.lbm_store_f64(None, None) == _lib.LBM_EINVAL
+    assert L.lbm_init(None, None) == _lib.LBM_EINVAL
+    L.lbm_destroy(None)
+    assert b"NULL" in L.lbm_last_error()
+
+
+def test_workspace_bytes(L):
+    p = _params()
+    n = 512
+    assert L.lbm_workspace_bytes(C.byref(p)) == n + 4 * n + 3 * n * 4 + 8 * 8 + 2 * 32 + 32

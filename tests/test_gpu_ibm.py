@@ -1,0 +1,197 @@
+"""GPU parity of the coupled LBM + immersed-boundary step against the FP64
+oracle, through the C ABI: FP64 to rounding on small cases, FP32 deviation
+storage within 1e-5 relative velocity error after 1000 steps, and the
+posts-and-cells / throughput workloads at full size."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1110_0995_amd import scenario as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    from paper_1110_0995_amd import lbm as mod
+    return mod
+
+
+def rel_l2(a, b, mask=None):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if mask is not None:
+        a, b = a[..., mask], b[..., mask]
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _pair(orc, lbm, s, prec, deform=0.0, seed=0, vel=0.0):
+    """GPU lattice+mesh and oracle lattice+mesh on the same seeded inputs.
+    Both take their rest shape from the generated (undeformed) mesh; a
+    seeded deformation and velocity are then applied to both."""
+    lat = lbm.Lattice.from_scenario(s, prec=prec)
+    mesh = lbm.Mesh(lat, s.cells)
+    L = orc.Lattice.from_scenario(s)
+    M = orc.Mesh(s.cells)
+    X = s.cells.positions()
+    M.rest_shape(X)
+    V = np.zeros_like(X)
+    if deform or vel:
+        rng = np.random.default_rng(seed)
+        off = (s.cells.offset.astype(np.float64) + deform * rng.standard_normal(X.shape)).astype(np.float32)
+        mesh.set_offsets(off)
+        X = s.cells.anchor[s.cells.vertex_cell()] + off.astype(np.float64)
+        Vn = (vel * rng.standard_normal(X.shape)).astype(np.float32)
+        mesh.v.copy_(__import__("torch").as_tensor(Vn.T.copy()).to(mesh.v.device, mesh.v.dtype))
+        V = Vn.astype(np.float64)
+    return lat, mesh, L, M, X, V
+
+
+def _small(nx=40, ny=32, nz=24, ncells=2, level=2, radius=3.0, posts=True, gx=1e-4, seed=11, tau=0.8):
+    s = S.posts_and_cells(nx, ny, nz, posts_x=1 if posts else 0, posts_y=1 if posts else 0, post_radius=4,
+                          gap=6, ncells=ncells, cell_radius=radius, level=level, tau=tau, gx=gx, seed=seed,
+                          moduli=(0.02, 0.005, 0.01, 0.1, 0.5))
+    return s
+
+
+def test_coupled_f64_matches_oracle(orc, lbm):
+    s = _small()
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f64", deform=0.05, seed=1, vel=1e-3)
+    f = L.rest()
+    for _ in range(25):
+        lat.couple(mesh)
+        lat.step(1)
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    fg = lat.populations_f64().cpu().numpy()
+    assert np.abs(fg[:, fl] - f[:, fl]).max() < 1e-14
+    assert np.abs(mesh.positions() - X).max() < 1e-12
+    assert np.abs(mesh.velocities() - V).max() < 1e-13
+    # the elastic force of the last step, against the oracle's at the previous positions
+    assert np.isfinite(mesh.f_el.cpu().numpy()).all()
+
+
+def test_coupled_f64_elastic_forces(orc, lbm):
+    s = _small(posts=False, ncells=3)
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f64", deform=0.1, seed=2)
+    Fo = M.forces(X)
+    lat.couple(mesh)
+    Fg = mesh.f_el.double().cpu().numpy().T
+    assert np.abs(Fg - Fo).max() < 1e-13 * max(1.0, np.abs(Fo).max())
+    assert np.abs(Fo).max() > 1e-4
+
+
+@pytest.mark.parametrize("prec", ["f32dev", "f32"])
+def test_coupled_f32_elastic_forces(orc, lbm, prec):
+    s = _small(posts=False, ncells=3, level=3, radius=4.0)
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, prec, deform=0.05, seed=3)
+    Fo = M.forces(X)
+    lat.couple(mesh)
+    Fg = mesh.f_el.double().cpu().numpy().T
+    err = np.abs(Fg - Fo).max() / np.abs(Fo).max()
+    print(f"elastic force {prec}: max error / max force {err:.3e}")
+    assert err < 2e-4
+
+
+def test_rest_state_with_cells_exact(lbm):
+    """Undeformed cells in a fluid at rest: FP32 deviation storage stays at
+    h = 0 bit-exactly and the points do not move."""
+    s = S.posts_and_cells(64, 48, 32, posts_x=1, posts_y=1, ncells=3, gx=0.0, seed=4)
+    lat = lbm.Lattice.from_scenario(s, prec="f32dev")
+    mesh = lbm.Mesh(lat, s.cells)
+    x0 = mesh.x.clone()
+    lat.run(100, mesh)
+    assert (lat.current() == 0).all()
+    assert (mesh.x == x0).all() and (mesh.v == 0).all()
+
+
+def test_momentum_periodic_box_with_cells(lbm):
+    """Fully periodic, no solids, g = 0: fluid momentum plus point momentum
+    is conserved (spread force sums equal the point force sums)."""
+    nx, ny, nz = 48, 40, 36
+    s = S.Scenario("box", nx, ny, nz, 0.8, (0.0, 0.0, 0.0), np.zeros((nz, ny, nx), np.uint8), 100,
+                   cells=S.make_cells(np.array([[20.3, 18.7, 17.9], [33.1, 9.4, 25.2]]), 4.0, 2,
+                                      moduli=(0.02, 0.005, 0.01, 0.1, 0.5)))
+    lat = lbm.Lattice.from_scenario(s, prec="f64")
+    mesh = lbm.Mesh(lat, s.cells)
+    rng = np.random.default_rng(5)
+    mesh.set_offsets(s.cells.offset + 0.1 * rng.standard_normal(s.cells.offset.shape))
+    import torch
+    mesh.v.copy_(torch.as_tensor(1e-3 * rng.standard_normal((3, s.cells.nverts)), dtype=mesh.v.dtype))
+    p0 = lat.sums()[1:] + mesh.velocities().sum(0)
+    scale = np.abs(mesh.velocities()).sum()
+    lat.run(100, mesh)
+    p1 = lat.sums()[1:] + mesh.velocities().sum(0)
+    assert np.abs(p1 - p0).max() < 1e-12 * scale
+
+
+def test_f32dev_1000_steps_small_posts_cells(orc, lbm):
+    """Posts and cells, FP32 deviation storage, 1000 coupled steps: velocity
+    relative L2 error against the FP64 oracle <= 1e-5."""
+    s = _small(64, 48, 32, ncells=3, level=3, radius=4.0, gx=1e-5, seed=12)
+    s.cells.moduli[:] = S.MODULI_CTC
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f32dev")
+    f = L.rest()
+    t = time.time()
+    orc.run(L, M, f, X, V, nsteps=1000)
+    lat.run(1000, mesh)
+    fl = s.solid.reshape(-1) == 0
+    _, uo = orc.fluid_velocity(L, f)
+    _, ug = lat.fields()
+    err = rel_l2(ug.double().cpu().numpy(), uo, fl)
+    perr = np.abs(mesh.positions() - X).max()
+    print(f"small posts+cells f32dev 1000 steps: u rel L2 {err:.3e}, max position error {perr:.3e} "
+          f"(oracle {time.time() - t:.1f}s)")
+    assert err < 1e-5
+    assert perr < 1e-4
+
+
+def test_posts_cells_full_size(orc, lbm):
+    """256x128x64 with 4x2 posts and 20 cells of 642 vertices (tau 0.8,
+    g 1e-5): FP32 deviation storage vs the oracle after 20 coupled steps."""
+    s = S.posts_and_cells()
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f32dev")
+    f = L.rest()
+    orc.run(L, M, f, X, V, nsteps=20)
+    lat.run(20, mesh)
+    fl = s.solid.reshape(-1) == 0
+    _, uo = orc.fluid_velocity(L, f)
+    _, ug = lat.fields()
+    err = rel_l2(ug.double().cpu().numpy(), uo, fl)
+    print(f"posts_cells full size, 20 steps: u rel L2 {err:.3e}")
+    assert err < 1e-5
+    assert np.abs(mesh.positions() - X).max() < 1e-5
+    mo = orc.mass_momentum(L, f)
+    mg = lat.sums()
+    assert abs(mg[0] - mo[0]) / mo[0] < 1e-12
+
+
+def test_throughput_workload_full_size(orc, lbm):
+    """512x256x128, 8x4 posts, 400 cells (the timed workload, in the launch
+    configuration the benchmark uses): 2 coupled steps vs the oracle."""
+    s = S.throughput()
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f32dev")
+    f = L.rest()
+    orc.run(L, M, f, X, V, nsteps=2)
+    lat.run(2, mesh)
+    fl = s.solid.reshape(-1) == 0
+    _, uo = orc.fluid_velocity(L, f)
+    _, ug = lat.fields()
+    err = rel_l2(ug.double().cpu().numpy(), uo, fl)
+    print(f"throughput full size, 2 steps: u rel L2 {err:.3e}")
+    assert err < 1e-5
+    assert np.abs(mesh.positions() - X).max() < 1e-5
+
+
+def test_couple_requires_rest_shape(lbm):
+    from paper_1110_0995_amd import _lib
+    s = _small(posts=False, ncells=1)
+    lat = lbm.Lattice.from_scenario(s, prec="f32")
+    mesh = lbm.Mesh(lat, s.cells)
+    mesh.s.checked = 0
+    with pytest.raises(_lib.LbmError) as e:
+        lat.couple(mesh)
+    assert e.value.code == _lib.LBM_ESTATE
