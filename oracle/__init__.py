@@ -47,7 +47,7 @@ class _Mesh(C.Structure):
     _fields_ = [("ncells", C.c_int), ("nverts", C.c_int), ("ntris", C.c_int), ("nedges", C.c_int),
                 ("vert_off", _ip), ("tri_off", _ip), ("edge_off", _ip), ("tri", _ip), ("hinge", _ip),
                 ("moduli", _dp), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
-                ("l0", _dp), ("A0", _dp), ("th0", _dp), ("A0c", _dp), ("V0c", _dp)]
+                ("l0", _dp), ("A0", _dp), ("th0", _dp), ("A0c", _dp), ("V0c", _dp), ("Av", _dp)]
 
 
 class _Trace(C.Structure):
@@ -143,7 +143,9 @@ class Lattice:
 
 
 class Mesh:
-    """Membrane population; holds its own FP64 rest-shape arrays."""
+    """Membrane population; holds its own FP64 rest-shape arrays (edge
+    lengths, triangle areas, hinge angles, cell area and volume, and the
+    rest area Av carried by each vertex)."""
 
     def __init__(self, cells, moduli=None):
         self.cells = cells
@@ -159,14 +161,19 @@ class Mesh:
         self.th0 = np.zeros(ne)
         self.A0c = np.zeros(nc)
         self.V0c = np.zeros(nc)
+        self.Av = np.zeros(nv)
         self.s = _Mesh(nc, nv, nt, ne, _i(self.vert_off), _i(self.tri_off), _i(self.edge_off),
                        _i(self.tri), _i(self.hinge), _d(self.moduli), float(cells.xi),
                        float(cells.mass), float(cells.dt),
-                       _d(self.l0), _d(self.A0), _d(self.th0), _d(self.A0c), _d(self.V0c))
+                       _d(self.l0), _d(self.A0), _d(self.th0), _d(self.A0c), _d(self.V0c), _d(self.Av))
         self.nverts = nv
 
     def rest_shape(self, X: np.ndarray) -> None:
         lib().orc_rest_shape(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)))
+
+    def point_mass(self) -> np.ndarray:
+        """Mass of each IB point (mass density times its rest area)."""
+        return self.cells.mass * self.Av
 
     def energy(self, X) -> float:
         return lib().orc_membrane_energy(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)))

@@ -17,12 +17,15 @@
  *      (trilinear discrete delta, periodic wrap)        [Sec. 2.2 step 1]
  *   3. per cell: total area A_c and enclosed volume V_c, then the elastic
  *      force F_el = -grad(E_s + E_b + E_al + E_ag + E_v)  [Sec. 2.3.1, 2.3.3]
- *      and the coupling force F_c = xi (u_k - V_k)        [Sec. 2.2 step 2]
+ *      and the coupling force F_c = xi A_k (u_k - V_k)    [Sec. 2.2 step 2]
  *   4. F(x) = F_ext(x) + sum_k W(x - X_k) (-F_c,k)         [Sec. 2.2 step 3]
  *   5. BGK collision with the Guo source on fluid nodes, u = (j + F/2)/rho,
  *      then streaming to x + c_i, or halfway bounce-back into the opposite
  *      slot when x + c_i is a solid node                   [Sec. 2.1, 2.4]
- *   6. V_k += dt/m (F_el + F_c), X_k += dt V_k              [Sec. 2.2 step 4]
+ *   6. V_k += dt/m_k (F_el + F_c), X_k += dt V_k            [Sec. 2.2 step 4]
+ *      Reading: friction xi and point mass are densities per unit membrane
+ *      area, so vertex k, carrying the rest area A_k (a third of its
+ *      triangles' areas), has friction xi A_k and mass m_k = mass A_k.
  * The points where the paper is silent (form of f_eq, of the source term, of
  * the delta function, of the membrane energies, the ordering above) are the
  * readings listed in the design notes; each is marked "reading" below.
@@ -73,13 +76,14 @@ typedef struct {
     const int *tri;      /* [ntris][3], outward counter-clockwise */
     const int *hinge;    /* [nedges][4] = (p1, p2, qa, qb) */
     const double *moduli;/* [ncells][5] = (k_s, k_b, k_al, k_ag, k_v) */
-    double xi, mass, dt;
+    double xi, mass, dt; /* friction and mass per unit membrane area, time step */
     /* rest shape, filled by orc_rest_shape */
     double *l0;  /* [nedges] */
     double *A0;  /* [ntris]  */
     double *th0; /* [nedges] */
     double *A0c; /* [ncells] */
     double *V0c; /* [ncells] */
+    double *Av;  /* [nverts] rest area carried by each vertex */
 } orc_mesh;
 
 /* Threads the OpenMP loops below will use. */
@@ -399,6 +403,10 @@ void orc_mesh_geometry(const orc_mesh *M, const double *X, double *l, double *A,
 void orc_rest_shape(orc_mesh *M, const double *X) {
     orc_mesh_geometry(M, X, M->l0, M->A0, M->th0);
     orc_cell_area_volume(M, X, M->A0c, M->V0c);
+    /* each vertex carries one third of the rest area of its triangles */
+    for (int k = 0; k < M->nverts; k++) M->Av[k] = 0.0;
+    for (int t = 0; t < M->ntris; t++)
+        for (int j = 0; j < 3; j++) M->Av[M->tri[3 * t + j]] += M->A0[t] / 3.0;
 }
 
 /* Reading of the four moduli as energies (all values from Table 1):
@@ -554,7 +562,7 @@ int orc_step(const orc_lattice *L, const orc_mesh *M, const double *f, double *f
         orc_interpolate(L, uext, nv, X, uk);                 /* step 1 */
         orc_membrane_forces(M, X, Fel);                      /* step 2 */
         for (int i = 0; i < 3 * nv; i++) {
-            Fc[i] = M->xi * (uk[i] - V[i]);
+            Fc[i] = M->xi * M->Av[i / 3] * (uk[i] - V[i]);
             mFc[i] = -Fc[i];
         }
         orc_spread(L, nv, X, mFc, F);                        /* step 3 */
@@ -565,7 +573,7 @@ int orc_step(const orc_lattice *L, const orc_mesh *M, const double *f, double *f
             if (L->solid[n]) fnew[i * N + n] = f[i * N + n];
     orc_collide_stream(L, f, F, fnew);                      /* step 4, fluid */
     for (int i = 0; i < 3 * nv; i++) {                      /* step 4, points */
-        V[i] += M->dt / M->mass * (Fel[i] + Fc[i]);
+        V[i] += M->dt / (M->mass * M->Av[i / 3]) * (Fel[i] + Fc[i]);
         X[i] += M->dt * V[i];
     }
     if (tr) {

@@ -214,8 +214,8 @@ class Cells:
     anchor: np.ndarray     # int32 [ncells, 3]
     offset: np.ndarray     # float32 [nverts, 3]
     moduli: np.ndarray     # float64 [ncells, 5]  (k_s, k_b, k_al, k_ag, k_v)
-    xi: float = 1.0        # friction of the fluid-object coupling
-    mass: float = 1.0      # IB-point mass
+    xi: float = 1.0        # coupling friction per unit membrane area
+    mass: float = 2.0      # membrane mass per unit area (IB-point mass = mass * its rest area)
     dt: float = 1.0        # IB time step (one per lattice step)
 
     @property

@@ -100,7 +100,8 @@ class Brute:
 
     def step(self, f, X=None, V=None, Fel=None, xi=1.0, mass=1.0, dt=1.0):
         """f [19, nz, ny, nx].  Fel (elastic forces at the current X) is an
-        input: the membrane forces are pinned on their own."""
+        input: the membrane forces are pinned on their own.  xi and mass may
+        be per-point arrays [nv, 1]."""
         nx, ny, nz = self.dims
         F = np.zeros((3, nz, ny, nx))
         for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
