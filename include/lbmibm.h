@@ -15,9 +15,10 @@
  *   - Sec. 2.4, halfway bounce-back at solid nodes.
  * Where the paper leaves the form open, the library implements: second-order
  * polynomial equilibrium, Guo's forcing with u = (j + F/2)/rho, trilinear
- * delta, coupling force F_c = xi (u(X) - V), linear-spring/area/volume/angle
- * energies, and the step order interpolate -> forces -> spread ->
- * collide/stream -> move points.
+ * delta, frictional coupling F_c = xi A_k (u(X_k) - V_k) with friction and
+ * point mass taken per unit membrane area (A_k = rest area of vertex k),
+ * linear-spring/area/volume/angle energies, and the step order interpolate
+ * -> forces -> spread -> collide/stream -> move points.
  *
  * Conventions
  *   - Lattice node n = x + nx*(y + ny*z), N = nx*ny*nz, x fastest.
@@ -98,13 +99,14 @@ typedef struct {
     void *v;                 /* [3][nverts] real: velocity (updated by ibm_couple) */
     void *f_el;              /* [3][nverts] real: written with the elastic force of the last ibm_couple */
     const void *moduli;      /* [5][ncells] real: k_s, k_b, k_al, k_ag, k_v per cell (Table 1 order K^S, K^B, K^A_l, K^A_g, K^V) */
-    void *l0;                /* [nedges] real: rest edge lengths   (written by ibm_rest_shape) */
-    void *a0;                /* [ntris]  real: rest triangle areas (written by ibm_rest_shape) */
-    void *th0;               /* [nedges] real: rest hinge angles   (written by ibm_rest_shape) */
-    double *a0c;             /* [ncells] rest cell areas           (written by ibm_rest_shape) */
-    double *v0c;             /* [ncells] rest cell volumes         (written by ibm_rest_shape) */
-    double xi;               /* friction of the coupling force F_c = xi (u(X) - V), > 0 */
-    double mass;             /* IB-point mass m (Newton equation of Sec. 2.2), > 0 */
+    double *l0;              /* [nedges] rest edge lengths           (written by ibm_rest_shape) */
+    double *a0;              /* [ntris]  rest triangle areas         (written by ibm_rest_shape) */
+    double *th0;             /* [nedges] rest hinge angles           (written by ibm_rest_shape) */
+    double *a0c;             /* [ncells] rest cell areas             (written by ibm_rest_shape) */
+    double *v0c;             /* [ncells] rest cell volumes           (written by ibm_rest_shape) */
+    double *avert;           /* [nverts] rest area carried by each vertex, a third of its triangles' (written by ibm_rest_shape) */
+    double xi;               /* coupling friction per unit membrane area: vertex k feels F_c = xi*avert[k]*(u(X_k) - V_k); > 0 */
+    double mass;             /* membrane mass per unit area: vertex k has mass mass*avert[k] (Newton equation of Sec. 2.2); > 0 */
     double dt;               /* IB time step, > 0 */
     /* filled by ibm_rest_shape; the caller must not edit them */
     int32_t max_cell_verts, max_cell_tris, max_cell_edges;
@@ -132,8 +134,8 @@ int lbm_init(const lbm_params *p, lbm_ctx **out);
 int lbm_step(lbm_ctx *c, int32_t nsteps);
 
 /* Compute the rest shape (edge lengths, triangle areas, hinge angles, cell
- * area and volume) of the mesh at its current positions into m->l0, a0,
- * th0, a0c, v0c, after checking the topology (read back to the host; this
+ * area and volume, vertex areas; all in FP64) of the mesh at its current
+ * positions into m->l0, a0, th0, a0c, v0c, avert, after checking the topology (read back to the host; this
  * call waits on the stream).  Must be called once per mesh before
  * ibm_couple; fills the trailing fields of *m. */
 int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m);
@@ -141,8 +143,11 @@ int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m);
 /* The immersed-boundary part of one step (Sec. 2.2 steps 1-3 and the point
  * half of step 4): per cell, area/volume then elastic forces (written to
  * m->f_el); per point, interpolated velocity u_k from the current
- * populations, F_c = xi (u_k - V), spreading of -F_c to the 8 surrounding
- * nodes for the next lbm_step, then V += dt/m (F_el + F_c), X += dt V. */
+ * populations, F_c = xi A_k (u_k - V), spreading of -F_c to the 8
+ * surrounding nodes for the next lbm_step, then V += dt/m_k (F_el + F_c),
+ * X += dt V.  Lengths, areas, angles, cell area and volume are evaluated in
+ * FP64 from the stored positions in every precision, so their small
+ * departures from the rest shape are not lost to rounding. */
 int ibm_couple(lbm_ctx *c, const ibm_mesh *m);
 
 /* rho [N] and u [3][N] (real, device, either may be NULL) of the current

@@ -1,15 +1,26 @@
 // Immersed-boundary kernels (Sec. 2.2) and membrane forces (Sec. 2.3).
 //
-// k_membrane: one workgroup per cell.  The cell's vertex offsets are staged
-// in LDS; the cell's total area and volume (the global constraints that need
-// every vertex of the cell, Sec. 2.3.3) are reduced in FP64 first, then each
-// triangle and each edge/hinge adds its energy gradient to its vertices with
-// LDS atomics, and the result is written out once.
+// One coupled step runs three kernels before the collide-stream pass:
 //
-// k_couple: one thread per IB point: trilinear interpolation of the fluid
-// velocity from the 8 surrounding nodes, coupling force, spreading of its
-// reaction onto the same 8 nodes (global atomics into the force
-// accumulator, tile flags for the collide kernel), then the point update.
+// k_membrane (one workgroup per cell): the cell's vertex offsets are staged
+//   in LDS; the cell's total area and volume (the global constraints that
+//   need every vertex of the cell, Sec. 2.3.3) are reduced first, then each
+//   triangle and each edge/hinge adds its energy gradient to its vertices
+//   with LDS atomics, and the forces are written out once.  Lengths, areas,
+//   angles and volumes are evaluated in FP64 from the stored positions, so
+//   their small departures from the (FP64) rest shape keep full accuracy in
+//   every storage precision.  The same pass marks every 64-node lattice tile
+//   that a vertex's 2x2x2 stencil touches and appends it once to a tile list.
+//
+// k_tile_velocity (one wave per listed tile): u_ext = (j + F_ext/2)/rho of
+//   the tile's 64 nodes from their current populations (coalesced loads),
+//   written to a 3-component field; each node is evaluated once however many
+//   IB points use it.
+//
+// k_couple (one thread per IB point): trilinear interpolation of that field
+//   (Sec. 2.2 step 1), coupling force (step 2), spreading of its reaction
+//   with global atomics into the force accumulator, flagging the tiles for
+//   the collide kernel (step 3), and the point update (step 4).
 #pragma once
 
 #include "d3q19.hpp"
@@ -17,75 +28,51 @@
 
 namespace lbm {
 
-// ---- geometry helpers --------------------------------------------------
-// Contraction is switched off here so that the rest shape and the later
-// force evaluations compute bit-identical lengths, areas and angles from the
-// same positions (undeformed cells then feel exactly zero force).
+// tile flag bits
+enum : uint32_t { TILE_FORCE = 1u, TILE_NEED_U = 2u };
 
-template <class R>
 struct V3 {
-    R x, y, z;
+    double x, y, z;
 };
-template <class R>
-__device__ __forceinline__ V3<R> sub(V3<R> a, V3<R> b) {
-#pragma clang fp contract(off)
-    return {a.x - b.x, a.y - b.y, a.z - b.z};
-}
-template <class R>
-__device__ __forceinline__ V3<R> crs(V3<R> a, V3<R> b) {
-#pragma clang fp contract(off)
+__device__ __forceinline__ V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ V3 crs(V3 a, V3 b) {
     return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-template <class R>
-__device__ __forceinline__ R dot(V3<R> a, V3<R> b) {
-#pragma clang fp contract(off)
-    return a.x * b.x + a.y * b.y + a.z * b.z;
-}
-template <class R>
-__device__ __forceinline__ V3<R> scl(R s, V3<R> a) {
-    return {s * a.x, s * a.y, s * a.z};
-}
+__device__ __forceinline__ double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 scl(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
 
-// Unnormalised outward normal (b-a)x(c-a); area = |n|/2.
-template <class R>
-__device__ __forceinline__ V3<R> tri_normal(V3<R> a, V3<R> b, V3<R> c) {
-    return crs(sub(b, a), sub(c, a));
-}
-template <class R>
-__device__ __forceinline__ R tri_area(V3<R> n) {
-#pragma clang fp contract(off)
-    return R(0.5) * sqrt(dot(n, n));
-}
-// a.(b x c)/6: volume of the tetrahedron (anchor, a, b, c).
-template <class R>
-__device__ __forceinline__ R tri_vol(V3<R> a, V3<R> b, V3<R> c) {
-#pragma clang fp contract(off)
-    return dot(a, crs(b, c)) / R(6);
-}
 // Signed angle between the outward normals of (p1,p2,qa) and (p2,p1,qb):
-// zero when flat, positive for a convex fold.
-template <class R>
-__device__ __forceinline__ R hinge_angle(V3<R> p1, V3<R> p2, V3<R> qa, V3<R> qb, V3<R> &na, V3<R> &nb, V3<R> &e) {
-#pragma clang fp contract(off)
+// zero when flat, positive for a convex fold.  Also returns the unnormalised
+// normals and the edge vector.
+__device__ __forceinline__ double hinge_angle(V3 p1, V3 p2, V3 qa, V3 qb, V3 &na, V3 &nb, V3 &e) {
     e = sub(p2, p1);
     na = crs(e, sub(qa, p1));
     nb = crs(sub(p1, p2), sub(qb, p2));
-    const R s = dot(crs(na, nb), e) / sqrt(dot(e, e));
-    const R c = dot(na, nb);
-    return atan2(s, c);
+    return atan2(dot(crs(na, nb), e) / sqrt(dot(e, e)), dot(na, nb));
 }
 
 struct MembArgs {
-    const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge;
+    const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge, *anchor;
     const void *x;  // [3][nverts] offsets
     void *f_el;     // [3][nverts]
     const void *moduli;
-    void *l0, *a0, *th0;
-    double *a0c, *v0c;
+    double *l0, *a0, *th0, *a0c, *v0c, *avert;
     int ncells, nverts, ntris, nedges, maxv;
+    // lattice, for marking the stencil tiles
+    int nx, ny, nz, tpr;
+    uint32_t *tflag;
+    uint32_t *tlist;
+    uint32_t *tcount;
 };
 
-// REST = true: write the rest shape; false: elastic forces.
+// LDS layout: 8 doubles of reduction scratch, maxv doubles (vertex areas in
+// the rest pass), then x, y, z positions and x, y, z force accumulators.
+template <class R>
+__host__ __device__ inline size_t membrane_lds_bytes(int maxv) {
+    return 8 * sizeof(double) + (size_t)maxv * sizeof(double) + 6 * (size_t)maxv * sizeof(R);
+}
+
+// REST = true: write the rest shape; false: elastic forces + tile marking.
 template <class R, bool REST>
 __global__ __launch_bounds__(256) void k_membrane(MembArgs a) {
     extern __shared__ double smem_d[];
@@ -93,8 +80,9 @@ __global__ __launch_bounds__(256) void k_membrane(MembArgs a) {
     const int v0 = a.vert_off[c], nv = a.vert_off[c + 1] - v0;
     const int t0 = a.tri_off[c], nt = a.tri_off[c + 1] - t0;
     const int e0 = a.edge_off[c], ne = a.edge_off[c + 1] - e0;
-    double *red = smem_d;  // 4 waves x 2
-    R *px = reinterpret_cast<R *>(smem_d + 8);
+    double *red = smem_d;       // 4 waves x 2
+    double *av = smem_d + 8;    // [maxv]
+    R *px = reinterpret_cast<R *>(av + a.maxv);
     R *py = px + a.maxv, *pz = py + a.maxv;
     R *fx = pz + a.maxv, *fy = fx + a.maxv, *fz = fy + a.maxv;
     const R *X = static_cast<const R *>(a.x);
@@ -103,99 +91,127 @@ __global__ __launch_bounds__(256) void k_membrane(MembArgs a) {
         px[k] = X[v0 + k];
         py[k] = X[NV + v0 + k];
         pz[k] = X[2 * NV + v0 + k];
-        if (!REST) fx[k] = fy[k] = fz[k] = R(0);
+        fx[k] = fy[k] = fz[k] = R(0);
+        av[k] = 0.0;
     }
     __syncthreads();
-    auto P = [&](int k) { return V3<R>{px[k], py[k], pz[k]}; };
+    auto P = [&](int k) { return V3{(double)px[k], (double)py[k], (double)pz[k]}; };
     const int NT = a.ntris, NE = a.nedges;
 
-    // cell area and volume (FP64 sums of per-triangle values)
+    if (!REST) {
+        // mark the tiles under every vertex's stencil (positions of this step)
+        const int ax = a.anchor[c], ay = a.anchor[a.ncells + c], az = a.anchor[2 * a.ncells + c];
+        for (int k = threadIdx.x; k < nv; k += blockDim.x) {
+            const int x0 = pmod(ax + (int)floor(px[k]), a.nx);
+            const int y0 = pmod(ay + (int)floor(py[k]), a.ny);
+            const int z0 = pmod(az + (int)floor(pz[k]), a.nz);
+            const int x1 = x0 + 1 == a.nx ? 0 : x0 + 1;
+            const int ys[2] = {y0, y0 + 1 == a.ny ? 0 : y0 + 1};
+            const int zs[2] = {z0, z0 + 1 == a.nz ? 0 : z0 + 1};
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int row = ys[q & 1] + a.ny * zs[q >> 1];
+                const uint32_t t0i = (uint32_t)row * a.tpr + (x0 >> 6), t1i = (uint32_t)row * a.tpr + (x1 >> 6);
+                if (!(a.tflag[t0i] & TILE_NEED_U) && !(atomicOr(&a.tflag[t0i], TILE_NEED_U) & TILE_NEED_U))
+                    a.tlist[atomicAdd(a.tcount, 1u)] = t0i;
+                if (t1i != t0i && !(a.tflag[t1i] & TILE_NEED_U) &&
+                    !(atomicOr(&a.tflag[t1i], TILE_NEED_U) & TILE_NEED_U))
+                    a.tlist[atomicAdd(a.tcount, 1u)] = t1i;
+            }
+        }
+    }
+
+    // cell area and volume (FP64 sums of FP64 per-triangle values, fixed order)
     double acc[2] = {0.0, 0.0};
     for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-        const V3<R> A = P(a.tri[t0 + t] - v0), B = P(a.tri[NT + t0 + t] - v0), C = P(a.tri[2 * NT + t0 + t] - v0);
-        acc[0] += (double)tri_area(tri_normal(A, B, C));
-        acc[1] += (double)tri_vol(A, B, C);
+        const V3 A = P(a.tri[t0 + t] - v0), B = P(a.tri[NT + t0 + t] - v0), C = P(a.tri[2 * NT + t0 + t] - v0);
+        const V3 n = crs(sub(B, A), sub(C, A));
+        acc[0] += 0.5 * sqrt(dot(n, n));
+        acc[1] += dot(A, crs(B, C)) / 6.0;
     }
     block_sum<2>(acc, red);
-    if (REST) {
-        if (threadIdx.x == 0) {
-            a.a0c[c] = acc[0];
-            a.v0c[c] = acc[1];
-        }
+    if (REST && threadIdx.x == 0) {
+        a.a0c[c] = acc[0];
+        a.v0c[c] = acc[1];
     }
     const R *mod = static_cast<const R *>(a.moduli);
     const int NC = a.ncells;
-    const R ks = mod[c], kb = mod[NC + c], kal = mod[2 * NC + c];
-    const double kag = (double)mod[3 * NC + c], kv = (double)mod[4 * NC + c];
-    const R cag = REST ? R(0) : R(kag * (acc[0] - a.a0c[c]) / a.a0c[c]);
-    const R cv6 = REST ? R(0) : R(kv * (acc[1] - a.v0c[c]) / a.v0c[c] / 6.0);
-    R *A0 = static_cast<R *>(a.a0), *L0 = static_cast<R *>(a.l0), *TH0 = static_cast<R *>(a.th0);
+    const double ks = mod[c], kb = mod[NC + c], kal = mod[2 * NC + c], kag = mod[3 * NC + c],
+                 kv = mod[4 * NC + c];
+    const double cag = REST ? 0.0 : kag * (acc[0] - a.a0c[c]) / a.a0c[c];
+    const double cv6 = REST ? 0.0 : kv * (acc[1] - a.v0c[c]) / a.v0c[c] / 6.0;
 
     // triangles: local + global area, volume
     for (int t = threadIdx.x; t < nt; t += blockDim.x) {
         const int ia = a.tri[t0 + t] - v0, ib = a.tri[NT + t0 + t] - v0, ic = a.tri[2 * NT + t0 + t] - v0;
-        const V3<R> A = P(ia), B = P(ib), C = P(ic);
-        const V3<R> n = tri_normal(A, B, C);
-        const R area = tri_area(n);
+        const V3 A = P(ia), B = P(ib), C = P(ic);
+        const V3 n = crs(sub(B, A), sub(C, A));
+        const double nn = sqrt(dot(n, n));
+        const double area = 0.5 * nn;
         if (REST) {
-            A0[t0 + t] = area;
+            a.a0[t0 + t] = area;
+            atomicAdd(&av[ia], area / 3.0);
+            atomicAdd(&av[ib], area / 3.0);
+            atomicAdd(&av[ic], area / 3.0);
             continue;
         }
-        const R ref = A0[t0 + t];
-        const R ca = kal * (area - ref) / ref + cag;
-        const R h = -R(0.5) * ca / (R(2) * area);  // -ca/2 * (1/|n|), |n| = 2 area
-        // -ca * grad_a A = -ca/2 (b - c) x n_hat, cyclic
-        const V3<R> ga = crs(sub(B, C), n), gb = crs(sub(C, A), n), gc = crs(sub(A, B), n);
-        const V3<R> va = crs(B, C), vb = crs(C, A), vc = crs(A, B);
-        atomicAdd(&fx[ia], h * ga.x - cv6 * va.x);
-        atomicAdd(&fy[ia], h * ga.y - cv6 * va.y);
-        atomicAdd(&fz[ia], h * ga.z - cv6 * va.z);
-        atomicAdd(&fx[ib], h * gb.x - cv6 * vb.x);
-        atomicAdd(&fy[ib], h * gb.y - cv6 * vb.y);
-        atomicAdd(&fz[ib], h * gb.z - cv6 * vb.z);
-        atomicAdd(&fx[ic], h * gc.x - cv6 * vc.x);
-        atomicAdd(&fy[ic], h * gc.y - cv6 * vc.y);
-        atomicAdd(&fz[ic], h * gc.z - cv6 * vc.z);
+        const double ref = a.a0[t0 + t];
+        const double ca = kal * (area - ref) / ref + cag;
+        const double h = -0.5 * ca / nn;  // -ca grad_a A = -ca/2 (b - c) x n/|n|, cyclic
+        const V3 ga = crs(sub(B, C), n), gb = crs(sub(C, A), n), gc = crs(sub(A, B), n);
+        const V3 va = crs(B, C), vb = crs(C, A), vc = crs(A, B);
+        atomicAdd(&fx[ia], R(h * ga.x - cv6 * va.x));
+        atomicAdd(&fy[ia], R(h * ga.y - cv6 * va.y));
+        atomicAdd(&fz[ia], R(h * ga.z - cv6 * va.z));
+        atomicAdd(&fx[ib], R(h * gb.x - cv6 * vb.x));
+        atomicAdd(&fy[ib], R(h * gb.y - cv6 * vb.y));
+        atomicAdd(&fz[ib], R(h * gb.z - cv6 * vb.z));
+        atomicAdd(&fx[ic], R(h * gc.x - cv6 * vc.x));
+        atomicAdd(&fy[ic], R(h * gc.y - cv6 * vc.y));
+        atomicAdd(&fz[ic], R(h * gc.z - cv6 * vc.z));
     }
     // edges: stretching and bending
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
         const int i1 = a.hinge[e0 + e] - v0, i2 = a.hinge[NE + e0 + e] - v0;
         const int ia = a.hinge[2 * NE + e0 + e] - v0, ib = a.hinge[3 * NE + e0 + e] - v0;
-        const V3<R> p1 = P(i1), p2 = P(i2), qa = P(ia), qb = P(ib);
-        V3<R> na, nb, ev;
-        const R th = hinge_angle(p1, p2, qa, qb, na, nb, ev);
-        const R l = sqrt(dot(ev, ev));
+        const V3 p1 = P(i1), p2 = P(i2), qa = P(ia), qb = P(ib);
+        V3 na, nb, ev;
+        const double th = hinge_angle(p1, p2, qa, qb, na, nb, ev);
+        const double l = sqrt(dot(ev, ev));
         if (REST) {
-            L0[e0 + e] = l;
-            TH0[e0 + e] = th;
+            a.l0[e0 + e] = l;
+            a.th0[e0 + e] = th;
             continue;
         }
-        const R ref = L0[e0 + e];
-        const R cs = ks * (l - ref) / ref / l;  // force on p1 = cs (p2 - p1)
-        const R cb = kb * (th - TH0[e0 + e]);
+        const double ref = a.l0[e0 + e];
+        const double cs = ks * (l - ref) / ref / l;  // force on p1 = cs (p2 - p1)
+        const double cb = kb * (th - a.th0[e0 + e]);
         // d theta/d qa = -|e| na/|na|^2, d theta/d qb = -|e| nb/|nb|^2; the edge ends
         // take the combinations that keep net force and torque zero.
-        const V3<R> ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
-        const R il2 = R(1) / (l * l);
-        const R sa = dot(sub(qa, p1), ev) * il2, sb = dot(sub(qb, p1), ev) * il2;
-        const V3<R> g1 = {-(R(1) - sa) * ga.x - (R(1) - sb) * gb.x, -(R(1) - sa) * ga.y - (R(1) - sb) * gb.y,
-                          -(R(1) - sa) * ga.z - (R(1) - sb) * gb.z};
-        const V3<R> g2 = {-sa * ga.x - sb * gb.x, -sa * ga.y - sb * gb.y, -sa * ga.z - sb * gb.z};
-        atomicAdd(&fx[i1], cs * ev.x - cb * g1.x);
-        atomicAdd(&fy[i1], cs * ev.y - cb * g1.y);
-        atomicAdd(&fz[i1], cs * ev.z - cb * g1.z);
-        atomicAdd(&fx[i2], -cs * ev.x - cb * g2.x);
-        atomicAdd(&fy[i2], -cs * ev.y - cb * g2.y);
-        atomicAdd(&fz[i2], -cs * ev.z - cb * g2.z);
-        atomicAdd(&fx[ia], -cb * ga.x);
-        atomicAdd(&fy[ia], -cb * ga.y);
-        atomicAdd(&fz[ia], -cb * ga.z);
-        atomicAdd(&fx[ib], -cb * gb.x);
-        atomicAdd(&fy[ib], -cb * gb.y);
-        atomicAdd(&fz[ib], -cb * gb.z);
+        const V3 ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
+        const double il2 = 1.0 / (l * l);
+        const double sa = dot(sub(qa, p1), ev) * il2, sb = dot(sub(qb, p1), ev) * il2;
+        const V3 g1 = {-(1 - sa) * ga.x - (1 - sb) * gb.x, -(1 - sa) * ga.y - (1 - sb) * gb.y,
+                       -(1 - sa) * ga.z - (1 - sb) * gb.z};
+        const V3 g2 = {-sa * ga.x - sb * gb.x, -sa * ga.y - sb * gb.y, -sa * ga.z - sb * gb.z};
+        atomicAdd(&fx[i1], R(cs * ev.x - cb * g1.x));
+        atomicAdd(&fy[i1], R(cs * ev.y - cb * g1.y));
+        atomicAdd(&fz[i1], R(cs * ev.z - cb * g1.z));
+        atomicAdd(&fx[i2], R(-cs * ev.x - cb * g2.x));
+        atomicAdd(&fy[i2], R(-cs * ev.y - cb * g2.y));
+        atomicAdd(&fz[i2], R(-cs * ev.z - cb * g2.z));
+        atomicAdd(&fx[ia], R(-cb * ga.x));
+        atomicAdd(&fy[ia], R(-cb * ga.y));
+        atomicAdd(&fz[ia], R(-cb * ga.z));
+        atomicAdd(&fx[ib], R(-cb * gb.x));
+        atomicAdd(&fy[ib], R(-cb * gb.y));
+        atomicAdd(&fz[ib], R(-cb * gb.z));
     }
-    if (REST) return;
     __syncthreads();
+    if (REST) {
+        for (int k = threadIdx.x; k < nv; k += blockDim.x) a.avert[v0 + k] = av[k];
+        return;
+    }
     R *FE = static_cast<R *>(a.f_el);
     for (int k = threadIdx.x; k < nv; k += blockDim.x) {
         FE[v0 + k] = fx[k];
@@ -204,52 +220,82 @@ __global__ __launch_bounds__(256) void k_membrane(MembArgs a) {
     }
 }
 
-struct CoupleArgs {
-    const void *f;  // current populations
+struct TileVelArgs {
+    const void *f;
     int64_t stride;
     const uint8_t *cls;
     const void *gfield;
-    void *fibm;
-    uint8_t *tflag;
-    int nx, ny, nz, tpr;
+    void *ufield;  // [3][N]
+    const uint32_t *tlist;
+    const uint32_t *tcount;
+    int nx, tpr;
     int64_t N;
     double g[3];
+};
+
+// u_ext of the nodes of every listed tile.  A fixed grid of waves strides
+// over the list (its length is only known on the device).
+template <class S, class R, bool DEV, bool HAS_G>
+__global__ __launch_bounds__(256) void k_tile_velocity(TileVelArgs a) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t count = *a.tcount;
+    const S *f = static_cast<const S *>(a.f);
+    R *U = static_cast<R *>(a.ufield);
+    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
+        const uint32_t tile = a.tlist[w];
+        const uint32_t row = tile / a.tpr;
+        const int x = (int)(tile - row * a.tpr) * 64 + lane;
+        if (x >= a.nx) continue;
+        const int64_t n = (int64_t)row * a.nx + x;
+        R ux = R(0), uy = R(0), uz = R(0);
+        if (a.cls[n] != CLS_SOLID) {
+            R v[Q];
+#pragma unroll
+            for (int i = 0; i < Q; i++) v[i] = R(f[i * a.stride + n]);
+            R s = R(0);
+#pragma unroll
+            for (int i = 0; i < Q; i++) s += v[i];
+            const R jx = (v[1] - v[2]) + (v[7] - v[8]) + (v[9] - v[10]) + (v[11] - v[12]) + (v[13] - v[14]);
+            const R jy = (v[3] - v[4]) + (v[7] - v[8]) + (v[10] - v[9]) + (v[15] - v[16]) + (v[17] - v[18]);
+            const R jz = (v[5] - v[6]) + (v[11] - v[12]) + (v[14] - v[13]) + (v[15] - v[16]) + (v[18] - v[17]);
+            R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
+            if (HAS_G) {
+                const R *G = static_cast<const R *>(a.gfield);
+                Fx += G[n];
+                Fy += G[a.N + n];
+                Fz += G[2 * a.N + n];
+            }
+            const R ir = R(1) / (DEV ? R(1) + s : s);
+            ux = (jx + R(0.5) * Fx) * ir;
+            uy = (jy + R(0.5) * Fy) * ir;
+            uz = (jz + R(0.5) * Fz) * ir;
+        }
+        U[n] = ux;
+        U[a.N + n] = uy;
+        U[2 * a.N + n] = uz;
+    }
+}
+
+struct CoupleArgs {
+    const void *ufield;
+    void *fibm;
+    uint32_t *tflag;
+    uint32_t *tcount;
+    int nx, ny, nz, tpr;
+    int64_t N;
     const int32_t *vert_off, *anchor;
     void *x, *v;
     const void *f_el;
+    const double *avert;
     int ncells, nverts;
     double xi, dt_over_m, dt;
 };
 
-// u_ext = (j + F_ext/2)/rho at node n from its current populations.
-template <class S, class R, bool DEV, bool HAS_G>
-__device__ __forceinline__ void node_velocity(const CoupleArgs &a, int64_t n, R &ux, R &uy, R &uz) {
-    const S *f = static_cast<const S *>(a.f);
-    R v[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) v[i] = R(f[i * a.stride + n]);
-    R s = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; i++) s += v[i];
-    const R jx = (v[1] - v[2]) + (v[7] - v[8]) + (v[9] - v[10]) + (v[11] - v[12]) + (v[13] - v[14]);
-    const R jy = (v[3] - v[4]) + (v[7] - v[8]) + (v[10] - v[9]) + (v[15] - v[16]) + (v[17] - v[18]);
-    const R jz = (v[5] - v[6]) + (v[11] - v[12]) + (v[14] - v[13]) + (v[15] - v[16]) + (v[18] - v[17]);
-    R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
-    if (HAS_G) {
-        const R *G = static_cast<const R *>(a.gfield);
-        Fx += G[n];
-        Fy += G[a.N + n];
-        Fz += G[2 * a.N + n];
-    }
-    const R ir = R(1) / (DEV ? R(1) + s : s);
-    ux = (jx + R(0.5) * Fx) * ir;
-    uy = (jy + R(0.5) * Fy) * ir;
-    uz = (jz + R(0.5) * Fz) * ir;
-}
-
-template <class S, class R, bool DEV, bool HAS_G>
+template <class R>
 __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const int c = blockIdx.y;
+    if (c == 0 && blockIdx.x == 0 && threadIdx.x == 0) *a.tcount = 0;  // the tile list was consumed
     const int vb = a.vert_off[c], ve = a.vert_off[c + 1];
     const int k = vb + blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ve) return;
@@ -257,6 +303,7 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     R *X = static_cast<R *>(a.x);
     R *Vv = static_cast<R *>(a.v);
     const R *FE = static_cast<const R *>(a.f_el);
+    const R *U = static_cast<const R *>(a.ufield);
     const R ox = X[k], oy = X[NV + k], oz = X[2 * NV + k];
     const R flx = floor(ox), fly = floor(oy), flz = floor(oz);
     const R dx = ox - flx, dy = oy - fly, dz = oz - flz;
@@ -274,17 +321,15 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     for (int q = 0; q < 8; q++) {
         const int bx = q & 1, by = (q >> 1) & 1, bz = q >> 2;
         const int64_t n = xs[bx] + (int64_t)a.nx * (ys[by] + (int64_t)a.ny * zs[bz]);
-        if (a.cls[n] == CLS_SOLID) continue;
-        R u, v, w;
-        node_velocity<S, R, DEV, HAS_G>(a, n, u, v, w);
         const R wt = wx[bx] * wy[by] * wz[bz];
-        ux += wt * u;
-        uy += wt * v;
-        uz += wt * w;
+        ux += wt * U[n];
+        uy += wt * U[a.N + n];
+        uz += wt * U[2 * a.N + n];
     }
-    // step 2: coupling force
+    // step 2: coupling force, friction per unit area times the vertex's area
+    const double ak = a.avert[k];
     const R vx = Vv[k], vy = Vv[NV + k], vz = Vv[2 * NV + k];
-    const R xi = R(a.xi);
+    const R xi = R(a.xi * ak);
     const R fcx = xi * (ux - vx), fcy = xi * (uy - vy), fcz = xi * (uz - vz);
     // step 3: spread -F_c
     R *FI = static_cast<R *>(a.fibm);
@@ -297,10 +342,10 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
         atomicAdd(&FI[n], -wt * fcx);
         atomicAdd(&FI[a.N + n], -wt * fcy);
         atomicAdd(&FI[2 * a.N + n], -wt * fcz);
-        a.tflag[(int64_t)row * a.tpr + (xs[bx] >> 6)] = 1;
+        a.tflag[(int64_t)row * a.tpr + (xs[bx] >> 6)] = TILE_FORCE;
     }
-    // step 4 (points): semi-implicit Euler
-    const R h = R(a.dt_over_m), dt = R(a.dt);
+    // step 4 (points): semi-implicit Euler with the vertex's mass
+    const R h = R(a.dt_over_m / ak), dt = R(a.dt);
     const R nvx = vx + h * (FE[k] + fcx), nvy = vy + h * (FE[NV + k] + fcy), nvz = vz + h * (FE[2 * NV + k] + fcz);
     Vv[k] = nvx;
     Vv[NV + k] = nvy;

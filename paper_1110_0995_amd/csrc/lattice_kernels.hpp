@@ -89,6 +89,25 @@ __device__ __forceinline__ void collide(R (&f)[Q], R Fx, R Fy, R Fz, R omega, R 
     }
 }
 
+// Element i of an array addressed from its base: with a 32-bit IDX the byte
+// offset is formed in 32 bits (the host only picks IDX = uint32_t when every
+// buffer the kernel touches is below 4 GiB), so loads and stores use a
+// uniform 64-bit base plus a 32-bit per-lane offset.
+template <class T, class IDX>
+__device__ __forceinline__ T &at(T *base, IDX i) {
+    if constexpr (sizeof(IDX) == 4)
+        return *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+    else
+        return base[i];
+}
+template <class T, class IDX>
+__device__ __forceinline__ const T &at(const T *base, IDX i) {
+    if constexpr (sizeof(IDX) == 4)
+        return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (uint32_t)(i * (uint32_t)sizeof(T)));
+    else
+        return base[i];
+}
+
 struct StepArgs {
     const void *fa;
     void *fb;
@@ -96,7 +115,7 @@ struct StepArgs {
     const uint8_t *cls;
     const uint32_t *links;
     void *fibm;           // [3][N] immersed-boundary force accumulator
-    uint8_t *tflag;       // [ntiles] 1 = the tile holds spread force
+    uint32_t *tflag;      // [ntiles] bit 0: the tile holds spread force
     const void *gfield;   // [3][N] or null
     int nx, ny, nz, tpr;  // tpr = 64-node tiles per x-row
     int ntiles;
@@ -111,7 +130,10 @@ struct StepArgs {
 // straight to its destination slot (neighbour along c_i, or the opposite
 // slot of the same node when that link is a wall link).  The spread force of
 // a tile is read, and cleared, only when the tile's flag says it has one.
-template <class S, class R, bool DEV, bool HAS_G>
+// IDX is the index type of element offsets from the buffer base: uint32_t
+// when 19 planes fit in 4 GiB (single 64-bit base + 32-bit lane offsets),
+// int64_t otherwise.
+template <class S, class R, bool DEV, bool HAS_G, class IDX>
 __global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
@@ -119,34 +141,38 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
     const int row = tile / a.tpr;
     const int x = (tile - row * a.tpr) * 64 + lane;
     if (x >= a.nx) return;
-    const int64_t n = (int64_t)row * a.nx + x;
-    const int64_t N = a.N;
+    const IDX n = (IDX)row * (IDX)a.nx + (IDX)x;
+    const IDX N = (IDX)a.N;
+    const IDX stride = (IDX)a.stride;
 
     R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
     if (HAS_G) {
         const R *G = static_cast<const R *>(a.gfield);
-        Fx += G[n];
-        Fy += G[N + n];
-        Fz += G[2 * N + n];
+        Fx += at(G, n);
+        Fy += at(G, N + n);
+        Fz += at(G, 2 * N + n);
     }
-    if (a.tflag[tile]) {
-        R *fi = static_cast<R *>(a.fibm);
-        Fx += fi[n];
-        Fy += fi[N + n];
-        Fz += fi[2 * N + n];
-        fi[n] = R(0);
-        fi[N + n] = R(0);
-        fi[2 * N + n] = R(0);
-        if (lane == 0) a.tflag[tile] = 0;
+    const uint32_t tf = a.tflag[tile];
+    if (tf) {
+        if (tf & 1u) {
+            R *fi = static_cast<R *>(a.fibm);
+            Fx += at(fi, n);
+            Fy += at(fi, N + n);
+            Fz += at(fi, 2 * N + n);
+            at(fi, n) = R(0);
+            at(fi, N + n) = R(0);
+            at(fi, 2 * N + n) = R(0);
+        }
+        if (lane == 0) a.tflag[tile] = 0u;
     }
-    const uint8_t cl = a.cls[n];
+    const uint8_t cl = at(a.cls, n);
     if (cl == CLS_SOLID) return;
 
     const S *__restrict__ fa = static_cast<const S *>(a.fa);
     S *__restrict__ fb = static_cast<S *>(a.fb);
     R f[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) f[i] = R(fa[i * a.stride + n]);
+    for (int i = 0; i < Q; i++) f[i] = R(at(fa, (IDX)i * stride + n));
 
     collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
 
@@ -157,15 +183,15 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
     const int ym = (y == 0) ? a.ny - 1 : y - 1;
     const int zp = (z + 1 == a.nz) ? 0 : z + 1;
     const int zm = (z == 0) ? a.nz - 1 : z - 1;
-    const uint32_t links = (cl == CLS_WALL) ? a.links[n] : 0u;
+    const uint32_t links = (cl == CLS_WALL) ? at(a.links, n) : 0u;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const int xq = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
         const int yq = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
         const int zq = cz(i) > 0 ? zp : (cz(i) < 0 ? zm : z);
-        const int64_t dst = ((links >> i) & 1u) ? (int64_t)opp(i) * a.stride + n
-                                               : (int64_t)i * a.stride + xq + (int64_t)a.nx * (yq + (int64_t)a.ny * zq);
-        fb[dst] = S(f[i]);
+        const IDX dst = ((links >> i) & 1u) ? (IDX)opp(i) * stride + n
+                                           : (IDX)i * stride + (IDX)xq + (IDX)a.nx * ((IDX)yq + (IDX)a.ny * (IDX)zq);
+        at(fb, dst) = S(f[i]);
     }
 }
 

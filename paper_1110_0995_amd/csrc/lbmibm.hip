@@ -69,7 +69,11 @@ struct lbm_ctx {
     uint8_t *cls = nullptr;
     uint32_t *links = nullptr;
     void *fibm = nullptr;
-    uint8_t *tflag = nullptr;
+    void *ufield = nullptr;      // [3][N] fluid velocity of the listed tiles
+    uint32_t *tflag = nullptr;   // [ntiles] TILE_FORCE / TILE_NEED_U
+    uint32_t *tlist = nullptr;   // [ntiles] tiles under some IB stencil this step
+    uint32_t *tcount = nullptr;  // length of tlist
+    bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
     int64_t nparts = 0;
     double *sums = nullptr;
@@ -118,7 +122,7 @@ LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int64_t es = p->prec == LBM_F64 ? 8 : 4;
     const int64_t tiles = cdiv(p->nx, 64) * (int64_t)p->ny * p->nz;
-    return N + 4 * N + 3 * N * es + tiles + cdiv(N, 256) * 32 + 32;
+    return N + 4 * N + 6 * N * es + 8 * tiles + 4 + cdiv(N, 256) * 32 + 32;
 }
 
 LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
@@ -135,12 +139,16 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
     c->ntiles = c->tpr * p->ny * p->nz;
     c->rsize = p->prec == LBM_F64 ? 8 : 4;
     c->nparts = cdiv(c->N, 256);
+    c->off32 = 19 * c->stride * (int64_t)c->rsize < (int64_t(1) << 32);
     auto cleanup = [&](int rc) {
         lbm_destroy(c);
         return rc;
     };
     if (hipMalloc(&c->cls, c->N) != hipSuccess || hipMalloc(&c->links, 4 * c->N) != hipSuccess ||
-        hipMalloc(&c->fibm, 3 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->tflag, c->ntiles) != hipSuccess ||
+        hipMalloc(&c->fibm, 3 * c->N * c->rsize) != hipSuccess ||
+        hipMalloc(&c->ufield, 3 * c->N * c->rsize) != hipSuccess ||
+        hipMalloc(&c->tflag, 4 * (size_t)c->ntiles) != hipSuccess ||
+        hipMalloc(&c->tlist, 4 * (size_t)c->ntiles) != hipSuccess || hipMalloc(&c->tcount, 4) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
         hipHostMalloc(&c->host_sums, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -151,7 +159,8 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
     const int nb = (int)cdiv(c->N, 256);
     k_classify<<<nb, 256, 0, c->s>>>(g, p->solid, c->cls, c->links);
     if (hipMemsetAsync(c->fibm, 0, 3 * c->N * c->rsize, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tflag, 0, c->ntiles, c->s) != hipSuccess)
+        hipMemsetAsync(c->tflag, 0, 4 * (size_t)c->ntiles, c->s) != hipSuccess ||
+        hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess)
         return cleanup(fail(LBM_EHIP, "clearing the force accumulator failed"));
     for (void *f : {p->f_a, p->f_b}) {
         switch (p->prec) {
@@ -172,7 +181,10 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->cls) (void)hipFree(c->cls);
     if (c->links) (void)hipFree(c->links);
     if (c->fibm) (void)hipFree(c->fibm);
+    if (c->ufield) (void)hipFree(c->ufield);
     if (c->tflag) (void)hipFree(c->tflag);
+    if (c->tlist) (void)hipFree(c->tlist);
+    if (c->tcount) (void)hipFree(c->tcount);
     if (c->partials) (void)hipFree(c->partials);
     if (c->sums) (void)hipFree(c->sums);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -185,10 +197,17 @@ static void *nxt_f(const lbm_ctx *c) { return c->cur ? c->p.f_a : c->p.f_b; }
 template <class S, class R, bool DEV>
 static void launch_step(lbm_ctx *c, const StepArgs &a) {
     const int nb = (int)cdiv(c->ntiles, 4);
-    if (c->p.gfield)
-        k_collide_stream<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
-    else
-        k_collide_stream<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
+    if (c->off32) {
+        if (c->p.gfield)
+            k_collide_stream<S, R, DEV, true, uint32_t><<<nb, 256, 0, c->s>>>(a);
+        else
+            k_collide_stream<S, R, DEV, false, uint32_t><<<nb, 256, 0, c->s>>>(a);
+    } else {
+        if (c->p.gfield)
+            k_collide_stream<S, R, DEV, true, int64_t><<<nb, 256, 0, c->s>>>(a);
+        else
+            k_collide_stream<S, R, DEV, false, int64_t><<<nb, 256, 0, c->s>>>(a);
+    }
 }
 
 LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
@@ -302,7 +321,7 @@ static int check_mesh_ptrs(const ibm_mesh *m) {
     if (m->ncells < 1 || m->nverts < 1 || m->ntris < 1 || m->nedges < 1)
         return fail(LBM_EINVAL, "mesh counts must be >= 1");
     if (!m->vert_off || !m->tri_off || !m->edge_off || !m->tri || !m->hinge || !m->anchor || !m->x || !m->v ||
-        !m->f_el || !m->moduli || !m->l0 || !m->a0 || !m->th0 || !m->a0c || !m->v0c)
+        !m->f_el || !m->moduli || !m->l0 || !m->a0 || !m->th0 || !m->a0c || !m->v0c || !m->avert)
         return fail(LBM_EINVAL, "mesh has a NULL array");
     if (!(m->xi > 0) || !(m->mass > 0) || !(m->dt > 0) || !std::isfinite(m->xi) || !std::isfinite(m->mass) ||
         !std::isfinite(m->dt))
@@ -310,15 +329,39 @@ static int check_mesh_ptrs(const ibm_mesh *m) {
     return LBM_OK;
 }
 
-static size_t membrane_smem(int maxv, size_t rsize) { return 8 * sizeof(double) + 6 * (size_t)maxv * rsize; }
-static constexpr size_t kMaxSmem = 64 * 1024;
+static constexpr size_t kMaxLds = 64 * 1024;
 
 template <class R>
 static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
-    MembArgs a{m->vert_off, m->tri_off, m->edge_off, m->tri, m->hinge, m->x, m->f_el, m->moduli,
-               m->l0, m->a0, m->th0, m->a0c, m->v0c, m->ncells, m->nverts, m->ntris, m->nedges,
-               m->max_cell_verts};
-    const size_t sm = membrane_smem(m->max_cell_verts, sizeof(R));
+    MembArgs a{};
+    a.vert_off = m->vert_off;
+    a.tri_off = m->tri_off;
+    a.edge_off = m->edge_off;
+    a.tri = m->tri;
+    a.hinge = m->hinge;
+    a.anchor = m->anchor;
+    a.x = m->x;
+    a.f_el = m->f_el;
+    a.moduli = m->moduli;
+    a.l0 = m->l0;
+    a.a0 = m->a0;
+    a.th0 = m->th0;
+    a.a0c = m->a0c;
+    a.v0c = m->v0c;
+    a.avert = m->avert;
+    a.ncells = m->ncells;
+    a.nverts = m->nverts;
+    a.ntris = m->ntris;
+    a.nedges = m->nedges;
+    a.maxv = m->max_cell_verts;
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.nz = c->p.nz;
+    a.tpr = c->tpr;
+    a.tflag = c->tflag;
+    a.tlist = c->tlist;
+    a.tcount = c->tcount;
+    const size_t sm = membrane_lds_bytes<R>(m->max_cell_verts);
     if (rest)
         k_membrane<R, true><<<m->ncells, 256, sm, c->s>>>(a);
     else
@@ -350,17 +393,18 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
         for (int t = to[k]; t < to[k + 1]; t++)
             for (int j = 0; j < 3; j++) {
                 const int v = tri[(size_t)j * m->ntris + t];
-                if (v < vo[k] || v >= vo[k + 1]) return fail(LBM_EINVAL, "triangle %d of cell %d uses vertex %d outside the cell", t, k, v);
+                if (v < vo[k] || v >= vo[k + 1])
+                    return fail(LBM_EINVAL, "triangle %d of cell %d uses vertex %d outside the cell", t, k, v);
             }
         for (int e = eo[k]; e < eo[k + 1]; e++)
             for (int j = 0; j < 4; j++) {
                 const int v = hin[(size_t)j * m->nedges + e];
-                if (v < vo[k] || v >= vo[k + 1]) return fail(LBM_EINVAL, "edge %d of cell %d uses vertex %d outside the cell", e, k, v);
+                if (v < vo[k] || v >= vo[k + 1])
+                    return fail(LBM_EINVAL, "edge %d of cell %d uses vertex %d outside the cell", e, k, v);
             }
     }
-    if (membrane_smem(mv, c->rsize) > kMaxSmem)
-        return fail(LBM_EINVAL, "a cell has %d vertices; at most %d fit one workgroup's LDS", mv,
-                    (int)((kMaxSmem - 8 * sizeof(double)) / (6 * c->rsize)));
+    const size_t lds = c->rsize == 8 ? membrane_lds_bytes<double>(mv) : membrane_lds_bytes<float>(mv);
+    if (lds > kMaxLds) return fail(LBM_EINVAL, "a cell has %d vertices, too many for one workgroup's LDS", mv);
     m->max_cell_verts = mv;
     m->max_cell_tris = mt;
     m->max_cell_edges = me;
@@ -374,50 +418,74 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
 }
 
 template <class S, class R, bool DEV>
-static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
-    CoupleArgs a{};
+static void launch_tile_velocity(lbm_ctx *c) {
+    TileVelArgs a{};
     a.f = cur_f(c);
     a.stride = c->stride;
     a.cls = c->cls;
     a.gfield = c->p.gfield;
+    a.ufield = c->ufield;
+    a.tlist = c->tlist;
+    a.tcount = c->tcount;
+    a.nx = c->p.nx;
+    a.tpr = c->tpr;
+    a.N = c->N;
+    for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
+    // enough waves to cover a tile list of up to a quarter of the lattice in one pass
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
+    if (c->p.gfield)
+        k_tile_velocity<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
+    else
+        k_tile_velocity<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
+}
+
+template <class R>
+static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
+    CoupleArgs a{};
+    a.ufield = c->ufield;
     a.fibm = c->fibm;
     a.tflag = c->tflag;
+    a.tcount = c->tcount;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.nz = c->p.nz;
     a.tpr = c->tpr;
     a.N = c->N;
-    for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
     a.vert_off = m->vert_off;
     a.anchor = m->anchor;
     a.x = m->x;
     a.v = m->v;
     a.f_el = m->f_el;
+    a.avert = m->avert;
     a.ncells = m->ncells;
     a.nverts = m->nverts;
     a.xi = m->xi;
     a.dt_over_m = m->dt / m->mass;
     a.dt = m->dt;
     dim3 grid((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells);
-    if (c->p.gfield)
-        k_couple<S, R, DEV, true><<<grid, 128, 0, c->s>>>(a);
-    else
-        k_couple<S, R, DEV, false><<<grid, 128, 0, c->s>>>(a);
+    k_couple<R><<<grid, 128, 0, c->s>>>(a);
 }
 
 LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
     if (int rc = check_mesh_ptrs(m)) return rc;
     if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
-    if (c->p.prec == LBM_F64) {
-        launch_membrane<double>(c, m, false);
-        launch_couple<double, double, false>(c, m);
-    } else {
-        launch_membrane<float>(c, m, false);
-        if (c->p.prec == LBM_F32)
-            launch_couple<float, float, false>(c, m);
-        else
-            launch_couple<float, float, true>(c, m);
+    switch (c->p.prec) {
+        case LBM_F64:
+            launch_membrane<double>(c, m, false);
+            launch_tile_velocity<double, double, false>(c);
+            launch_couple<double>(c, m);
+            break;
+        case LBM_F32:
+            launch_membrane<float>(c, m, false);
+            launch_tile_velocity<float, float, false>(c);
+            launch_couple<float>(c, m);
+            break;
+        default:
+            launch_membrane<float>(c, m, false);
+            launch_tile_velocity<float, float, true>(c);
+            launch_couple<float>(c, m);
+            break;
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;

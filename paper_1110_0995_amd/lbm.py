@@ -144,16 +144,18 @@ class Mesh:
         self.v = torch.zeros_like(self.x)
         self.f_el = torch.zeros_like(self.x)
         self.moduli = torch.as_tensor(np.ascontiguousarray(np.asarray(cells.moduli, np.float64).T)).to(dev, R).contiguous()
-        self.l0 = torch.zeros(cells.nedges, dtype=R, device=dev)
-        self.th0 = torch.zeros(cells.nedges, dtype=R, device=dev)
-        self.a0 = torch.zeros(cells.ntris, dtype=R, device=dev)
-        self.a0c = torch.zeros(cells.ncells, dtype=torch.float64, device=dev)
-        self.v0c = torch.zeros(cells.ncells, dtype=torch.float64, device=dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.l0 = torch.zeros(cells.nedges, **f64)
+        self.th0 = torch.zeros(cells.nedges, **f64)
+        self.a0 = torch.zeros(cells.ntris, **f64)
+        self.a0c = torch.zeros(cells.ncells, **f64)
+        self.v0c = torch.zeros(cells.ncells, **f64)
+        self.avert = torch.zeros(cells.nverts, **f64)
         p = lambda t: t.data_ptr()
         self.s = _lib.IbmMesh(cells.ncells, cells.nverts, cells.ntris, cells.nedges, p(self.vert_off),
                               p(self.tri_off), p(self.edge_off), p(self.tri), p(self.hinge), p(self.anchor),
                               p(self.x), p(self.v), p(self.f_el), p(self.moduli), p(self.l0), p(self.a0),
-                              p(self.th0), p(self.a0c), p(self.v0c), float(cells.xi), float(cells.mass),
+                              p(self.th0), p(self.a0c), p(self.v0c), p(self.avert), float(cells.xi), float(cells.mass),
                               float(cells.dt), 0, 0, 0, 0)
         _lib.check(lat.lib.ibm_rest_shape(lat.ctx, C.byref(self.s)))
         lat.meshes.append(self)
@@ -162,6 +164,10 @@ class Mesh:
         """Absolute positions (float64 [nverts, 3]) = anchor + offset."""
         x = self.x.double().cpu().numpy().T
         return self.cells.anchor[self.cells.vertex_cell()].astype(np.float64) + x
+
+    def point_mass(self) -> np.ndarray:
+        """Mass of each IB point: the areal mass density times its rest area."""
+        return self.cells.mass * self.avert.cpu().numpy()
 
     def velocities(self) -> np.ndarray:
         return self.v.double().cpu().numpy().T.copy()

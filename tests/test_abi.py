@@ -94,4 +94,7 @@ def test_null_context_calls(L):
 def test_workspace_bytes(L):
     p = _params()
     n = 512
-    assert L.lbm_workspace_bytes(C.byref(p)) == n + 4 * n + 3 * n * 4 + 8 * 8 + 2 * 32 + 32
+    tiles = 8 * 8  # one 64-wide tile per x-row
+    # node class + link mask + force accumulator and velocity field (3 floats each)
+    # + tile flags and tile list + list length + reduction partials + sums
+    assert L.lbm_workspace_bytes(C.byref(p)) == n + 4 * n + 6 * n * 4 + 8 * tiles + 4 + 2 * 32 + 32

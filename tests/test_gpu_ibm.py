@@ -121,10 +121,11 @@ def test_momentum_periodic_box_with_cells(lbm):
     mesh.set_offsets(s.cells.offset + 0.1 * rng.standard_normal(s.cells.offset.shape))
     import torch
     mesh.v.copy_(torch.as_tensor(1e-3 * rng.standard_normal((3, s.cells.nverts)), dtype=mesh.v.dtype))
-    p0 = lat.sums()[1:] + mesh.velocities().sum(0)
-    scale = np.abs(mesh.velocities()).sum()
+    mk = mesh.point_mass()[:, None]
+    p0 = lat.sums()[1:] + (mk * mesh.velocities()).sum(0)
+    scale = (mk * np.abs(mesh.velocities())).sum()
     lat.run(100, mesh)
-    p1 = lat.sums()[1:] + mesh.velocities().sum(0)
+    p1 = lat.sums()[1:] + (mk * mesh.velocities()).sum(0)
     assert np.abs(p1 - p0).max() < 1e-12 * scale
 
 
@@ -166,24 +167,52 @@ def test_posts_cells_full_size(orc, lbm):
     assert np.abs(mesh.positions() - X).max() < 1e-5
     mo = orc.mass_momentum(L, f)
     mg = lat.sums()
-    assert abs(mg[0] - mo[0]) / mo[0] < 1e-12
+    assert abs(mg[0] - mo[0]) / mo[0] < 1e-10
 
 
 def test_throughput_workload_full_size(orc, lbm):
     """512x256x128, 8x4 posts, 400 cells (the timed workload, in the launch
-    configuration the benchmark uses): 2 coupled steps vs the oracle."""
+    configuration the benchmark uses): 5 coupled steps vs the oracle."""
     s = S.throughput()
     lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f32dev")
     f = L.rest()
-    orc.run(L, M, f, X, V, nsteps=2)
-    lat.run(2, mesh)
+    orc.run(L, M, f, X, V, nsteps=5)
+    lat.run(5, mesh)
     fl = s.solid.reshape(-1) == 0
     _, uo = orc.fluid_velocity(L, f)
     _, ug = lat.fields()
     err = rel_l2(ug.double().cpu().numpy(), uo, fl)
-    print(f"throughput full size, 2 steps: u rel L2 {err:.3e}")
+    print(f"throughput full size, 5 steps: u rel L2 {err:.3e}")
     assert err < 1e-5
     assert np.abs(mesh.positions() - X).max() < 1e-5
+
+
+def test_two_meshes_in_one_step(orc, lbm):
+    """Two membrane populations coupled before the same collide-stream pass
+    (tiles shared by both) equal one merged population in the oracle."""
+    s = _small(48, 40, 28, ncells=4, level=2, radius=3.0, posts=False, seed=21)
+    c = s.cells
+    half = lambda lo, hi: S.make_cells(c.anchor[lo:hi] + 0.0, 3.0, 2, moduli=(0.02, 0.005, 0.01, 0.1, 0.5))
+    # rebuild the same cells as two populations with the same offsets
+    a, b = half(0, 2), half(2, 4)
+    a.offset[:] = c.offset[: a.nverts]
+    b.offset[:] = c.offset[a.nverts:]
+    lat = lbm.Lattice.from_scenario(s, prec="f64")
+    ma, mb = lbm.Mesh(lat, a), lbm.Mesh(lat, b)
+    L = orc.Lattice.from_scenario(s)
+    M = orc.Mesh(c)
+    X = c.positions()
+    M.rest_shape(X)
+    V = np.zeros_like(X)
+    f = L.rest()
+    for _ in range(15):
+        lat.couple(ma)
+        lat.couple(mb)
+        lat.step(1)
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    assert np.abs(lat.populations_f64().cpu().numpy()[:, fl] - f[:, fl]).max() < 1e-14
+    assert np.abs(np.concatenate([ma.positions(), mb.positions()]) - X).max() < 1e-12
 
 
 def test_couple_requires_rest_shape(lbm):
