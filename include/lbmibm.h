@@ -95,7 +95,7 @@ typedef struct {
     const int32_t *tri;      /* [3][ntris] vertices (a,b,c), counter-clockwise seen from outside */
     const int32_t *hinge;    /* [4][nedges] (p1,p2,qa,qb): triangles (p1,p2,qa) and (p2,p1,qb) share edge p1-p2 */
     const int32_t *anchor;   /* [3][ncells] integer anchor of each cell */
-    void *x;                 /* [3][nverts] real: position minus the cell's anchor (updated by ibm_couple) */
+    double *x;               /* [3][nverts] position minus the cell's anchor, FP64 in every precision (updated by ibm_couple) */
     void *v;                 /* [3][nverts] real: velocity (updated by ibm_couple) */
     void *f_el;              /* [3][nverts] real: written with the elastic force of the last ibm_couple */
     const void *moduli;      /* [5][ncells] real: k_s, k_b, k_al, k_ag, k_v per cell (Table 1 order K^S, K^B, K^A_l, K^A_g, K^V) */

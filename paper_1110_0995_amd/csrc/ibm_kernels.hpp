@@ -1,26 +1,29 @@
 // Immersed-boundary kernels (Sec. 2.2) and membrane forces (Sec. 2.3).
 //
-// One coupled step runs three kernels before the collide-stream pass:
+// One coupled step runs four kernels before the collide-stream pass:
 //
-// k_membrane (one workgroup per cell): the cell's vertex offsets are staged
-//   in LDS; the cell's total area and volume (the global constraints that
-//   need every vertex of the cell, Sec. 2.3.3) are reduced first, then each
-//   triangle and each edge/hinge adds its energy gradient to its vertices
-//   with LDS atomics, and the forces are written out once.  Lengths, areas,
-//   angles and volumes are evaluated in FP64 from the stored positions, so
-//   their small departures from the (FP64) rest shape keep full accuracy in
-//   every storage precision.  The same pass marks every 64-node lattice tile
-//   that a vertex's 2x2x2 stencil touches and appends it once to a tile list.
+// k_membrane (one workgroup per cell): the cell's vertex positions are
+//   staged in LDS; the cell's total area and volume (the global constraints
+//   that need every vertex of the cell, Sec. 2.3.3) are reduced first, then
+//   each triangle and each edge/hinge adds its energy gradient to its
+//   vertices with LDS atomics, and the forces are written out once.
+//   Lengths, areas, angles and volumes are evaluated in FP64 from the FP64
+//   positions, so their small departures from the (FP64) rest shape keep
+//   full accuracy in every storage precision.  The same pass marks, with
+//   plain byte stores, every lattice node of every vertex's 2x2x2 stencil
+//   and the 64-node tile holding it.
 //
-// k_tile_velocity (one wave per listed tile): u_ext = (j + F_ext/2)/rho of
-//   the tile's 64 nodes from their current populations (coalesced loads),
-//   written to a 3-component field; each node is evaluated once however many
-//   IB points use it.
+// k_compact: the marked tiles become a dense list (one atomic per wave).
+//
+// k_node_velocity (one wave per listed tile): u_ext = (j + F_ext/2)/rho of
+//   the marked nodes only, from their current populations, into an AoS
+//   field (one 16-byte record per node); each node is evaluated once however
+//   many IB points use it.
 //
 // k_couple (one thread per IB point): trilinear interpolation of that field
 //   (Sec. 2.2 step 1), coupling force (step 2), spreading of its reaction
-//   with global atomics into the force accumulator, flagging the tiles for
-//   the collide kernel (step 3), and the point update (step 4).
+//   with global atomics into the AoS force accumulator and flagging of the
+//   tiles for the collide kernel (step 3), and the point update (step 4).
 #pragma once
 
 #include "d3q19.hpp"
@@ -28,8 +31,17 @@
 
 namespace lbm {
 
-// tile flag bits
-enum : uint32_t { TILE_FORCE = 1u, TILE_NEED_U = 2u };
+// 4-wide AoS record of the force accumulator and the velocity field
+template <class R>
+struct Vec4;
+template <>
+struct Vec4<float> {
+    using T = float4;
+};
+template <>
+struct Vec4<double> {
+    using T = double4;
+};
 
 struct V3 {
     double x, y, z;
@@ -53,39 +65,40 @@ __device__ __forceinline__ double hinge_angle(V3 p1, V3 p2, V3 qa, V3 qb, V3 &na
 
 struct MembArgs {
     const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge, *anchor;
-    const void *x;  // [3][nverts] offsets
-    void *f_el;     // [3][nverts]
+    const double *x;  // [3][nverts] offsets
+    void *f_el;       // [3][nverts]
     const void *moduli;
     double *l0, *a0, *th0, *a0c, *v0c, *avert;
     int ncells, nverts, ntris, nedges, maxv;
-    // lattice, for marking the stencil tiles
+    // lattice, for marking the stencil nodes
     int nx, ny, nz, tpr;
-    uint32_t *tflag;
-    uint32_t *tlist;
-    uint32_t *tcount;
+    uint8_t *need;   // [N]
+    uint8_t *tneed;  // [ntiles]
 };
 
-// LDS layout: 8 doubles of reduction scratch, maxv doubles (vertex areas in
-// the rest pass), then x, y, z positions and x, y, z force accumulators.
+constexpr int kMembThreads = 512;
+
+// LDS layout: reduction scratch (2 doubles per wave), maxv doubles (vertex
+// areas in the rest pass), x, y, z positions (double) and x, y, z force
+// accumulators (R).
 template <class R>
 __host__ __device__ inline size_t membrane_lds_bytes(int maxv) {
-    return 8 * sizeof(double) + (size_t)maxv * sizeof(double) + 6 * (size_t)maxv * sizeof(R);
+    return 2 * (kMembThreads / 64) * sizeof(double) + 4 * (size_t)maxv * sizeof(double) + 3 * (size_t)maxv * sizeof(R);
 }
 
 // REST = true: write the rest shape; false: elastic forces + tile marking.
 template <class R, bool REST>
-__global__ __launch_bounds__(256) void k_membrane(MembArgs a) {
+__global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     extern __shared__ double smem_d[];
     const int c = blockIdx.x;
     const int v0 = a.vert_off[c], nv = a.vert_off[c + 1] - v0;
     const int t0 = a.tri_off[c], nt = a.tri_off[c + 1] - t0;
     const int e0 = a.edge_off[c], ne = a.edge_off[c + 1] - e0;
-    double *red = smem_d;       // 4 waves x 2
-    double *av = smem_d + 8;    // [maxv]
-    R *px = reinterpret_cast<R *>(av + a.maxv);
-    R *py = px + a.maxv, *pz = py + a.maxv;
-    R *fx = pz + a.maxv, *fy = fx + a.maxv, *fz = fy + a.maxv;
-    const R *X = static_cast<const R *>(a.x);
+    double *red = smem_d;                      // 2 per wave
+    double *av = smem_d + 2 * (kMembThreads / 64);  // [maxv]
+    double *px = av + a.maxv, *py = px + a.maxv, *pz = py + a.maxv;
+    R *fx = reinterpret_cast<R *>(pz + a.maxv), *fy = fx + a.maxv, *fz = fy + a.maxv;
+    const double *X = a.x;
     const int NV = a.nverts;
     for (int k = threadIdx.x; k < nv; k += blockDim.x) {
         px[k] = X[v0 + k];
@@ -95,28 +108,26 @@ __global__ __launch_bounds__(256) void k_membrane(MembArgs a) {
         av[k] = 0.0;
     }
     __syncthreads();
-    auto P = [&](int k) { return V3{(double)px[k], (double)py[k], (double)pz[k]}; };
+    auto P = [&](int k) { return V3{px[k], py[k], pz[k]}; };
     const int NT = a.ntris, NE = a.nedges;
 
     if (!REST) {
-        // mark the tiles under every vertex's stencil (positions of this step)
+        // mark every node of every vertex's stencil (positions of this step)
         const int ax = a.anchor[c], ay = a.anchor[a.ncells + c], az = a.anchor[2 * a.ncells + c];
         for (int k = threadIdx.x; k < nv; k += blockDim.x) {
             const int x0 = pmod(ax + (int)floor(px[k]), a.nx);
             const int y0 = pmod(ay + (int)floor(py[k]), a.ny);
             const int z0 = pmod(az + (int)floor(pz[k]), a.nz);
-            const int x1 = x0 + 1 == a.nx ? 0 : x0 + 1;
+            const int xs[2] = {x0, x0 + 1 == a.nx ? 0 : x0 + 1};
             const int ys[2] = {y0, y0 + 1 == a.ny ? 0 : y0 + 1};
             const int zs[2] = {z0, z0 + 1 == a.nz ? 0 : z0 + 1};
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int row = ys[q & 1] + a.ny * zs[q >> 1];
-                const uint32_t t0i = (uint32_t)row * a.tpr + (x0 >> 6), t1i = (uint32_t)row * a.tpr + (x1 >> 6);
-                if (!(a.tflag[t0i] & TILE_NEED_U) && !(atomicOr(&a.tflag[t0i], TILE_NEED_U) & TILE_NEED_U))
-                    a.tlist[atomicAdd(a.tcount, 1u)] = t0i;
-                if (t1i != t0i && !(a.tflag[t1i] & TILE_NEED_U) &&
-                    !(atomicOr(&a.tflag[t1i], TILE_NEED_U) & TILE_NEED_U))
-                    a.tlist[atomicAdd(a.tcount, 1u)] = t1i;
+                a.need[(int64_t)row * a.nx + xs[0]] = 1;
+                a.need[(int64_t)row * a.nx + xs[1]] = 1;
+                a.tneed[(int64_t)row * a.tpr + (xs[0] >> 6)] = 1;
+                a.tneed[(int64_t)row * a.tpr + (xs[1] >> 6)] = 1;
             }
         }
     }
@@ -220,12 +231,30 @@ __global__ __launch_bounds__(256) void k_membrane(MembArgs a) {
     }
 }
 
-struct TileVelArgs {
+// Marked tiles -> dense list (cleared as they are taken).
+__global__ __launch_bounds__(256) void k_compact(uint8_t *__restrict__ tneed, int ntiles, uint32_t *__restrict__ tlist,
+                                                 uint32_t *tcount) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool flag = t < ntiles && tneed[t];
+    const uint64_t m = __ballot(flag);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    uint32_t base = 0;
+    if (lane == __ffsll((unsigned long long)m) - 1) base = atomicAdd(tcount, (uint32_t)__popcll(m));
+    base = __shfl(base, __ffsll((unsigned long long)m) - 1, 64);
+    if (flag) {
+        tlist[base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)t;
+        tneed[t] = 0;
+    }
+}
+
+struct NodeVelArgs {
     const void *f;
     int64_t stride;
     const uint8_t *cls;
     const void *gfield;
-    void *ufield;  // [3][N]
+    void *ufield;  // [N] Vec4
+    uint8_t *need;
     const uint32_t *tlist;
     const uint32_t *tcount;
     int nx, tpr;
@@ -233,21 +262,24 @@ struct TileVelArgs {
     double g[3];
 };
 
-// u_ext of the nodes of every listed tile.  A fixed grid of waves strides
-// over the list (its length is only known on the device).
+// u_ext of the marked nodes of every listed tile.  A fixed grid of waves
+// strides over the list (its length is only known on the device).
 template <class S, class R, bool DEV, bool HAS_G>
-__global__ __launch_bounds__(256) void k_tile_velocity(TileVelArgs a) {
+__global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
+    using R4 = typename Vec4<R>::T;
     const int lane = threadIdx.x & 63;
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     const uint32_t count = *a.tcount;
     const S *f = static_cast<const S *>(a.f);
-    R *U = static_cast<R *>(a.ufield);
+    R4 *U = static_cast<R4 *>(a.ufield);
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
         const uint32_t tile = a.tlist[w];
         const uint32_t row = tile / a.tpr;
         const int x = (int)(tile - row * a.tpr) * 64 + lane;
         if (x >= a.nx) continue;
         const int64_t n = (int64_t)row * a.nx + x;
+        if (!a.need[n]) continue;
+        a.need[n] = 0;
         R ux = R(0), uy = R(0), uz = R(0);
         if (a.cls[n] != CLS_SOLID) {
             R v[Q];
@@ -271,21 +303,20 @@ __global__ __launch_bounds__(256) void k_tile_velocity(TileVelArgs a) {
             uy = (jy + R(0.5) * Fy) * ir;
             uz = (jz + R(0.5) * Fz) * ir;
         }
-        U[n] = ux;
-        U[a.N + n] = uy;
-        U[2 * a.N + n] = uz;
+        U[n] = R4{ux, uy, uz, R(0)};
     }
 }
 
 struct CoupleArgs {
-    const void *ufield;
-    void *fibm;
-    uint32_t *tflag;
+    const void *ufield;  // [N] Vec4
+    void *fibm;          // [N] Vec4
+    uint8_t *tforce;
     uint32_t *tcount;
     int nx, ny, nz, tpr;
     int64_t N;
     const int32_t *vert_off, *anchor;
-    void *x, *v;
+    double *x;
+    void *v;
     const void *f_el;
     const double *avert;
     int ncells, nverts;
@@ -294,19 +325,20 @@ struct CoupleArgs {
 
 template <class R>
 __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
+    using R4 = typename Vec4<R>::T;
     const int c = blockIdx.y;
     if (c == 0 && blockIdx.x == 0 && threadIdx.x == 0) *a.tcount = 0;  // the tile list was consumed
     const int vb = a.vert_off[c], ve = a.vert_off[c + 1];
     const int k = vb + blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ve) return;
     const int NV = a.nverts;
-    R *X = static_cast<R *>(a.x);
+    double *X = a.x;
     R *Vv = static_cast<R *>(a.v);
     const R *FE = static_cast<const R *>(a.f_el);
-    const R *U = static_cast<const R *>(a.ufield);
-    const R ox = X[k], oy = X[NV + k], oz = X[2 * NV + k];
-    const R flx = floor(ox), fly = floor(oy), flz = floor(oz);
-    const R dx = ox - flx, dy = oy - fly, dz = oz - flz;
+    const R4 *U = static_cast<const R4 *>(a.ufield);
+    const double ox = X[k], oy = X[NV + k], oz = X[2 * NV + k];
+    const double flx = floor(ox), fly = floor(oy), flz = floor(oz);
+    const R dx = R(ox - flx), dy = R(oy - fly), dz = R(oz - flz);
     const int x0 = pmod(a.anchor[c] + (int)flx, a.nx);
     const int y0 = pmod(a.anchor[a.ncells + c] + (int)fly, a.ny);
     const int z0 = pmod(a.anchor[2 * a.ncells + c] + (int)flz, a.nz);
@@ -322,9 +354,10 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
         const int bx = q & 1, by = (q >> 1) & 1, bz = q >> 2;
         const int64_t n = xs[bx] + (int64_t)a.nx * (ys[by] + (int64_t)a.ny * zs[bz]);
         const R wt = wx[bx] * wy[by] * wz[bz];
-        ux += wt * U[n];
-        uy += wt * U[a.N + n];
-        uz += wt * U[2 * a.N + n];
+        const R4 u = U[n];
+        ux += wt * u.x;
+        uy += wt * u.y;
+        uz += wt * u.z;
     }
     // step 2: coupling force, friction per unit area times the vertex's area
     const double ak = a.avert[k];
@@ -332,27 +365,28 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const R xi = R(a.xi * ak);
     const R fcx = xi * (ux - vx), fcy = xi * (uy - vy), fcz = xi * (uz - vz);
     // step 3: spread -F_c
-    R *FI = static_cast<R *>(a.fibm);
+    R4 *FI = static_cast<R4 *>(a.fibm);
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const int bx = q & 1, by = (q >> 1) & 1, bz = q >> 2;
         const int row = ys[by] + a.ny * zs[bz];
         const int64_t n = xs[bx] + (int64_t)a.nx * row;
         const R wt = wx[bx] * wy[by] * wz[bz];
-        atomicAdd(&FI[n], -wt * fcx);
-        atomicAdd(&FI[a.N + n], -wt * fcy);
-        atomicAdd(&FI[2 * a.N + n], -wt * fcz);
-        a.tflag[(int64_t)row * a.tpr + (xs[bx] >> 6)] = TILE_FORCE;
+        R *rec = reinterpret_cast<R *>(&FI[n]);
+        atomicAdd(rec + 0, -wt * fcx);
+        atomicAdd(rec + 1, -wt * fcy);
+        atomicAdd(rec + 2, -wt * fcz);
+        a.tforce[(int64_t)row * a.tpr + (xs[bx] >> 6)] = 1;
     }
     // step 4 (points): semi-implicit Euler with the vertex's mass
-    const R h = R(a.dt_over_m / ak), dt = R(a.dt);
+    const R h = R(a.dt_over_m / ak);
     const R nvx = vx + h * (FE[k] + fcx), nvy = vy + h * (FE[NV + k] + fcy), nvz = vz + h * (FE[2 * NV + k] + fcz);
     Vv[k] = nvx;
     Vv[NV + k] = nvy;
     Vv[2 * NV + k] = nvz;
-    X[k] = ox + dt * nvx;
-    X[NV + k] = oy + dt * nvy;
-    X[2 * NV + k] = oz + dt * nvz;
+    X[k] = ox + a.dt * (double)nvx;
+    X[NV + k] = oy + a.dt * (double)nvy;
+    X[2 * NV + k] = oz + a.dt * (double)nvz;
 }
 
 }  // namespace lbm

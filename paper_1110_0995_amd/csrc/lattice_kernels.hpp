@@ -114,8 +114,8 @@ struct StepArgs {
     int64_t stride;
     const uint8_t *cls;
     const uint32_t *links;
-    void *fibm;           // [3][N] immersed-boundary force accumulator
-    uint32_t *tflag;      // [ntiles] bit 0: the tile holds spread force
+    void *fibm;           // [N] x 4 immersed-boundary force accumulator (x, y, z, unused)
+    uint8_t *tforce;      // [ntiles] 1: the tile holds spread force
     const void *gfield;   // [3][N] or null
     int nx, ny, nz, tpr;  // tpr = 64-node tiles per x-row
     int ntiles;
@@ -152,18 +152,15 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
         Fy += at(G, N + n);
         Fz += at(G, 2 * N + n);
     }
-    const uint32_t tf = a.tflag[tile];
-    if (tf) {
-        if (tf & 1u) {
-            R *fi = static_cast<R *>(a.fibm);
-            Fx += at(fi, n);
-            Fy += at(fi, N + n);
-            Fz += at(fi, 2 * N + n);
-            at(fi, n) = R(0);
-            at(fi, N + n) = R(0);
-            at(fi, 2 * N + n) = R(0);
-        }
-        if (lane == 0) a.tflag[tile] = 0u;
+    if (a.tforce[tile]) {
+        R *fi = static_cast<R *>(a.fibm);
+        Fx += at(fi, 4 * n);
+        Fy += at(fi, 4 * n + 1);
+        Fz += at(fi, 4 * n + 2);
+        at(fi, 4 * n) = R(0);
+        at(fi, 4 * n + 1) = R(0);
+        at(fi, 4 * n + 2) = R(0);
+        if (lane == 0) a.tforce[tile] = 0;
     }
     const uint8_t cl = at(a.cls, n);
     if (cl == CLS_SOLID) return;

@@ -68,10 +68,12 @@ struct lbm_ctx {
     size_t rsize;  // sizeof(real)
     uint8_t *cls = nullptr;
     uint32_t *links = nullptr;
-    void *fibm = nullptr;
-    void *ufield = nullptr;      // [3][N] fluid velocity of the listed tiles
-    uint32_t *tflag = nullptr;   // [ntiles] TILE_FORCE / TILE_NEED_U
-    uint32_t *tlist = nullptr;   // [ntiles] tiles under some IB stencil this step
+    void *fibm = nullptr;        // [N] x 4 real: spread force accumulator
+    void *ufield = nullptr;      // [N] x 4 real: fluid velocity of the marked nodes
+    uint8_t *need = nullptr;     // [N] 1 = node under some IB stencil this step
+    uint8_t *tneed = nullptr;    // [ntiles] 1 = tile holds a marked node
+    uint8_t *tforce = nullptr;   // [ntiles] 1 = tile holds spread force
+    uint32_t *tlist = nullptr;   // [ntiles] marked tiles, compacted
     uint32_t *tcount = nullptr;  // length of tlist
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
@@ -122,7 +124,7 @@ LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int64_t es = p->prec == LBM_F64 ? 8 : 4;
     const int64_t tiles = cdiv(p->nx, 64) * (int64_t)p->ny * p->nz;
-    return N + 4 * N + 6 * N * es + 8 * tiles + 4 + cdiv(N, 256) * 32 + 32;
+    return N + 4 * N + 8 * N * es + N + 6 * tiles + 4 + cdiv(N, 256) * 32 + 32;
 }
 
 LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
@@ -145,9 +147,9 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
         return rc;
     };
     if (hipMalloc(&c->cls, c->N) != hipSuccess || hipMalloc(&c->links, 4 * c->N) != hipSuccess ||
-        hipMalloc(&c->fibm, 3 * c->N * c->rsize) != hipSuccess ||
-        hipMalloc(&c->ufield, 3 * c->N * c->rsize) != hipSuccess ||
-        hipMalloc(&c->tflag, 4 * (size_t)c->ntiles) != hipSuccess ||
+        hipMalloc(&c->fibm, 4 * c->N * c->rsize) != hipSuccess ||
+        hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
+        hipMalloc(&c->tneed, c->ntiles) != hipSuccess || hipMalloc(&c->tforce, c->ntiles) != hipSuccess ||
         hipMalloc(&c->tlist, 4 * (size_t)c->ntiles) != hipSuccess || hipMalloc(&c->tcount, 4) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
@@ -158,8 +160,11 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
     Geometry g{p->nx, p->ny, p->nz, {p->periodic[0], p->periodic[1], p->periodic[2]}};
     const int nb = (int)cdiv(c->N, 256);
     k_classify<<<nb, 256, 0, c->s>>>(g, p->solid, c->cls, c->links);
-    if (hipMemsetAsync(c->fibm, 0, 3 * c->N * c->rsize, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tflag, 0, 4 * (size_t)c->ntiles, c->s) != hipSuccess ||
+    if (hipMemsetAsync(c->fibm, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
+        hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
+        hipMemsetAsync(c->need, 0, c->N, c->s) != hipSuccess ||
+        hipMemsetAsync(c->tneed, 0, c->ntiles, c->s) != hipSuccess ||
+        hipMemsetAsync(c->tforce, 0, c->ntiles, c->s) != hipSuccess ||
         hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess)
         return cleanup(fail(LBM_EHIP, "clearing the force accumulator failed"));
     for (void *f : {p->f_a, p->f_b}) {
@@ -182,7 +187,9 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->links) (void)hipFree(c->links);
     if (c->fibm) (void)hipFree(c->fibm);
     if (c->ufield) (void)hipFree(c->ufield);
-    if (c->tflag) (void)hipFree(c->tflag);
+    if (c->need) (void)hipFree(c->need);
+    if (c->tneed) (void)hipFree(c->tneed);
+    if (c->tforce) (void)hipFree(c->tforce);
     if (c->tlist) (void)hipFree(c->tlist);
     if (c->tcount) (void)hipFree(c->tcount);
     if (c->partials) (void)hipFree(c->partials);
@@ -218,7 +225,7 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     a.cls = c->cls;
     a.links = c->links;
     a.fibm = c->fibm;
-    a.tflag = c->tflag;
+    a.tforce = c->tforce;
     a.gfield = c->p.gfield;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -340,7 +347,7 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.tri = m->tri;
     a.hinge = m->hinge;
     a.anchor = m->anchor;
-    a.x = m->x;
+    a.x = static_cast<const double *>(m->x);
     a.f_el = m->f_el;
     a.moduli = m->moduli;
     a.l0 = m->l0;
@@ -358,14 +365,13 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.ny = c->p.ny;
     a.nz = c->p.nz;
     a.tpr = c->tpr;
-    a.tflag = c->tflag;
-    a.tlist = c->tlist;
-    a.tcount = c->tcount;
+    a.need = c->need;
+    a.tneed = c->tneed;
     const size_t sm = membrane_lds_bytes<R>(m->max_cell_verts);
     if (rest)
-        k_membrane<R, true><<<m->ncells, 256, sm, c->s>>>(a);
+        k_membrane<R, true><<<m->ncells, kMembThreads, sm, c->s>>>(a);
     else
-        k_membrane<R, false><<<m->ncells, 256, sm, c->s>>>(a);
+        k_membrane<R, false><<<m->ncells, kMembThreads, sm, c->s>>>(a);
 }
 
 LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
@@ -418,25 +424,27 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
 }
 
 template <class S, class R, bool DEV>
-static void launch_tile_velocity(lbm_ctx *c) {
-    TileVelArgs a{};
+static void launch_node_velocity(lbm_ctx *c) {
+    k_compact<<<(int)cdiv(c->ntiles, 256), 256, 0, c->s>>>(c->tneed, c->ntiles, c->tlist, c->tcount);
+    NodeVelArgs a{};
     a.f = cur_f(c);
     a.stride = c->stride;
     a.cls = c->cls;
     a.gfield = c->p.gfield;
     a.ufield = c->ufield;
+    a.need = c->need;
     a.tlist = c->tlist;
     a.tcount = c->tcount;
     a.nx = c->p.nx;
     a.tpr = c->tpr;
     a.N = c->N;
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
-    // enough waves to cover a tile list of up to a quarter of the lattice in one pass
+    // one wave per listed tile for lists up to a quarter of the lattice
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
     if (c->p.gfield)
-        k_tile_velocity<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
+        k_node_velocity<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
     else
-        k_tile_velocity<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
+        k_node_velocity<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
 }
 
 template <class R>
@@ -444,7 +452,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     CoupleArgs a{};
     a.ufield = c->ufield;
     a.fibm = c->fibm;
-    a.tflag = c->tflag;
+    a.tforce = c->tforce;
     a.tcount = c->tcount;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -453,7 +461,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     a.N = c->N;
     a.vert_off = m->vert_off;
     a.anchor = m->anchor;
-    a.x = m->x;
+    a.x = static_cast<double *>(m->x);
     a.v = m->v;
     a.f_el = m->f_el;
     a.avert = m->avert;
@@ -473,17 +481,17 @@ LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
     switch (c->p.prec) {
         case LBM_F64:
             launch_membrane<double>(c, m, false);
-            launch_tile_velocity<double, double, false>(c);
+            launch_node_velocity<double, double, false>(c);
             launch_couple<double>(c, m);
             break;
         case LBM_F32:
             launch_membrane<float>(c, m, false);
-            launch_tile_velocity<float, float, false>(c);
+            launch_node_velocity<float, float, false>(c);
             launch_couple<float>(c, m);
             break;
         default:
             launch_membrane<float>(c, m, false);
-            launch_tile_velocity<float, float, true>(c);
+            launch_node_velocity<float, float, true>(c);
             launch_couple<float>(c, m);
             break;
     }

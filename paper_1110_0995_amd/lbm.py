@@ -140,9 +140,9 @@ class Mesh:
         self.tri = i32(np.asarray(cells.tri).T)
         self.hinge = i32(np.asarray(cells.hinge).T)
         self.anchor = i32(np.asarray(cells.anchor).T)
-        self.x = torch.as_tensor(np.ascontiguousarray(np.asarray(cells.offset, np.float64).T)).to(dev, R).contiguous()
-        self.v = torch.zeros_like(self.x)
-        self.f_el = torch.zeros_like(self.x)
+        self.x = torch.as_tensor(np.ascontiguousarray(np.asarray(cells.offset, np.float64).T)).to(dev).contiguous()
+        self.v = torch.zeros(3, cells.nverts, dtype=R, device=dev)
+        self.f_el = torch.zeros_like(self.v)
         self.moduli = torch.as_tensor(np.ascontiguousarray(np.asarray(cells.moduli, np.float64).T)).to(dev, R).contiguous()
         f64 = dict(dtype=torch.float64, device=dev)
         self.l0 = torch.zeros(cells.nedges, **f64)

@@ -242,10 +242,30 @@ class Cells:
         return self.anchor[self.vertex_cell()].astype(np.float64) + self.offset.astype(np.float64)
 
 
+def morton_order(unit: np.ndarray, bits: int = 10) -> np.ndarray:
+    """Permutation sorting points of [-1,1]^3 along a Z-order curve."""
+    q = np.clip(((unit + 1.0) * 0.5 * ((1 << bits) - 1)).round().astype(np.int64), 0, (1 << bits) - 1)
+    code = np.zeros(len(unit), dtype=np.int64)
+    for b in range(bits):
+        for d in range(3):
+            code |= ((q[:, d] >> b) & 1) << (3 * b + d)
+    return np.argsort(code, kind="stable")
+
+
 def make_cells(centres: np.ndarray, radius: float, level: int,
                moduli: Sequence[float] = MODULI_CTC, xi: float = 1.0) -> Cells:
-    """Icosphere cells of the given radius around ``centres`` [n,3]."""
+    """Icosphere cells of the given radius around ``centres`` [n,3].
+
+    The template's vertices are numbered along a Z-order curve, so
+    consecutive vertex ids are neighbours on the surface (and so are the
+    lattice nodes their stencils touch)."""
     unit, tris = icosphere(level)
+    perm = morton_order(unit)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    unit = unit[perm]
+    tris = inv[tris]
+    tris = tris[np.argsort(tris.min(axis=1), kind="stable")]
     hin = hinges(tris)
     nv, nt, ne = len(unit), len(tris), len(hin)
     n = len(centres)

@@ -95,6 +95,7 @@ def test_workspace_bytes(L):
     p = _params()
     n = 512
     tiles = 8 * 8  # one 64-wide tile per x-row
-    # node class + link mask + force accumulator and velocity field (3 floats each)
-    # + tile flags and tile list + list length + reduction partials + sums
-    assert L.lbm_workspace_bytes(C.byref(p)) == n + 4 * n + 6 * n * 4 + 8 * tiles + 4 + 2 * 32 + 32
+    # node class + link mask + force accumulator and velocity field (4 floats
+    # each) + node marks + tile flags (2 bytes) and tile list (4) + list
+    # length + reduction partials + sums
+    assert L.lbm_workspace_bytes(C.byref(p)) == n + 4 * n + 8 * n * 4 + n + 6 * tiles + 4 + 2 * 32 + 32
