@@ -13,7 +13,7 @@
 //   plain byte stores, every lattice node of every vertex's 2x2x2 stencil
 //   and the 64-node tile holding it.
 //
-// k_compact: the marked tiles become a dense list (one atomic per wave).
+// k_compact: the marked tiles become a dense list.
 //
 // k_node_velocity (one wave per listed tile): u_ext = (j + F_ext/2)/rho of
 //   the marked nodes only, from their current populations, into an AoS
@@ -22,8 +22,12 @@
 //
 // k_couple (one thread per IB point): trilinear interpolation of that field
 //   (Sec. 2.2 step 1), coupling force (step 2), spreading of its reaction
-//   with global atomics into the AoS force accumulator and flagging of the
-//   tiles for the collide kernel (step 3), and the point update (step 4).
+//   with global atomics into the AoS force accumulator (step 3), and the
+//   point update (step 4).
+//
+// The node and tile marks stay set until the collide-stream pass: they are
+// exactly the nodes that received spread force, so that pass reads (and
+// clears) the force record of marked nodes only, then clears the marks.
 #pragma once
 
 #include "d3q19.hpp"
@@ -231,20 +235,50 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     }
 }
 
-// Marked tiles -> dense list (cleared as they are taken).
-__global__ __launch_bounds__(256) void k_compact(uint8_t *__restrict__ tneed, int ntiles, uint32_t *__restrict__ tlist,
-                                                 uint32_t *tcount) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool flag = t < ntiles && tneed[t];
-    const uint64_t m = __ballot(flag);
-    if (!m) return;
-    const int lane = threadIdx.x & 63;
-    uint32_t base = 0;
-    if (lane == __ffsll((unsigned long long)m) - 1) base = atomicAdd(tcount, (uint32_t)__popcll(m));
-    base = __shfl(base, __ffsll((unsigned long long)m) - 1, 64);
-    if (flag) {
-        tlist[base + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)t;
-        tneed[t] = 0;
+// Marked tiles -> dense list.  Each thread reads the flags of 16 tiles with
+// one 16-byte load; the block scans its counts and reserves its slots with a
+// single atomic, so the list length costs one atomic per 4096 tiles.
+constexpr int kCompactThreads = 256, kCompactPerThread = 16;
+__global__ __launch_bounds__(kCompactThreads) void k_compact(const uint8_t *__restrict__ tneed, int ntiles,
+                                                             uint32_t *__restrict__ tlist, uint32_t *tcount) {
+    __shared__ uint32_t wsum[kCompactThreads / 64];
+    __shared__ uint32_t base_s;
+    const int t0 = (blockIdx.x * kCompactThreads + threadIdx.x) * kCompactPerThread;
+    uint32_t bits = 0;  // bit j: tile t0 + j is marked
+    if (t0 + kCompactPerThread <= ntiles) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(tneed + t0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if ((w[i] >> (8 * k)) & 0xffu) bits |= 1u << (4 * i + k);
+    } else {
+        for (int j = 0; j < kCompactPerThread; j++)
+            if (t0 + j < ntiles && tneed[t0 + j]) bits |= 1u << j;
+    }
+    const uint32_t cnt = __popc(bits);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kCompactThreads / 64; w++) tot += wsum[w];
+        base_s = tot ? atomicAdd(tcount, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = base_s + inc - cnt;
+    for (int w = 0; w < wave; w++) pos += wsum[w];
+    while (bits) {
+        const int j = __ffs(bits) - 1;
+        bits &= bits - 1;
+        tlist[pos++] = (uint32_t)(t0 + j);
     }
 }
 
@@ -254,7 +288,7 @@ struct NodeVelArgs {
     const uint8_t *cls;
     const void *gfield;
     void *ufield;  // [N] Vec4
-    uint8_t *need;
+    const uint8_t *need;
     const uint32_t *tlist;
     const uint32_t *tcount;
     int nx, tpr;
@@ -279,7 +313,6 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
         if (x >= a.nx) continue;
         const int64_t n = (int64_t)row * a.nx + x;
         if (!a.need[n]) continue;
-        a.need[n] = 0;
         R ux = R(0), uy = R(0), uz = R(0);
         if (a.cls[n] != CLS_SOLID) {
             R v[Q];
@@ -310,7 +343,6 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
 struct CoupleArgs {
     const void *ufield;  // [N] Vec4
     void *fibm;          // [N] Vec4
-    uint8_t *tforce;
     uint32_t *tcount;
     int nx, ny, nz, tpr;
     int64_t N;
@@ -376,7 +408,6 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
         atomicAdd(rec + 0, -wt * fcx);
         atomicAdd(rec + 1, -wt * fcy);
         atomicAdd(rec + 2, -wt * fcz);
-        a.tforce[(int64_t)row * a.tpr + (xs[bx] >> 6)] = 1;
     }
     // step 4 (points): semi-implicit Euler with the vertex's mass
     const R h = R(a.dt_over_m / ak);

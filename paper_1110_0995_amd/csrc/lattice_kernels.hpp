@@ -115,7 +115,8 @@ struct StepArgs {
     const uint8_t *cls;
     const uint32_t *links;
     void *fibm;           // [N] x 4 immersed-boundary force accumulator (x, y, z, unused)
-    uint8_t *tforce;      // [ntiles] 1: the tile holds spread force
+    uint8_t *need;        // [N] 1: the node received spread force this step
+    uint8_t *tneed;       // [ntiles] 1: the tile holds such a node
     const void *gfield;   // [3][N] or null
     int nx, ny, nz, tpr;  // tpr = 64-node tiles per x-row
     int ntiles;
@@ -128,8 +129,8 @@ struct StepArgs {
 // consecutive x of one (y,z) row, reads the 19 planes of its nodes
 // coalesced, collides in registers and writes every post-collision value
 // straight to its destination slot (neighbour along c_i, or the opposite
-// slot of the same node when that link is a wall link).  The spread force of
-// a tile is read, and cleared, only when the tile's flag says it has one.
+// slot of the same node when that link is a wall link).  The spread force is
+// read, and cleared, only at nodes marked as stencil nodes of this step.
 // IDX is the index type of element offsets from the buffer base: uint32_t
 // when 19 planes fit in 4 GiB (single 64-bit base + 32-bit lane offsets),
 // int64_t otherwise.
@@ -152,15 +153,18 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
         Fy += at(G, N + n);
         Fz += at(G, 2 * N + n);
     }
-    if (a.tforce[tile]) {
-        R *fi = static_cast<R *>(a.fibm);
-        Fx += at(fi, 4 * n);
-        Fy += at(fi, 4 * n + 1);
-        Fz += at(fi, 4 * n + 2);
-        at(fi, 4 * n) = R(0);
-        at(fi, 4 * n + 1) = R(0);
-        at(fi, 4 * n + 2) = R(0);
-        if (lane == 0) a.tforce[tile] = 0;
+    if (a.tneed[tile]) {
+        if (at(a.need, n)) {
+            R *fi = static_cast<R *>(a.fibm);
+            Fx += at(fi, 4 * n);
+            Fy += at(fi, 4 * n + 1);
+            Fz += at(fi, 4 * n + 2);
+            at(fi, 4 * n) = R(0);
+            at(fi, 4 * n + 1) = R(0);
+            at(fi, 4 * n + 2) = R(0);
+            at(a.need, n) = 0;
+        }
+        if (lane == 0) a.tneed[tile] = 0;
     }
     const uint8_t cl = at(a.cls, n);
     if (cl == CLS_SOLID) return;

@@ -72,7 +72,6 @@ struct lbm_ctx {
     void *ufield = nullptr;      // [N] x 4 real: fluid velocity of the marked nodes
     uint8_t *need = nullptr;     // [N] 1 = node under some IB stencil this step
     uint8_t *tneed = nullptr;    // [ntiles] 1 = tile holds a marked node
-    uint8_t *tforce = nullptr;   // [ntiles] 1 = tile holds spread force
     uint32_t *tlist = nullptr;   // [ntiles] marked tiles, compacted
     uint32_t *tcount = nullptr;  // length of tlist
     bool off32 = false;          // every lattice buffer below 4 GiB
@@ -124,7 +123,7 @@ LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int64_t es = p->prec == LBM_F64 ? 8 : 4;
     const int64_t tiles = cdiv(p->nx, 64) * (int64_t)p->ny * p->nz;
-    return N + 4 * N + 8 * N * es + N + 6 * tiles + 4 + cdiv(N, 256) * 32 + 32;
+    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + cdiv(N, 256) * 32 + 32;
 }
 
 LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
@@ -149,7 +148,7 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
     if (hipMalloc(&c->cls, c->N) != hipSuccess || hipMalloc(&c->links, 4 * c->N) != hipSuccess ||
         hipMalloc(&c->fibm, 4 * c->N * c->rsize) != hipSuccess ||
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
-        hipMalloc(&c->tneed, c->ntiles) != hipSuccess || hipMalloc(&c->tforce, c->ntiles) != hipSuccess ||
+        hipMalloc(&c->tneed, cdiv(c->ntiles, 16) * 16) != hipSuccess ||
         hipMalloc(&c->tlist, 4 * (size_t)c->ntiles) != hipSuccess || hipMalloc(&c->tcount, 4) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
@@ -163,8 +162,7 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
     if (hipMemsetAsync(c->fibm, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
         hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
         hipMemsetAsync(c->need, 0, c->N, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tneed, 0, c->ntiles, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tforce, 0, c->ntiles, c->s) != hipSuccess ||
+        hipMemsetAsync(c->tneed, 0, cdiv(c->ntiles, 16) * 16, c->s) != hipSuccess ||
         hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess)
         return cleanup(fail(LBM_EHIP, "clearing the force accumulator failed"));
     for (void *f : {p->f_a, p->f_b}) {
@@ -189,7 +187,6 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->ufield) (void)hipFree(c->ufield);
     if (c->need) (void)hipFree(c->need);
     if (c->tneed) (void)hipFree(c->tneed);
-    if (c->tforce) (void)hipFree(c->tforce);
     if (c->tlist) (void)hipFree(c->tlist);
     if (c->tcount) (void)hipFree(c->tcount);
     if (c->partials) (void)hipFree(c->partials);
@@ -225,7 +222,8 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     a.cls = c->cls;
     a.links = c->links;
     a.fibm = c->fibm;
-    a.tforce = c->tforce;
+    a.need = c->need;
+    a.tneed = c->tneed;
     a.gfield = c->p.gfield;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -425,7 +423,8 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
 
 template <class S, class R, bool DEV>
 static void launch_node_velocity(lbm_ctx *c) {
-    k_compact<<<(int)cdiv(c->ntiles, 256), 256, 0, c->s>>>(c->tneed, c->ntiles, c->tlist, c->tcount);
+    k_compact<<<(int)cdiv(c->ntiles, kCompactThreads * kCompactPerThread), kCompactThreads, 0, c->s>>>(
+        c->tneed, c->ntiles, c->tlist, c->tcount);
     NodeVelArgs a{};
     a.f = cur_f(c);
     a.stride = c->stride;
@@ -452,7 +451,6 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     CoupleArgs a{};
     a.ufield = c->ufield;
     a.fibm = c->fibm;
-    a.tforce = c->tforce;
     a.tcount = c->tcount;
     a.nx = c->p.nx;
     a.ny = c->p.ny;

@@ -121,7 +121,9 @@ def test_random_state_ragged_tiles(orc, lbm, prec):
     assert rel_l2(ug, uo, fl) < {"f64": 1e-13, "f32": 1e-4, "f32dev": 1e-5}[prec]
     sums = lat.sums()
     so = orc.mass_momentum(L, f)
-    assert abs(sums[0] - so[0]) / so[0] < {"f64": 1e-14, "f32": 1e-7, "f32dev": 1e-9}[prec]
+    # plain FP32 storage rounds rho = sum f_i near 1 every step (the reason for
+    # the deviation storage), so its mass drifts by ~1e-7 relative
+    assert abs(sums[0] - so[0]) / so[0] < {"f64": 1e-14, "f32": 1e-6, "f32dev": 1e-9}[prec]
 
 
 def test_zero_steps_and_state_pointer(lbm):
