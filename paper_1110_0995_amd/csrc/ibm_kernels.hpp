@@ -21,9 +21,16 @@
 //   many IB points use it.
 //
 // k_couple (one thread per IB point): trilinear interpolation of that field
-//   (Sec. 2.2 step 1), coupling force (step 2), spreading of its reaction
-//   with global atomics into the AoS force accumulator (step 3), and the
-//   point update (step 4).
+//   (Sec. 2.2 step 1), coupling force (step 2), and the point update (step
+//   4).  The reaction force is not scattered with float atomics (device-scope
+//   float atomics run at a small fraction of store throughput): the point
+//   writes a spread record (stencil base, weights, force) and files its id in
+//   the bucket of its stencil's base tile with one integer atomic.
+//
+// k_gather (one wave per listed tile): spreading, Sec. 2.2 step 3, as a
+//   gather: the tile's 64 nodes sum the weighted forces of the points filed
+//   in the (up to 8) buckets whose stencils can reach them, ids sorted
+//   within each bucket so the sum is bit-reproducible.
 //
 // The node and tile marks stay set until the collide-stream pass: they are
 // exactly the nodes that received spread force, so that pass reads (and
@@ -68,6 +75,7 @@ __device__ __forceinline__ double hinge_angle(V3 p1, V3 p2, V3 qa, V3 qb, V3 &na
 }
 
 struct MembArgs {
+    uint32_t *tcount;  // tile-list length, reset here for this step
     const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge, *anchor;
     const double *x;  // [3][nverts] offsets
     void *f_el;       // [3][nverts]
@@ -116,6 +124,7 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     const int NT = a.ntris, NE = a.nedges;
 
     if (!REST) {
+        if (c == 0 && threadIdx.x == 0) *a.tcount = 0;
         // mark every node of every vertex's stencil (positions of this step)
         const int ax = a.anchor[c], ay = a.anchor[a.ncells + c], az = a.anchor[2 * a.ncells + c];
         for (int k = threadIdx.x; k < nv; k += blockDim.x) {
@@ -291,6 +300,7 @@ struct NodeVelArgs {
     const uint8_t *need;
     const uint32_t *tlist;
     const uint32_t *tcount;
+    uint32_t *bcount;  // bucket fill counts, emptied here for the listed tiles
     int nx, tpr;
     int64_t N;
     double g[3];
@@ -308,6 +318,7 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     R4 *U = static_cast<R4 *>(a.ufield);
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
         const uint32_t tile = a.tlist[w];
+        if (lane == 0) a.bcount[tile] = 0;
         const uint32_t row = tile / a.tpr;
         const int x = (int)(tile - row * a.tpr) * 64 + lane;
         if (x >= a.nx) continue;
@@ -340,10 +351,22 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     }
 }
 
+constexpr int kBucketCap = 64;  // point ids per base-tile bucket; overflow spreads with atomics
+
+// Spread record of one IB point: stencil base node, fractional offsets, and
+// the force it exerts on the fluid (-F_c).
+template <class R>
+struct SRec {
+    int32_t bx, by, bz, pad;
+    R dx, dy, dz, fx, fy, fz;
+};
+
 struct CoupleArgs {
     const void *ufield;  // [N] Vec4
-    void *fibm;          // [N] Vec4
-    uint32_t *tcount;
+    void *fibm;          // [N] Vec4 (overflow points only)
+    uint32_t *bcount;    // [ntiles]
+    uint32_t *bucket;    // [ntiles][kBucketCap]
+    void *srec;          // [nverts] SRec
     int nx, ny, nz, tpr;
     int64_t N;
     const int32_t *vert_off, *anchor;
@@ -359,7 +382,6 @@ template <class R>
 __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     using R4 = typename Vec4<R>::T;
     const int c = blockIdx.y;
-    if (c == 0 && blockIdx.x == 0 && threadIdx.x == 0) *a.tcount = 0;  // the tile list was consumed
     const int vb = a.vert_off[c], ve = a.vert_off[c + 1];
     const int k = vb + blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= ve) return;
@@ -396,18 +418,25 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const R vx = Vv[k], vy = Vv[NV + k], vz = Vv[2 * NV + k];
     const R xi = R(a.xi * ak);
     const R fcx = xi * (ux - vx), fcy = xi * (uy - vy), fcz = xi * (uz - vz);
-    // step 3: spread -F_c
-    R4 *FI = static_cast<R4 *>(a.fibm);
+    // step 3 (filing): spread record + bucket of the base tile
+    SRec<R> *SR = static_cast<SRec<R> *>(a.srec);
+    SR[k] = SRec<R>{x0, y0, z0, 0, dx, dy, dz, -fcx, -fcy, -fcz};
+    const uint32_t bt = (uint32_t)(y0 + a.ny * z0) * a.tpr + (x0 >> 6);
+    const uint32_t slot = atomicAdd(&a.bcount[bt], 1u);
+    if (slot < kBucketCap) {
+        a.bucket[(size_t)bt * kBucketCap + slot] = (uint32_t)k;
+    } else {
+        R4 *FI = static_cast<R4 *>(a.fibm);
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-        const int bx = q & 1, by = (q >> 1) & 1, bz = q >> 2;
-        const int row = ys[by] + a.ny * zs[bz];
-        const int64_t n = xs[bx] + (int64_t)a.nx * row;
-        const R wt = wx[bx] * wy[by] * wz[bz];
-        R *rec = reinterpret_cast<R *>(&FI[n]);
-        atomicAdd(rec + 0, -wt * fcx);
-        atomicAdd(rec + 1, -wt * fcy);
-        atomicAdd(rec + 2, -wt * fcz);
+        for (int q = 0; q < 8; q++) {
+            const int bx = q & 1, by = (q >> 1) & 1, bz = q >> 2;
+            const int64_t n = xs[bx] + (int64_t)a.nx * (ys[by] + (int64_t)a.ny * zs[bz]);
+            const R wt = wx[bx] * wy[by] * wz[bz];
+            R *rec = reinterpret_cast<R *>(&FI[n]);
+            atomicAdd(rec + 0, -wt * fcx);
+            atomicAdd(rec + 1, -wt * fcy);
+            atomicAdd(rec + 2, -wt * fcz);
+        }
     }
     // step 4 (points): semi-implicit Euler with the vertex's mass
     const R h = R(a.dt_over_m / ak);
@@ -418,6 +447,85 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     X[k] = ox + a.dt * (double)nvx;
     X[NV + k] = oy + a.dt * (double)nvy;
     X[2 * NV + k] = oz + a.dt * (double)nvz;
+}
+
+// Ascending bitonic sort of one value per lane across a 64-lane wave.
+__device__ __forceinline__ uint32_t wave_sort(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const uint32_t o = __shfl_xor(v, j, 64);
+            const bool up = (lane & k) == 0, lower = (lane & j) == 0;
+            v = (lower == up) ? min(v, o) : max(v, o);
+        }
+    }
+    return v;
+}
+
+struct GatherArgs {
+    const uint32_t *tlist, *tcount, *bcount, *bucket;
+    const void *srec;
+    const uint8_t *need;
+    void *fibm;  // [N] Vec4
+    int nx, ny, nz, tpr;
+};
+
+template <class R>
+__global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
+    using R4 = typename Vec4<R>::T;
+    const int lane = threadIdx.x & 63;
+    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t count = *a.tcount;
+    const SRec<R> *SR = static_cast<const SRec<R> *>(a.srec);
+    R4 *FI = static_cast<R4 *>(a.fibm);
+    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
+        const uint32_t tile = __builtin_amdgcn_readfirstlane(a.tlist[w]);
+        const int row = (int)(tile / a.tpr), tx = (int)(tile - (uint32_t)row * a.tpr);
+        const int y = row % a.ny, z = row / a.ny;
+        const int x = tx * 64 + lane;
+        // buckets whose stencils reach this row segment: base rows y-1, y and
+        // z-1, z; base tiles of x-1 .. x+63 (this tile and the one holding x-1)
+        const int yr[2] = {y, y == 0 ? a.ny - 1 : y - 1};
+        const int zr[2] = {z, z == 0 ? a.nz - 1 : z - 1};
+        const int tr[2] = {tx, (tx * 64 == 0 ? a.nx - 1 : tx * 64 - 1) >> 6};
+        const int nyc = yr[1] == yr[0] ? 1 : 2, nzc = zr[1] == zr[0] ? 1 : 2, ntc = tr[1] == tr[0] ? 1 : 2;
+        R Fx = R(0), Fy = R(0), Fz = R(0);
+        for (int iz = 0; iz < nzc; iz++)
+            for (int iy = 0; iy < nyc; iy++)
+                for (int it = 0; it < ntc; it++) {
+                    const uint32_t b = (uint32_t)(yr[iy] + a.ny * zr[iz]) * a.tpr + tr[it];
+                    const uint32_t cnt = min(__builtin_amdgcn_readfirstlane(a.bcount[b]), (uint32_t)kBucketCap);
+                    if (cnt == 0) continue;
+                    uint32_t id = lane < (int)cnt ? a.bucket[(size_t)b * kBucketCap + lane] : 0xffffffffu;
+                    id = wave_sort(id);
+                    for (uint32_t i = 0; i < cnt; i++) {
+                        const uint32_t pid = __builtin_amdgcn_readfirstlane(__shfl(id, (int)i, 64));
+                        const SRec<R> r = SR[pid];
+                        const int bx1 = r.bx + 1 == a.nx ? 0 : r.bx + 1;
+                        const int by1 = r.by + 1 == a.ny ? 0 : r.by + 1;
+                        const int bz1 = r.bz + 1 == a.nz ? 0 : r.bz + 1;
+                        const R wxl = (r.bx == x ? R(1) - r.dx : R(0)) + (bx1 == x ? r.dx : R(0));
+                        const R wyl = (r.by == y ? R(1) - r.dy : R(0)) + (by1 == y ? r.dy : R(0));
+                        const R wzl = (r.bz == z ? R(1) - r.dz : R(0)) + (bz1 == z ? r.dz : R(0));
+                        const R wt = wxl * wyl * wzl;
+                        Fx += wt * r.fx;
+                        Fy += wt * r.fy;
+                        Fz += wt * r.fz;
+                    }
+                }
+        if (x < a.nx) {
+            const int64_t n = (int64_t)row * a.nx + x;
+            if (a.need[n]) {
+                R4 f = FI[n];
+                f.x += Fx;
+                f.y += Fy;
+                f.z += Fz;
+                FI[n] = f;
+            }
+        }
+    }
 }
 
 }  // namespace lbm

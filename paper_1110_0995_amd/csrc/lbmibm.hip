@@ -74,6 +74,10 @@ struct lbm_ctx {
     uint8_t *tneed = nullptr;    // [ntiles] 1 = tile holds a marked node
     uint32_t *tlist = nullptr;   // [ntiles] marked tiles, compacted
     uint32_t *tcount = nullptr;  // length of tlist
+    uint32_t *bcount = nullptr;  // [ntiles] points filed per base tile
+    uint32_t *bucket = nullptr;  // [ntiles][kBucketCap] point ids
+    void *srec = nullptr;        // spread records, one per IB point of the largest mesh
+    int64_t srec_cap = 0;
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
     int64_t nparts = 0;
@@ -123,7 +127,8 @@ LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int64_t es = p->prec == LBM_F64 ? 8 : 4;
     const int64_t tiles = cdiv(p->nx, 64) * (int64_t)p->ny * p->nz;
-    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + cdiv(N, 256) * 32 + 32;
+    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 * tiles +
+           4 * tiles * kBucketCap + cdiv(N, 256) * 32 + 32;
 }
 
 LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
@@ -150,6 +155,8 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
         hipMalloc(&c->tneed, cdiv(c->ntiles, 16) * 16) != hipSuccess ||
         hipMalloc(&c->tlist, 4 * (size_t)c->ntiles) != hipSuccess || hipMalloc(&c->tcount, 4) != hipSuccess ||
+        hipMalloc(&c->bcount, 4 * (size_t)c->ntiles) != hipSuccess ||
+        hipMalloc(&c->bucket, 4 * (size_t)c->ntiles * kBucketCap) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
         hipHostMalloc(&c->host_sums, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -163,7 +170,8 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
         hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
         hipMemsetAsync(c->need, 0, c->N, c->s) != hipSuccess ||
         hipMemsetAsync(c->tneed, 0, cdiv(c->ntiles, 16) * 16, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess)
+        hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess ||
+        hipMemsetAsync(c->bcount, 0, 4 * (size_t)c->ntiles, c->s) != hipSuccess)
         return cleanup(fail(LBM_EHIP, "clearing the force accumulator failed"));
     for (void *f : {p->f_a, p->f_b}) {
         switch (p->prec) {
@@ -189,6 +197,9 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->tneed) (void)hipFree(c->tneed);
     if (c->tlist) (void)hipFree(c->tlist);
     if (c->tcount) (void)hipFree(c->tcount);
+    if (c->bcount) (void)hipFree(c->bcount);
+    if (c->bucket) (void)hipFree(c->bucket);
+    if (c->srec) (void)hipFree(c->srec);
     if (c->partials) (void)hipFree(c->partials);
     if (c->sums) (void)hipFree(c->sums);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -224,6 +235,7 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     a.fibm = c->fibm;
     a.need = c->need;
     a.tneed = c->tneed;
+    a.bcount = c->bcount;
     a.gfield = c->p.gfield;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -339,6 +351,7 @@ static constexpr size_t kMaxLds = 64 * 1024;
 template <class R>
 static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     MembArgs a{};
+    a.tcount = c->tcount;
     a.vert_off = m->vert_off;
     a.tri_off = m->tri_off;
     a.edge_off = m->edge_off;
@@ -412,6 +425,17 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     m->max_cell_verts = mv;
     m->max_cell_tris = mt;
     m->max_cell_edges = me;
+    const int64_t need_rec = (int64_t)m->nverts * (c->rsize == 8 ? sizeof(SRec<double>) : sizeof(SRec<float>));
+    if (need_rec > c->srec_cap) {
+        if (c->srec) HIPCHK(hipFree(c->srec));
+        c->srec = nullptr;
+        c->srec_cap = 0;
+        if (hipMalloc(&c->srec, need_rec) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "allocating spread records for %d points failed", m->nverts);
+        }
+        c->srec_cap = need_rec;
+    }
     if (c->p.prec == LBM_F64)
         launch_membrane<double>(c, m, true);
     else
@@ -419,6 +443,11 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     HIPCHK(hipGetLastError());
     m->checked = mesh_tag(m);
     return LBM_OK;
+}
+
+static int waves_grid(const lbm_ctx *c) {
+    // one wave per listed tile for lists up to a quarter of the lattice
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
 }
 
 template <class S, class R, bool DEV>
@@ -434,16 +463,15 @@ static void launch_node_velocity(lbm_ctx *c) {
     a.need = c->need;
     a.tlist = c->tlist;
     a.tcount = c->tcount;
+    a.bcount = c->bcount;
     a.nx = c->p.nx;
     a.tpr = c->tpr;
     a.N = c->N;
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
-    // one wave per listed tile for lists up to a quarter of the lattice
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
     if (c->p.gfield)
-        k_node_velocity<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
+        k_node_velocity<S, R, DEV, true><<<waves_grid(c), 256, 0, c->s>>>(a);
     else
-        k_node_velocity<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
+        k_node_velocity<S, R, DEV, false><<<waves_grid(c), 256, 0, c->s>>>(a);
 }
 
 template <class R>
@@ -451,7 +479,9 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     CoupleArgs a{};
     a.ufield = c->ufield;
     a.fibm = c->fibm;
-    a.tcount = c->tcount;
+    a.bcount = c->bcount;
+    a.bucket = c->bucket;
+    a.srec = c->srec;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.nz = c->p.nz;
@@ -470,6 +500,19 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     a.dt = m->dt;
     dim3 grid((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells);
     k_couple<R><<<grid, 128, 0, c->s>>>(a);
+    GatherArgs g{};
+    g.tlist = c->tlist;
+    g.tcount = c->tcount;
+    g.bcount = c->bcount;
+    g.bucket = c->bucket;
+    g.srec = c->srec;
+    g.need = c->need;
+    g.fibm = c->fibm;
+    g.nx = c->p.nx;
+    g.ny = c->p.ny;
+    g.nz = c->p.nz;
+    g.tpr = c->tpr;
+    k_gather<R><<<waves_grid(c), 256, 0, c->s>>>(g);
 }
 
 LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
