@@ -22,15 +22,21 @@
 //
 // k_couple (one thread per IB point): trilinear interpolation of that field
 //   (Sec. 2.2 step 1), coupling force (step 2), and the point update (step
-//   4).  The reaction force is not scattered with float atomics (device-scope
-//   float atomics run at a small fraction of store throughput): the point
-//   writes a spread record (stencil base, weights, force) and files its id in
-//   the bucket of its stencil's base tile with one integer atomic.
+//   4).  The point also writes a spread record: its stencil's base node,
+//   fractional offsets and the force it exerts on the fluid (-F_c).
 //
-// k_gather (one wave per listed tile): spreading, Sec. 2.2 step 3, as a
-//   gather: the tile's 64 nodes sum the weighted forces of the points filed
-//   in the (up to 8) buckets whose stencils can reach them, ids sorted
-//   within each bucket so the sum is bit-reproducible.
+// Spreading (step 3) avoids per-contribution float atomics, which run at a
+// small fraction of store throughput on this GPU:
+// k_spread_cells (one workgroup per cell) sorts the cell's records by base
+//   node in LDS, sums each base node's points into its 8 corner
+//   contributions, and writes them to that base node's slot after claiming
+//   it with one 64-bit compare-and-swap (a base node already claimed by
+//   another cell in this call falls back to float atomics into the force
+//   accumulator; that needs two membranes inside one lattice cell).
+// k_gather_nodes (one wave per listed tile) adds, at each marked node, the
+//   slots of the 8 base nodes whose stencils reach it, in a fixed order.
+// All sums except the fallback are in a fixed order, so the spread is
+// bit-reproducible.
 //
 // The node and tile marks stay set until the collide-stream pass: they are
 // exactly the nodes that received spread force, so that pass reads (and
@@ -300,7 +306,6 @@ struct NodeVelArgs {
     const uint8_t *need;
     const uint32_t *tlist;
     const uint32_t *tcount;
-    uint32_t *bcount;  // bucket fill counts, emptied here for the listed tiles
     int nx, tpr;
     int64_t N;
     double g[3];
@@ -318,7 +323,6 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     R4 *U = static_cast<R4 *>(a.ufield);
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
         const uint32_t tile = a.tlist[w];
-        if (lane == 0) a.bcount[tile] = 0;
         const uint32_t row = tile / a.tpr;
         const int x = (int)(tile - row * a.tpr) * 64 + lane;
         if (x >= a.nx) continue;
@@ -351,23 +355,18 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     }
 }
 
-constexpr int kBucketCap = 64;  // point ids per base-tile bucket; overflow spreads with atomics
-
-// Spread record of one IB point: stencil base node, fractional offsets, and
-// the force it exerts on the fluid (-F_c).
+// Spread record of one IB point: its stencil's base node, fractional
+// offsets, and the force it exerts on the fluid (-F_c).
 template <class R>
 struct SRec {
-    int32_t bx, by, bz, pad;
+    uint32_t base;
     R dx, dy, dz, fx, fy, fz;
 };
 
 struct CoupleArgs {
     const void *ufield;  // [N] Vec4
-    void *fibm;          // [N] Vec4 (overflow points only)
-    uint32_t *bcount;    // [ntiles]
-    uint32_t *bucket;    // [ntiles][kBucketCap]
     void *srec;          // [nverts] SRec
-    int nx, ny, nz, tpr;
+    int nx, ny, nz;
     int64_t N;
     const int32_t *vert_off, *anchor;
     double *x;
@@ -418,26 +417,9 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const R vx = Vv[k], vy = Vv[NV + k], vz = Vv[2 * NV + k];
     const R xi = R(a.xi * ak);
     const R fcx = xi * (ux - vx), fcy = xi * (uy - vy), fcz = xi * (uz - vz);
-    // step 3 (filing): spread record + bucket of the base tile
+    // step 3 input: the spread record
     SRec<R> *SR = static_cast<SRec<R> *>(a.srec);
-    SR[k] = SRec<R>{x0, y0, z0, 0, dx, dy, dz, -fcx, -fcy, -fcz};
-    const uint32_t bt = (uint32_t)(y0 + a.ny * z0) * a.tpr + (x0 >> 6);
-    const uint32_t slot = atomicAdd(&a.bcount[bt], 1u);
-    if (slot < kBucketCap) {
-        a.bucket[(size_t)bt * kBucketCap + slot] = (uint32_t)k;
-    } else {
-        R4 *FI = static_cast<R4 *>(a.fibm);
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int bx = q & 1, by = (q >> 1) & 1, bz = q >> 2;
-            const int64_t n = xs[bx] + (int64_t)a.nx * (ys[by] + (int64_t)a.ny * zs[bz]);
-            const R wt = wx[bx] * wy[by] * wz[bz];
-            R *rec = reinterpret_cast<R *>(&FI[n]);
-            atomicAdd(rec + 0, -wt * fcx);
-            atomicAdd(rec + 1, -wt * fcy);
-            atomicAdd(rec + 2, -wt * fcz);
-        }
-    }
+    SR[k] = SRec<R>{(uint32_t)(x0 + (int64_t)a.nx * (y0 + (int64_t)a.ny * z0)), dx, dy, dz, -fcx, -fcy, -fcz};
     // step 4 (points): semi-implicit Euler with the vertex's mass
     const R h = R(a.dt_over_m / ak);
     const R nvx = vx + h * (FE[k] + fcx), nvy = vy + h * (FE[NV + k] + fcy), nvz = vz + h * (FE[2 * NV + k] + fcz);
@@ -449,82 +431,143 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     X[2 * NV + k] = oz + a.dt * (double)nvz;
 }
 
-// Ascending bitonic sort of one value per lane across a 64-lane wave.
-__device__ __forceinline__ uint32_t wave_sort(uint32_t v) {
-    const int lane = threadIdx.x & 63;
+constexpr int kSpreadThreads = 512;
+constexpr int kSpreadMaxPoints = 2048;  // per cell (bounded by the membrane pass's LDS anyway)
+
+struct SpreadArgs {
+    const int32_t *vert_off;
+    const void *srec;
+    unsigned long long *owner;  // [N] (call epoch << 32) | (cell + 1)
+    void *cslot;                // [N][8] Vec4: corner contributions of a base node
+    void *fibm;                 // [N] Vec4 (fallback)
+    uint32_t epoch;
+    int nx, ny, nz;
+};
+
+template <class R>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
+    using R4 = typename Vec4<R>::T;
+    __shared__ unsigned long long key[kSpreadMaxPoints];
+    const int c = blockIdx.x;
+    const int v0 = a.vert_off[c], nv = a.vert_off[c + 1] - v0;
+    int P = 64;
+    while (P < nv) P <<= 1;
+    const SRec<R> *SR = static_cast<const SRec<R> *>(a.srec) + v0;
+    for (int i = threadIdx.x; i < P; i += blockDim.x)
+        key[i] = i < nv ? ((unsigned long long)SR[i].base << 32) | (unsigned)i : ~0ull;
+    __syncthreads();
+    // bitonic sort of (base node, point) keys
+    for (int kk = 2; kk <= P; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const unsigned long long ki = key[i], kl = key[l];
+                    const bool up = (i & kk) == 0;
+                    if ((ki > kl) == up) {
+                        key[i] = kl;
+                        key[l] = ki;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    // one thread per run of equal base nodes
+    const unsigned long long me = ((unsigned long long)a.epoch << 32) | (unsigned)(c + 1);
+    R4 *CS = static_cast<R4 *>(a.cslot);
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const uint32_t b = (uint32_t)(key[i] >> 32);
+        if (i > 0 && (uint32_t)(key[i - 1] >> 32) == b) continue;
+        R F[8][3];
 #pragma unroll
-    for (int k = 2; k <= 64; k <<= 1) {
+        for (int q = 0; q < 8; q++) F[q][0] = F[q][1] = F[q][2] = R(0);
+        for (int j = i; j < nv && (uint32_t)(key[j] >> 32) == b; j++) {
+            const SRec<R> r = SR[(uint32_t)key[j]];
+            const R wx[2] = {R(1) - r.dx, r.dx}, wy[2] = {R(1) - r.dy, r.dy}, wz[2] = {R(1) - r.dz, r.dz};
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            const uint32_t o = __shfl_xor(v, j, 64);
-            const bool up = (lane & k) == 0, lower = (lane & j) == 0;
-            v = (lower == up) ? min(v, o) : max(v, o);
+            for (int q = 0; q < 8; q++) {
+                const R wt = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
+                F[q][0] += wt * r.fx;
+                F[q][1] += wt * r.fy;
+                F[q][2] += wt * r.fz;
+            }
+        }
+        // claim the base node's slot for this call
+        unsigned long long old = a.owner[b];
+        bool won = false;
+        while ((old >> 32) != a.epoch) {
+            const unsigned long long seen = atomicCAS(&a.owner[b], old, me);
+            if (seen == old) {
+                won = true;
+                break;
+            }
+            old = seen;
+        }
+        if (won) {
+#pragma unroll
+            for (int q = 0; q < 8; q++) CS[(size_t)b * 8 + q] = R4{F[q][0], F[q][1], F[q][2], R(0)};
+        } else {
+            const int bx = (int)(b % a.nx), by = (int)((b / a.nx) % a.ny), bz = (int)(b / ((uint32_t)a.nx * a.ny));
+            const int xs[2] = {bx, bx + 1 == a.nx ? 0 : bx + 1};
+            const int ys[2] = {by, by + 1 == a.ny ? 0 : by + 1};
+            const int zs[2] = {bz, bz + 1 == a.nz ? 0 : bz + 1};
+            R4 *FI = static_cast<R4 *>(a.fibm);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int64_t n = xs[q & 1] + (int64_t)a.nx * (ys[(q >> 1) & 1] + (int64_t)a.ny * zs[q >> 2]);
+                R *rec = reinterpret_cast<R *>(&FI[n]);
+                atomicAdd(rec + 0, F[q][0]);
+                atomicAdd(rec + 1, F[q][1]);
+                atomicAdd(rec + 2, F[q][2]);
+            }
         }
     }
-    return v;
 }
 
 struct GatherArgs {
-    const uint32_t *tlist, *tcount, *bcount, *bucket;
-    const void *srec;
+    const uint32_t *tlist, *tcount;
+    const unsigned long long *owner;
+    const void *cslot;
     const uint8_t *need;
     void *fibm;  // [N] Vec4
+    uint32_t epoch;
     int nx, ny, nz, tpr;
 };
 
 template <class R>
-__global__ __launch_bounds__(256) void k_gather(GatherArgs a) {
+__global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
     using R4 = typename Vec4<R>::T;
     const int lane = threadIdx.x & 63;
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     const uint32_t count = *a.tcount;
-    const SRec<R> *SR = static_cast<const SRec<R> *>(a.srec);
+    const R4 *CS = static_cast<const R4 *>(a.cslot);
     R4 *FI = static_cast<R4 *>(a.fibm);
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
-        const uint32_t tile = __builtin_amdgcn_readfirstlane(a.tlist[w]);
-        const int row = (int)(tile / a.tpr), tx = (int)(tile - (uint32_t)row * a.tpr);
+        const uint32_t tile = a.tlist[w];
+        const int row = (int)(tile / a.tpr), x = (int)(tile - (uint32_t)row * a.tpr) * 64 + lane;
+        if (x >= a.nx) continue;
+        const int64_t n = (int64_t)row * a.nx + x;
+        if (!a.need[n]) continue;
         const int y = row % a.ny, z = row / a.ny;
-        const int x = tx * 64 + lane;
-        // buckets whose stencils reach this row segment: base rows y-1, y and
-        // z-1, z; base tiles of x-1 .. x+63 (this tile and the one holding x-1)
-        const int yr[2] = {y, y == 0 ? a.ny - 1 : y - 1};
-        const int zr[2] = {z, z == 0 ? a.nz - 1 : z - 1};
-        const int tr[2] = {tx, (tx * 64 == 0 ? a.nx - 1 : tx * 64 - 1) >> 6};
-        const int nyc = yr[1] == yr[0] ? 1 : 2, nzc = zr[1] == zr[0] ? 1 : 2, ntc = tr[1] == tr[0] ? 1 : 2;
+        const int xb[2] = {x, x == 0 ? a.nx - 1 : x - 1};
+        const int yb[2] = {y, y == 0 ? a.ny - 1 : y - 1};
+        const int zb[2] = {z, z == 0 ? a.nz - 1 : z - 1};
+        // node n is corner q of base node (x - qx, y - qy, z - qz)
         R Fx = R(0), Fy = R(0), Fz = R(0);
-        for (int iz = 0; iz < nzc; iz++)
-            for (int iy = 0; iy < nyc; iy++)
-                for (int it = 0; it < ntc; it++) {
-                    const uint32_t b = (uint32_t)(yr[iy] + a.ny * zr[iz]) * a.tpr + tr[it];
-                    const uint32_t cnt = min(__builtin_amdgcn_readfirstlane(a.bcount[b]), (uint32_t)kBucketCap);
-                    if (cnt == 0) continue;
-                    uint32_t id = lane < (int)cnt ? a.bucket[(size_t)b * kBucketCap + lane] : 0xffffffffu;
-                    id = wave_sort(id);
-                    for (uint32_t i = 0; i < cnt; i++) {
-                        const uint32_t pid = __builtin_amdgcn_readfirstlane(__shfl(id, (int)i, 64));
-                        const SRec<R> r = SR[pid];
-                        const int bx1 = r.bx + 1 == a.nx ? 0 : r.bx + 1;
-                        const int by1 = r.by + 1 == a.ny ? 0 : r.by + 1;
-                        const int bz1 = r.bz + 1 == a.nz ? 0 : r.bz + 1;
-                        const R wxl = (r.bx == x ? R(1) - r.dx : R(0)) + (bx1 == x ? r.dx : R(0));
-                        const R wyl = (r.by == y ? R(1) - r.dy : R(0)) + (by1 == y ? r.dy : R(0));
-                        const R wzl = (r.bz == z ? R(1) - r.dz : R(0)) + (bz1 == z ? r.dz : R(0));
-                        const R wt = wxl * wyl * wzl;
-                        Fx += wt * r.fx;
-                        Fy += wt * r.fy;
-                        Fz += wt * r.fz;
-                    }
-                }
-        if (x < a.nx) {
-            const int64_t n = (int64_t)row * a.nx + x;
-            if (a.need[n]) {
-                R4 f = FI[n];
-                f.x += Fx;
-                f.y += Fy;
-                f.z += Fz;
-                FI[n] = f;
-            }
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int64_t b = xb[q & 1] + (int64_t)a.nx * (yb[(q >> 1) & 1] + (int64_t)a.ny * zb[q >> 2]);
+            if ((uint32_t)(a.owner[b] >> 32) != a.epoch) continue;
+            const R4 f = CS[b * 8 + q];
+            Fx += f.x;
+            Fy += f.y;
+            Fz += f.z;
         }
+        R4 f = FI[n];
+        f.x += Fx;
+        f.y += Fy;
+        f.z += Fz;
+        FI[n] = f;
     }
 }
 

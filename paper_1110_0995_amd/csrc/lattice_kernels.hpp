@@ -117,7 +117,6 @@ struct StepArgs {
     void *fibm;           // [N] x 4 immersed-boundary force accumulator (x, y, z, unused)
     uint8_t *need;        // [N] 1: the node received spread force this step
     uint8_t *tneed;       // [ntiles] 1: the tile holds such a node
-    uint32_t *bcount;     // [ntiles] spread-bucket fill counts, emptied with the marks
     const void *gfield;   // [3][N] or null
     int nx, ny, nz, tpr;  // tpr = 64-node tiles per x-row
     int ntiles;
@@ -165,10 +164,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
             at(fi, 4 * n + 2) = R(0);
             at(a.need, n) = 0;
         }
-        if (lane == 0) {
-            a.tneed[tile] = 0;
-            a.bcount[tile] = 0;
-        }
+        if (lane == 0) a.tneed[tile] = 0;
     }
     const uint8_t cl = at(a.cls, n);
     if (cl == CLS_SOLID) return;

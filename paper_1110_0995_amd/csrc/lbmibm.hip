@@ -74,10 +74,12 @@ struct lbm_ctx {
     uint8_t *tneed = nullptr;    // [ntiles] 1 = tile holds a marked node
     uint32_t *tlist = nullptr;   // [ntiles] marked tiles, compacted
     uint32_t *tcount = nullptr;  // length of tlist
-    uint32_t *bcount = nullptr;  // [ntiles] points filed per base tile
-    uint32_t *bucket = nullptr;  // [ntiles][kBucketCap] point ids
-    void *srec = nullptr;        // spread records, one per IB point of the largest mesh
+    // spreading workspace, allocated by the first ibm_rest_shape
+    void *srec = nullptr;              // spread records, one per IB point of the largest mesh
     int64_t srec_cap = 0;
+    unsigned long long *owner = nullptr;  // [N] claim of each base node's slot
+    void *cslot = nullptr;             // [N][8] x 4 real: corner contributions per base node
+    uint32_t epoch = 0;                // ibm_couple calls so far
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
     int64_t nparts = 0;
@@ -127,8 +129,7 @@ LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int64_t es = p->prec == LBM_F64 ? 8 : 4;
     const int64_t tiles = cdiv(p->nx, 64) * (int64_t)p->ny * p->nz;
-    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 * tiles +
-           4 * tiles * kBucketCap + cdiv(N, 256) * 32 + 32;
+    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + cdiv(N, 256) * 32 + 32;
 }
 
 LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
@@ -155,8 +156,6 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
         hipMalloc(&c->tneed, cdiv(c->ntiles, 16) * 16) != hipSuccess ||
         hipMalloc(&c->tlist, 4 * (size_t)c->ntiles) != hipSuccess || hipMalloc(&c->tcount, 4) != hipSuccess ||
-        hipMalloc(&c->bcount, 4 * (size_t)c->ntiles) != hipSuccess ||
-        hipMalloc(&c->bucket, 4 * (size_t)c->ntiles * kBucketCap) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
         hipHostMalloc(&c->host_sums, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -170,8 +169,7 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
         hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
         hipMemsetAsync(c->need, 0, c->N, c->s) != hipSuccess ||
         hipMemsetAsync(c->tneed, 0, cdiv(c->ntiles, 16) * 16, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess ||
-        hipMemsetAsync(c->bcount, 0, 4 * (size_t)c->ntiles, c->s) != hipSuccess)
+        hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess)
         return cleanup(fail(LBM_EHIP, "clearing the force accumulator failed"));
     for (void *f : {p->f_a, p->f_b}) {
         switch (p->prec) {
@@ -197,9 +195,9 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->tneed) (void)hipFree(c->tneed);
     if (c->tlist) (void)hipFree(c->tlist);
     if (c->tcount) (void)hipFree(c->tcount);
-    if (c->bcount) (void)hipFree(c->bcount);
-    if (c->bucket) (void)hipFree(c->bucket);
     if (c->srec) (void)hipFree(c->srec);
+    if (c->owner) (void)hipFree(c->owner);
+    if (c->cslot) (void)hipFree(c->cslot);
     if (c->partials) (void)hipFree(c->partials);
     if (c->sums) (void)hipFree(c->sums);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -235,7 +233,6 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     a.fibm = c->fibm;
     a.need = c->need;
     a.tneed = c->tneed;
-    a.bcount = c->bcount;
     a.gfield = c->p.gfield;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
@@ -425,6 +422,7 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     m->max_cell_verts = mv;
     m->max_cell_tris = mt;
     m->max_cell_edges = me;
+    if (mv > kSpreadMaxPoints) return fail(LBM_EINVAL, "a cell has %d vertices (at most %d)", mv, kSpreadMaxPoints);
     const int64_t need_rec = (int64_t)m->nverts * (c->rsize == 8 ? sizeof(SRec<double>) : sizeof(SRec<float>));
     if (need_rec > c->srec_cap) {
         if (c->srec) HIPCHK(hipFree(c->srec));
@@ -435,6 +433,14 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
             return fail(LBM_ENOMEM, "allocating spread records for %d points failed", m->nverts);
         }
         c->srec_cap = need_rec;
+    }
+    if (!c->owner) {
+        if (hipMalloc(&c->owner, 8 * c->N) != hipSuccess || hipMalloc(&c->cslot, 8 * 4 * c->rsize * c->N) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "allocating the spreading slots (%lld bytes) failed",
+                        (long long)((8 + 32 * c->rsize) * c->N));
+        }
+        HIPCHK(hipMemsetAsync(c->owner, 0, 8 * c->N, c->s));
     }
     if (c->p.prec == LBM_F64)
         launch_membrane<double>(c, m, true);
@@ -463,7 +469,6 @@ static void launch_node_velocity(lbm_ctx *c) {
     a.need = c->need;
     a.tlist = c->tlist;
     a.tcount = c->tcount;
-    a.bcount = c->bcount;
     a.nx = c->p.nx;
     a.tpr = c->tpr;
     a.N = c->N;
@@ -478,14 +483,10 @@ template <class R>
 static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     CoupleArgs a{};
     a.ufield = c->ufield;
-    a.fibm = c->fibm;
-    a.bcount = c->bcount;
-    a.bucket = c->bucket;
     a.srec = c->srec;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
     a.nz = c->p.nz;
-    a.tpr = c->tpr;
     a.N = c->N;
     a.vert_off = m->vert_off;
     a.anchor = m->anchor;
@@ -500,25 +501,40 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     a.dt = m->dt;
     dim3 grid((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells);
     k_couple<R><<<grid, 128, 0, c->s>>>(a);
+    SpreadArgs sp{};
+    sp.vert_off = m->vert_off;
+    sp.srec = c->srec;
+    sp.owner = c->owner;
+    sp.cslot = c->cslot;
+    sp.fibm = c->fibm;
+    sp.epoch = c->epoch;
+    sp.nx = c->p.nx;
+    sp.ny = c->p.ny;
+    sp.nz = c->p.nz;
+    k_spread_cells<R><<<m->ncells, kSpreadThreads, 0, c->s>>>(sp);
     GatherArgs g{};
     g.tlist = c->tlist;
     g.tcount = c->tcount;
-    g.bcount = c->bcount;
-    g.bucket = c->bucket;
-    g.srec = c->srec;
+    g.owner = c->owner;
+    g.cslot = c->cslot;
     g.need = c->need;
     g.fibm = c->fibm;
+    g.epoch = c->epoch;
     g.nx = c->p.nx;
     g.ny = c->p.ny;
     g.nz = c->p.nz;
     g.tpr = c->tpr;
-    k_gather<R><<<waves_grid(c), 256, 0, c->s>>>(g);
+    k_gather_nodes<R><<<waves_grid(c), 256, 0, c->s>>>(g);
 }
 
 LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
     if (int rc = check_mesh_ptrs(m)) return rc;
     if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
+    if (++c->epoch == 0) {  // the claim epochs wrapped: forget every old claim
+        HIPCHK(hipMemsetAsync(c->owner, 0, 8 * c->N, c->s));
+        c->epoch = 1;
+    }
     switch (c->p.prec) {
         case LBM_F64:
             launch_membrane<double>(c, m, false);

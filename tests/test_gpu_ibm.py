@@ -215,18 +215,38 @@ def test_two_meshes_in_one_step(orc, lbm):
     assert np.abs(np.concatenate([ma.positions(), mb.positions()]) - X).max() < 1e-12
 
 
-def test_dense_cell_bucket_overflow_f64(orc, lbm):
-    """A 642-vertex cell of radius 1.5 files hundreds of points into a single
-    base tile, more than a spread bucket holds: the overflow points take the
-    atomic path, the rest the gather; the sum must still match the oracle."""
+def test_dense_cell_f64(orc, lbm):
+    """A 642-vertex cell of radius 1.5: many points share each stencil base
+    node, so the per-base-node sums run over long sorted runs."""
     nx, ny, nz = 24, 20, 18
     cells = S.make_cells(np.array([[11.3, 9.6, 8.7]]), 1.5, 3, moduli=(0.01, 0.002, 0.005, 0.05, 0.2))
     s = S.Scenario("dense", nx, ny, nz, 0.8, (1e-4, 0, 0), S.channel_mask(nx, ny, nz), 10, cells=cells)
-    X = cells.positions()
-    b = np.floor(X).astype(int)
-    per_tile = np.bincount((b[:, 1] + ny * b[:, 2]) * 1 + b[:, 0] // 64)
-    assert per_tile.max() > 64
+    b = np.floor(cells.positions()).astype(int)
+    assert np.unique(b[:, 0] + nx * (b[:, 1] + ny * b[:, 2]), return_counts=True)[1].max() > 8
     lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f64", deform=0.02, seed=8)
+    f = L.rest()
+    for _ in range(6):
+        lat.couple(mesh)
+        lat.step(1)
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    assert np.abs(lat.populations_f64().cpu().numpy()[:, fl] - f[:, fl]).max() < 1e-14
+    assert np.abs(mesh.positions() - X).max() < 1e-12
+
+
+def test_overlapping_cells_share_base_nodes_f64(orc, lbm):
+    """Two cells of one population overlap, so some stencil base nodes hold
+    points of both: the second cell to claim such a node spreads through the
+    fallback path.  Results must still match the oracle."""
+    nx, ny, nz = 32, 24, 20
+    cells = S.make_cells(np.array([[12.2, 11.7, 9.6], [14.9, 12.3, 10.1]]), 3.0, 2,
+                         moduli=(0.01, 0.002, 0.005, 0.05, 0.2))
+    s = S.Scenario("overlap", nx, ny, nz, 0.8, (1e-4, 0, 0), S.channel_mask(nx, ny, nz), 10, cells=cells)
+    b = np.floor(cells.positions()).astype(int)
+    key = b[:, 0] + nx * (b[:, 1] + ny * b[:, 2])
+    cell = cells.vertex_cell()
+    assert len(set(key[cell == 0]) & set(key[cell == 1])) > 0
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f64", deform=0.02, seed=9)
     f = L.rest()
     for _ in range(6):
         lat.couple(mesh)
