@@ -30,11 +30,14 @@
 // k_spread_cells (one workgroup per cell) sorts the cell's records by base
 //   node in LDS, sums each base node's points into its 8 corner
 //   contributions, and writes them to that base node's slot after claiming
-//   it with one 64-bit compare-and-swap (a base node already claimed by
-//   another cell in this call falls back to float atomics into the force
-//   accumulator; that needs two membranes inside one lattice cell).
-// k_gather_nodes (one wave per listed tile) adds, at each marked node, the
-//   slots of the 8 base nodes whose stencils reach it, in a fixed order.
+//   it with one compare-and-swap of the call's epoch (a base node already
+//   claimed by another cell in this call falls back to float atomics into
+//   the force accumulator; that needs two membranes inside one lattice
+//   cell).  The owner also sets, at each of the 8 corner nodes, the byte
+//   that says "base node in role q has a slot for you".
+// k_gather_nodes (one wave per listed tile) reads its node's 8 role bytes
+//   with one load, adds the flagged slots in a fixed order and clears the
+//   bytes.
 // All sums except the fallback are in a fixed order, so the spread is
 // bit-reproducible.
 //
@@ -437,9 +440,10 @@ constexpr int kSpreadMaxPoints = 2048;  // per cell (bounded by the membrane pas
 struct SpreadArgs {
     const int32_t *vert_off;
     const void *srec;
-    unsigned long long *owner;  // [N] (call epoch << 32) | (cell + 1)
-    void *cslot;                // [N][8] Vec4: corner contributions of a base node
-    void *fibm;                 // [N] Vec4 (fallback)
+    uint32_t *owner;   // [N] epoch of the call that last claimed the base node's slot
+    void *cslot;       // [N][8] Vec4: corner contributions of a base node
+    uint8_t *role;     // [N][8] role[n][q] = 1: base node of n in role q holds a slot
+    void *fibm;        // [N] Vec4 (fallback)
     uint32_t epoch;
     int nx, ny, nz;
 };
@@ -473,7 +477,6 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
             __syncthreads();
         }
     // one thread per run of equal base nodes
-    const unsigned long long me = ((unsigned long long)a.epoch << 32) | (unsigned)(c + 1);
     R4 *CS = static_cast<R4 *>(a.cslot);
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
         const uint32_t b = (uint32_t)(key[i] >> 32);
@@ -493,24 +496,28 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
             }
         }
         // claim the base node's slot for this call
-        unsigned long long old = a.owner[b];
+        uint32_t old = a.owner[b];
         bool won = false;
-        while ((old >> 32) != a.epoch) {
-            const unsigned long long seen = atomicCAS(&a.owner[b], old, me);
+        while (old != a.epoch) {
+            const uint32_t seen = atomicCAS(&a.owner[b], old, a.epoch);
             if (seen == old) {
                 won = true;
                 break;
             }
             old = seen;
         }
+        const int bx = (int)(b % a.nx), by = (int)((b / a.nx) % a.ny), bz = (int)(b / ((uint32_t)a.nx * a.ny));
+        const int xs[2] = {bx, bx + 1 == a.nx ? 0 : bx + 1};
+        const int ys[2] = {by, by + 1 == a.ny ? 0 : by + 1};
+        const int zs[2] = {bz, bz + 1 == a.nz ? 0 : bz + 1};
         if (won) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) CS[(size_t)b * 8 + q] = R4{F[q][0], F[q][1], F[q][2], R(0)};
+            for (int q = 0; q < 8; q++) {
+                CS[(size_t)b * 8 + q] = R4{F[q][0], F[q][1], F[q][2], R(0)};
+                const int64_t n = xs[q & 1] + (int64_t)a.nx * (ys[(q >> 1) & 1] + (int64_t)a.ny * zs[q >> 2]);
+                a.role[n * 8 + q] = 1;
+            }
         } else {
-            const int bx = (int)(b % a.nx), by = (int)((b / a.nx) % a.ny), bz = (int)(b / ((uint32_t)a.nx * a.ny));
-            const int xs[2] = {bx, bx + 1 == a.nx ? 0 : bx + 1};
-            const int ys[2] = {by, by + 1 == a.ny ? 0 : by + 1};
-            const int zs[2] = {bz, bz + 1 == a.nz ? 0 : bz + 1};
             R4 *FI = static_cast<R4 *>(a.fibm);
 #pragma unroll
             for (int q = 0; q < 8; q++) {
@@ -526,11 +533,10 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
 
 struct GatherArgs {
     const uint32_t *tlist, *tcount;
-    const unsigned long long *owner;
+    uint8_t *role;  // [N][8], cleared here
     const void *cslot;
     const uint8_t *need;
     void *fibm;  // [N] Vec4
-    uint32_t epoch;
     int nx, ny, nz, tpr;
 };
 
@@ -553,11 +559,15 @@ __global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
         const int yb[2] = {y, y == 0 ? a.ny - 1 : y - 1};
         const int zb[2] = {z, z == 0 ? a.nz - 1 : z - 1};
         // node n is corner q of base node (x - qx, y - qy, z - qz)
+        unsigned long long *rp = reinterpret_cast<unsigned long long *>(a.role) + n;
+        const unsigned long long roles = *rp;
+        if (!roles) continue;
+        *rp = 0ull;
         R Fx = R(0), Fy = R(0), Fz = R(0);
 #pragma unroll
         for (int q = 0; q < 8; q++) {
+            if (!((roles >> (8 * q)) & 0xffull)) continue;
             const int64_t b = xb[q & 1] + (int64_t)a.nx * (yb[(q >> 1) & 1] + (int64_t)a.ny * zb[q >> 2]);
-            if ((uint32_t)(a.owner[b] >> 32) != a.epoch) continue;
             const R4 f = CS[b * 8 + q];
             Fx += f.x;
             Fy += f.y;

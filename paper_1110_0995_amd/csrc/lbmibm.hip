@@ -77,8 +77,9 @@ struct lbm_ctx {
     // spreading workspace, allocated by the first ibm_rest_shape
     void *srec = nullptr;              // spread records, one per IB point of the largest mesh
     int64_t srec_cap = 0;
-    unsigned long long *owner = nullptr;  // [N] claim of each base node's slot
+    uint32_t *owner = nullptr;         // [N] epoch of the last claim of each base node's slot
     void *cslot = nullptr;             // [N][8] x 4 real: corner contributions per base node
+    uint8_t *role = nullptr;           // [N][8] slot flags read by the node gather
     uint32_t epoch = 0;                // ibm_couple calls so far
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
@@ -198,6 +199,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->srec) (void)hipFree(c->srec);
     if (c->owner) (void)hipFree(c->owner);
     if (c->cslot) (void)hipFree(c->cslot);
+    if (c->role) (void)hipFree(c->role);
     if (c->partials) (void)hipFree(c->partials);
     if (c->sums) (void)hipFree(c->sums);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -435,12 +437,14 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
         c->srec_cap = need_rec;
     }
     if (!c->owner) {
-        if (hipMalloc(&c->owner, 8 * c->N) != hipSuccess || hipMalloc(&c->cslot, 8 * 4 * c->rsize * c->N) != hipSuccess) {
+        if (hipMalloc(&c->owner, 4 * c->N) != hipSuccess || hipMalloc(&c->cslot, 8 * 4 * c->rsize * c->N) != hipSuccess ||
+            hipMalloc(&c->role, 8 * c->N) != hipSuccess) {
             (void)hipGetLastError();
             return fail(LBM_ENOMEM, "allocating the spreading slots (%lld bytes) failed",
-                        (long long)((8 + 32 * c->rsize) * c->N));
+                        (long long)((12 + 32 * c->rsize) * c->N));
         }
-        HIPCHK(hipMemsetAsync(c->owner, 0, 8 * c->N, c->s));
+        HIPCHK(hipMemsetAsync(c->owner, 0, 4 * c->N, c->s));
+        HIPCHK(hipMemsetAsync(c->role, 0, 8 * c->N, c->s));
     }
     if (c->p.prec == LBM_F64)
         launch_membrane<double>(c, m, true);
@@ -506,6 +510,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.srec = c->srec;
     sp.owner = c->owner;
     sp.cslot = c->cslot;
+    sp.role = c->role;
     sp.fibm = c->fibm;
     sp.epoch = c->epoch;
     sp.nx = c->p.nx;
@@ -515,11 +520,10 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     GatherArgs g{};
     g.tlist = c->tlist;
     g.tcount = c->tcount;
-    g.owner = c->owner;
+    g.role = c->role;
     g.cslot = c->cslot;
     g.need = c->need;
     g.fibm = c->fibm;
-    g.epoch = c->epoch;
     g.nx = c->p.nx;
     g.ny = c->p.ny;
     g.nz = c->p.nz;
@@ -532,7 +536,7 @@ LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
     if (int rc = check_mesh_ptrs(m)) return rc;
     if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
     if (++c->epoch == 0) {  // the claim epochs wrapped: forget every old claim
-        HIPCHK(hipMemsetAsync(c->owner, 0, 8 * c->N, c->s));
+        HIPCHK(hipMemsetAsync(c->owner, 0, 4 * c->N, c->s));
         c->epoch = 1;
     }
     switch (c->p.prec) {
