@@ -105,6 +105,10 @@ typedef struct {
     double *a0c;             /* [ncells] rest cell areas             (written by ibm_rest_shape) */
     double *v0c;             /* [ncells] rest cell volumes           (written by ibm_rest_shape) */
     double *avert;           /* [nverts] rest area carried by each vertex, a third of its triangles' (written by ibm_rest_shape) */
+    int32_t *vtri_off;       /* [nverts+1] incident-triangle list offsets     (written by ibm_rest_shape) */
+    int32_t *vtri;           /* [3*ntris]  triangle*4 + corner, per vertex    (written by ibm_rest_shape) */
+    int32_t *vedge_off;      /* [nverts+1] incident-edge list offsets         (written by ibm_rest_shape) */
+    int32_t *vedge;          /* [4*nedges] edge*4 + role (p1,p2,qa,qb)        (written by ibm_rest_shape) */
     double xi;               /* coupling friction per unit membrane area: vertex k feels F_c = xi*avert[k]*(u(X_k) - V_k); > 0 */
     double mass;             /* membrane mass per unit area: vertex k has mass mass*avert[k] (Newton equation of Sec. 2.2); > 0 */
     double dt;               /* IB time step, > 0 */
@@ -137,7 +141,8 @@ int lbm_step(lbm_ctx *c, int32_t nsteps);
 
 /* Compute the rest shape (edge lengths, triangle areas, hinge angles, cell
  * area and volume, vertex areas; all in FP64) of the mesh at its current
- * positions into m->l0, a0, th0, a0c, v0c, avert, after checking the topology (read back to the host; this
+ * positions into m->l0, a0, th0, a0c, v0c, avert, and the per-vertex
+ * incidence lists into m->vtri_off, vtri, vedge_off, vedge, after checking the topology (read back to the host; this
  * call waits on the stream).  Must be called once per mesh before
  * ibm_couple; fills the trailing fields of *m. */
 int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m);

@@ -33,7 +33,8 @@ class IbmMesh(C.Structure):
                 ("tri", C.c_void_p), ("hinge", C.c_void_p), ("anchor", C.c_void_p),
                 ("x", C.c_void_p), ("v", C.c_void_p), ("f_el", C.c_void_p), ("moduli", C.c_void_p),
                 ("l0", C.c_void_p), ("a0", C.c_void_p), ("th0", C.c_void_p), ("a0c", C.c_void_p),
-                ("v0c", C.c_void_p), ("avert", C.c_void_p), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
+                ("v0c", C.c_void_p), ("avert", C.c_void_p), ("vtri_off", C.c_void_p), ("vtri", C.c_void_p),
+                ("vedge_off", C.c_void_p), ("vedge", C.c_void_p), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
                 ("max_cell_verts", C.c_int32), ("max_cell_tris", C.c_int32), ("max_cell_edges", C.c_int32),
                 ("checked", C.c_uint32)]
 

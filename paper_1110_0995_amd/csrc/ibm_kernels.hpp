@@ -86,11 +86,13 @@ __device__ __forceinline__ double hinge_angle(V3 p1, V3 p2, V3 qa, V3 qb, V3 &na
 struct MembArgs {
     uint32_t *tcount;  // tile-list length, reset here for this step
     const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge, *anchor;
+    // per-vertex incidence (global vertex ids; entries are element*4 + role)
+    const int32_t *vtri_off, *vtri, *vedge_off, *vedge;
     const double *x;  // [3][nverts] offsets
     void *f_el;       // [3][nverts]
     const void *moduli;
     double *l0, *a0, *th0, *a0c, *v0c, *avert;
-    int ncells, nverts, ntris, nedges, maxv;
+    int ncells, nverts, ntris, nedges, maxv, maxt, maxe;
     // lattice, for marking the stencil nodes
     int nx, ny, nz, tpr;
     uint8_t *need;   // [N]
@@ -99,15 +101,23 @@ struct MembArgs {
 
 constexpr int kMembThreads = 512;
 
-// LDS layout: reduction scratch (2 doubles per wave), maxv doubles (vertex
-// areas in the rest pass), x, y, z positions (double) and x, y, z force
-// accumulators (R).
+// LDS layout: reduction scratch (2 doubles per wave), x, y, z positions
+// (double), then one coefficient per triangle and two per edge (R).
 template <class R>
-__host__ __device__ inline size_t membrane_lds_bytes(int maxv) {
-    return 2 * (kMembThreads / 64) * sizeof(double) + 4 * (size_t)maxv * sizeof(double) + 3 * (size_t)maxv * sizeof(R);
+__host__ __device__ inline size_t membrane_lds_bytes(int maxv, int maxt, int maxe) {
+    return 2 * (kMembThreads / 64) * sizeof(double) + 3 * (size_t)maxv * sizeof(double) +
+           ((size_t)maxt + 2 * (size_t)maxe) * sizeof(R);
 }
 
-// REST = true: write the rest shape; false: elastic forces + tile marking.
+// REST = true: write the rest shape; false: elastic forces + stencil marks.
+//
+// Forces are the exact gradients of the energies written element by
+// element.  A first pass computes each element's scalar coefficient (a
+// triangle's area factor, an edge's stretch and bend factors; after the
+// cell's area and volume are reduced).  A second pass gives each vertex the
+// sum over its incident elements, walked in a fixed order from the
+// incidence lists, of coefficient times the element's gradient with respect
+// to that vertex.  No atomics, so the forces are bit-reproducible.
 template <class R, bool REST>
 __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     extern __shared__ double smem_d[];
@@ -115,18 +125,16 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     const int v0 = a.vert_off[c], nv = a.vert_off[c + 1] - v0;
     const int t0 = a.tri_off[c], nt = a.tri_off[c + 1] - t0;
     const int e0 = a.edge_off[c], ne = a.edge_off[c + 1] - e0;
-    double *red = smem_d;                      // 2 per wave
-    double *av = smem_d + 2 * (kMembThreads / 64);  // [maxv]
-    double *px = av + a.maxv, *py = px + a.maxv, *pz = py + a.maxv;
-    R *fx = reinterpret_cast<R *>(pz + a.maxv), *fy = fx + a.maxv, *fz = fy + a.maxv;
+    double *red = smem_d;  // 2 per wave
+    double *px = smem_d + 2 * (kMembThreads / 64), *py = px + a.maxv, *pz = py + a.maxv;
+    R *tco = reinterpret_cast<R *>(pz + a.maxv);  // [maxt]
+    R *eco = tco + a.maxt;                        // [2*maxe]
     const double *X = a.x;
     const int NV = a.nverts;
     for (int k = threadIdx.x; k < nv; k += blockDim.x) {
         px[k] = X[v0 + k];
         py[k] = X[NV + v0 + k];
         pz[k] = X[2 * NV + v0 + k];
-        fx[k] = fy[k] = fz[k] = R(0);
-        av[k] = 0.0;
     }
     __syncthreads();
     auto P = [&](int k) { return V3{px[k], py[k], pz[k]}; };
@@ -163,51 +171,37 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
         acc[1] += dot(A, crs(B, C)) / 6.0;
     }
     block_sum<2>(acc, red);
-    if (REST && threadIdx.x == 0) {
-        a.a0c[c] = acc[0];
-        a.v0c[c] = acc[1];
-    }
     const R *mod = static_cast<const R *>(a.moduli);
     const int NC = a.ncells;
     const double ks = mod[c], kb = mod[NC + c], kal = mod[2 * NC + c], kag = mod[3 * NC + c],
                  kv = mod[4 * NC + c];
+    if (REST) {
+        if (threadIdx.x == 0) {
+            a.a0c[c] = acc[0];
+            a.v0c[c] = acc[1];
+        }
+    }
     const double cag = REST ? 0.0 : kag * (acc[0] - a.a0c[c]) / a.a0c[c];
     const double cv6 = REST ? 0.0 : kv * (acc[1] - a.v0c[c]) / a.v0c[c] / 6.0;
 
-    // triangles: local + global area, volume
+    // element pass: one coefficient per triangle, two per edge
     for (int t = threadIdx.x; t < nt; t += blockDim.x) {
-        const int ia = a.tri[t0 + t] - v0, ib = a.tri[NT + t0 + t] - v0, ic = a.tri[2 * NT + t0 + t] - v0;
-        const V3 A = P(ia), B = P(ib), C = P(ic);
+        const V3 A = P(a.tri[t0 + t] - v0), B = P(a.tri[NT + t0 + t] - v0), C = P(a.tri[2 * NT + t0 + t] - v0);
         const V3 n = crs(sub(B, A), sub(C, A));
         const double nn = sqrt(dot(n, n));
         const double area = 0.5 * nn;
         if (REST) {
             a.a0[t0 + t] = area;
-            atomicAdd(&av[ia], area / 3.0);
-            atomicAdd(&av[ib], area / 3.0);
-            atomicAdd(&av[ic], area / 3.0);
+            tco[t] = R(area);
             continue;
         }
         const double ref = a.a0[t0 + t];
-        const double ca = kal * (area - ref) / ref + cag;
-        const double h = -0.5 * ca / nn;  // -ca grad_a A = -ca/2 (b - c) x n/|n|, cyclic
-        const V3 ga = crs(sub(B, C), n), gb = crs(sub(C, A), n), gc = crs(sub(A, B), n);
-        const V3 va = crs(B, C), vb = crs(C, A), vc = crs(A, B);
-        atomicAdd(&fx[ia], R(h * ga.x - cv6 * va.x));
-        atomicAdd(&fy[ia], R(h * ga.y - cv6 * va.y));
-        atomicAdd(&fz[ia], R(h * ga.z - cv6 * va.z));
-        atomicAdd(&fx[ib], R(h * gb.x - cv6 * vb.x));
-        atomicAdd(&fy[ib], R(h * gb.y - cv6 * vb.y));
-        atomicAdd(&fz[ib], R(h * gb.z - cv6 * vb.z));
-        atomicAdd(&fx[ic], R(h * gc.x - cv6 * vc.x));
-        atomicAdd(&fy[ic], R(h * gc.y - cv6 * vc.y));
-        atomicAdd(&fz[ic], R(h * gc.z - cv6 * vc.z));
+        // -dE/dA * grad A with grad_a A = (b - c) x n / (2|n|)
+        tco[t] = R(-0.5 * (kal * (area - ref) / ref + cag) / nn);
     }
-    // edges: stretching and bending
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
-        const int i1 = a.hinge[e0 + e] - v0, i2 = a.hinge[NE + e0 + e] - v0;
-        const int ia = a.hinge[2 * NE + e0 + e] - v0, ib = a.hinge[3 * NE + e0 + e] - v0;
-        const V3 p1 = P(i1), p2 = P(i2), qa = P(ia), qb = P(ib);
+        const V3 p1 = P(a.hinge[e0 + e] - v0), p2 = P(a.hinge[NE + e0 + e] - v0);
+        const V3 qa = P(a.hinge[2 * NE + e0 + e] - v0), qb = P(a.hinge[3 * NE + e0 + e] - v0);
         V3 na, nb, ev;
         const double th = hinge_angle(p1, p2, qa, qb, na, nb, ev);
         const double l = sqrt(dot(ev, ev));
@@ -217,39 +211,64 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
             continue;
         }
         const double ref = a.l0[e0 + e];
-        const double cs = ks * (l - ref) / ref / l;  // force on p1 = cs (p2 - p1)
-        const double cb = kb * (th - a.th0[e0 + e]);
-        // d theta/d qa = -|e| na/|na|^2, d theta/d qb = -|e| nb/|nb|^2; the edge ends
-        // take the combinations that keep net force and torque zero.
-        const V3 ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
-        const double il2 = 1.0 / (l * l);
-        const double sa = dot(sub(qa, p1), ev) * il2, sb = dot(sub(qb, p1), ev) * il2;
-        const V3 g1 = {-(1 - sa) * ga.x - (1 - sb) * gb.x, -(1 - sa) * ga.y - (1 - sb) * gb.y,
-                       -(1 - sa) * ga.z - (1 - sb) * gb.z};
-        const V3 g2 = {-sa * ga.x - sb * gb.x, -sa * ga.y - sb * gb.y, -sa * ga.z - sb * gb.z};
-        atomicAdd(&fx[i1], R(cs * ev.x - cb * g1.x));
-        atomicAdd(&fy[i1], R(cs * ev.y - cb * g1.y));
-        atomicAdd(&fz[i1], R(cs * ev.z - cb * g1.z));
-        atomicAdd(&fx[i2], R(-cs * ev.x - cb * g2.x));
-        atomicAdd(&fy[i2], R(-cs * ev.y - cb * g2.y));
-        atomicAdd(&fz[i2], R(-cs * ev.z - cb * g2.z));
-        atomicAdd(&fx[ia], R(-cb * ga.x));
-        atomicAdd(&fy[ia], R(-cb * ga.y));
-        atomicAdd(&fz[ia], R(-cb * ga.z));
-        atomicAdd(&fx[ib], R(-cb * gb.x));
-        atomicAdd(&fy[ib], R(-cb * gb.y));
-        atomicAdd(&fz[ib], R(-cb * gb.z));
+        eco[2 * e] = R(ks * (l - ref) / ref / l);     // force on p1 = cs (p2 - p1)
+        eco[2 * e + 1] = R(kb * (th - a.th0[e0 + e]));  // force = -cb grad theta
     }
     __syncthreads();
-    if (REST) {
-        for (int k = threadIdx.x; k < nv; k += blockDim.x) a.avert[v0 + k] = av[k];
-        return;
-    }
-    R *FE = static_cast<R *>(a.f_el);
+
+    // vertex pass
     for (int k = threadIdx.x; k < nv; k += blockDim.x) {
-        FE[v0 + k] = fx[k];
-        FE[NV + v0 + k] = fy[k];
-        FE[2 * NV + v0 + k] = fz[k];
+        const int vg = v0 + k;
+        if (REST) {  // each vertex carries a third of its triangles' rest area
+            double s = 0.0;
+            for (int i = a.vtri_off[vg]; i < a.vtri_off[vg + 1]; i++) s += a.a0[a.vtri[i] >> 2] / 3.0;
+            a.avert[vg] = s;
+            continue;
+        }
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int i = a.vtri_off[vg]; i < a.vtri_off[vg + 1]; i++) {
+            const int code = a.vtri[i], t = (code >> 2) - t0, r = code & 3;
+            const V3 A = P(a.tri[t0 + t] - v0), B = P(a.tri[NT + t0 + t] - v0), C = P(a.tri[2 * NT + t0 + t] - v0);
+            const V3 n = crs(sub(B, A), sub(C, A));
+            // role r: grad of area ~ (next - prev) x n, of volume (next x prev)/6
+            const V3 nx_ = r == 0 ? B : (r == 1 ? C : A), pv = r == 0 ? C : (r == 1 ? A : B);
+            const V3 g = crs(sub(nx_, pv), n), vg3 = crs(nx_, pv);
+            const double h = (double)tco[t];
+            fx += h * g.x - cv6 * vg3.x;
+            fy += h * g.y - cv6 * vg3.y;
+            fz += h * g.z - cv6 * vg3.z;
+        }
+        for (int i = a.vedge_off[vg]; i < a.vedge_off[vg + 1]; i++) {
+            const int code = a.vedge[i], e = (code >> 2) - e0, r = code & 3;
+            const V3 p1 = P(a.hinge[e0 + e] - v0), p2 = P(a.hinge[NE + e0 + e] - v0);
+            const V3 qa = P(a.hinge[2 * NE + e0 + e] - v0), qb = P(a.hinge[3 * NE + e0 + e] - v0);
+            const V3 ev = sub(p2, p1);
+            const V3 na = crs(ev, sub(qa, p1)), nb = crs(sub(p1, p2), sub(qb, p2));
+            const double l2 = dot(ev, ev), l = sqrt(l2);
+            const double cs = (double)eco[2 * e], cb = (double)eco[2 * e + 1];
+            // d theta/d qa = -|e| na/|na|^2, d theta/d qb = -|e| nb/|nb|^2; the edge ends
+            // take the combinations that keep net force and torque zero.
+            const V3 ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
+            V3 g;
+            double s = 0.0;
+            if (r == 2) {
+                g = ga;
+            } else if (r == 3) {
+                g = gb;
+            } else {
+                const double sa = dot(sub(qa, p1), ev) / l2, sb = dot(sub(qb, p1), ev) / l2;
+                const double ca_ = r == 0 ? -(1.0 - sa) : -sa, cb_ = r == 0 ? -(1.0 - sb) : -sb;
+                g = V3{ca_ * ga.x + cb_ * gb.x, ca_ * ga.y + cb_ * gb.y, ca_ * ga.z + cb_ * gb.z};
+                s = r == 0 ? cs : -cs;
+            }
+            fx += s * ev.x - cb * g.x;
+            fy += s * ev.y - cb * g.y;
+            fz += s * ev.z - cb * g.z;
+        }
+        R *FE = static_cast<R *>(a.f_el);
+        FE[vg] = R(fx);
+        FE[NV + vg] = R(fy);
+        FE[2 * NV + vg] = R(fz);
     }
 }
 

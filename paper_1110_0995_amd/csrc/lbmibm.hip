@@ -54,6 +54,8 @@ uint32_t mesh_tag(const ibm_mesh *m) {
     mix((uint64_t)(uintptr_t)m->tri);
     mix((uint64_t)(uintptr_t)m->hinge);
     mix((uint64_t)(uintptr_t)m->vert_off);
+    mix((uint64_t)(uintptr_t)m->vtri);
+    mix((uint64_t)(uintptr_t)m->vedge);
     mix((uint64_t)m->max_cell_verts);
     return kMeshMagic ^ (uint32_t)(h ^ (h >> 32));
 }
@@ -337,7 +339,8 @@ static int check_mesh_ptrs(const ibm_mesh *m) {
     if (m->ncells < 1 || m->nverts < 1 || m->ntris < 1 || m->nedges < 1)
         return fail(LBM_EINVAL, "mesh counts must be >= 1");
     if (!m->vert_off || !m->tri_off || !m->edge_off || !m->tri || !m->hinge || !m->anchor || !m->x || !m->v ||
-        !m->f_el || !m->moduli || !m->l0 || !m->a0 || !m->th0 || !m->a0c || !m->v0c || !m->avert)
+        !m->f_el || !m->moduli || !m->l0 || !m->a0 || !m->th0 || !m->a0c || !m->v0c || !m->avert || !m->vtri_off ||
+        !m->vtri || !m->vedge_off || !m->vedge)
         return fail(LBM_EINVAL, "mesh has a NULL array");
     if (!(m->xi > 0) || !(m->mass > 0) || !(m->dt > 0) || !std::isfinite(m->xi) || !std::isfinite(m->mass) ||
         !std::isfinite(m->dt))
@@ -351,6 +354,12 @@ template <class R>
 static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     MembArgs a{};
     a.tcount = c->tcount;
+    a.vtri_off = m->vtri_off;
+    a.vtri = m->vtri;
+    a.vedge_off = m->vedge_off;
+    a.vedge = m->vedge;
+    a.maxt = m->max_cell_tris;
+    a.maxe = m->max_cell_edges;
     a.vert_off = m->vert_off;
     a.tri_off = m->tri_off;
     a.edge_off = m->edge_off;
@@ -377,7 +386,7 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.tpr = c->tpr;
     a.need = c->need;
     a.tneed = c->tneed;
-    const size_t sm = membrane_lds_bytes<R>(m->max_cell_verts);
+    const size_t sm = membrane_lds_bytes<R>(m->max_cell_verts, m->max_cell_tris, m->max_cell_edges);
     if (rest)
         k_membrane<R, true><<<m->ncells, kMembThreads, sm, c->s>>>(a);
     else
@@ -419,8 +428,35 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
                     return fail(LBM_EINVAL, "edge %d of cell %d uses vertex %d outside the cell", e, k, v);
             }
     }
-    const size_t lds = c->rsize == 8 ? membrane_lds_bytes<double>(mv) : membrane_lds_bytes<float>(mv);
-    if (lds > kMaxLds) return fail(LBM_EINVAL, "a cell has %d vertices, too many for one workgroup's LDS", mv);
+    const size_t lds = c->rsize == 8 ? membrane_lds_bytes<double>(mv, mt, me) : membrane_lds_bytes<float>(mv, mt, me);
+    if (lds > kMaxLds)
+        return fail(LBM_EINVAL, "a cell with %d vertices, %d triangles, %d edges does not fit one workgroup's LDS", mv,
+                    mt, me);
+    // per-vertex incidence lists, elements in increasing order (the force
+    // pass sums over them in this order)
+    {
+        std::vector<int32_t> toff(m->nverts + 1, 0), eoff(m->nverts + 1, 0), tl(3 * (size_t)m->ntris),
+            el(4 * (size_t)m->nedges);
+        for (int t = 0; t < m->ntris; t++)
+            for (int j = 0; j < 3; j++) toff[tri[(size_t)j * m->ntris + t] + 1]++;
+        for (int e = 0; e < m->nedges; e++)
+            for (int j = 0; j < 4; j++) eoff[hin[(size_t)j * m->nedges + e] + 1]++;
+        for (int v = 0; v < m->nverts; v++) {
+            toff[v + 1] += toff[v];
+            eoff[v + 1] += eoff[v];
+        }
+        std::vector<int32_t> tf(toff.begin(), toff.end() - 1), ef(eoff.begin(), eoff.end() - 1);
+        for (int t = 0; t < m->ntris; t++)
+            for (int j = 0; j < 3; j++) tl[tf[tri[(size_t)j * m->ntris + t]]++] = 4 * t + j;
+        for (int e = 0; e < m->nedges; e++)
+            for (int j = 0; j < 4; j++) el[ef[hin[(size_t)j * m->nedges + e]]++] = 4 * e + j;
+        if ((int64_t)m->ntris * 4 > INT32_MAX || (int64_t)m->nedges * 4 > INT32_MAX)
+            return fail(LBM_EINVAL, "mesh too large for 32-bit incidence codes");
+        HIPCHK(hipMemcpy(m->vtri_off, toff.data(), toff.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(m->vtri, tl.data(), tl.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(m->vedge_off, eoff.data(), eoff.size() * 4, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(m->vedge, el.data(), el.size() * 4, hipMemcpyHostToDevice));
+    }
     m->max_cell_verts = mv;
     m->max_cell_tris = mt;
     m->max_cell_edges = me;

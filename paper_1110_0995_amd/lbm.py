@@ -151,11 +151,15 @@ class Mesh:
         self.a0c = torch.zeros(cells.ncells, **f64)
         self.v0c = torch.zeros(cells.ncells, **f64)
         self.avert = torch.zeros(cells.nverts, **f64)
+        i32z = lambda n: torch.zeros(n, dtype=torch.int32, device=dev)
+        self.vtri_off, self.vtri = i32z(cells.nverts + 1), i32z(3 * cells.ntris)
+        self.vedge_off, self.vedge = i32z(cells.nverts + 1), i32z(4 * cells.nedges)
         p = lambda t: t.data_ptr()
         self.s = _lib.IbmMesh(cells.ncells, cells.nverts, cells.ntris, cells.nedges, p(self.vert_off),
                               p(self.tri_off), p(self.edge_off), p(self.tri), p(self.hinge), p(self.anchor),
                               p(self.x), p(self.v), p(self.f_el), p(self.moduli), p(self.l0), p(self.a0),
-                              p(self.th0), p(self.a0c), p(self.v0c), p(self.avert), float(cells.xi), float(cells.mass),
+                              p(self.th0), p(self.a0c), p(self.v0c), p(self.avert), p(self.vtri_off), p(self.vtri),
+                              p(self.vedge_off), p(self.vedge), float(cells.xi), float(cells.mass),
                               float(cells.dt), 0, 0, 0, 0)
         _lib.check(lat.lib.ibm_rest_shape(lat.ctx, C.byref(self.s)))
         lat.meshes.append(self)

@@ -258,6 +258,22 @@ def test_overlapping_cells_share_base_nodes_f64(orc, lbm):
     assert np.abs(mesh.positions() - X).max() < 1e-12
 
 
+def test_coupled_step_is_bit_reproducible(lbm):
+    """Two identical runs give identical populations, positions and forces:
+    membrane forces are gathered per vertex in a fixed order and the spread
+    sums each base node's points in sorted order."""
+    s = _small(48, 40, 28, ncells=3, level=3, radius=4.0, seed=13)
+    out = []
+    for _ in range(2):
+        lat = lbm.Lattice.from_scenario(s, prec="f32dev")
+        mesh = lbm.Mesh(lat, s.cells)
+        lat.run(30, mesh)
+        out.append((lat.current().cpu().numpy().copy(), mesh.x.cpu().numpy().copy(), mesh.f_el.cpu().numpy().copy()))
+        lat.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_couple_requires_rest_shape(lbm):
     from paper_1110_0995_amd import _lib
     s = _small(posts=False, ncells=1)
