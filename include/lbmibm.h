@@ -21,7 +21,11 @@
  * -> forces -> spread -> collide/stream -> move points.
  *
  * Conventions
- *   - Lattice node n = x + nx*(y + ny*z), N = nx*ny*nz, x fastest.
+ *   - Lattice node n = x + nx*(y + ny*z), N = nx*ny*nz, x fastest.  A
+ *     context made by lbm_init_channels holds several independent lattices
+ *     ("channels") back to back: channel k owns nodes [noff_k, noff_k + N_k)
+ *     with noff_k = N_0 + ... + N_(k-1), N = the sum of all N_k, and every
+ *     per-node array below uses that concatenated index.
  *   - Populations: 19 planes, plane i at element offset i*plane_stride.
  *     D3Q19 order: 0 rest; 1,2 = +-x; 3,4 = +-y; 5,6 = +-z; 7,8 = (1,1,0),
  *     (-1,-1,0); 9,10 = (1,-1,0),(-1,1,0); 11,12 = (1,0,1),(-1,0,-1);
@@ -95,6 +99,8 @@ typedef struct {
     const int32_t *tri;      /* [3][ntris] vertices (a,b,c), counter-clockwise seen from outside */
     const int32_t *hinge;    /* [4][nedges] (p1,p2,qa,qb): triangles (p1,p2,qa) and (p2,p1,qb) share edge p1-p2 */
     const int32_t *anchor;   /* [3][ncells] integer anchor of each cell */
+    const int32_t *cell_chan;/* [ncells] channel holding each cell (see lbm_init_channels); NULL = channel 0,
+                                allowed only when the context has one channel */
     double *x;               /* [3][nverts] position minus the cell's anchor, FP64 in every precision (updated by ibm_couple) */
     void *v;                 /* [3][nverts] real: velocity (updated by ibm_couple) */
     void *f_el;              /* [3][nverts] real: written with the elastic force of the last ibm_couple */
@@ -131,6 +137,36 @@ int64_t lbm_workspace_bytes(const lbm_params *p);
  * rest (f_i = w_i; h_i = 0 in LBM_F32_DEV).  The LBM equation of Sec. 2.1
  * starts from this state.  On failure *out is NULL. */
 int lbm_init(const lbm_params *p, lbm_ctx **out);
+
+/* Batched form: one context over nch >= 1 independent channels, dims
+ * (host memory) = [nch][3] sizes (nx, ny, nz) of each, stepped together by
+ * every call below, one launch per kernel for the whole batch.  Each
+ * channel is its own lattice of Sec. 2.1/2.4 (its own periodic wrap, no
+ * link between channels); p->nx, ny, nz are ignored; periodic, tau,
+ * body_force and prec apply to all channels; solid, f_a, f_b, gfield and
+ * plane_stride refer to the concatenated node index.  A channel alone and
+ * the same channel inside a batch give bitwise equal results. */
+int lbm_init_channels(const lbm_params *p, int32_t nch, const int32_t *dims, lbm_ctx **out);
+
+/* lbm_workspace_bytes for lbm_init_channels (-1 on invalid arguments). */
+int64_t lbm_workspace_bytes_channels(const lbm_params *p, int32_t nch, const int32_t *dims);
+
+/* Launch shape, results unchanged: collide_waves_per_block = 64-node tiles
+ * per collide-stream workgroup (1, 2, 4 or 8; 0 = 4), list_blocks =
+ * workgroups of the kernels that walk the list of tiles under a membrane
+ * stencil (0 = by lattice size, at most 65536).  Drops a captured graph. */
+int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t list_blocks);
+
+/* nsteps >= 0 coupled steps: for each, ibm_couple(c, m) (skipped when m is
+ * NULL) then lbm_step(c, 1).  With steps_per_graph > 0 (even, at most
+ * 4096) the steps are taken in groups of steps_per_graph, captured once into
+ * a HIP graph and replayed with one graph launch per group on
+ * params.stream; the remainder runs as ordinary launches.  The graph is
+ * captured again when the mesh (its buffers, xi, mass or dt), the group
+ * length, the launch shape or the parity of the state buffer changes.
+ * Graph and ordinary launches run the same kernels on the same data, so
+ * the results are bitwise those of the eager loop. */
+int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps_per_graph);
 
 /* Advance the lattice nsteps >= 0 times: fused BGK collision with Guo
  * forcing (force = g + G + the immersed-boundary force spread by the last

@@ -16,7 +16,8 @@ ERRORS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EHIP: "EHIP", LBM_ENON
           LBM_ESTATE: "ESTATE"}
 
 # every symbol include/lbmibm.h declares
-EXPORTS = ("lbm_plane_stride", "lbm_workspace_bytes", "lbm_init", "lbm_step", "ibm_rest_shape", "ibm_couple",
+EXPORTS = ("lbm_plane_stride", "lbm_workspace_bytes", "lbm_init", "lbm_init_channels",
+           "lbm_workspace_bytes_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape", "ibm_couple",
            "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "lbm_destroy", "lbm_last_error")
 
 
@@ -30,7 +31,7 @@ class LbmParams(C.Structure):
 class IbmMesh(C.Structure):
     _fields_ = [("ncells", C.c_int32), ("nverts", C.c_int32), ("ntris", C.c_int32), ("nedges", C.c_int32),
                 ("vert_off", C.c_void_p), ("tri_off", C.c_void_p), ("edge_off", C.c_void_p),
-                ("tri", C.c_void_p), ("hinge", C.c_void_p), ("anchor", C.c_void_p),
+                ("tri", C.c_void_p), ("hinge", C.c_void_p), ("anchor", C.c_void_p), ("cell_chan", C.c_void_p),
                 ("x", C.c_void_p), ("v", C.c_void_p), ("f_el", C.c_void_p), ("moduli", C.c_void_p),
                 ("l0", C.c_void_p), ("a0", C.c_void_p), ("th0", C.c_void_p), ("a0c", C.c_void_p),
                 ("v0c", C.c_void_p), ("avert", C.c_void_p), ("vtri_off", C.c_void_p), ("vtri", C.c_void_p),
@@ -62,6 +63,11 @@ def load() -> C.CDLL:
     L.lbm_workspace_bytes.argtypes = [C.POINTER(LbmParams)]
     L.lbm_workspace_bytes.restype = C.c_int64
     L.lbm_init.argtypes = [C.POINTER(LbmParams), C.POINTER(vp)]
+    L.lbm_init_channels.argtypes = [C.POINTER(LbmParams), C.c_int32, C.POINTER(C.c_int32), C.POINTER(vp)]
+    L.lbm_workspace_bytes_channels.argtypes = [C.POINTER(LbmParams), C.c_int32, C.POINTER(C.c_int32)]
+    L.lbm_workspace_bytes_channels.restype = C.c_int64
+    L.lbm_set_launch.argtypes = [vp, C.c_int32, C.c_int32]
+    L.lbm_run.argtypes = [vp, C.POINTER(IbmMesh), C.c_int32, C.c_int32]
     L.lbm_step.argtypes = [vp, C.c_int32]
     L.ibm_rest_shape.argtypes = [vp, C.POINTER(IbmMesh)]
     L.ibm_couple.argtypes = [vp, C.POINTER(IbmMesh)]
@@ -73,8 +79,8 @@ def load() -> C.CDLL:
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = C.c_char_p
-    for name in ("lbm_init", "lbm_step", "ibm_rest_shape", "ibm_couple", "lbm_read_fields", "lbm_current",
-                 "lbm_store_f64", "lbm_load_f64"):
+    for name in ("lbm_init", "lbm_init_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape",
+                 "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

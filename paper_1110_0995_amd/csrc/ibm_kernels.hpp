@@ -85,6 +85,9 @@ __device__ __forceinline__ double hinge_angle(V3 p1, V3 p2, V3 qa, V3 qb, V3 &na
 
 struct MembArgs {
     uint32_t *tcount;  // tile-list length, reset here for this step
+    uint32_t *epoch;   // spreading-claim epoch, advanced here for this step
+    const Chan *chans;
+    const int32_t *cell_chan;  // [ncells] channel of each cell, null for a single channel
     const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge, *anchor;
     // per-vertex incidence (global vertex ids; entries are element*4 + role)
     const int32_t *vtri_off, *vtri, *vedge_off, *vedge;
@@ -93,13 +96,13 @@ struct MembArgs {
     const void *moduli;
     double *l0, *a0, *th0, *a0c, *v0c, *avert;
     int ncells, nverts, ntris, nedges, maxv, maxt, maxe;
-    // lattice, for marking the stencil nodes
-    int nx, ny, nz, tpr;
-    uint8_t *need;   // [N]
-    uint8_t *tneed;  // [ntiles]
+    uint8_t *need;   // [N] stencil-node marks
+    uint8_t *tneed;  // [ntiles] tile marks
 };
 
 constexpr int kMembThreads = 512;
+
+__device__ __forceinline__ int cell_channel(const int32_t *cell_chan, int c) { return cell_chan ? cell_chan[c] : 0; }
 
 // LDS layout: reduction scratch (2 doubles per wave), x, y, z positions
 // (double), then one coefficient per triangle and two per edge (R).
@@ -141,23 +144,27 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     const int NT = a.ntris, NE = a.nedges;
 
     if (!REST) {
-        if (c == 0 && threadIdx.x == 0) *a.tcount = 0;
+        if (c == 0 && threadIdx.x == 0) {
+            *a.tcount = 0;
+            *a.epoch += 1u;
+        }
         // mark every node of every vertex's stencil (positions of this step)
+        const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
         const int ax = a.anchor[c], ay = a.anchor[a.ncells + c], az = a.anchor[2 * a.ncells + c];
         for (int k = threadIdx.x; k < nv; k += blockDim.x) {
-            const int x0 = pmod(ax + (int)floor(px[k]), a.nx);
-            const int y0 = pmod(ay + (int)floor(py[k]), a.ny);
-            const int z0 = pmod(az + (int)floor(pz[k]), a.nz);
-            const int xs[2] = {x0, x0 + 1 == a.nx ? 0 : x0 + 1};
-            const int ys[2] = {y0, y0 + 1 == a.ny ? 0 : y0 + 1};
-            const int zs[2] = {z0, z0 + 1 == a.nz ? 0 : z0 + 1};
+            const int x0 = pmod(ax + (int)floor(px[k]), ch.nx);
+            const int y0 = pmod(ay + (int)floor(py[k]), ch.ny);
+            const int z0 = pmod(az + (int)floor(pz[k]), ch.nz);
+            const int xs[2] = {x0, x0 + 1 == ch.nx ? 0 : x0 + 1};
+            const int ys[2] = {y0, y0 + 1 == ch.ny ? 0 : y0 + 1};
+            const int zs[2] = {z0, z0 + 1 == ch.nz ? 0 : z0 + 1};
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int row = ys[q & 1] + a.ny * zs[q >> 1];
-                a.need[(int64_t)row * a.nx + xs[0]] = 1;
-                a.need[(int64_t)row * a.nx + xs[1]] = 1;
-                a.tneed[(int64_t)row * a.tpr + (xs[0] >> 6)] = 1;
-                a.tneed[(int64_t)row * a.tpr + (xs[1] >> 6)] = 1;
+                const int row = ys[q & 1] + ch.ny * zs[q >> 1];
+                a.need[ch.noff + (int64_t)row * ch.nx + xs[0]] = 1;
+                a.need[ch.noff + (int64_t)row * ch.nx + xs[1]] = 1;
+                a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[0] >> 6)] = 1;
+                a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[1] >> 6)] = 1;
             }
         }
     }
@@ -328,7 +335,8 @@ struct NodeVelArgs {
     const uint8_t *need;
     const uint32_t *tlist;
     const uint32_t *tcount;
-    int nx, tpr;
+    const Chan *chans;
+    const uint16_t *tile_chan;
     int64_t N;
     double g[3];
 };
@@ -344,11 +352,12 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     const S *f = static_cast<const S *>(a.f);
     R4 *U = static_cast<R4 *>(a.ufield);
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
-        const uint32_t tile = a.tlist[w];
-        const uint32_t row = tile / a.tpr;
-        const int x = (int)(tile - row * a.tpr) * 64 + lane;
-        if (x >= a.nx) continue;
-        const int64_t n = (int64_t)row * a.nx + x;
+        const int tile = __builtin_amdgcn_readfirstlane((int)a.tlist[w]);
+        const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
+        const int lt = tile - ch.toff, row = lt / ch.tpr;
+        const int x = (lt - row * ch.tpr) * 64 + lane;
+        if (x >= ch.nx) continue;
+        const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
         if (!a.need[n]) continue;
         R ux = R(0), uy = R(0), uz = R(0);
         if (a.cls[n] != CLS_SOLID) {
@@ -388,8 +397,8 @@ struct SRec {
 struct CoupleArgs {
     const void *ufield;  // [N] Vec4
     void *srec;          // [nverts] SRec
-    int nx, ny, nz;
-    int64_t N;
+    const Chan *chans;
+    const int32_t *cell_chan;
     const int32_t *vert_off, *anchor;
     double *x;
     void *v;
@@ -414,12 +423,13 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const double ox = X[k], oy = X[NV + k], oz = X[2 * NV + k];
     const double flx = floor(ox), fly = floor(oy), flz = floor(oz);
     const R dx = R(ox - flx), dy = R(oy - fly), dz = R(oz - flz);
-    const int x0 = pmod(a.anchor[c] + (int)flx, a.nx);
-    const int y0 = pmod(a.anchor[a.ncells + c] + (int)fly, a.ny);
-    const int z0 = pmod(a.anchor[2 * a.ncells + c] + (int)flz, a.nz);
-    const int xs[2] = {x0, x0 + 1 == a.nx ? 0 : x0 + 1};
-    const int ys[2] = {y0, y0 + 1 == a.ny ? 0 : y0 + 1};
-    const int zs[2] = {z0, z0 + 1 == a.nz ? 0 : z0 + 1};
+    const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
+    const int x0 = pmod(a.anchor[c] + (int)flx, ch.nx);
+    const int y0 = pmod(a.anchor[a.ncells + c] + (int)fly, ch.ny);
+    const int z0 = pmod(a.anchor[2 * a.ncells + c] + (int)flz, ch.nz);
+    const int xs[2] = {x0, x0 + 1 == ch.nx ? 0 : x0 + 1};
+    const int ys[2] = {y0, y0 + 1 == ch.ny ? 0 : y0 + 1};
+    const int zs[2] = {z0, z0 + 1 == ch.nz ? 0 : z0 + 1};
     const R wx[2] = {R(1) - dx, dx}, wy[2] = {R(1) - dy, dy}, wz[2] = {R(1) - dz, dz};
 
     // step 1: interpolate u_ext
@@ -427,7 +437,7 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         const int bx = q & 1, by = (q >> 1) & 1, bz = q >> 2;
-        const int64_t n = xs[bx] + (int64_t)a.nx * (ys[by] + (int64_t)a.ny * zs[bz]);
+        const int64_t n = ch.noff + xs[bx] + (int64_t)ch.nx * (ys[by] + (int64_t)ch.ny * zs[bz]);
         const R wt = wx[bx] * wy[by] * wz[bz];
         const R4 u = U[n];
         ux += wt * u.x;
@@ -441,7 +451,7 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const R fcx = xi * (ux - vx), fcy = xi * (uy - vy), fcz = xi * (uz - vz);
     // step 3 input: the spread record
     SRec<R> *SR = static_cast<SRec<R> *>(a.srec);
-    SR[k] = SRec<R>{(uint32_t)(x0 + (int64_t)a.nx * (y0 + (int64_t)a.ny * z0)), dx, dy, dz, -fcx, -fcy, -fcz};
+    SR[k] = SRec<R>{(uint32_t)(ch.noff + x0 + (int64_t)ch.nx * (y0 + (int64_t)ch.ny * z0)), dx, dy, dz, -fcx, -fcy, -fcz};
     // step 4 (points): semi-implicit Euler with the vertex's mass
     const R h = R(a.dt_over_m / ak);
     const R nvx = vx + h * (FE[k] + fcx), nvy = vy + h * (FE[NV + k] + fcy), nvz = vz + h * (FE[2 * NV + k] + fcz);
@@ -463,8 +473,9 @@ struct SpreadArgs {
     void *cslot;       // [N][8] Vec4: corner contributions of a base node
     uint8_t *role;     // [N][8] role[n][q] = 1: base node of n in role q holds a slot
     void *fibm;        // [N] Vec4 (fallback)
-    uint32_t epoch;
-    int nx, ny, nz;
+    const uint32_t *epoch;
+    const Chan *chans;
+    const int32_t *cell_chan;
 };
 
 template <class R>
@@ -497,6 +508,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         }
     // one thread per run of equal base nodes
     R4 *CS = static_cast<R4 *>(a.cslot);
+    const uint32_t epoch = *a.epoch;
+    const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
         const uint32_t b = (uint32_t)(key[i] >> 32);
         if (i > 0 && (uint32_t)(key[i - 1] >> 32) == b) continue;
@@ -517,30 +530,31 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         // claim the base node's slot for this call
         uint32_t old = a.owner[b];
         bool won = false;
-        while (old != a.epoch) {
-            const uint32_t seen = atomicCAS(&a.owner[b], old, a.epoch);
+        while (old != epoch) {
+            const uint32_t seen = atomicCAS(&a.owner[b], old, epoch);
             if (seen == old) {
                 won = true;
                 break;
             }
             old = seen;
         }
-        const int bx = (int)(b % a.nx), by = (int)((b / a.nx) % a.ny), bz = (int)(b / ((uint32_t)a.nx * a.ny));
-        const int xs[2] = {bx, bx + 1 == a.nx ? 0 : bx + 1};
-        const int ys[2] = {by, by + 1 == a.ny ? 0 : by + 1};
-        const int zs[2] = {bz, bz + 1 == a.nz ? 0 : bz + 1};
+        const int64_t lb = (int64_t)b - ch.noff;
+        const int bx = (int)(lb % ch.nx), by = (int)((lb / ch.nx) % ch.ny), bz = (int)(lb / ((int64_t)ch.nx * ch.ny));
+        const int xs[2] = {bx, bx + 1 == ch.nx ? 0 : bx + 1};
+        const int ys[2] = {by, by + 1 == ch.ny ? 0 : by + 1};
+        const int zs[2] = {bz, bz + 1 == ch.nz ? 0 : bz + 1};
         if (won) {
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 CS[(size_t)b * 8 + q] = R4{F[q][0], F[q][1], F[q][2], R(0)};
-                const int64_t n = xs[q & 1] + (int64_t)a.nx * (ys[(q >> 1) & 1] + (int64_t)a.ny * zs[q >> 2]);
+                const int64_t n = ch.noff + xs[q & 1] + (int64_t)ch.nx * (ys[(q >> 1) & 1] + (int64_t)ch.ny * zs[q >> 2]);
                 a.role[n * 8 + q] = 1;
             }
         } else {
             R4 *FI = static_cast<R4 *>(a.fibm);
 #pragma unroll
             for (int q = 0; q < 8; q++) {
-                const int64_t n = xs[q & 1] + (int64_t)a.nx * (ys[(q >> 1) & 1] + (int64_t)a.ny * zs[q >> 2]);
+                const int64_t n = ch.noff + xs[q & 1] + (int64_t)ch.nx * (ys[(q >> 1) & 1] + (int64_t)ch.ny * zs[q >> 2]);
                 R *rec = reinterpret_cast<R *>(&FI[n]);
                 atomicAdd(rec + 0, F[q][0]);
                 atomicAdd(rec + 1, F[q][1]);
@@ -556,7 +570,8 @@ struct GatherArgs {
     const void *cslot;
     const uint8_t *need;
     void *fibm;  // [N] Vec4
-    int nx, ny, nz, tpr;
+    const Chan *chans;
+    const uint16_t *tile_chan;
 };
 
 template <class R>
@@ -568,15 +583,17 @@ __global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
     const R4 *CS = static_cast<const R4 *>(a.cslot);
     R4 *FI = static_cast<R4 *>(a.fibm);
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
-        const uint32_t tile = a.tlist[w];
-        const int row = (int)(tile / a.tpr), x = (int)(tile - (uint32_t)row * a.tpr) * 64 + lane;
-        if (x >= a.nx) continue;
-        const int64_t n = (int64_t)row * a.nx + x;
+        const int tile = __builtin_amdgcn_readfirstlane((int)a.tlist[w]);
+        const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
+        const int lt = tile - ch.toff, row = lt / ch.tpr;
+        const int x = (lt - row * ch.tpr) * 64 + lane;
+        if (x >= ch.nx) continue;
+        const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
         if (!a.need[n]) continue;
-        const int y = row % a.ny, z = row / a.ny;
-        const int xb[2] = {x, x == 0 ? a.nx - 1 : x - 1};
-        const int yb[2] = {y, y == 0 ? a.ny - 1 : y - 1};
-        const int zb[2] = {z, z == 0 ? a.nz - 1 : z - 1};
+        const int y = row % ch.ny, z = row / ch.ny;
+        const int xb[2] = {x, x == 0 ? ch.nx - 1 : x - 1};
+        const int yb[2] = {y, y == 0 ? ch.ny - 1 : y - 1};
+        const int zb[2] = {z, z == 0 ? ch.nz - 1 : z - 1};
         // node n is corner q of base node (x - qx, y - qy, z - qz)
         unsigned long long *rp = reinterpret_cast<unsigned long long *>(a.role) + n;
         const unsigned long long roles = *rp;
@@ -586,7 +603,7 @@ __global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             if (!((roles >> (8 * q)) & 0xffull)) continue;
-            const int64_t b = xb[q & 1] + (int64_t)a.nx * (yb[(q >> 1) & 1] + (int64_t)a.ny * zb[q >> 2]);
+            const int64_t b = ch.noff + xb[q & 1] + (int64_t)ch.nx * (yb[(q >> 1) & 1] + (int64_t)ch.ny * zb[q >> 2]);
             const R4 f = CS[b * 8 + q];
             Fx += f.x;
             Fy += f.y;

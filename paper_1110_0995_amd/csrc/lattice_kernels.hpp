@@ -11,38 +11,53 @@ namespace lbm {
 // for CLS_BULK nodes and consults the per-node link mask only for CLS_WALL.
 enum : uint8_t { CLS_BULK = 0, CLS_WALL = 1, CLS_SOLID = 2 };
 
-struct Geometry {
-    int nx, ny, nz;
-    int per[3];
+// A context holds one or more independent lattices ("channels") in one
+// concatenated node index space (channel c owns nodes [noff, noff + N_c))
+// and one concatenated tile space (tiles [toff, toff + ntiles_c)).  A tile
+// is 64 consecutive x of one (y, z) row of one channel.
+struct Chan {
+    int nx, ny, nz, tpr;  // size; tpr = 64-node tiles per x-row
+    int64_t noff;         // first node
+    int toff, pad;        // first tile
 };
 
+// Channel of a global tile, uniform across the wave.
+__device__ __forceinline__ int tile_channel(const uint16_t *tile_chan, int tile) {
+    return tile_chan ? __builtin_amdgcn_readfirstlane((int)tile_chan[tile]) : 0;
+}
+
 // cls[n] and links[n] (bit i set = the link along c_i ends on a solid node
-// or leaves a non-periodic axis, so population i bounces back).
-__global__ void k_classify(Geometry g, const uint8_t *__restrict__ solid, uint8_t *__restrict__ cls,
-                           uint32_t *__restrict__ links) {
-    const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// or leaves a non-periodic axis, so population i bounces back).  One wave
+// per tile.
+__global__ __launch_bounds__(256) void k_classify(const Chan *__restrict__ chans, const uint16_t *__restrict__ tile_chan,
+                                                  int ntiles, int px, int py, int pz,
+                                                  const uint8_t *__restrict__ solid, uint8_t *__restrict__ cls,
+                                                  uint32_t *__restrict__ links) {
+    const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const Chan ch = chans[tile_channel(tile_chan, tile)];
+    const int lt = tile - ch.toff, row = lt / ch.tpr;
+    const int x = (lt - row * ch.tpr) * 64 + (threadIdx.x & 63);
+    if (x >= ch.nx) return;
+    const int y = row % ch.ny, z = row / ch.ny;
+    const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
     if (solid[n]) {
         cls[n] = CLS_SOLID;
         links[n] = 0;
         return;
     }
-    const int x = (int)(n % g.nx);
-    const int y = (int)((n / g.nx) % g.ny);
-    const int z = (int)(n / ((int64_t)g.nx * g.ny));
+    const int per[3] = {px, py, pz}, d[3] = {ch.nx, ch.ny, ch.nz};
     uint32_t m = 0;
     for (int i = 1; i < Q; i++) {
         int p[3] = {x + cx(i), y + cy(i), z + cz(i)};
-        const int d[3] = {g.nx, g.ny, g.nz};
         bool out = false;
-        for (int a = 0; a < 3; a++) {
-            if (p[a] < 0 || p[a] >= d[a]) {
-                if (g.per[a]) p[a] = pmod(p[a], d[a]);
+        for (int k = 0; k < 3; k++) {
+            if (p[k] < 0 || p[k] >= d[k]) {
+                if (per[k]) p[k] = pmod(p[k], d[k]);
                 else out = true;
             }
         }
-        if (out || solid[p[0] + (int64_t)g.nx * (p[1] + (int64_t)g.ny * p[2])]) m |= 1u << i;
+        if (out || solid[ch.noff + p[0] + (int64_t)ch.nx * (p[1] + (int64_t)ch.ny * p[2])]) m |= 1u << i;
     }
     cls[n] = m ? CLS_WALL : CLS_BULK;
     links[n] = m;
@@ -118,7 +133,8 @@ struct StepArgs {
     uint8_t *need;        // [N] 1: the node received spread force this step
     uint8_t *tneed;       // [ntiles] 1: the tile holds such a node
     const void *gfield;   // [3][N] or null
-    int nx, ny, nz, tpr;  // tpr = 64-node tiles per x-row
+    const Chan *chans;
+    const uint16_t *tile_chan;  // null for a single channel
     int ntiles;
     int64_t N;
     double g[3];
@@ -131,18 +147,22 @@ struct StepArgs {
 // straight to its destination slot (neighbour along c_i, or the opposite
 // slot of the same node when that link is a wall link).  The spread force is
 // read, and cleared, only at nodes marked as stencil nodes of this step.
-// IDX is the index type of element offsets from the buffer base: uint32_t
-// when 19 planes fit in 4 GiB (single 64-bit base + 32-bit lane offsets),
-// int64_t otherwise.
+// A workgroup is blockDim/64 consecutive tiles (the tile shape is a launch
+// parameter).  IDX is the index type of element offsets from the buffer
+// base: uint32_t when 19 planes fit in 4 GiB (single 64-bit base + 32-bit
+// lane offsets), int64_t otherwise.
 template <class S, class R, bool DEV, bool HAS_G, class IDX>
-__global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
+__global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * 4 + wave;
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
     if (tile >= a.ntiles) return;
-    const int row = tile / a.tpr;
-    const int x = (tile - row * a.tpr) * 64 + lane;
-    if (x >= a.nx) return;
-    const IDX n = (IDX)row * (IDX)a.nx + (IDX)x;
+    const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
+    const int lt = tile - ch.toff;
+    const int row = lt / ch.tpr;
+    const int x = (lt - row * ch.tpr) * 64 + lane;
+    if (x >= ch.nx) return;
+    const IDX base = (IDX)ch.noff;
+    const IDX n = base + (IDX)row * (IDX)ch.nx + (IDX)x;
     const IDX N = (IDX)a.N;
     const IDX stride = (IDX)a.stride;
 
@@ -177,21 +197,22 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepArgs a) {
 
     collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
 
-    const int y = row % a.ny, z = row / a.ny;
-    const int xp = (x + 1 == a.nx) ? 0 : x + 1;
-    const int xm = (x == 0) ? a.nx - 1 : x - 1;
-    const int yp = (y + 1 == a.ny) ? 0 : y + 1;
-    const int ym = (y == 0) ? a.ny - 1 : y - 1;
-    const int zp = (z + 1 == a.nz) ? 0 : z + 1;
-    const int zm = (z == 0) ? a.nz - 1 : z - 1;
+    const int y = row % ch.ny, z = row / ch.ny;
+    const int xp = (x + 1 == ch.nx) ? 0 : x + 1;
+    const int xm = (x == 0) ? ch.nx - 1 : x - 1;
+    const int yp = (y + 1 == ch.ny) ? 0 : y + 1;
+    const int ym = (y == 0) ? ch.ny - 1 : y - 1;
+    const int zp = (z + 1 == ch.nz) ? 0 : z + 1;
+    const int zm = (z == 0) ? ch.nz - 1 : z - 1;
     const uint32_t links = (cl == CLS_WALL) ? at(a.links, n) : 0u;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const int xq = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
         const int yq = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
         const int zq = cz(i) > 0 ? zp : (cz(i) < 0 ? zm : z);
-        const IDX dst = ((links >> i) & 1u) ? (IDX)opp(i) * stride + n
-                                           : (IDX)i * stride + (IDX)xq + (IDX)a.nx * ((IDX)yq + (IDX)a.ny * (IDX)zq);
+        const IDX dst = ((links >> i) & 1u)
+                            ? (IDX)opp(i) * stride + n
+                            : (IDX)i * stride + base + (IDX)xq + (IDX)ch.nx * ((IDX)yq + (IDX)ch.ny * (IDX)zq);
         at(fb, dst) = S(f[i]);
     }
 }

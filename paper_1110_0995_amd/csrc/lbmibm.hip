@@ -1,9 +1,11 @@
 // C-ABI implementation of the gfx950 D3Q19 + immersed-boundary library.
-// Host side: argument checks, context buffers, kernel dispatch by precision.
+// Host side: argument checks, context buffers, channel tables, kernel
+// dispatch by precision, and hipGraph capture of coupled steps.
 #include "lbmibm.h"
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -39,35 +41,70 @@ int fail(int code, const char *fmt, ...) {
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 constexpr uint32_t kMeshMagic = 0x1B3A0C5Du;
+constexpr int64_t kMaxNodes = (int64_t)INT32_MAX / 2;
+constexpr int kMaxChannels = 65535;
 
-uint32_t mesh_tag(const ibm_mesh *m) {
+struct Fnv {
     uint64_t h = 1469598103934665603ull;
-    auto mix = [&](uint64_t v) {
+    void mix(uint64_t v) {
         h ^= v;
         h *= 1099511628211ull;
-    };
-    mix((uint64_t)m->ncells);
-    mix((uint64_t)m->nverts);
-    mix((uint64_t)m->ntris);
-    mix((uint64_t)m->nedges);
-    mix((uint64_t)(uintptr_t)m->x);
-    mix((uint64_t)(uintptr_t)m->tri);
-    mix((uint64_t)(uintptr_t)m->hinge);
-    mix((uint64_t)(uintptr_t)m->vert_off);
-    mix((uint64_t)(uintptr_t)m->vtri);
-    mix((uint64_t)(uintptr_t)m->vedge);
-    mix((uint64_t)m->max_cell_verts);
-    return kMeshMagic ^ (uint32_t)(h ^ (h >> 32));
+    }
+    void mixd(double d) {
+        uint64_t v;
+        std::memcpy(&v, &d, 8);
+        mix(v);
+    }
+    uint32_t fold() const { return (uint32_t)(h ^ (h >> 32)); }
+};
+
+// Identity of a mesh's topology and buffers (set by ibm_rest_shape).
+uint32_t mesh_tag(const ibm_mesh *m) {
+    Fnv f;
+    f.mix((uint64_t)m->ncells);
+    f.mix((uint64_t)m->nverts);
+    f.mix((uint64_t)m->ntris);
+    f.mix((uint64_t)m->nedges);
+    f.mix((uint64_t)(uintptr_t)m->x);
+    f.mix((uint64_t)(uintptr_t)m->tri);
+    f.mix((uint64_t)(uintptr_t)m->hinge);
+    f.mix((uint64_t)(uintptr_t)m->vert_off);
+    f.mix((uint64_t)(uintptr_t)m->vtri);
+    f.mix((uint64_t)(uintptr_t)m->vedge);
+    f.mix((uint64_t)(uintptr_t)m->cell_chan);
+    f.mix((uint64_t)m->max_cell_verts);
+    return kMeshMagic ^ f.fold();
+}
+
+// Everything a captured coupled step bakes into its kernel arguments.
+uint64_t mesh_launch_key(const ibm_mesh *m) {
+    if (!m) return 0;
+    Fnv f;
+    f.mix(mesh_tag(m));
+    const void *ptrs[] = {m->tri_off, m->edge_off, m->anchor, m->v,         m->f_el,  m->moduli,
+                          m->l0,      m->a0,       m->th0,    m->a0c,       m->v0c,   m->avert,
+                          m->vtri_off, m->vedge_off};
+    for (const void *p : ptrs) f.mix((uint64_t)(uintptr_t)p);
+    f.mixd(m->xi);
+    f.mixd(m->mass);
+    f.mixd(m->dt);
+    f.mix((uint64_t)m->max_cell_tris);
+    f.mix((uint64_t)m->max_cell_edges);
+    return f.h | 1ull;
 }
 
 }  // namespace
 
 struct lbm_ctx {
     lbm_params p;
-    hipStream_t s;
-    int64_t N, stride;
-    int tpr, ntiles;
-    size_t rsize;  // sizeof(real)
+    hipStream_t s = nullptr;
+    int nch = 1;
+    std::vector<Chan> hchans;
+    Chan *chans = nullptr;          // device copy of hchans
+    uint16_t *tile_chan = nullptr;  // [ntiles] channel of each tile, null for one channel
+    int64_t N = 0, stride = 0;
+    int ntiles = 0;
+    size_t rsize = 4;  // sizeof(real)
     uint8_t *cls = nullptr;
     uint32_t *links = nullptr;
     void *fibm = nullptr;        // [N] x 4 real: spread force accumulator
@@ -76,13 +113,13 @@ struct lbm_ctx {
     uint8_t *tneed = nullptr;    // [ntiles] 1 = tile holds a marked node
     uint32_t *tlist = nullptr;   // [ntiles] marked tiles, compacted
     uint32_t *tcount = nullptr;  // length of tlist
+    uint32_t *epoch = nullptr;   // spreading-claim epoch, advanced on the device by each coupled step
     // spreading workspace, allocated by the first ibm_rest_shape
-    void *srec = nullptr;              // spread records, one per IB point of the largest mesh
+    void *srec = nullptr;        // spread records, one per IB point of the largest mesh
     int64_t srec_cap = 0;
-    uint32_t *owner = nullptr;         // [N] epoch of the last claim of each base node's slot
-    void *cslot = nullptr;             // [N][8] x 4 real: corner contributions per base node
-    uint8_t *role = nullptr;           // [N][8] slot flags read by the node gather
-    uint32_t epoch = 0;                // ibm_couple calls so far
+    uint32_t *owner = nullptr;   // [N] epoch of the last claim of each base node's slot
+    void *cslot = nullptr;       // [N][8] x 4 real: corner contributions per base node
+    uint8_t *role = nullptr;     // [N][8] slot flags read by the node gather
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
     int64_t nparts = 0;
@@ -90,9 +127,22 @@ struct lbm_ctx {
     double *host_sums = nullptr;
     int cur = 0;  // 0: state in f_a, 1: in f_b
     int64_t steps = 0;
+    // launch shape
+    int cs_waves = 4;     // tiles (waves) per collide-stream workgroup
+    int list_blocks = 0;  // workgroups of the tile-list kernels (0: by lattice size)
+    // captured coupled steps
+    hipStream_t cap_s = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gsteps = 0, gcur = 0;
+    uint64_t gkey = 0;
 };
 
 #define LBM_API extern "C" __attribute__((visibility("default")))
+
+static void drop_graph(lbm_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+}
 
 LBM_API const char *lbm_last_error(void) { return g_err.c_str(); }
 
@@ -105,11 +155,9 @@ LBM_API int64_t lbm_plane_stride(int64_t n, int32_t prec) {
     return s;
 }
 
-static int check_params(const lbm_params *p) {
-    if (!p) return fail(LBM_EINVAL, "params is NULL");
-    if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "lattice size must be >= 1 (got %d %d %d)", p->nx, p->ny, p->nz);
-    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-    if (N > (int64_t)INT32_MAX / 2) return fail(LBM_EINVAL, "lattice too large (%lld nodes)", (long long)N);
+// Checks shared by both init calls; N is the node count of all channels.
+static int check_common(const lbm_params *p, int64_t N) {
+    if (N > kMaxNodes) return fail(LBM_EINVAL, "lattice too large (%lld nodes)", (long long)N);
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be finite and > 1/2 (got %g)", p->tau);
     for (int d = 0; d < 3; d++) {
         if (p->periodic[d] != 0 && p->periodic[d] != 1) return fail(LBM_EINVAL, "periodic[%d] must be 0 or 1", d);
@@ -127,12 +175,126 @@ static int check_params(const lbm_params *p) {
     return LBM_OK;
 }
 
+static int check_params(const lbm_params *p) {
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(LBM_EINVAL, "lattice size must be >= 1 (got %d %d %d)", p->nx, p->ny, p->nz);
+    return check_common(p, (int64_t)p->nx * p->ny * p->nz);
+}
+
+// Channel table of dims [nch][3]; fails on sizes below 1 or too many nodes.
+static int make_channels(int32_t nch, const int32_t *dims, std::vector<Chan> &out, int64_t &N, int64_t &T) {
+    out.clear();
+    N = 0;
+    T = 0;
+    for (int k = 0; k < nch; k++) {
+        const int nx = dims[3 * k], ny = dims[3 * k + 1], nz = dims[3 * k + 2];
+        if (nx < 1 || ny < 1 || nz < 1)
+            return fail(LBM_EINVAL, "channel %d size must be >= 1 (got %d %d %d)", k, nx, ny, nz);
+        const Chan ch{nx, ny, nz, (int)cdiv(nx, 64), N, (int)T, 0};
+        out.push_back(ch);
+        N += (int64_t)nx * ny * nz;
+        T += (int64_t)ch.tpr * ny * nz;
+        if (N > kMaxNodes) return fail(LBM_EINVAL, "lattice too large (more than %lld nodes)", (long long)kMaxNodes);
+    }
+    return LBM_OK;
+}
+
+static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch) {
+    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
+           (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
+}
+
 LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {
     if (check_params(p)) return -1;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-    const int64_t es = p->prec == LBM_F64 ? 8 : 4;
-    const int64_t tiles = cdiv(p->nx, 64) * (int64_t)p->ny * p->nz;
-    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + cdiv(N, 256) * 32 + 32;
+    return workspace(N, cdiv(p->nx, 64) * (int64_t)p->ny * p->nz, p->prec == LBM_F64 ? 8 : 4, 1);
+}
+
+LBM_API int64_t lbm_workspace_bytes_channels(const lbm_params *p, int32_t nch, const int32_t *dims) {
+    if (!p || !dims || nch < 1 || nch > kMaxChannels) return -1;
+    std::vector<Chan> chs;
+    int64_t N, T;
+    if (make_channels(nch, dims, chs, N, T) || check_common(p, N)) return -1;
+    return workspace(N, T, p->prec == LBM_F64 ? 8 : 4, nch);
+}
+
+LBM_API void lbm_destroy(lbm_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->s);
+    if (c->cap_s) (void)hipStreamSynchronize(c->cap_s);
+    drop_graph(c);
+    if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
+    void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm,  c->ufield,   c->need, c->tneed, c->tlist,
+                    c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (c->host_sums) (void)hipHostFree(c->host_sums);
+    delete c;
+}
+
+// Allocate the work buffers for the channels in c->hchans, classify the
+// nodes and set both state buffers to rest.
+static int init_ctx(lbm_ctx *c) {
+    const lbm_params *p = &c->p;
+    c->s = (hipStream_t)p->stream;
+    c->stride = p->plane_stride ? p->plane_stride : lbm_plane_stride(c->N, p->prec);
+    c->p.plane_stride = c->stride;
+    c->rsize = p->prec == LBM_F64 ? 8 : 4;
+    c->nparts = cdiv(c->N, 256);
+    c->off32 = 19 * c->stride * (int64_t)c->rsize < (int64_t(1) << 32);
+    c->nch = (int)c->hchans.size();
+    const size_t tn = (size_t)c->ntiles;
+    const size_t tpad = (size_t)cdiv((int64_t)tn, 16) * 16;
+    if (hipMalloc(&c->chans, sizeof(Chan) * c->nch) != hipSuccess || hipMalloc(&c->cls, c->N) != hipSuccess ||
+        hipMalloc(&c->links, 4 * c->N) != hipSuccess || hipMalloc(&c->fibm, 4 * c->N * c->rsize) != hipSuccess ||
+        hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
+        hipMalloc(&c->tneed, tpad) != hipSuccess || hipMalloc(&c->tlist, 4 * tn) != hipSuccess ||
+        hipMalloc(&c->tcount, 4) != hipSuccess || hipMalloc(&c->epoch, 4) != hipSuccess ||
+        hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
+        (c->nch > 1 && hipMalloc(&c->tile_chan, 2 * tn) != hipSuccess) ||
+        hipHostMalloc(&c->host_sums, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_ENOMEM, "device allocation of the context work buffers failed");
+    }
+    HIPCHK(hipMemcpy(c->chans, c->hchans.data(), sizeof(Chan) * c->nch, hipMemcpyHostToDevice));
+    if (c->nch > 1) {
+        std::vector<uint16_t> tc(tn);
+        for (int k = 0; k < c->nch; k++) {
+            const Chan &ch = c->hchans[k];
+            const int nt = ch.tpr * ch.ny * ch.nz;
+            std::fill(tc.begin() + ch.toff, tc.begin() + ch.toff + nt, (uint16_t)k);
+        }
+        HIPCHK(hipMemcpy(c->tile_chan, tc.data(), 2 * tn, hipMemcpyHostToDevice));
+    }
+    k_classify<<<(int)cdiv(c->ntiles, 4), 256, 0, c->s>>>(c->chans, c->tile_chan, c->ntiles, p->periodic[0],
+                                                           p->periodic[1], p->periodic[2], p->solid, c->cls, c->links);
+    HIPCHK(hipMemsetAsync(c->fibm, 0, 4 * c->N * c->rsize, c->s));
+    HIPCHK(hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s));
+    HIPCHK(hipMemsetAsync(c->need, 0, c->N, c->s));
+    HIPCHK(hipMemsetAsync(c->tneed, 0, tpad, c->s));
+    HIPCHK(hipMemsetAsync(c->tcount, 0, 4, c->s));
+    HIPCHK(hipMemsetAsync(c->epoch, 0, 4, c->s));
+    const int nb = (int)cdiv(c->N, 256);
+    for (void *f : {p->f_a, p->f_b}) {
+        switch (p->prec) {
+            case LBM_F64: k_rest<double, false><<<nb, 256, 0, c->s>>>((double *)f, c->stride, c->N); break;
+            case LBM_F32: k_rest<float, false><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N); break;
+            default: k_rest<float, true><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N); break;
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+static int finish_init(lbm_ctx *c, lbm_ctx **out) {
+    if (int rc = init_ctx(c)) {
+        lbm_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
 }
 
 LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
@@ -141,71 +303,41 @@ LBM_API int lbm_init(const lbm_params *p, lbm_ctx **out) {
     if (int rc = check_params(p)) return rc;
     lbm_ctx *c = new lbm_ctx();
     c->p = *p;
-    c->s = (hipStream_t)p->stream;
-    c->N = (int64_t)p->nx * p->ny * p->nz;
-    c->stride = p->plane_stride ? p->plane_stride : lbm_plane_stride(c->N, p->prec);
-    c->p.plane_stride = c->stride;
-    c->tpr = (int)cdiv(p->nx, 64);
-    c->ntiles = c->tpr * p->ny * p->nz;
-    c->rsize = p->prec == LBM_F64 ? 8 : 4;
-    c->nparts = cdiv(c->N, 256);
-    c->off32 = 19 * c->stride * (int64_t)c->rsize < (int64_t(1) << 32);
-    auto cleanup = [&](int rc) {
-        lbm_destroy(c);
-        return rc;
-    };
-    if (hipMalloc(&c->cls, c->N) != hipSuccess || hipMalloc(&c->links, 4 * c->N) != hipSuccess ||
-        hipMalloc(&c->fibm, 4 * c->N * c->rsize) != hipSuccess ||
-        hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
-        hipMalloc(&c->tneed, cdiv(c->ntiles, 16) * 16) != hipSuccess ||
-        hipMalloc(&c->tlist, 4 * (size_t)c->ntiles) != hipSuccess || hipMalloc(&c->tcount, 4) != hipSuccess ||
-        hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&c->host_sums, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        (void)hipGetLastError();
-        return cleanup(fail(LBM_ENOMEM, "device allocation of the context work buffers failed"));
-    }
-    Geometry g{p->nx, p->ny, p->nz, {p->periodic[0], p->periodic[1], p->periodic[2]}};
-    const int nb = (int)cdiv(c->N, 256);
-    k_classify<<<nb, 256, 0, c->s>>>(g, p->solid, c->cls, c->links);
-    if (hipMemsetAsync(c->fibm, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
-        hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s) != hipSuccess ||
-        hipMemsetAsync(c->need, 0, c->N, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tneed, 0, cdiv(c->ntiles, 16) * 16, c->s) != hipSuccess ||
-        hipMemsetAsync(c->tcount, 0, 4, c->s) != hipSuccess)
-        return cleanup(fail(LBM_EHIP, "clearing the force accumulator failed"));
-    for (void *f : {p->f_a, p->f_b}) {
-        switch (p->prec) {
-            case LBM_F64: k_rest<double, false><<<nb, 256, 0, c->s>>>((double *)f, c->stride, c->N); break;
-            case LBM_F32: k_rest<float, false><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N); break;
-            default: k_rest<float, true><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N); break;
-        }
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return cleanup(fail(LBM_EHIP, "init kernels: %s", hipGetErrorString(e)));
-    *out = c;
-    return LBM_OK;
+    const int32_t dims[3] = {p->nx, p->ny, p->nz};
+    int64_t T;
+    make_channels(1, dims, c->hchans, c->N, T);
+    c->ntiles = (int)T;
+    return finish_init(c, out);
 }
 
-LBM_API void lbm_destroy(lbm_ctx *c) {
-    if (!c) return;
-    (void)hipStreamSynchronize(c->s);
-    if (c->cls) (void)hipFree(c->cls);
-    if (c->links) (void)hipFree(c->links);
-    if (c->fibm) (void)hipFree(c->fibm);
-    if (c->ufield) (void)hipFree(c->ufield);
-    if (c->need) (void)hipFree(c->need);
-    if (c->tneed) (void)hipFree(c->tneed);
-    if (c->tlist) (void)hipFree(c->tlist);
-    if (c->tcount) (void)hipFree(c->tcount);
-    if (c->srec) (void)hipFree(c->srec);
-    if (c->owner) (void)hipFree(c->owner);
-    if (c->cslot) (void)hipFree(c->cslot);
-    if (c->role) (void)hipFree(c->role);
-    if (c->partials) (void)hipFree(c->partials);
-    if (c->sums) (void)hipFree(c->sums);
-    if (c->host_sums) (void)hipHostFree(c->host_sums);
-    delete c;
+LBM_API int lbm_init_channels(const lbm_params *p, int32_t nch, const int32_t *dims, lbm_ctx **out) {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(LBM_EINVAL, "params is NULL");
+    if (nch < 1 || nch > kMaxChannels) return fail(LBM_EINVAL, "nch must be in [1, %d] (got %d)", kMaxChannels, nch);
+    if (!dims) return fail(LBM_EINVAL, "dims is NULL");
+    std::vector<Chan> chs;
+    int64_t N, T;
+    if (int rc = make_channels(nch, dims, chs, N, T)) return rc;
+    if (int rc = check_common(p, N)) return rc;
+    lbm_ctx *c = new lbm_ctx();
+    c->p = *p;
+    c->hchans = chs;
+    c->N = N;
+    c->ntiles = (int)T;
+    return finish_init(c, out);
+}
+
+LBM_API int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t list_blocks) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    const int w = collide_waves_per_block;
+    if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8)
+        return fail(LBM_EINVAL, "collide_waves_per_block must be 0, 1, 2, 4 or 8 (got %d)", w);
+    if (list_blocks < 0 || list_blocks > 65536) return fail(LBM_EINVAL, "list_blocks must be in [0, 65536]");
+    c->cs_waves = w ? w : 4;
+    c->list_blocks = list_blocks;
+    drop_graph(c);  // a captured graph holds the old launch shape
+    return LBM_OK;
 }
 
 static const void *cur_f(const lbm_ctx *c) { return c->cur ? c->p.f_b : c->p.f_a; }
@@ -213,23 +345,22 @@ static void *nxt_f(const lbm_ctx *c) { return c->cur ? c->p.f_a : c->p.f_b; }
 
 template <class S, class R, bool DEV>
 static void launch_step(lbm_ctx *c, const StepArgs &a) {
-    const int nb = (int)cdiv(c->ntiles, 4);
+    const int nb = (int)cdiv(c->ntiles, c->cs_waves);
+    const int bs = 64 * c->cs_waves;
     if (c->off32) {
         if (c->p.gfield)
-            k_collide_stream<S, R, DEV, true, uint32_t><<<nb, 256, 0, c->s>>>(a);
+            k_collide_stream<S, R, DEV, true, uint32_t><<<nb, bs, 0, c->s>>>(a);
         else
-            k_collide_stream<S, R, DEV, false, uint32_t><<<nb, 256, 0, c->s>>>(a);
+            k_collide_stream<S, R, DEV, false, uint32_t><<<nb, bs, 0, c->s>>>(a);
     } else {
         if (c->p.gfield)
-            k_collide_stream<S, R, DEV, true, int64_t><<<nb, 256, 0, c->s>>>(a);
+            k_collide_stream<S, R, DEV, true, int64_t><<<nb, bs, 0, c->s>>>(a);
         else
-            k_collide_stream<S, R, DEV, false, int64_t><<<nb, 256, 0, c->s>>>(a);
+            k_collide_stream<S, R, DEV, false, int64_t><<<nb, bs, 0, c->s>>>(a);
     }
 }
 
-LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
-    if (!c) return fail(LBM_EINVAL, "context is NULL");
-    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+static void enqueue_steps(lbm_ctx *c, int32_t nsteps) {
     StepArgs a{};
     a.stride = c->stride;
     a.cls = c->cls;
@@ -238,10 +369,8 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     a.need = c->need;
     a.tneed = c->tneed;
     a.gfield = c->p.gfield;
-    a.nx = c->p.nx;
-    a.ny = c->p.ny;
-    a.nz = c->p.nz;
-    a.tpr = c->tpr;
+    a.chans = c->chans;
+    a.tile_chan = c->tile_chan;
     a.ntiles = c->ntiles;
     a.N = c->N;
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
@@ -258,6 +387,12 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
         c->cur ^= 1;
         c->steps++;
     }
+}
+
+LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    enqueue_steps(c, nsteps);
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }
@@ -334,7 +469,7 @@ LBM_API int lbm_load_f64(lbm_ctx *c, const double *f64) {
 // ---------------------------------------------------------------------------
 // immersed boundary
 
-static int check_mesh_ptrs(const ibm_mesh *m) {
+static int check_mesh_ptrs(const lbm_ctx *c, const ibm_mesh *m) {
     if (!m) return fail(LBM_EINVAL, "mesh is NULL");
     if (m->ncells < 1 || m->nverts < 1 || m->ntris < 1 || m->nedges < 1)
         return fail(LBM_EINVAL, "mesh counts must be >= 1");
@@ -342,6 +477,8 @@ static int check_mesh_ptrs(const ibm_mesh *m) {
         !m->f_el || !m->moduli || !m->l0 || !m->a0 || !m->th0 || !m->a0c || !m->v0c || !m->avert || !m->vtri_off ||
         !m->vtri || !m->vedge_off || !m->vedge)
         return fail(LBM_EINVAL, "mesh has a NULL array");
+    if (c->nch > 1 && !m->cell_chan)
+        return fail(LBM_EINVAL, "cell_chan must be given when the context holds several channels");
     if (!(m->xi > 0) || !(m->mass > 0) || !(m->dt > 0) || !std::isfinite(m->xi) || !std::isfinite(m->mass) ||
         !std::isfinite(m->dt))
         return fail(LBM_EINVAL, "xi, mass and dt must be finite and > 0");
@@ -350,10 +487,21 @@ static int check_mesh_ptrs(const ibm_mesh *m) {
 
 static constexpr size_t kMaxLds = 64 * 1024;
 
+// Workgroups of the kernels that walk the compacted tile list.
+static int waves_grid(const lbm_ctx *c) {
+    if (c->list_blocks) return c->list_blocks;
+    // four waves per workgroup, one wave per listed tile for lists up to a
+    // quarter of the lattice (the waves stride over longer lists)
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
+}
+
 template <class R>
 static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     MembArgs a{};
     a.tcount = c->tcount;
+    a.epoch = c->epoch;
+    a.chans = c->chans;
+    a.cell_chan = m->cell_chan;
     a.vtri_off = m->vtri_off;
     a.vtri = m->vtri;
     a.vedge_off = m->vedge_off;
@@ -366,7 +514,7 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.tri = m->tri;
     a.hinge = m->hinge;
     a.anchor = m->anchor;
-    a.x = static_cast<const double *>(m->x);
+    a.x = m->x;
     a.f_el = m->f_el;
     a.moduli = m->moduli;
     a.l0 = m->l0;
@@ -380,10 +528,6 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.ntris = m->ntris;
     a.nedges = m->nedges;
     a.maxv = m->max_cell_verts;
-    a.nx = c->p.nx;
-    a.ny = c->p.ny;
-    a.nz = c->p.nz;
-    a.tpr = c->tpr;
     a.need = c->need;
     a.tneed = c->tneed;
     const size_t sm = membrane_lds_bytes<R>(m->max_cell_verts, m->max_cell_tris, m->max_cell_edges);
@@ -395,7 +539,7 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
 
 LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
-    if (int rc = check_mesh_ptrs(m)) return rc;
+    if (int rc = check_mesh_ptrs(c, m)) return rc;
     // read the topology back and check every index against its cell's range
     std::vector<int32_t> vo(m->ncells + 1), to(m->ncells + 1), eo(m->ncells + 1), tri(3 * (size_t)m->ntris),
         hin(4 * (size_t)m->nedges);
@@ -405,6 +549,13 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     HIPCHK(hipMemcpy(eo.data(), m->edge_off, eo.size() * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(tri.data(), m->tri, tri.size() * 4, hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(hin.data(), m->hinge, hin.size() * 4, hipMemcpyDeviceToHost));
+    if (m->cell_chan) {
+        std::vector<int32_t> cch(m->ncells);
+        HIPCHK(hipMemcpy(cch.data(), m->cell_chan, cch.size() * 4, hipMemcpyDeviceToHost));
+        for (int k = 0; k < m->ncells; k++)
+            if (cch[k] < 0 || cch[k] >= c->nch)
+                return fail(LBM_EINVAL, "cell %d names channel %d (the context has %d)", k, cch[k], c->nch);
+    }
     if (vo[0] != 0 || to[0] != 0 || eo[0] != 0 || vo[m->ncells] != m->nverts || to[m->ncells] != m->ntris ||
         eo[m->ncells] != m->nedges)
         return fail(LBM_EINVAL, "offset arrays must start at 0 and end at the counts");
@@ -432,6 +583,9 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     if (lds > kMaxLds)
         return fail(LBM_EINVAL, "a cell with %d vertices, %d triangles, %d edges does not fit one workgroup's LDS", mv,
                     mt, me);
+    if (mv > kSpreadMaxPoints) return fail(LBM_EINVAL, "a cell has %d vertices (at most %d)", mv, kSpreadMaxPoints);
+    if ((int64_t)m->ntris * 4 > INT32_MAX || (int64_t)m->nedges * 4 > INT32_MAX)
+        return fail(LBM_EINVAL, "mesh too large for 32-bit incidence codes");
     // per-vertex incidence lists, elements in increasing order (the force
     // pass sums over them in this order)
     {
@@ -450,8 +604,6 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
             for (int j = 0; j < 3; j++) tl[tf[tri[(size_t)j * m->ntris + t]]++] = 4 * t + j;
         for (int e = 0; e < m->nedges; e++)
             for (int j = 0; j < 4; j++) el[ef[hin[(size_t)j * m->nedges + e]]++] = 4 * e + j;
-        if ((int64_t)m->ntris * 4 > INT32_MAX || (int64_t)m->nedges * 4 > INT32_MAX)
-            return fail(LBM_EINVAL, "mesh too large for 32-bit incidence codes");
         HIPCHK(hipMemcpy(m->vtri_off, toff.data(), toff.size() * 4, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(m->vtri, tl.data(), tl.size() * 4, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(m->vedge_off, eoff.data(), eoff.size() * 4, hipMemcpyHostToDevice));
@@ -460,9 +612,9 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     m->max_cell_verts = mv;
     m->max_cell_tris = mt;
     m->max_cell_edges = me;
-    if (mv > kSpreadMaxPoints) return fail(LBM_EINVAL, "a cell has %d vertices (at most %d)", mv, kSpreadMaxPoints);
     const int64_t need_rec = (int64_t)m->nverts * (c->rsize == 8 ? sizeof(SRec<double>) : sizeof(SRec<float>));
     if (need_rec > c->srec_cap) {
+        drop_graph(c);  // a captured graph names the old record buffer
         if (c->srec) HIPCHK(hipFree(c->srec));
         c->srec = nullptr;
         c->srec_cap = 0;
@@ -491,11 +643,6 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     return LBM_OK;
 }
 
-static int waves_grid(const lbm_ctx *c) {
-    // one wave per listed tile for lists up to a quarter of the lattice
-    return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
-}
-
 template <class S, class R, bool DEV>
 static void launch_node_velocity(lbm_ctx *c) {
     k_compact<<<(int)cdiv(c->ntiles, kCompactThreads * kCompactPerThread), kCompactThreads, 0, c->s>>>(
@@ -509,8 +656,8 @@ static void launch_node_velocity(lbm_ctx *c) {
     a.need = c->need;
     a.tlist = c->tlist;
     a.tcount = c->tcount;
-    a.nx = c->p.nx;
-    a.tpr = c->tpr;
+    a.chans = c->chans;
+    a.tile_chan = c->tile_chan;
     a.N = c->N;
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
     if (c->p.gfield)
@@ -524,13 +671,11 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     CoupleArgs a{};
     a.ufield = c->ufield;
     a.srec = c->srec;
-    a.nx = c->p.nx;
-    a.ny = c->p.ny;
-    a.nz = c->p.nz;
-    a.N = c->N;
+    a.chans = c->chans;
+    a.cell_chan = m->cell_chan;
     a.vert_off = m->vert_off;
     a.anchor = m->anchor;
-    a.x = static_cast<double *>(m->x);
+    a.x = m->x;
     a.v = m->v;
     a.f_el = m->f_el;
     a.avert = m->avert;
@@ -549,9 +694,8 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.role = c->role;
     sp.fibm = c->fibm;
     sp.epoch = c->epoch;
-    sp.nx = c->p.nx;
-    sp.ny = c->p.ny;
-    sp.nz = c->p.nz;
+    sp.chans = c->chans;
+    sp.cell_chan = m->cell_chan;
     k_spread_cells<R><<<m->ncells, kSpreadThreads, 0, c->s>>>(sp);
     GatherArgs g{};
     g.tlist = c->tlist;
@@ -560,21 +704,12 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     g.cslot = c->cslot;
     g.need = c->need;
     g.fibm = c->fibm;
-    g.nx = c->p.nx;
-    g.ny = c->p.ny;
-    g.nz = c->p.nz;
-    g.tpr = c->tpr;
+    g.chans = c->chans;
+    g.tile_chan = c->tile_chan;
     k_gather_nodes<R><<<waves_grid(c), 256, 0, c->s>>>(g);
 }
 
-LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
-    if (!c) return fail(LBM_EINVAL, "context is NULL");
-    if (int rc = check_mesh_ptrs(m)) return rc;
-    if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
-    if (++c->epoch == 0) {  // the claim epochs wrapped: forget every old claim
-        HIPCHK(hipMemsetAsync(c->owner, 0, 4 * c->N, c->s));
-        c->epoch = 1;
-    }
+static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m) {
     switch (c->p.prec) {
         case LBM_F64:
             launch_membrane<double>(c, m, false);
@@ -591,6 +726,78 @@ LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
             launch_node_velocity<float, float, true>(c);
             launch_couple<float>(c, m);
             break;
+    }
+}
+
+LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (int rc = check_mesh_ptrs(c, m)) return rc;
+    if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
+    enqueue_couple(c, m);
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+// Capture steps_per_graph coupled steps into c->gexec.  The capture runs on
+// a private stream so that nothing else the process enqueues is recorded;
+// the kernels of a coupled step contain no memset or copy nodes.
+static int capture(lbm_ctx *c, const ibm_mesh *m, int32_t steps_per_graph) {
+    drop_graph(c);
+    if (!c->cap_s) HIPCHK(hipStreamCreate(&c->cap_s));
+    const hipStream_t user = c->s;
+    const int cur0 = c->cur;
+    const int64_t steps0 = c->steps;
+    c->s = c->cap_s;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->s, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        for (int k = 0; k < steps_per_graph; k++) {
+            if (m) enqueue_couple(c, m);
+            enqueue_steps(c, 1);
+        }
+        e = hipStreamEndCapture(c->s, &g);
+    }
+    c->s = user;
+    c->cur = cur0;  // an even number of swaps leaves the state where it was
+    c->steps = steps0;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(LBM_EHIP, "capturing the coupled steps failed: %s", hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c->gexec = nullptr;
+        (void)hipGetLastError();
+        return fail(LBM_EHIP, "instantiating the coupled-step graph failed: %s", hipGetErrorString(e));
+    }
+    c->gsteps = steps_per_graph;
+    c->gcur = c->cur;
+    c->gkey = mesh_launch_key(m);
+    return LBM_OK;
+}
+
+LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps_per_graph) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (steps_per_graph < 0 || steps_per_graph % 2 || steps_per_graph > 4096)
+        return fail(LBM_EINVAL, "steps_per_graph must be 0 or even and at most 4096 (got %d)", steps_per_graph);
+    if (m) {
+        if (int rc = check_mesh_ptrs(c, m)) return rc;
+        if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
+    }
+    int32_t left = nsteps;
+    if (steps_per_graph > 0 && nsteps >= steps_per_graph) {
+        if (!c->gexec || c->gsteps != steps_per_graph || c->gcur != c->cur || c->gkey != mesh_launch_key(m))
+            if (int rc = capture(c, m, steps_per_graph)) return rc;
+        for (; left >= steps_per_graph; left -= steps_per_graph) {
+            HIPCHK(hipGraphLaunch(c->gexec, c->s));
+            c->steps += steps_per_graph;
+        }
+    }
+    for (int32_t k = 0; k < left; k++) {
+        if (m) enqueue_couple(c, m);
+        enqueue_steps(c, 1);
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;

@@ -3,7 +3,7 @@ the HIP kernels behind the C ABI (include/lbmibm.h)."""
 from __future__ import annotations
 
 import ctypes as C
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import numpy as np
 import torch
@@ -24,13 +24,17 @@ class Lattice:
     def __init__(self, nx: int, ny: int, nz: int, tau: float, g: Sequence[float] = (0.0, 0.0, 0.0),
                  solid: Optional[np.ndarray] = None, prec: str = "f32dev",
                  periodic: Sequence[int] = (1, 1, 1), gfield: Optional[np.ndarray] = None,
-                 device: str = "cuda", plane_stride: int = 0):
+                 device: str = "cuda", plane_stride: int = 0,
+                 channels: Optional[Sequence[Tuple[int, int, int]]] = None):
         self.lib = _lib.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lattice kernels run only on an MI355X")
         self.device = torch.device(device)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
-        self.N = self.nx * self.ny * self.nz
+        # channel k holds nodes [noff[k], noff[k+1]) of the concatenated index
+        self.channels = [(self.nx, self.ny, self.nz)] if channels is None else [tuple(map(int, d)) for d in channels]
+        self.noff = np.concatenate([[0], np.cumsum([a * b * c for a, b, c in self.channels])]).astype(np.int64)
+        self.N = int(self.noff[-1])
         self.prec = prec
         self.code = _lib.PRECISIONS[prec]
         self.rdtype = torch.float64 if prec == "f64" else torch.float32
@@ -53,7 +57,11 @@ class Lattice:
                                      self.stream.cuda_stream)
         self.tau, self.g = float(tau), tuple(float(v) for v in g)
         ctx = C.c_void_p()
-        _lib.check(self.lib.lbm_init(C.byref(self.params), C.byref(ctx)))
+        if channels is None:
+            _lib.check(self.lib.lbm_init(C.byref(self.params), C.byref(ctx)))
+        else:
+            dims = (C.c_int32 * (3 * len(self.channels)))(*[v for d in self.channels for v in d])
+            _lib.check(self.lib.lbm_init_channels(C.byref(self.params), len(self.channels), dims, C.byref(ctx)))
         self.ctx = ctx
         self.meshes = []
 
@@ -62,6 +70,27 @@ class Lattice:
         return cls(s.nx, s.ny, s.nz, s.tau, s.g, s.solid, prec, s.periodic,
                    kw.pop("gfield", s.gfield), **kw)
 
+    @classmethod
+    def batch(cls, scenarios: Sequence[Scenario], prec: str = "f32dev", **kw) -> "Lattice":
+        """One context over independent channels (one per scenario), stepped
+        together.  tau, g and the periodic axes must agree across them."""
+        s0 = scenarios[0]
+        for s in scenarios:
+            if s.tau != s0.tau or tuple(s.g) != tuple(s0.g) or tuple(s.periodic) != tuple(s0.periodic):
+                raise ValueError("batched channels must share tau, g and the periodic axes")
+            if s.gfield is not None:
+                raise ValueError("a forcing field is not supported in a batch")
+        solid = np.concatenate([np.asarray(s.solid, np.uint8).reshape(-1) for s in scenarios])
+        return cls(s0.nx, s0.ny, s0.nz, s0.tau, s0.g, solid, prec, s0.periodic, None,
+                   channels=[(s.nx, s.ny, s.nz) for s in scenarios], **kw)
+
+    def channel(self, k: int) -> slice:
+        """Node range of channel k in the concatenated index."""
+        return slice(int(self.noff[k]), int(self.noff[k + 1]))
+
+    def set_launch(self, collide_waves_per_block: int = 0, list_blocks: int = 0) -> None:
+        _lib.check(self.lib.lbm_set_launch(self.ctx, int(collide_waves_per_block), int(list_blocks)))
+
     # -- the four calls of the path --------------------------------------
     def step(self, nsteps: int = 1) -> None:
         _lib.check(self.lib.lbm_step(self.ctx, int(nsteps)))
@@ -69,14 +98,12 @@ class Lattice:
     def couple(self, mesh: "Mesh") -> None:
         _lib.check(self.lib.ibm_couple(self.ctx, C.byref(mesh.s)))
 
-    def run(self, nsteps: int, mesh: Optional["Mesh"] = None) -> None:
-        """nsteps full steps (immersed-boundary coupling then collide-stream)."""
-        if mesh is None:
-            self.step(nsteps)
-            return
-        for _ in range(nsteps):
-            self.couple(mesh)
-            self.step(1)
+    def run(self, nsteps: int, mesh: Optional["Mesh"] = None, steps_per_graph: int = 0) -> None:
+        """nsteps full steps (immersed-boundary coupling then collide-stream),
+        replayed from a captured HIP graph in groups of steps_per_graph (even)
+        when that is non-zero."""
+        _lib.check(self.lib.lbm_run(self.ctx, None if mesh is None else C.byref(mesh.s), int(nsteps),
+                                    int(steps_per_graph)))
 
     def fields(self):
         """(rho [N], u [3, N]) of the current state as device tensors."""
@@ -129,11 +156,12 @@ class Lattice:
 class Mesh:
     """Membrane population on a lattice's device (SoA arrays, rest shape computed on the GPU)."""
 
-    def __init__(self, lat: Lattice, cells: Cells):
+    def __init__(self, lat: Lattice, cells: Cells, cell_chan: Optional[np.ndarray] = None):
         dev, R = lat.device, lat.rdtype
         i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32)).to(dev)
         self.cells = cells
         self.lat = lat
+        self.cell_chan = None if cell_chan is None else i32(np.asarray(cell_chan).reshape(-1))
         self.vert_off = i32(cells.vert_off)
         self.tri_off = i32(cells.tri_off)
         self.edge_off = i32(cells.edge_off)
@@ -157,7 +185,7 @@ class Mesh:
         p = lambda t: t.data_ptr()
         self.s = _lib.IbmMesh(cells.ncells, cells.nverts, cells.ntris, cells.nedges, p(self.vert_off),
                               p(self.tri_off), p(self.edge_off), p(self.tri), p(self.hinge), p(self.anchor),
-                              p(self.x), p(self.v), p(self.f_el), p(self.moduli), p(self.l0), p(self.a0),
+                              None if self.cell_chan is None else p(self.cell_chan), p(self.x), p(self.v), p(self.f_el), p(self.moduli), p(self.l0), p(self.a0),
                               p(self.th0), p(self.a0c), p(self.v0c), p(self.avert), p(self.vtri_off), p(self.vtri),
                               p(self.vedge_off), p(self.vedge), float(cells.xi), float(cells.mass),
                               float(cells.dt), 0, 0, 0, 0)

@@ -385,6 +385,35 @@ def gap_sweep(nch: int = 64, *, lengths=(64, 128, 192, 256), ny: int = 64, nz: i
     return out
 
 
+def batch_cells(scenarios: Sequence[Scenario]) -> Tuple[Optional[Cells], np.ndarray]:
+    """Concatenate the cell populations of several channels into one (vertex,
+    triangle and edge ids renumbered) and give the channel of each cell."""
+    parts = [(k, s.cells) for k, s in enumerate(scenarios) if s.cells is not None]
+    if not parts:
+        return None, np.zeros(0, np.int32)
+    vo, to, eo = [0], [0], [0]
+    tri, hin, anc, off, mod, chan = [], [], [], [], [], []
+    for k, c in parts:
+        tri.append(c.tri + vo[-1])
+        hin.append(c.hinge + vo[-1])
+        vo.extend((c.vert_off[1:] + vo[-1]).tolist())
+        to.extend((c.tri_off[1:] + to[-1]).tolist())
+        eo.extend((c.edge_off[1:] + eo[-1]).tolist())
+        anc.append(c.anchor)
+        off.append(c.offset)
+        mod.append(c.moduli)
+        chan.append(np.full(c.ncells, k, np.int32))
+    c0 = parts[0][1]
+    for _, c in parts:
+        if (c.xi, c.mass, c.dt) != (c0.xi, c0.mass, c0.dt):
+            raise ValueError("batched cells must share xi, mass and dt")
+    cells = Cells(np.asarray(vo, np.int32), np.asarray(to, np.int32), np.asarray(eo, np.int32),
+                  np.concatenate(tri).astype(np.int32), np.concatenate(hin).astype(np.int32),
+                  np.concatenate(anc).astype(np.int32), np.concatenate(off), np.concatenate(mod),
+                  xi=c0.xi, mass=c0.mass, dt=c0.dt)
+    return cells, np.concatenate(chan)
+
+
 def adjoint_channel(nx: int = 128, ny: int = 64, nz: int = 32, *, ncells: int = 3,
                     cell_radius: float = 4.0, level: int = 2, tau: float = 0.8, gx: float = 1e-5,
                     steps: int = 300, seed: int = 5, design_x=(32, 96)) -> Scenario:

@@ -87,8 +87,14 @@ def test_null_context_calls(L):
     assert L.lbm_current(None, None, None) == _lib.LBM_EINVAL
     assert L.lbm_store_f64(None, None) == _lib.LBM_EINVAL
     assert L.lbm_init(None, None) == _lib.LBM_EINVAL
+    assert L.lbm_init_channels(None, 1, None, None) == _lib.LBM_EINVAL
+    assert L.lbm_set_launch(None, 4, 0) == _lib.LBM_EINVAL
+    assert L.lbm_run(None, None, 1, 0) == _lib.LBM_EINVAL
     L.lbm_destroy(None)
     assert b"NULL" in L.lbm_last_error()
+
+
+CHAN_BYTES = 32  # one channel record: nx, ny, nz, tiles per row, first node (8 bytes), first tile, pad
 
 
 def test_workspace_bytes(L):
@@ -97,5 +103,45 @@ def test_workspace_bytes(L):
     tiles = 8 * 8  # one 64-wide tile per x-row
     # node class + link mask + force accumulator and velocity field (4 floats
     # each) + node marks + tile marks (padded to 16) and tile list (4 bytes
-    # each) + list length + reduction partials + sums
-    assert L.lbm_workspace_bytes(C.byref(p)) == n + 4 * n + 8 * n * 4 + n + tiles + 4 * tiles + 4 + 2 * 32 + 32
+    # each) + list length + claim epoch + reduction partials + sums + the
+    # channel record
+    one = n + 4 * n + 8 * n * 4 + n + tiles + 4 * tiles + 4 + 4 + 2 * 32 + 32 + CHAN_BYTES
+    assert L.lbm_workspace_bytes(C.byref(p)) == one
+    dims = (C.c_int32 * 3)(8, 8, 8)
+    assert L.lbm_workspace_bytes_channels(C.byref(p), 1, dims) == one
+
+
+def test_workspace_bytes_channels(L):
+    p = _params()
+    dims = (C.c_int32 * 6)(100, 3, 2, 8, 8, 8)
+    n = 600 + 512
+    tiles = 2 * 3 * 2 + 8 * 8
+    # as for one channel, plus a 2-byte channel id per tile
+    expect = (n + 4 * n + 8 * n * 4 + n + 80 + 4 * tiles + 4 + 4 + 5 * 32 + 32 + 2 * CHAN_BYTES + 2 * tiles)
+    assert L.lbm_workspace_bytes_channels(C.byref(p), 2, dims) == expect
+
+
+@pytest.mark.parametrize("nch,dims,msg", [
+    (0, [8, 8, 8], "nch"), (70000, [8, 8, 8], "nch"), (2, [8, 8, 8, 8, 0, 8], "channel 1 size"),
+    (1, [-1, 8, 8], "channel 0 size"), (2, [1024, 1024, 1024, 8, 8, 8], "too large"),
+])
+def test_init_channels_rejects(L, nch, dims, msg):
+    from paper_1110_0995_amd import _lib
+    p = _params()
+    arr = (C.c_int32 * max(len(dims), 3 * max(nch, 1)))(*dims)
+    ctx = C.c_void_p(1234)
+    rc = L.lbm_init_channels(C.byref(p), nch, arr, C.byref(ctx))
+    assert rc == _lib.LBM_EINVAL and ctx.value is None
+    assert msg in L.lbm_last_error().decode()
+    assert L.lbm_init_channels(C.byref(p), 1, None, C.byref(ctx)) == _lib.LBM_EINVAL
+    assert "dims" in L.lbm_last_error().decode()
+    assert L.lbm_workspace_bytes_channels(C.byref(p), nch, arr) == -1
+
+
+def test_init_channels_checks_params(L):
+    from paper_1110_0995_amd import _lib
+    p = _params(tau=0.4)
+    dims = (C.c_int32 * 3)(8, 8, 8)
+    ctx = C.c_void_p(1234)
+    assert L.lbm_init_channels(C.byref(p), 1, dims, C.byref(ctx)) == _lib.LBM_EINVAL
+    assert "tau" in L.lbm_last_error().decode() and ctx.value is None
