@@ -5,7 +5,9 @@ One "step" is one full coupled step of the hot path: membrane forces, IBM
 interpolation/coupling/spreading/point update, and the fused collide-stream
 of the whole lattice.  The default workload is the throughput channel:
 512x256x128 lattice, 8x4 posts (gaps U{6..14}), 400 cells of 642 vertices,
-tau 0.7, FP32 deviation storage.  Prints ONE JSON line.
+tau 0.7, FP32 deviation storage.  A second leg times the batched form: the
+64-channel gap sweep as one batch against the same channels run one after
+another.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -37,7 +39,7 @@ def bytes_per_node(prec: str) -> int:
 # two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the same
 # counters on a plain copy kernel; see profiles/.  Valid only while the
 # kernel source hashes to "sha".
-MEASURED_TRAFFIC = {"sha": "d5684fde3af68eaa", "bytes_per_launch": 2.644e9}
+MEASURED_TRAFFIC = {"sha": "1c5feabcf9159751", "bytes_per_launch": 2.6443e9}
 KERNEL_SOURCES = ["paper_1110_0995_amd/csrc/lattice_kernels.hpp", "paper_1110_0995_amd/csrc/d3q19.hpp"]
 
 
@@ -103,6 +105,81 @@ def cpu_baseline(s, prec, steps, lbm_mod):
             {"u_rel_l2": err, "max_position_err": perr, "steps": steps})
 
 
+def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool) -> dict:
+    """The 64-channel gap sweep stepped as one batch (one launch per kernel
+    for all channels, graph-captured steps, autotuned launch shape) against
+    the same 64 channels run one after another as plain single-channel
+    contexts with ordinary launches."""
+    import torch
+    from paper_1110_0995_amd import autotune
+    from paper_1110_0995_amd import scenario as S
+    scs = S.gap_sweep()
+    prec = "f32dev"  # FP32 storage in the deviation form (same bytes as plain FP32)
+    cells, chan = S.batch_cells(scs)
+    lat = lbm_mod.Lattice.batch(scs, prec=prec)
+    mesh = lbm_mod.Mesh(lat, cells, chan)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "gap_sweep", "channels": len(scs), "nodes": lat.N, "ib_points": cells.nverts,
+           "cells": cells.ncells, "storage": prec, "lengths": sorted({s.nx for s in scs}), "steps": steps}
+    err = None
+    if cpu:
+        # error of the shortest channel against the oracle after the first
+        # coupled steps (they count as warm-up)
+        import oracle
+        k = min(range(len(scs)), key=lambda i: scs[i].n)
+        s = scs[k]
+        lat.run(4, mesh)
+        _, ug = lat.fields()
+        ug = ug[:, lat.channel(k)].double().cpu().numpy()
+        L = oracle.Lattice.from_scenario(s)
+        M = oracle.Mesh(s.cells)
+        X = s.cells.positions()
+        M.rest_shape(X)
+        f = oracle.run(L, M, L.rest(), X, np.zeros_like(X), nsteps=4)
+        _, uo = oracle.fluid_velocity(L, f)
+        fl = s.solid.reshape(-1) == 0
+        err = {"channel": k, "u_rel_l2": float(np.linalg.norm(ug[:, fl] - uo[:, fl]) / np.linalg.norm(uo[:, fl])),
+               "steps": 4}
+    best = autotune.tune(lat, mesh)
+    g = best["steps_per_graph"]
+    K = max(g, steps - steps % g)
+    lat.run(max(g, warmup - warmup % g), mesh, steps_per_graph=g)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    lat.run(K, mesh, steps_per_graph=g)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / K
+    sums = lat.sums()
+    lat.close()
+    del lat, mesh
+    torch.cuda.empty_cache()
+    # the same channels one after another, plain contexts, ordinary launches
+    runs = []
+    for s in scs:
+        la = lbm_mod.Lattice.from_scenario(s, prec=prec)
+        ma = lbm_mod.Mesh(la, s.cells)
+        la.run(2, ma)
+        runs.append((la, ma))
+    torch.cuda.synchronize()
+    a.record(stream)
+    for la, ma in runs:
+        la.run(K, ma)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = a.elapsed_time(b) / K
+    for la, _ in runs:
+        la.close()
+    N = out["nodes"]
+    out.update(steps=K, ms_per_step=round(ms, 5), mlups=round(N / (ms * 1e-3) / 1e6, 1),
+               sequential_ms_per_step=round(ms_seq, 5), sequential_mlups=round(N / (ms_seq * 1e-3) / 1e6, 1),
+               speedup=round(ms_seq / ms, 3), launch=best, mass=sums[0])
+    if err is not None:
+        out["error_vs_oracle"] = err
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +188,8 @@ def main():
     ap.add_argument("--workload", default="throughput")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=200,
+                    help="steps of the 64-channel gap sweep, batched and sequential (0 skips the leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -197,6 +276,10 @@ def main():
         out["cpu_baseline"] = cb
         out["error_vs_oracle"] = perr
     lat.close()
+    del lat, mesh
+    torch.cuda.empty_cache()
+    if args.batched_steps > 0:
+        out["batched"] = batched_leg(lbm, args.batched_steps, 20, not args.no_cpu_baseline)
     print(json.dumps(out), flush=True)
 
 

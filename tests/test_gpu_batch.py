@@ -189,3 +189,25 @@ def test_gap_sweep_full_size_sampled_channels(lbm):
         v0, v1 = _vert_range(cells, chan, k)
         assert np.array_equal(xb[:, v0:v1], xa), f"channel {k}"
         la.close()
+
+
+def test_autotune_restores_state_and_caches(lbm, tmp_path):
+    from paper_1110_0995_amd import autotune
+    scs = _small_batch(seed=12, nch=3)
+    A, MA, _, _ = _batch(lbm, scs)
+    B, MB, _, _ = _batch(lbm, scs)
+    A.run(6, MA)
+    B.run(6, MB)
+    cache = str(tmp_path / "tune.json")
+    best = autotune.tune(B, MB, steps=4, cache=cache)
+    assert best["collide_waves_per_block"] in autotune.WAVES
+    assert best["list_blocks"] in autotune.LIST_BLOCKS
+    assert best["steps_per_graph"] in autotune.GRAPH_STEPS
+    fa, xa, va = _state(A, MA)
+    fb, xb, vb = _state(B, MB)
+    assert np.array_equal(fa, fb) and np.array_equal(xa, xb) and np.array_equal(va, vb)
+    g = best["steps_per_graph"]
+    A.run(g, MA)
+    B.run(g, MB, steps_per_graph=g)
+    assert np.array_equal(_state(A, MA)[0], _state(B, MB)[0])
+    assert autotune.tune(B, MB, cache=cache) == best  # second call reads the cache
