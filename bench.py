@@ -7,7 +7,8 @@ of the whole lattice.  The default workload is the throughput channel:
 512x256x128 lattice, 8x4 posts (gaps U{6..14}), 400 cells of 642 vertices,
 tau 0.7, FP32 deviation storage.  A second leg times the batched form: the
 64-channel gap sweep as one batch against the same channels run one after
-another.  Prints ONE JSON line.
+another; a third the differentiation form: a checkpointed 300-step run and
+its backward pass against the plain forward run.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -180,6 +181,73 @@ def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool) -> dict:
     return out
 
 
+def adjoint_leg(lbm_mod) -> dict:
+    """The differentiation form on the adjoint workload (128x64x32, 3 cells,
+    300 steps, checkpoints every 20): the plain forward run against the
+    checkpointed forward plus the backward (segment recompute + reverse
+    kernels).  The gradient of the objective along the 16 seeded directions
+    of G is compared with the FP64 oracle's central differences stored by
+    tests/golden/make_adjoint_fd.py."""
+    import torch
+    from paper_1110_0995_amd import adjoint
+    from paper_1110_0995_amd import scenario as S
+    s = S.adjoint_channel()
+    every = s.meta["checkpoint_every"]
+    prec = "f32dev"
+    lat = lbm_mod.Lattice.from_scenario(s, prec=prec)
+    mesh = lbm_mod.Mesh(lat, s.cells)
+    x0 = mesh.x.clone()
+    start = [t.clone() for t in (lat.current_buffer(), mesh.x, mesh.v)]
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def reset():
+        lat.current_buffer().copy_(start[0])
+        mesh.x.copy_(start[1])
+        mesh.v.copy_(start[2])
+
+    lat.run(s.steps, mesh)  # warm-up
+    reset()
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    lat.run(s.steps, mesh)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_plain = ev[0].elapsed_time(ev[1])
+    reset()
+    G = torch.zeros(3, s.n, dtype=lat.rdtype, device="cuda", requires_grad=True)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    fT, xT, vT = adjoint.run_with_grad(G, lat, mesh, s.steps, every)
+    ev[1].record(stream)
+    J = adjoint.objective(lat, mesh, fT, xT, G, x0)
+    ev[2].record(stream)
+    J.backward()
+    ev[3].record(stream)
+    torch.cuda.synchronize()
+    t_fwd = ev[0].elapsed_time(ev[1])
+    t_bwd = ev[2].elapsed_time(ev[3])
+    out = {"workload": "adjoint_channel", "lattice": [s.nx, s.ny, s.nz], "nodes": s.n, "steps": s.steps,
+           "checkpoint_every": every, "ib_points": s.cells.nverts, "storage": prec,
+           "plain_forward_ms": round(t_plain, 3), "checkpointed_forward_ms": round(t_fwd, 3),
+           "backward_ms": round(t_bwd, 3), "backward_over_forward": round(t_bwd / t_plain, 3),
+           "total_over_forward": round((t_fwd + t_bwd) / t_plain, 3),
+           "forward_mlups": round(s.n * s.steps / (t_plain * 1e-3) / 1e6, 1)}
+    gold_path = os.path.join(ROOT, "tests", "golden", "adjoint_fd.json")
+    if os.path.exists(gold_path):
+        with open(gold_path) as fh:
+            gold = json.load(fh)
+        dirs = S.random_directions(s, len(gold["fd"]))
+        g = G.grad.double().cpu().numpy().reshape(3, s.nz, s.ny, s.nx)
+        xa, xb = s.meta["design_x"]
+        ad = np.array([float((g[..., xa:xb] * d).sum()) for d in dirs])
+        fd = np.array(gold["fd"])
+        out["error_vs_oracle"] = {"max_rel_dir_err": float(np.max(np.abs(ad - fd) / np.abs(fd))),
+                                  "directions": len(fd), "J_rel_err": abs(float(J.item()) - gold["J0"]) / abs(gold["J0"])}
+    lat.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,6 +258,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=200,
                     help="steps of the 64-channel gap sweep, batched and sequential (0 skips the leg)")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -280,6 +349,8 @@ def main():
     torch.cuda.empty_cache()
     if args.batched_steps > 0:
         out["batched"] = batched_leg(lbm, args.batched_steps, 20, not args.no_cpu_baseline)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_leg(lbm)
     print(json.dumps(out), flush=True)
 
 

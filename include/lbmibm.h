@@ -209,6 +209,42 @@ int lbm_current(lbm_ctx *c, void **f_cur, int64_t *steps);
 int lbm_store_f64(lbm_ctx *c, double *f64);
 int lbm_load_f64(lbm_ctx *c, const double *f64);
 
+/* Membrane force and its directional derivative (Sec. 2.3 energies,
+ * Sec. 2.3.3 global terms), in FP64 at any positions: f_out = F_el(x)
+ * (may be NULL) and jvp_out = (dF_el/dx) w, with x and w device [3][nverts]
+ * doubles (x as offsets from the anchors, like m->x).  F_el = -grad E, so
+ * the Jacobian is minus the energy Hessian and is symmetric: jvp_out is
+ * also the transposed product the adjoint needs.  Exact to rounding
+ * (forward-mode dual numbers through the energy gradient).  The mesh must
+ * have had ibm_rest_shape. */
+int ibm_force_jvp(lbm_ctx *c, const ibm_mesh *m, const double *x, const double *w, double *f_out, double *jvp_out);
+
+/* One reverse step of the coupled map: the adjoint (transposed derivative)
+ * of the step (f_n, X_n, V_n; G) -> (f_{n+1}, X_{n+1}, V_{n+1}) that
+ * ibm_couple + lbm_step(c, 1) take (Sec. 2.1 LBM equation with forcing, the
+ * four immersed-boundary steps of Sec. 2.2, the membrane forces of Sec.
+ * 2.3, bounce-back of Sec. 2.4), for the differentiation of an objective J
+ * of a run with respect to its inputs.
+ *   f_n       [19*plane_stride] storage type: the populations at step n
+ *             (the layout of f_a / f_b); read only.
+ *   x_n, v_n  [3][nverts] FP64 offsets and real velocities at step n.
+ *   lam_next  [19*plane_stride] real: dJ/df_{n+1}; read only.
+ *   lam       [19*plane_stride] real, written with dJ/df_n (0 at solid nodes);
+ *             must not alias lam_next or f_n.
+ *   lam_x, lam_v  [3][nverts] FP64: on entry dJ/dX_{n+1}, dJ/dV_{n+1}; on
+ *             exit dJ/dX_n, dJ/dV_n (updated in place).
+ *   dgrad     [3][N] real or NULL: dJ/dG of this step is ADDED (G = the
+ *             forcing field of lbm_params, whether or not one was given).
+ * m may be NULL for a run without cells (then the point arguments are
+ * ignored).  The call recomputes the immersed-boundary half of step n from
+ * (f_n, x_n, v_n) in its own scratch (the context's lattice state and the
+ * mesh's x, v, f_el are not touched) and then runs the reverse kernels.
+ * Arithmetic is in the context's real type; the points' adjoints are FP64.
+ * The order of the float additions that spread lambda_u to the lattice is
+ * not fixed, so repeated calls may differ in the last bits. */
+int lbm_adjoint_step(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const double *x_n, const void *v_n,
+                     const void *lam_next, void *lam, double *lam_x, double *lam_v, void *dgrad);
+
 /* Free the context's own buffers (waits for its stream). NULL is a no-op. */
 void lbm_destroy(lbm_ctx *c);
 

@@ -18,7 +18,8 @@ ERRORS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EHIP: "EHIP", LBM_ENON
 # every symbol include/lbmibm.h declares
 EXPORTS = ("lbm_plane_stride", "lbm_workspace_bytes", "lbm_init", "lbm_init_channels",
            "lbm_workspace_bytes_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape", "ibm_couple",
-           "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "lbm_destroy", "lbm_last_error")
+           "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp", "lbm_adjoint_step",
+           "lbm_destroy", "lbm_last_error")
 
 
 class LbmParams(C.Structure):
@@ -75,12 +76,15 @@ def load() -> C.CDLL:
     L.lbm_current.argtypes = [vp, C.POINTER(vp), C.POINTER(C.c_int64)]
     L.lbm_store_f64.argtypes = [vp, vp]
     L.lbm_load_f64.argtypes = [vp, vp]
+    L.ibm_force_jvp.argtypes = [vp, C.POINTER(IbmMesh), vp, vp, vp, vp]
+    L.lbm_adjoint_step.argtypes = [vp, C.POINTER(IbmMesh), vp, vp, vp, vp, vp, vp, vp, vp]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_init", "lbm_init_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape",
-                 "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64"):
+                 "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp",
+                 "lbm_adjoint_step"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -5,8 +5,9 @@
 // k_membrane (one workgroup per cell): the cell's vertex positions are
 //   staged in LDS; the cell's total area and volume (the global constraints
 //   that need every vertex of the cell, Sec. 2.3.3) are reduced first, then
-//   each triangle and each edge/hinge adds its energy gradient to its
-//   vertices with LDS atomics, and the forces are written out once.
+//   each triangle and each edge/hinge stores its scalar force coefficient in
+//   LDS, and each vertex sums its incident elements' gradients in a fixed
+//   order and writes its force once.
 //   Lengths, areas, angles and volumes are evaluated in FP64 from the FP64
 //   positions, so their small departures from the (FP64) rest shape keep
 //   full accuracy in every storage precision.  The same pass marks, with
@@ -17,8 +18,8 @@
 //
 // k_node_velocity (one wave per listed tile): u_ext = (j + F_ext/2)/rho of
 //   the marked nodes only, from their current populations, into an AoS
-//   field (one 16-byte record per node); each node is evaluated once however
-//   many IB points use it.
+//   field (one 16-byte record per node: u_ext and rho); each node is
+//   evaluated once however many IB points use it.
 //
 // k_couple (one thread per IB point): trilinear interpolation of that field
 //   (Sec. 2.2 step 1), coupling force (step 2), and the point update (step
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
         if (x >= ch.nx) continue;
         const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
         if (!a.need[n]) continue;
-        R ux = R(0), uy = R(0), uz = R(0);
+        R ux = R(0), uy = R(0), uz = R(0), rho = R(0);
         if (a.cls[n] != CLS_SOLID) {
             R v[Q];
 #pragma unroll
@@ -377,12 +378,13 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
                 Fy += G[a.N + n];
                 Fz += G[2 * a.N + n];
             }
-            const R ir = R(1) / (DEV ? R(1) + s : s);
+            rho = DEV ? R(1) + s : s;
+            const R ir = R(1) / rho;
             ux = (jx + R(0.5) * Fx) * ir;
             uy = (jy + R(0.5) * Fy) * ir;
             uz = (jz + R(0.5) * Fz) * ir;
         }
-        U[n] = R4{ux, uy, uz, R(0)};
+        U[n] = R4{ux, uy, uz, rho};
     }
 }
 

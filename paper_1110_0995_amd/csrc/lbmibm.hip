@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint_kernels.hpp"
 #include "ibm_kernels.hpp"
 #include "lattice_kernels.hpp"
 
@@ -130,6 +131,14 @@ struct lbm_ctx {
     // launch shape
     int cs_waves = 4;     // tiles (waves) per collide-stream workgroup
     int list_blocks = 0;  // workgroups of the tile-list kernels (0: by lattice size)
+    // adjoint work buffers, allocated by the first lbm_adjoint_step
+    void *lamF = nullptr;  // [N] x 4 real: lambda of the node force at stencil nodes
+    void *lamU = nullptr;  // [N] x 4 real: lambda of u_ext at stencil nodes (kept zero between calls)
+    int64_t adj_nv = 0;    // IB points the scratch below holds
+    double *xs = nullptr;  // [3][nv] positions advanced by the recomputed forward step
+    void *vs = nullptr;    // [3][nv] real velocities, likewise
+    void *fels = nullptr;  // [3][nv] real elastic forces, likewise
+    double *hv = nullptr;  // [3][nv] membrane Jacobian times direction
     // captured coupled steps
     hipStream_t cap_s = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -226,7 +235,8 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     drop_graph(c);
     if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm,  c->ufield,   c->need, c->tneed, c->tlist,
-                    c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums};
+                    c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums,
+                    c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -644,11 +654,11 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
 }
 
 template <class S, class R, bool DEV>
-static void launch_node_velocity(lbm_ctx *c) {
+static void launch_node_velocity(lbm_ctx *c, const void *f) {
     k_compact<<<(int)cdiv(c->ntiles, kCompactThreads * kCompactPerThread), kCompactThreads, 0, c->s>>>(
         c->tneed, c->ntiles, c->tlist, c->tcount);
     NodeVelArgs a{};
-    a.f = cur_f(c);
+    a.f = f;
     a.stride = c->stride;
     a.cls = c->cls;
     a.gfield = c->p.gfield;
@@ -709,25 +719,27 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     k_gather_nodes<R><<<waves_grid(c), 256, 0, c->s>>>(g);
 }
 
-static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m) {
+// The immersed-boundary half of a coupled step with the populations f.
+static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f) {
     switch (c->p.prec) {
         case LBM_F64:
             launch_membrane<double>(c, m, false);
-            launch_node_velocity<double, double, false>(c);
+            launch_node_velocity<double, double, false>(c, f);
             launch_couple<double>(c, m);
             break;
         case LBM_F32:
             launch_membrane<float>(c, m, false);
-            launch_node_velocity<float, float, false>(c);
+            launch_node_velocity<float, float, false>(c, f);
             launch_couple<float>(c, m);
             break;
         default:
             launch_membrane<float>(c, m, false);
-            launch_node_velocity<float, float, true>(c);
+            launch_node_velocity<float, float, true>(c, f);
             launch_couple<float>(c, m);
             break;
     }
 }
+static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m) { enqueue_couple(c, m, cur_f(c)); }
 
 LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
@@ -798,6 +810,205 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
     for (int32_t k = 0; k < left; k++) {
         if (m) enqueue_couple(c, m);
         enqueue_steps(c, 1);
+    }
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint
+
+static int ensure_adjoint(lbm_ctx *c, const ibm_mesh *m) {
+    if (!c->lamF) {
+        if (hipMalloc(&c->lamF, 4 * c->N * c->rsize) != hipSuccess ||
+            hipMalloc(&c->lamU, 4 * c->N * c->rsize) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "allocating the adjoint node buffers failed");
+        }
+        HIPCHK(hipMemsetAsync(c->lamF, 0, 4 * c->N * c->rsize, c->s));
+        HIPCHK(hipMemsetAsync(c->lamU, 0, 4 * c->N * c->rsize, c->s));
+    }
+    if (m && m->nverts > c->adj_nv) {
+        for (void *b : {(void *)c->xs, c->vs, c->fels, (void *)c->hv})
+            if (b) HIPCHK(hipFree(b));
+        c->xs = nullptr, c->vs = nullptr, c->fels = nullptr, c->hv = nullptr;
+        c->adj_nv = 0;
+        const size_t nv3 = 3 * (size_t)m->nverts;
+        if (hipMalloc(&c->xs, nv3 * 8) != hipSuccess || hipMalloc(&c->vs, nv3 * c->rsize) != hipSuccess ||
+            hipMalloc(&c->fels, nv3 * c->rsize) != hipSuccess || hipMalloc(&c->hv, nv3 * 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "allocating the adjoint point buffers failed");
+        }
+        c->adj_nv = m->nverts;
+    }
+    return LBM_OK;
+}
+
+static int check_jvp_mesh(const lbm_ctx *c, const ibm_mesh *m) {
+    if (int rc = check_mesh_ptrs(c, m)) return rc;
+    if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
+    if (adj_membrane_lds_bytes(m->max_cell_verts) > kMaxLds)
+        return fail(LBM_EINVAL, "a cell with %d vertices is too large for the membrane Jacobian pass",
+                    m->max_cell_verts);
+    return LBM_OK;
+}
+
+template <class R>
+static void launch_jvp(lbm_ctx *c, const ibm_mesh *m, const double *x, const double *w, const double *lam_x,
+                       const double *lam_v, double *f_out, double *jvp_out) {
+    JvpArgs a{};
+    a.vert_off = m->vert_off;
+    a.tri_off = m->tri_off;
+    a.edge_off = m->edge_off;
+    a.tri = m->tri;
+    a.hinge = m->hinge;
+    a.vtri_off = m->vtri_off;
+    a.vtri = m->vtri;
+    a.vedge_off = m->vedge_off;
+    a.vedge = m->vedge;
+    a.x = x;
+    a.w = w;
+    a.lam_x = lam_x;
+    a.lam_v = lam_v;
+    a.dt = m->dt;
+    a.mass = m->mass;
+    a.moduli = m->moduli;
+    a.l0 = m->l0;
+    a.a0 = m->a0;
+    a.th0 = m->th0;
+    a.a0c = m->a0c;
+    a.v0c = m->v0c;
+    a.avert = m->avert;
+    a.ncells = m->ncells;
+    a.nverts = m->nverts;
+    a.ntris = m->ntris;
+    a.nedges = m->nedges;
+    a.maxv = m->max_cell_verts;
+    a.f_out = f_out;
+    a.jvp_out = jvp_out;
+    k_adj_membrane<R><<<m->ncells, kMembThreads, adj_membrane_lds_bytes(m->max_cell_verts), c->s>>>(a);
+}
+
+LBM_API int ibm_force_jvp(lbm_ctx *c, const ibm_mesh *m, const double *x, const double *w, double *f_out,
+                          double *jvp_out) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (int rc = check_jvp_mesh(c, m)) return rc;
+    if (!x || !w || !jvp_out) return fail(LBM_EINVAL, "x, w and jvp_out must be non-NULL");
+    if (((uintptr_t)x | (uintptr_t)w | (uintptr_t)jvp_out | (uintptr_t)f_out) % 8)
+        return fail(LBM_EINVAL, "x, w, f_out and jvp_out must be 8-byte aligned");
+    if (c->p.prec == LBM_F64)
+        launch_jvp<double>(c, m, x, w, nullptr, nullptr, f_out, jvp_out);
+    else
+        launch_jvp<float>(c, m, x, w, nullptr, nullptr, f_out, jvp_out);
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+template <class S, class R, bool DEV>
+static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const double *x_n, const void *v_n,
+                           const void *lam_next, void *lam, double *lam_x, double *lam_v, void *dgrad) {
+    if (m) {
+        // recompute the forward immersed-boundary half of step n: stencil
+        // marks, u_ext and rho at the marked nodes, the spread force
+        ibm_mesh mm = *m;
+        mm.x = c->xs;
+        mm.v = c->vs;
+        mm.f_el = c->fels;
+        (void)hipMemcpyAsync(c->xs, x_n, 3 * (size_t)m->nverts * 8, hipMemcpyDeviceToDevice, c->s);
+        (void)hipMemcpyAsync(c->vs, v_n, 3 * (size_t)m->nverts * sizeof(R), hipMemcpyDeviceToDevice, c->s);
+        enqueue_couple(c, &mm, f_n);
+    }
+    AdjStepArgs a{};
+    a.f = f_n;
+    a.lam_next = lam_next;
+    a.lam = lam;
+    a.stride = c->stride;
+    a.cls = c->cls;
+    a.links = c->links;
+    a.fibm = c->fibm;
+    a.need = c->need;
+    a.tneed = c->tneed;
+    a.lamF = c->lamF;
+    a.dgrad = dgrad;
+    a.gfield = c->p.gfield;
+    a.chans = c->chans;
+    a.tile_chan = c->tile_chan;
+    a.ntiles = c->ntiles;
+    a.N = c->N;
+    for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
+    a.omega = 1.0 / c->p.tau;
+    a.kf = 1.0 - 0.5 / c->p.tau;
+    const int nb = (int)cdiv(c->ntiles, 4);
+    if (c->p.gfield)
+        k_adj_collide_stream<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
+    else
+        k_adj_collide_stream<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
+    if (!m) return;
+    launch_jvp<R>(c, m, x_n, nullptr, lam_x, lam_v, nullptr, c->hv);
+    AdjPointArgs p{};
+    p.ufield = c->ufield;
+    p.lamF = c->lamF;
+    p.lamU = c->lamU;
+    p.chans = c->chans;
+    p.cell_chan = m->cell_chan;
+    p.vert_off = m->vert_off;
+    p.anchor = m->anchor;
+    p.x = x_n;
+    p.v = v_n;
+    p.hv = c->hv;
+    p.lam_x = lam_x;
+    p.lam_v = lam_v;
+    p.avert = m->avert;
+    p.ncells = m->ncells;
+    p.nverts = m->nverts;
+    p.xi = m->xi;
+    p.mass = m->mass;
+    p.dt = m->dt;
+    dim3 grid((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells);
+    k_adj_points<R><<<grid, 128, 0, c->s>>>(p);
+    AdjNodeArgs q{};
+    q.tlist = c->tlist;
+    q.tcount = c->tcount;
+    q.need = c->need;
+    q.tneed = c->tneed;
+    q.ufield = c->ufield;
+    q.lamU = c->lamU;
+    q.lam = lam;
+    q.dgrad = dgrad;
+    q.cls = c->cls;
+    q.chans = c->chans;
+    q.tile_chan = c->tile_chan;
+    q.stride = c->stride;
+    q.N = c->N;
+    k_adj_nodes<R><<<waves_grid(c), 256, 0, c->s>>>(q);
+}
+
+LBM_API int lbm_adjoint_step(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const double *x_n, const void *v_n,
+                             const void *lam_next, void *lam, double *lam_x, double *lam_v, void *dgrad) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (!f_n || !lam_next || !lam) return fail(LBM_EINVAL, "f_n, lam_next and lam must be non-NULL");
+    if (lam == lam_next || lam == f_n) return fail(LBM_EINVAL, "lam must not alias lam_next or f_n");
+    const uintptr_t es = c->rsize;
+    if (((uintptr_t)f_n | (uintptr_t)lam_next | (uintptr_t)lam | (uintptr_t)dgrad) % es)
+        return fail(LBM_EINVAL, "f_n, lam_next, lam and dgrad must be aligned to their element size");
+    if (m) {
+        if (int rc = check_jvp_mesh(c, m)) return rc;
+        if (!x_n || !v_n || !lam_x || !lam_v) return fail(LBM_EINVAL, "x_n, v_n, lam_x and lam_v must be non-NULL");
+        if (((uintptr_t)x_n | (uintptr_t)lam_x | (uintptr_t)lam_v) % 8 || (uintptr_t)v_n % es)
+            return fail(LBM_EINVAL, "point arrays misaligned");
+        if (!c->owner) return fail(LBM_ESTATE, "call ibm_rest_shape first");
+    }
+    if (int rc = ensure_adjoint(c, m)) return rc;
+    switch (c->p.prec) {
+        case LBM_F64:
+            launch_adjoint<double, double, false>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
+            break;
+        case LBM_F32:
+            launch_adjoint<float, float, false>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
+            break;
+        default:
+            launch_adjoint<float, float, true>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
+            break;
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;

@@ -126,6 +126,26 @@ class Lattice:
         buf = self.f_a if p.value == self.f_a.data_ptr() else self.f_b
         return buf.view(19, self.stride)[:, :self.N]
 
+    def current_buffer(self) -> torch.Tensor:
+        """The whole state buffer ([19 * plane_stride], storage type) that
+        holds the current populations."""
+        p = C.c_void_p()
+        _lib.check(self.lib.lbm_current(self.ctx, C.byref(p), None))
+        return self.f_a if p.value == self.f_a.data_ptr() else self.f_b
+
+    def adjoint_step(self, mesh: Optional["Mesh"], f_n: torch.Tensor, x_n: Optional[torch.Tensor],
+                     v_n: Optional[torch.Tensor], lam_next: torch.Tensor, lam: torch.Tensor,
+                     lam_x: Optional[torch.Tensor], lam_v: Optional[torch.Tensor],
+                     dgrad: Optional[torch.Tensor] = None) -> None:
+        """One reverse step (lbm_adjoint_step): lam <- dJ/df_n from
+        lam_next = dJ/df_{n+1}; lam_x, lam_v updated in place; dJ/dG of the
+        step added to dgrad."""
+        for t, dt in ((f_n, self.rdtype), (lam_next, self.rdtype), (lam, self.rdtype)):
+            assert t.dtype == dt and t.is_contiguous() and t.numel() >= 19 * self.stride
+        _lib.check(self.lib.lbm_adjoint_step(
+            self.ctx, None if mesh is None else C.byref(mesh.s), _ptr(f_n), _ptr(x_n), _ptr(v_n), _ptr(lam_next),
+            _ptr(lam), _ptr(lam_x), _ptr(lam_v), _ptr(dgrad)))
+
     def steps_taken(self) -> int:
         st = C.c_int64()
         _lib.check(self.lib.lbm_current(self.ctx, None, C.byref(st)))
@@ -191,6 +211,15 @@ class Mesh:
                               float(cells.dt), 0, 0, 0, 0)
         _lib.check(lat.lib.ibm_rest_shape(lat.ctx, C.byref(self.s)))
         lat.meshes.append(self)
+
+    def force_jvp(self, x: torch.Tensor, w: torch.Tensor):
+        """(F_el(x), (dF_el/dx) w) in FP64 for offsets x and direction w,
+        both [3, nverts] float64 device tensors."""
+        f = torch.empty_like(x)
+        jvp = torch.empty_like(x)
+        _lib.check(self.lat.lib.ibm_force_jvp(self.lat.ctx, C.byref(self.s), _ptr(x.contiguous()),
+                                              _ptr(w.contiguous()), _ptr(f), _ptr(jvp)))
+        return f, jvp
 
     def positions(self) -> np.ndarray:
         """Absolute positions (float64 [nverts, 3]) = anchor + offset."""
