@@ -206,31 +206,37 @@ def adjoint_leg(lbm_mod) -> dict:
         mesh.x.copy_(start[1])
         mesh.v.copy_(start[2])
 
-    lat.run(s.steps, mesh)  # warm-up
+    spg = every - every % 2  # the plain run takes graphs of the same length as the checkpointed one
+    lat.run(s.steps, mesh, steps_per_graph=spg)  # warm-up and capture
     reset()
     torch.cuda.synchronize()
     ev[0].record(stream)
-    lat.run(s.steps, mesh)
+    lat.run(s.steps, mesh, steps_per_graph=spg)
     ev[1].record(stream)
     torch.cuda.synchronize()
     t_plain = ev[0].elapsed_time(ev[1])
-    reset()
-    G = torch.zeros(3, s.n, dtype=lat.rdtype, device="cuda", requires_grad=True)
-    torch.cuda.synchronize()
-    ev[0].record(stream)
-    fT, xT, vT = adjoint.run_with_grad(G, lat, mesh, s.steps, every)
-    ev[1].record(stream)
-    J = adjoint.objective(lat, mesh, fT, xT, G, x0)
-    ev[2].record(stream)
-    J.backward()
-    ev[3].record(stream)
-    torch.cuda.synchronize()
-    t_fwd = ev[0].elapsed_time(ev[1])
-    t_bwd = ev[2].elapsed_time(ev[3])
+    t_first = None
+    for rep in range(2):  # the first pass captures the graphs; the second is timed
+        reset()
+        G = torch.zeros(3, s.n, dtype=lat.rdtype, device="cuda", requires_grad=True)
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        fT, xT, vT = adjoint.run_with_grad(G, lat, mesh, s.steps, every)
+        ev[1].record(stream)
+        J = adjoint.objective(lat, mesh, fT, xT, G, x0)
+        ev[2].record(stream)
+        J.backward()
+        ev[3].record(stream)
+        torch.cuda.synchronize()
+        t_fwd = ev[0].elapsed_time(ev[1])
+        t_bwd = ev[2].elapsed_time(ev[3])
+        if rep == 0:
+            t_first = t_fwd + t_bwd
     out = {"workload": "adjoint_channel", "lattice": [s.nx, s.ny, s.nz], "nodes": s.n, "steps": s.steps,
            "checkpoint_every": every, "ib_points": s.cells.nverts, "storage": prec,
            "plain_forward_ms": round(t_plain, 3), "checkpointed_forward_ms": round(t_fwd, 3),
            "backward_ms": round(t_bwd, 3), "backward_over_forward": round(t_bwd / t_plain, 3),
+           "first_pass_ms_with_graph_capture": round(t_first, 3),
            "total_over_forward": round((t_fwd + t_bwd) / t_plain, 3),
            "forward_mlups": round(s.n * s.steps / (t_plain * 1e-3) / 1e6, 1)}
     gold_path = os.path.join(ROOT, "tests", "golden", "adjoint_fd.json")

@@ -245,6 +245,29 @@ int ibm_force_jvp(lbm_ctx *c, const ibm_mesh *m, const double *x, const double *
 int lbm_adjoint_step(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const double *x_n, const void *v_n,
                      const void *lam_next, void *lam, double *lam_x, double *lam_v, void *dgrad);
 
+/* nsteps coupled steps (as lbm_run) that also record the state at the start
+ * of every step, for a later reverse sweep: f_rec [nsteps][19*plane_stride]
+ * storage type (16-byte aligned), x_rec [nsteps][3][nverts] FP64 offsets,
+ * v_rec [nsteps][3][nverts] real (ignored when m is NULL).  Step k reads its
+ * populations from record k and writes record k+1 (the last step writes the
+ * context's current state buffer, so lbm_current does not change), so
+ * recording costs one copy of the state per call, not per step.  Only fluid
+ * nodes' entries of records 1.. are written.  use_graph != 0 captures the
+ * whole call into a HIP graph (reused while the arguments, the mesh and the
+ * state-buffer parity are the same) and replays it. */
+int lbm_run_record(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, void *f_rec, double *x_rec, void *v_rec,
+                   int32_t use_graph);
+
+/* Reverse sweep over steps recorded by lbm_run_record: lbm_adjoint_step for
+ * k = nsteps-1 down to 0.  lam_a [19*plane_stride] real holds dJ/df at the
+ * end of the recorded steps on entry and dJ/df at their start on exit; lam_b
+ * is scratch of the same size; lam_x, lam_v (FP64 [3][nverts]) are updated
+ * in place; dJ/dG of every step is added to dgrad ([3][N] real, or NULL).
+ * use_graph as for lbm_run_record. */
+int lbm_adjoint_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, const void *f_rec, const double *x_rec,
+                    const void *v_rec, void *lam_a, void *lam_b, double *lam_x, double *lam_v, void *dgrad,
+                    int32_t use_graph);
+
 /* Free the context's own buffers (waits for its stream). NULL is a no-op. */
 void lbm_destroy(lbm_ctx *c);
 

@@ -19,7 +19,7 @@ ERRORS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EHIP: "EHIP", LBM_ENON
 EXPORTS = ("lbm_plane_stride", "lbm_workspace_bytes", "lbm_init", "lbm_init_channels",
            "lbm_workspace_bytes_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape", "ibm_couple",
            "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp", "lbm_adjoint_step",
-           "lbm_destroy", "lbm_last_error")
+           "lbm_run_record", "lbm_adjoint_run", "lbm_destroy", "lbm_last_error")
 
 
 class LbmParams(C.Structure):
@@ -78,13 +78,15 @@ def load() -> C.CDLL:
     L.lbm_load_f64.argtypes = [vp, vp]
     L.ibm_force_jvp.argtypes = [vp, C.POINTER(IbmMesh), vp, vp, vp, vp]
     L.lbm_adjoint_step.argtypes = [vp, C.POINTER(IbmMesh), vp, vp, vp, vp, vp, vp, vp, vp]
+    L.lbm_run_record.argtypes = [vp, C.POINTER(IbmMesh), C.c_int32, vp, vp, vp, C.c_int32]
+    L.lbm_adjoint_run.argtypes = [vp, C.POINTER(IbmMesh), C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_init", "lbm_init_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape",
                  "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp",
-                 "lbm_adjoint_step"):
+                 "lbm_adjoint_step", "lbm_run_record", "lbm_adjoint_run"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

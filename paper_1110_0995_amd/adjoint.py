@@ -7,7 +7,9 @@ populations, IB-point offsets and velocities.  Its backward runs the
 hand-written reverse kernels (lbm_adjoint_step) from the last step to the
 first.  Memory is bounded by checkpointing: the forward keeps the state
 every ``every`` steps; the backward recomputes one segment at a time from its
-checkpoint, keeping that segment's states, and walks it in reverse.
+checkpoint, recording that segment's states (lbm_run_record), and walks it in
+reverse (lbm_adjoint_run); both are captured HIP graphs replayed for every
+segment of the same length.
 
 ``objective`` is the scalar studied on the adjoint workload: the x-momentum
 flux through the outlet plane x = nx - 1 at the final step plus the squared
@@ -48,7 +50,8 @@ class CoupledRun(torch.autograd.Function):
         ckpts = []
         for t0 in range(0, nsteps, every):
             ckpts.append(_snapshot(lat, mesh))
-            lat.run(min(every, nsteps - t0), mesh)
+            n = min(every, nsteps - t0)
+            lat.run(n, mesh, steps_per_graph=n - n % 2)
         ctx.lat, ctx.mesh, ctx.nsteps, ctx.every = lat, mesh, nsteps, every
         ctx.ckpts = ckpts
         ctx.final = _snapshot(lat, mesh)
@@ -62,31 +65,42 @@ class CoupledRun(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gf, gx, gv):
         lat, mesh = ctx.lat, ctx.mesh
-        N, st, R = lat.N, lat.stride, lat.rdtype
-        lam = torch.zeros(19 * st, dtype=R, device=lat.device)
+        N, st = lat.N, lat.stride
+        # work buffers live on the lattice, so that the captured graphs of
+        # the recording run and the reverse sweep (keyed by their buffer
+        # addresses) are reused by later backward passes
+        B = _buffers(lat, mesh, min(ctx.every, ctx.nsteps))
+        lam, lam2, lx, lv, dG, rec = B["lam"], B["lam2"], B["lx"], B["lv"], B["dG"], B["rec"]
+        lam.zero_()
         if gf is not None:
             lam.view(19, st)[:, :N].copy_(gf)
-        lam2 = torch.zeros_like(lam)
-        lx = lv = None
+        dG.zero_()
         if mesh is not None:
-            nv = mesh.cells.nverts
-            lx = gx.double().contiguous().clone() if gx is not None else torch.zeros(3, nv, dtype=torch.float64,
-                                                                                    device=lat.device)
-            lv = gv.double().contiguous().clone() if gv is not None else torch.zeros_like(lx)
-        dG = torch.zeros(3, N, dtype=R, device=lat.device)
+            lx.copy_(gx) if gx is not None else lx.zero_()
+            lv.copy_(gv) if gv is not None else lv.zero_()
         for seg in range(len(ctx.ckpts) - 1, -1, -1):
             _restore(lat, mesh, ctx.ckpts[seg])
             n = min(ctx.every, ctx.nsteps - seg * ctx.every)
-            states = []
-            for _ in range(n):
-                states.append(_snapshot(lat, mesh))
-                lat.run(1, mesh)
-            for f_n, x_n, v_n in reversed(states):
-                lat.adjoint_step(mesh, f_n, x_n, v_n, lam, lam2, lx, lv, dG)
-                lam, lam2 = lam2, lam
-            del states
+            lat.run_record(n, mesh, rec)
+            lat.adjoint_run(n, mesh, rec, lam, lam2, lx, lv, dG)
         _restore(lat, mesh, ctx.final)
-        return dG.reshape(ctx.G_shape).to(ctx.G_dtype), None, None, None, None
+        return dG.clone().reshape(ctx.G_shape).to(ctx.G_dtype), None, None, None, None
+
+
+def _buffers(lat, mesh, every: int) -> dict:
+    key = (every, id(mesh))
+    cache = lat.__dict__.setdefault("_adjoint_buffers", {})
+    if key not in cache:
+        R, dev = lat.rdtype, lat.device
+        B = {"lam": torch.zeros(19 * lat.stride, dtype=R, device=dev), "dG": torch.zeros(3, lat.N, dtype=R, device=dev),
+             "rec": lat.record_buffers(every, mesh), "lx": None, "lv": None}
+        B["lam2"] = torch.zeros_like(B["lam"])
+        if mesh is not None:
+            B["lx"] = torch.zeros(3, mesh.cells.nverts, dtype=torch.float64, device=dev)
+            B["lv"] = torch.zeros_like(B["lx"])
+        cache.clear()  # one set at a time
+        cache[key] = B
+    return cache[key]
 
 
 def run_with_grad(G: torch.Tensor, lat, mesh, nsteps: int, every: int = 20):

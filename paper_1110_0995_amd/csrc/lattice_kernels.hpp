@@ -269,6 +269,13 @@ __global__ __launch_bounds__(256) void k_final_sum(const double *__restrict__ pa
         for (int k = 0; k < 4; k++) out[k] = acc[k];
 }
 
+// Plain device copy (snapshots taken inside captured graphs, where a
+// memcpy node is avoided).
+template <class T>
+__global__ __launch_bounds__(256) void k_copy(const T *__restrict__ src, T *__restrict__ dst, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
+}
+
 template <class S, bool DEV>
 __global__ void k_store_f64(const S *__restrict__ f, int64_t stride, int64_t N, double *__restrict__ out) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

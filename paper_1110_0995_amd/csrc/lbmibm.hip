@@ -139,18 +139,22 @@ struct lbm_ctx {
     void *vs = nullptr;    // [3][nv] real velocities, likewise
     void *fels = nullptr;  // [3][nv] real elastic forces, likewise
     double *hv = nullptr;  // [3][nv] membrane Jacobian times direction
-    // captured coupled steps
+    // captured graphs: plain coupled steps, recorded steps, reverse sweep
     hipStream_t cap_s = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int gsteps = 0, gcur = 0;
-    uint64_t gkey = 0;
+    hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
+    uint64_t gk[3] = {0, 0, 0};
 };
+
+enum { G_RUN = 0, G_REC = 1, G_ADJ = 2 };
 
 #define LBM_API extern "C" __attribute__((visibility("default")))
 
 static void drop_graph(lbm_ctx *c) {
-    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
-    c->gexec = nullptr;
+    for (int k = 0; k < 3; k++) {
+        if (c->gx[k]) (void)hipGraphExecDestroy(c->gx[k]);
+        c->gx[k] = nullptr;
+        c->gk[k] = 0;
+    }
 }
 
 LBM_API const char *lbm_last_error(void) { return g_err.c_str(); }
@@ -370,7 +374,23 @@ static void launch_step(lbm_ctx *c, const StepArgs &a) {
     }
 }
 
-static void enqueue_steps(lbm_ctx *c, int32_t nsteps) {
+static void enqueue_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes) {
+    const uintptr_t al = (uintptr_t)dst | (uintptr_t)src | (uintptr_t)bytes;
+    auto go = [&](auto tag) {
+        using T = decltype(tag);
+        const int64_t n = (int64_t)(bytes / sizeof(T));
+        const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n, 256), 16384));
+        k_copy<T><<<nb, 256, 0, c->s>>>(static_cast<const T *>(src), static_cast<T *>(dst), n);
+    };
+    if (al % 16 == 0)
+        go(uint4{});
+    else if (al % 8 == 0)
+        go(uint2{});
+    else
+        go(uint32_t{});
+}
+
+static StepArgs step_args(const lbm_ctx *c) {
     StepArgs a{};
     a.stride = c->stride;
     a.cls = c->cls;
@@ -386,14 +406,24 @@ static void enqueue_steps(lbm_ctx *c, int32_t nsteps) {
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
     a.omega = 1.0 / c->p.tau;
     a.kf = 1.0 - 0.5 / c->p.tau;
+    return a;
+}
+
+// One collide-stream pass from fa into fb (the context's parity is untouched).
+static void enqueue_step_into(lbm_ctx *c, const void *fa, void *fb) {
+    StepArgs a = step_args(c);
+    a.fa = fa;
+    a.fb = fb;
+    switch (c->p.prec) {
+        case LBM_F64: launch_step<double, double, false>(c, a); break;
+        case LBM_F32: launch_step<float, float, false>(c, a); break;
+        default: launch_step<float, float, true>(c, a); break;
+    }
+}
+
+static void enqueue_steps(lbm_ctx *c, int32_t nsteps) {
     for (int s = 0; s < nsteps; s++) {
-        a.fa = cur_f(c);
-        a.fb = nxt_f(c);
-        switch (c->p.prec) {
-            case LBM_F64: launch_step<double, double, false>(c, a); break;
-            case LBM_F32: launch_step<float, float, false>(c, a); break;
-            default: launch_step<float, float, true>(c, a); break;
-        }
+        enqueue_step_into(c, cur_f(c), nxt_f(c));
         c->cur ^= 1;
         c->steps++;
     }
@@ -750,11 +780,16 @@ LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
     return LBM_OK;
 }
 
-// Capture steps_per_graph coupled steps into c->gexec.  The capture runs on
-// a private stream so that nothing else the process enqueues is recorded;
-// the kernels of a coupled step contain no memset or copy nodes.
-static int capture(lbm_ctx *c, const ibm_mesh *m, int32_t steps_per_graph) {
-    drop_graph(c);
+// Capture what enqueue() launches into graph slot `slot` unless the slot
+// already holds a graph with this key.  The capture runs on a private stream
+// so that nothing else the process enqueues is recorded; nothing captured is
+// a memset.  The context's state-buffer parity and step count are restored
+// afterwards: the caller applies the graph's effect on them at launch.
+template <class F>
+static int capture_slot(lbm_ctx *c, int slot, uint64_t key, F &&enqueue) {
+    if (c->gx[slot] && c->gk[slot] == key) return LBM_OK;
+    if (c->gx[slot]) HIPCHK(hipGraphExecDestroy(c->gx[slot]));
+    c->gx[slot] = nullptr;
     if (!c->cap_s) HIPCHK(hipStreamCreate(&c->cap_s));
     const hipStream_t user = c->s;
     const int cur0 = c->cur;
@@ -763,29 +798,24 @@ static int capture(lbm_ctx *c, const ibm_mesh *m, int32_t steps_per_graph) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(c->s, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-        for (int k = 0; k < steps_per_graph; k++) {
-            if (m) enqueue_couple(c, m);
-            enqueue_steps(c, 1);
-        }
+        enqueue();
         e = hipStreamEndCapture(c->s, &g);
     }
     c->s = user;
-    c->cur = cur0;  // an even number of swaps leaves the state where it was
+    c->cur = cur0;
     c->steps = steps0;
     if (e != hipSuccess) {
         (void)hipGetLastError();
-        return fail(LBM_EHIP, "capturing the coupled steps failed: %s", hipGetErrorString(e));
+        return fail(LBM_EHIP, "capturing a graph failed: %s", hipGetErrorString(e));
     }
-    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->gx[slot], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->gexec = nullptr;
+        c->gx[slot] = nullptr;
         (void)hipGetLastError();
-        return fail(LBM_EHIP, "instantiating the coupled-step graph failed: %s", hipGetErrorString(e));
+        return fail(LBM_EHIP, "instantiating a graph failed: %s", hipGetErrorString(e));
     }
-    c->gsteps = steps_per_graph;
-    c->gcur = c->cur;
-    c->gkey = mesh_launch_key(m);
+    c->gk[slot] = key;
     return LBM_OK;
 }
 
@@ -800,11 +830,21 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
     }
     int32_t left = nsteps;
     if (steps_per_graph > 0 && nsteps >= steps_per_graph) {
-        if (!c->gexec || c->gsteps != steps_per_graph || c->gcur != c->cur || c->gkey != mesh_launch_key(m))
-            if (int rc = capture(c, m, steps_per_graph)) return rc;
+        Fnv key;
+        key.mix(G_RUN);
+        key.mix((uint64_t)steps_per_graph);
+        key.mix((uint64_t)c->cur);
+        key.mix(mesh_launch_key(m));
+        if (int rc = capture_slot(c, G_RUN, key.h | 1ull, [&] {
+                for (int k = 0; k < steps_per_graph; k++) {
+                    if (m) enqueue_couple(c, m);
+                    enqueue_steps(c, 1);
+                }
+            }))
+            return rc;
         for (; left >= steps_per_graph; left -= steps_per_graph) {
-            HIPCHK(hipGraphLaunch(c->gexec, c->s));
-            c->steps += steps_per_graph;
+            HIPCHK(hipGraphLaunch(c->gx[G_RUN], c->s));
+            c->steps += steps_per_graph;  // an even number of swaps: the parity is unchanged
         }
     }
     for (int32_t k = 0; k < left; k++) {
@@ -914,8 +954,8 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
         mm.x = c->xs;
         mm.v = c->vs;
         mm.f_el = c->fels;
-        (void)hipMemcpyAsync(c->xs, x_n, 3 * (size_t)m->nverts * 8, hipMemcpyDeviceToDevice, c->s);
-        (void)hipMemcpyAsync(c->vs, v_n, 3 * (size_t)m->nverts * sizeof(R), hipMemcpyDeviceToDevice, c->s);
+        enqueue_copy(c, c->xs, x_n, 3 * (size_t)m->nverts * 8);
+        enqueue_copy(c, c->vs, v_n, 3 * (size_t)m->nverts * sizeof(R));
         enqueue_couple(c, &mm, f_n);
     }
     AdjStepArgs a{};
@@ -983,6 +1023,21 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     k_adj_nodes<R><<<waves_grid(c), 256, 0, c->s>>>(q);
 }
 
+static void enqueue_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const double *x_n, const void *v_n,
+                            const void *lam_next, void *lam, double *lam_x, double *lam_v, void *dgrad) {
+    switch (c->p.prec) {
+        case LBM_F64:
+            launch_adjoint<double, double, false>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
+            break;
+        case LBM_F32:
+            launch_adjoint<float, float, false>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
+            break;
+        default:
+            launch_adjoint<float, float, true>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
+            break;
+    }
+}
+
 LBM_API int lbm_adjoint_step(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const double *x_n, const void *v_n,
                              const void *lam_next, void *lam, double *lam_x, double *lam_v, void *dgrad) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
@@ -999,16 +1054,101 @@ LBM_API int lbm_adjoint_step(lbm_ctx *c, const ibm_mesh *m, const void *f_n, con
         if (!c->owner) return fail(LBM_ESTATE, "call ibm_rest_shape first");
     }
     if (int rc = ensure_adjoint(c, m)) return rc;
-    switch (c->p.prec) {
-        case LBM_F64:
-            launch_adjoint<double, double, false>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
-            break;
-        case LBM_F32:
-            launch_adjoint<float, float, false>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
-            break;
-        default:
-            launch_adjoint<float, float, true>(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
-            break;
+    enqueue_adjoint(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+// Checks shared by the recording run and the reverse sweep.
+static int check_record(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, const void *f_rec, const double *x_rec,
+                        const void *v_rec) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (nsteps > 0 && !f_rec) return fail(LBM_EINVAL, "f_rec is NULL");
+    if ((uintptr_t)f_rec % 16) return fail(LBM_EINVAL, "f_rec must be 16-byte aligned");
+    if (m) {
+        if (int rc = check_jvp_mesh(c, m)) return rc;
+        if (nsteps > 0 && (!x_rec || !v_rec)) return fail(LBM_EINVAL, "x_rec and v_rec must be non-NULL");
+        if ((uintptr_t)x_rec % 8 || (uintptr_t)v_rec % c->rsize) return fail(LBM_EINVAL, "x_rec/v_rec misaligned");
+        if (!c->owner) return fail(LBM_ESTATE, "call ibm_rest_shape first");
+    }
+    return LBM_OK;
+}
+
+LBM_API int lbm_run_record(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, void *f_rec, double *x_rec, void *v_rec,
+                           int32_t use_graph) {
+    if (int rc = check_record(c, m, nsteps, f_rec, x_rec, v_rec)) return rc;
+    if (nsteps == 0) return LBM_OK;
+    const size_t fb = 19 * (size_t)c->stride * c->rsize;
+    const size_t nv3 = m ? 3 * (size_t)m->nverts : 0;
+    char *F = static_cast<char *>(f_rec);
+    auto enqueue = [&] {
+        // step k reads state k from the record and writes state k+1 into the
+        // next record; the last step writes back into the current buffer
+        // (its content is record 0 by then), so the parity is unchanged
+        enqueue_copy(c, F, cur_f(c), fb);
+        for (int k = 0; k < nsteps; k++) {
+            const void *fa = F + k * fb;
+            if (m) {
+                enqueue_copy(c, x_rec + k * nv3, m->x, nv3 * 8);
+                enqueue_copy(c, static_cast<char *>(v_rec) + k * nv3 * c->rsize, m->v, nv3 * c->rsize);
+                enqueue_couple(c, m, fa);
+            }
+            enqueue_step_into(c, fa, k + 1 < nsteps ? (void *)(F + (k + 1) * fb) : const_cast<void *>(cur_f(c)));
+        }
+    };
+    if (use_graph) {
+        Fnv key;
+        key.mix(G_REC);
+        key.mix((uint64_t)nsteps);
+        key.mix((uint64_t)c->cur);
+        key.mix(mesh_launch_key(m));
+        for (const void *p : {(const void *)f_rec, (const void *)x_rec, (const void *)v_rec}) key.mix((uint64_t)(uintptr_t)p);
+        if (int rc = capture_slot(c, G_REC, key.h | 1ull, enqueue)) return rc;
+        HIPCHK(hipGraphLaunch(c->gx[G_REC], c->s));
+    } else {
+        enqueue();
+    }
+    c->steps += nsteps;
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+LBM_API int lbm_adjoint_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, const void *f_rec, const double *x_rec,
+                            const void *v_rec, void *lam_a, void *lam_b, double *lam_x, double *lam_v, void *dgrad,
+                            int32_t use_graph) {
+    if (int rc = check_record(c, m, nsteps, f_rec, x_rec, v_rec)) return rc;
+    if (!lam_a || !lam_b || lam_a == lam_b) return fail(LBM_EINVAL, "lam_a and lam_b must be distinct and non-NULL");
+    if (((uintptr_t)lam_a | (uintptr_t)lam_b) % 16 || (uintptr_t)dgrad % c->rsize)
+        return fail(LBM_EINVAL, "lam_a/lam_b must be 16-byte aligned and dgrad aligned to its element");
+    if (m && (!lam_x || !lam_v || ((uintptr_t)lam_x | (uintptr_t)lam_v) % 8))
+        return fail(LBM_EINVAL, "lam_x and lam_v must be non-NULL and 8-byte aligned");
+    if (nsteps == 0) return LBM_OK;
+    if (int rc = ensure_adjoint(c, m)) return rc;
+    const size_t fb = 19 * (size_t)c->stride * c->rsize;
+    const size_t nv3 = m ? 3 * (size_t)m->nverts : 0;
+    const char *F = static_cast<const char *>(f_rec);
+    auto enqueue = [&] {
+        void *lam[2] = {lam_a, lam_b};
+        for (int k = nsteps - 1, j = 0; k >= 0; k--, j ^= 1)
+            enqueue_adjoint(c, m, F + k * fb, m ? x_rec + k * nv3 : nullptr,
+                            m ? static_cast<const char *>(v_rec) + k * nv3 * c->rsize : nullptr, lam[j], lam[j ^ 1],
+                            lam_x, lam_v, dgrad);
+        if (nsteps % 2) enqueue_copy(c, lam_a, lam_b, fb);
+    };
+    if (use_graph) {
+        Fnv key;
+        key.mix(G_ADJ);
+        key.mix((uint64_t)nsteps);
+        key.mix(mesh_launch_key(m));
+        for (const void *p : {(const void *)f_rec, (const void *)x_rec, (const void *)v_rec, (const void *)lam_a,
+                              (const void *)lam_b, (const void *)lam_x, (const void *)lam_v, (const void *)dgrad,
+                              (const void *)c->xs, (const void *)c->hv, (const void *)c->lamF})
+            key.mix((uint64_t)(uintptr_t)p);
+        if (int rc = capture_slot(c, G_ADJ, key.h | 1ull, enqueue)) return rc;
+        HIPCHK(hipGraphLaunch(c->gx[G_ADJ], c->s));
+    } else {
+        enqueue();
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;

@@ -146,6 +146,32 @@ class Lattice:
             self.ctx, None if mesh is None else C.byref(mesh.s), _ptr(f_n), _ptr(x_n), _ptr(v_n), _ptr(lam_next),
             _ptr(lam), _ptr(lam_x), _ptr(lam_v), _ptr(dgrad)))
 
+    def record_buffers(self, nsteps: int, mesh: Optional["Mesh"] = None):
+        """Device buffers for lbm_run_record: (f_rec, x_rec, v_rec)."""
+        f = torch.empty(nsteps, 19 * self.stride, dtype=self.rdtype, device=self.device)
+        if mesh is None:
+            return f, None, None
+        nv = mesh.cells.nverts
+        return (f, torch.empty(nsteps, 3, nv, dtype=torch.float64, device=self.device),
+                torch.empty(nsteps, 3, nv, dtype=self.rdtype, device=self.device))
+
+    def run_record(self, nsteps: int, mesh: Optional["Mesh"], rec, use_graph: bool = True) -> None:
+        """nsteps coupled steps, recording the state at the start of each (lbm_run_record)."""
+        f, x, v = rec
+        assert f.shape[0] >= nsteps
+        _lib.check(self.lib.lbm_run_record(self.ctx, None if mesh is None else C.byref(mesh.s), int(nsteps),
+                                           _ptr(f), _ptr(x), _ptr(v), int(bool(use_graph))))
+
+    def adjoint_run(self, nsteps: int, mesh: Optional["Mesh"], rec, lam_a: torch.Tensor, lam_b: torch.Tensor,
+                    lam_x: Optional[torch.Tensor], lam_v: Optional[torch.Tensor],
+                    dgrad: Optional[torch.Tensor] = None, use_graph: bool = True) -> None:
+        """Reverse sweep over recorded steps (lbm_adjoint_run): lam_a goes
+        from dJ/df at the end to dJ/df at the start."""
+        f, x, v = rec
+        _lib.check(self.lib.lbm_adjoint_run(self.ctx, None if mesh is None else C.byref(mesh.s), int(nsteps),
+                                            _ptr(f), _ptr(x), _ptr(v), _ptr(lam_a), _ptr(lam_b), _ptr(lam_x),
+                                            _ptr(lam_v), _ptr(dgrad), int(bool(use_graph))))
+
     def steps_taken(self) -> int:
         st = C.c_int64()
         _lib.check(self.lib.lbm_current(self.ctx, None, C.byref(st)))

@@ -243,7 +243,7 @@ def test_coupled_run_leaves_final_state(lbm):
     lat = lbm.Lattice.from_scenario(s, prec="f32dev")
     mesh = lbm.Mesh(lat, s.cells)
     G = torch.zeros(3, s.n, dtype=torch.float32, device="cuda", requires_grad=True)
-    fT, xT, vT = adjoint.run_with_grad(G, lat, mesh, 30, 8)
+    fT, xT, vT = adjoint.run_with_grad(G, lat, mesh, 30, 8)  # segments 8, 8, 8, 6
     f_end = lat.current().clone()
     x_end = mesh.x.clone()
     J = adjoint.objective(lat, mesh, fT, xT, G, None)
@@ -253,3 +253,74 @@ def test_coupled_run_leaves_final_state(lbm):
     assert torch.equal(f_end, fT)
     assert torch.isfinite(G.grad).all() and G.grad.abs().max() > 0
     lat.close()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_run_record_matches_plain_steps(lbm, use_graph):
+    """Recording steps (graph or not) gives bitwise the plain run's states:
+    record k equals the state after k steps on every fluid node (records
+    after the first are written by the streaming pass, which never writes
+    the slots of solid nodes, and nothing reads them), and the final state
+    matches."""
+    import torch
+    s = _small(seed=12)
+    A = lbm.Lattice.from_scenario(s, prec="f32dev")
+    MA = lbm.Mesh(A, s.cells)
+    B = lbm.Lattice.from_scenario(s, prec="f32dev")
+    MB = lbm.Mesh(B, s.cells)
+    n = 6
+    rec = B.record_buffers(n, MB)
+    for rep in range(2):  # the second call replays the captured graph
+        states = []
+        for k in range(n):
+            torch.cuda.synchronize()
+            states.append((A.current_buffer().clone(), MA.x.clone(), MA.v.clone()))
+            A.run(1, MA)
+        B.run_record(n, MB, rec, use_graph=use_graph)
+        torch.cuda.synchronize()
+        fluid = torch.as_tensor(s.solid.reshape(-1) == 0, device="cuda")
+        for k in range(n):
+            got = rec[0][k].view(19, B.stride)[:, :s.n][:, fluid]
+            ref = states[k][0].view(19, A.stride)[:, :s.n][:, fluid]
+            assert torch.equal(got, ref), f"rep {rep} record {k}"
+            assert torch.equal(rec[1][k], states[k][1]) and torch.equal(rec[2][k], states[k][2])
+        assert torch.equal(A.current()[:, fluid], B.current()[:, fluid])
+        assert torch.equal(MA.x, MB.x) and torch.equal(MA.v, MB.v)
+        assert A.steps_taken() == B.steps_taken()
+
+
+@pytest.mark.parametrize("n", [5, 6])
+def test_adjoint_run_matches_stepwise(lbm, n):
+    """The native reverse sweep (graph-captured, replayed twice) equals
+    lbm_adjoint_step called step by step; only the order of the float adds
+    that spread lambda_u differs, so FP64 agrees to rounding."""
+    import torch
+    s = _small(seed=13)
+    rng = np.random.default_rng(5)
+    G = 1e-5 * rng.standard_normal((3, s.n))
+    lat = lbm.Lattice.from_scenario(s, prec="f64", gfield=G)
+    mesh = lbm.Mesh(lat, s.cells)
+    lat.run(3, mesh)
+    rec = lat.record_buffers(n, mesh)
+    lat.run_record(n, mesh, rec)
+    fluid = torch.as_tensor(s.solid.reshape(-1) == 0, device="cuda")
+    lam0 = torch.zeros(19, lat.stride, dtype=torch.float64, device="cuda")
+    lam0[:, :s.n] = torch.as_tensor(rng.standard_normal((19, s.n)), device="cuda") * fluid
+    lx0 = torch.as_tensor(rng.standard_normal((3, s.cells.nverts)), device="cuda")
+    lv0 = torch.as_tensor(rng.standard_normal((3, s.cells.nverts)), device="cuda")
+    # step by step
+    la, lb = lam0.reshape(-1).clone(), torch.zeros(19 * lat.stride, dtype=torch.float64, device="cuda")
+    lx, lv = lx0.clone(), lv0.clone()
+    dG1 = torch.zeros(3, s.n, dtype=torch.float64, device="cuda")
+    for k in range(n - 1, -1, -1):
+        lat.adjoint_step(mesh, rec[0][k], rec[1][k], rec[2][k], la, lb, lx, lv, dG1)
+        la, lb = lb, la
+    for rep in range(2):
+        a = lam0.reshape(-1).clone()
+        b = torch.zeros_like(a)
+        lx2, lv2 = lx0.clone(), lv0.clone()
+        dG2 = torch.zeros_like(dG1)
+        lat.adjoint_run(n, mesh, rec, a, b, lx2, lv2, dG2, use_graph=True)
+        torch.cuda.synchronize()
+        for got, ref in ((a, la), (lx2, lx), (lv2, lv), (dG2, dG1)):
+            assert torch.allclose(got, ref, rtol=1e-11, atol=1e-13 * ref.abs().max().item()), f"rep {rep}"
