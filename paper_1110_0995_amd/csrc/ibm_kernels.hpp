@@ -38,7 +38,8 @@
 //   that says "base node in role q has a slot for you".
 // k_gather_nodes (one wave per listed tile) reads its node's 8 role bytes
 //   with one load, adds the flagged slots in a fixed order and clears the
-//   bytes.
+//   bytes; the fallback path flags its tiles so that only those read the
+//   accumulated atomics back.
 // All sums except the fallback are in a fixed order, so the spread is
 // bit-reproducible.
 //
@@ -475,6 +476,7 @@ struct SpreadArgs {
     void *cslot;       // [N][8] Vec4: corner contributions of a base node
     uint8_t *role;     // [N][8] role[n][q] = 1: base node of n in role q holds a slot
     void *fibm;        // [N] Vec4 (fallback)
+    uint8_t *ftile;    // [ntiles] 1: a node of the tile got fallback atomics this call
     const uint32_t *epoch;
     const Chan *chans;
     const int32_t *cell_chan;
@@ -556,11 +558,13 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
             R4 *FI = static_cast<R4 *>(a.fibm);
 #pragma unroll
             for (int q = 0; q < 8; q++) {
-                const int64_t n = ch.noff + xs[q & 1] + (int64_t)ch.nx * (ys[(q >> 1) & 1] + (int64_t)ch.ny * zs[q >> 2]);
+                const int ys_ = ys[(q >> 1) & 1], zs_ = zs[q >> 2];
+                const int64_t n = ch.noff + xs[q & 1] + (int64_t)ch.nx * (ys_ + (int64_t)ch.ny * zs_);
                 R *rec = reinterpret_cast<R *>(&FI[n]);
                 atomicAdd(rec + 0, F[q][0]);
                 atomicAdd(rec + 1, F[q][1]);
                 atomicAdd(rec + 2, F[q][2]);
+                a.ftile[ch.toff + (int64_t)(ys_ + ch.ny * zs_) * ch.tpr + (xs[q & 1] >> 6)] = 1;
             }
         }
     }
@@ -568,14 +572,21 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
 
 struct GatherArgs {
     const uint32_t *tlist, *tcount;
-    uint8_t *role;  // [N][8], cleared here
+    uint8_t *role;   // [N][8], cleared here
     const void *cslot;
     const uint8_t *need;
-    void *fibm;  // [N] Vec4
+    uint8_t *ftile;  // [ntiles] fallback flags, cleared here
+    void *fibm;      // [N] Vec4
     const Chan *chans;
     const uint16_t *tile_chan;
 };
 
+// Each listed tile: every lane reads its node's 8 role bytes with one load
+// (zero away from the stencils), adds the flagged slots in a fixed order and
+// stores the sum as the node's spread force.  Only in a tile that the
+// fallback path flagged does the sum go on top of the accumulated atomics
+// (read-modify-write of the marked nodes), so the common chain is list ->
+// role word -> slots -> store.
 template <class R>
 __global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
     using R4 = typename Vec4<R>::T;
@@ -587,35 +598,43 @@ __global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
         const int tile = __builtin_amdgcn_readfirstlane((int)a.tlist[w]);
         const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
+        const bool fallback = __builtin_amdgcn_readfirstlane((int)a.ftile[tile]) != 0;
         const int lt = tile - ch.toff, row = lt / ch.tpr;
         const int x = (lt - row * ch.tpr) * 64 + lane;
+        if (fallback && lane == 0) a.ftile[tile] = 0;
         if (x >= ch.nx) continue;
         const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
-        if (!a.need[n]) continue;
-        const int y = row % ch.ny, z = row / ch.ny;
-        const int xb[2] = {x, x == 0 ? ch.nx - 1 : x - 1};
-        const int yb[2] = {y, y == 0 ? ch.ny - 1 : y - 1};
-        const int zb[2] = {z, z == 0 ? ch.nz - 1 : z - 1};
-        // node n is corner q of base node (x - qx, y - qy, z - qz)
         unsigned long long *rp = reinterpret_cast<unsigned long long *>(a.role) + n;
         const unsigned long long roles = *rp;
-        if (!roles) continue;
-        *rp = 0ull;
         R Fx = R(0), Fy = R(0), Fz = R(0);
+        if (roles) {
+            *rp = 0ull;
+            const int y = row % ch.ny, z = row / ch.ny;
+            const int xb[2] = {x, x == 0 ? ch.nx - 1 : x - 1};
+            const int yb[2] = {y, y == 0 ? ch.ny - 1 : y - 1};
+            const int zb[2] = {z, z == 0 ? ch.nz - 1 : z - 1};
+            // node n is corner q of base node (x - qx, y - qy, z - qz)
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            if (!((roles >> (8 * q)) & 0xffull)) continue;
-            const int64_t b = ch.noff + xb[q & 1] + (int64_t)ch.nx * (yb[(q >> 1) & 1] + (int64_t)ch.ny * zb[q >> 2]);
-            const R4 f = CS[b * 8 + q];
-            Fx += f.x;
-            Fy += f.y;
-            Fz += f.z;
+            for (int q = 0; q < 8; q++) {
+                if (!((roles >> (8 * q)) & 0xffull)) continue;
+                const int64_t b =
+                    ch.noff + xb[q & 1] + (int64_t)ch.nx * (yb[(q >> 1) & 1] + (int64_t)ch.ny * zb[q >> 2]);
+                const R4 f = CS[b * 8 + q];
+                Fx += f.x;
+                Fy += f.y;
+                Fz += f.z;
+            }
         }
-        R4 f = FI[n];
-        f.x += Fx;
-        f.y += Fy;
-        f.z += Fz;
-        FI[n] = f;
+        if (fallback) {
+            if (!a.need[n]) continue;
+            R4 f = FI[n];
+            f.x += Fx;
+            f.y += Fy;
+            f.z += Fz;
+            FI[n] = f;
+        } else if (roles) {
+            FI[n] = R4{Fx, Fy, Fz, R(0)};  // the accumulator is zero here
+        }
     }
 }
 

@@ -114,6 +114,7 @@ struct lbm_ctx {
     uint8_t *tneed = nullptr;    // [ntiles] 1 = tile holds a marked node
     uint32_t *tlist = nullptr;   // [ntiles] marked tiles, compacted
     uint32_t *tcount = nullptr;  // length of tlist
+    uint8_t *ftile = nullptr;    // [ntiles] 1 = the spread fell back to atomics in this tile
     uint32_t *epoch = nullptr;   // spreading-claim epoch, advanced on the device by each coupled step
     // spreading workspace, allocated by the first ibm_rest_shape
     void *srec = nullptr;        // spread records, one per IB point of the largest mesh
@@ -214,7 +215,7 @@ static int make_channels(int32_t nch, const int32_t *dims, std::vector<Chan> &ou
 }
 
 static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch) {
-    return N + 4 * N + 8 * N * es + N + cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
+    return N + 4 * N + 8 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
            (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
 }
 
@@ -239,7 +240,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     drop_graph(c);
     if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm,  c->ufield,   c->need, c->tneed, c->tlist,
-                    c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums,
+                    c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -265,6 +266,7 @@ static int init_ctx(lbm_ctx *c) {
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
         hipMalloc(&c->tneed, tpad) != hipSuccess || hipMalloc(&c->tlist, 4 * tn) != hipSuccess ||
         hipMalloc(&c->tcount, 4) != hipSuccess || hipMalloc(&c->epoch, 4) != hipSuccess ||
+        hipMalloc(&c->ftile, tpad) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
         (c->nch > 1 && hipMalloc(&c->tile_chan, 2 * tn) != hipSuccess) ||
@@ -288,6 +290,7 @@ static int init_ctx(lbm_ctx *c) {
     HIPCHK(hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s));
     HIPCHK(hipMemsetAsync(c->need, 0, c->N, c->s));
     HIPCHK(hipMemsetAsync(c->tneed, 0, tpad, c->s));
+    HIPCHK(hipMemsetAsync(c->ftile, 0, tpad, c->s));
     HIPCHK(hipMemsetAsync(c->tcount, 0, 4, c->s));
     HIPCHK(hipMemsetAsync(c->epoch, 0, 4, c->s));
     const int nb = (int)cdiv(c->N, 256);
@@ -733,6 +736,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.cslot = c->cslot;
     sp.role = c->role;
     sp.fibm = c->fibm;
+    sp.ftile = c->ftile;
     sp.epoch = c->epoch;
     sp.chans = c->chans;
     sp.cell_chan = m->cell_chan;
@@ -743,6 +747,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     g.role = c->role;
     g.cslot = c->cslot;
     g.need = c->need;
+    g.ftile = c->ftile;
     g.fibm = c->fibm;
     g.chans = c->chans;
     g.tile_chan = c->tile_chan;
