@@ -43,11 +43,18 @@ class _Lat(C.Structure):
                 ("solid", C.POINTER(C.c_uint8)), ("G", _dp)]
 
 
+class _Contact(C.Structure):
+    _fields_ = [("a", C.c_double), ("n", C.c_double), ("rcut", C.c_double), ("roff", C.c_double),
+                ("dmin", C.c_double), ("cell_cell", C.c_int), ("nplanes", C.c_int), ("planes", _dp),
+                ("ncyl", C.c_int), ("cyl", _dp)]
+
+
 class _Mesh(C.Structure):
     _fields_ = [("ncells", C.c_int), ("nverts", C.c_int), ("ntris", C.c_int), ("nedges", C.c_int),
                 ("vert_off", _ip), ("tri_off", _ip), ("edge_off", _ip), ("tri", _ip), ("hinge", _ip),
                 ("moduli", _dp), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
-                ("l0", _dp), ("A0", _dp), ("th0", _dp), ("A0c", _dp), ("V0c", _dp), ("Av", _dp)]
+                ("l0", _dp), ("A0", _dp), ("th0", _dp), ("A0c", _dp), ("V0c", _dp), ("Av", _dp),
+                ("contact", C.POINTER(_Contact))]
 
 
 class _Trace(C.Structure):
@@ -63,6 +70,7 @@ def lib():
         build()
         L = C.CDLL(_SO)
         L.orc_membrane_energy.restype = C.c_double
+        L.orc_contact_energy.restype = C.c_double
         L.orc_step.restype = C.c_int
         L.orc_run.restype = C.c_int
         _lib = L
@@ -147,7 +155,9 @@ class Mesh:
     lengths, triangle areas, hinge angles, cell area and volume, and the
     rest area Av carried by each vertex)."""
 
-    def __init__(self, cells, moduli=None):
+    def __init__(self, cells, moduli=None, contact=None):
+        """contact: None, or dict(a, n, rcut, roff, dmin, cell_cell, planes [np, 4], cyl [nc, 3]) of
+        the soft-sphere contact forces (see orc_contact in oracle.c)."""
         self.cells = cells
         self.vert_off = np.ascontiguousarray(cells.vert_off, np.int32)
         self.tri_off = np.ascontiguousarray(cells.tri_off, np.int32)
@@ -165,8 +175,27 @@ class Mesh:
         self.s = _Mesh(nc, nv, nt, ne, _i(self.vert_off), _i(self.tri_off), _i(self.edge_off),
                        _i(self.tri), _i(self.hinge), _d(self.moduli), float(cells.xi),
                        float(cells.mass), float(cells.dt),
-                       _d(self.l0), _d(self.A0), _d(self.th0), _d(self.A0c), _d(self.V0c), _d(self.Av))
+                       _d(self.l0), _d(self.A0), _d(self.th0), _d(self.A0c), _d(self.V0c), _d(self.Av),
+                       None)
         self.nverts = nv
+        self._contact = None
+        if contact is not None:
+            self.planes = np.ascontiguousarray(np.asarray(contact.get("planes", np.zeros((0, 4))), np.float64))
+            self.cyl = np.ascontiguousarray(np.asarray(contact.get("cyl", np.zeros((0, 3))), np.float64))
+            self._contact = _Contact(float(contact["a"]), float(contact["n"]), float(contact["rcut"]),
+                                     float(contact.get("roff", 0.0)), float(contact.get("dmin", 0.05)),
+                                     int(contact.get("cell_cell", 1)), len(self.planes),
+                                     _d(self.planes) if len(self.planes) else _dp(),
+                                     len(self.cyl), _d(self.cyl) if len(self.cyl) else _dp())
+            self.s.contact = C.pointer(self._contact)
+
+    def contact_energy(self, L, X) -> float:
+        return lib().orc_contact_energy(C.byref(L.s), C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)))
+
+    def contact_forces(self, L, X) -> np.ndarray:
+        F = np.zeros((self.nverts, 3))
+        lib().orc_contact_forces(C.byref(L.s), C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)), _d(F))
+        return F
 
     def rest_shape(self, X: np.ndarray) -> None:
         lib().orc_rest_shape(C.byref(self.s), _d(np.ascontiguousarray(X, np.float64)))

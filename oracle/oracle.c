@@ -23,6 +23,8 @@
  *      then streaming to x + c_i, or halfway bounce-back into the opposite
  *      slot when x + c_i is a solid node                   [Sec. 2.1, 2.4]
  *   6. V_k += dt/m_k (F_el + F_c), X_k += dt V_k            [Sec. 2.2 step 4]
+ *      (with contact forces enabled, F_el also carries the soft-sphere
+ *      repulsion between cells and from the walls, Sec. 2.4)
  *      Reading: friction xi and point mass are densities per unit membrane
  *      area, so vertex k, carrying the rest area A_k (a third of its
  *      triangles' areas), has friction xi A_k and mass m_k = mass A_k.
@@ -68,6 +70,23 @@ typedef struct {
     const double *G;      /* [3][N] external forcing field, or NULL */
 } orc_lattice;
 
+/* Contact forces (Sec. 2.4, collisions): a soft-sphere potential between IB
+ * points of different cells and between IB points and the walls, cut at an
+ * interaction range.  Reading: U(d) = a d^-n for d = r - roff in (0, rcut),
+ * zero beyond; below dmin the potential continues linearly with the slope
+ * it has at dmin (a finite force for overlapping points).  Walls are
+ * analytic surfaces: planes n.x = offset (unit normal n into the fluid) and
+ * z-axis cylinders of radius R (fluid outside); r is then the distance to
+ * the surface on the fluid side. */
+typedef struct {
+    double a, n, rcut, roff, dmin;
+    int cell_cell;          /* 1: points of different cells repel each other */
+    int nplanes;
+    const double *planes;   /* [nplanes][4] = (nx, ny, nz, offset) */
+    int ncyl;
+    const double *cyl;      /* [ncyl][3] = (xc, yc, R) */
+} orc_contact;
+
 typedef struct {
     int ncells, nverts, ntris, nedges;
     const int *vert_off; /* [ncells+1] */
@@ -84,6 +103,7 @@ typedef struct {
     double *A0c; /* [ncells] */
     double *V0c; /* [ncells] */
     double *Av;  /* [nverts] rest area carried by each vertex */
+    const orc_contact *contact; /* contact forces, or NULL */
 } orc_mesh;
 
 /* Threads the OpenMP loops below will use. */
@@ -529,13 +549,101 @@ void orc_membrane_forces(const orc_mesh *M, const double *X, double *F) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* contact forces                                                            */
+/* ------------------------------------------------------------------------ */
+
+/* potential and -dU/dd of the contact law at surface distance d */
+static void soft_sphere(const orc_contact *P, double d, double *U, double *f) {
+    *U = 0.0;
+    *f = 0.0;
+    if (d >= P->rcut) return;
+    if (d >= P->dmin) {
+        *U = P->a * pow(d, -P->n);
+        *f = P->n * P->a * pow(d, -P->n - 1.0);
+    } else {
+        double fm = P->n * P->a * pow(P->dmin, -P->n - 1.0);
+        *U = P->a * pow(P->dmin, -P->n) + fm * (P->dmin - d);
+        *f = fm;
+    }
+}
+
+/* minimum-image difference along a periodic axis of length L */
+static double min_image(double d, int L, int periodic) {
+    if (!periodic) return d;
+    return d - L * floor(d / L + 0.5);
+}
+
+static int cell_of(const orc_mesh *M, int k) {
+    int c = 0;
+    while (M->vert_off[c + 1] <= k) c++;
+    return c;
+}
+
+/* Energy of the contact potential and forces F = -grad (F [nv][3], overwritten). */
+static double contact(const orc_lattice *L, const orc_mesh *M, const double *X, double *F) {
+    const orc_contact *P = M->contact;
+    const int dims[3] = {L->nx, L->ny, L->nz};
+    double E = 0.0;
+    if (F) memset(F, 0, sizeof(double) * 3 * M->nverts);
+    if (!P) return 0.0;
+    if (P->cell_cell) {
+        for (int i = 0; i < M->nverts; i++) {
+            int ci = cell_of(M, i);
+            for (int j = M->vert_off[ci + 1]; j < M->nverts; j++) {
+                double d[3];
+                for (int a = 0; a < 3; a++) d[a] = min_image(X[3 * i + a] - X[3 * j + a], dims[a], L->periodic[a]);
+                double r = norm3(d);
+                if (r == 0.0) continue; /* coincident points: no direction */
+                double U, f;
+                soft_sphere(P, r - P->roff, &U, &f);
+                E += U;
+                if (F && f != 0.0) {
+                    addv(F, i, f / r, d);
+                    addv(F, j, -f / r, d);
+                }
+            }
+        }
+    }
+    for (int k = 0; k < M->nverts; k++) {
+        const double *x = X + 3 * k;
+        for (int p = 0; p < P->nplanes; p++) {
+            const double *pl = P->planes + 4 * p;
+            double U, f;
+            soft_sphere(P, dot3(pl, x) - pl[3] - P->roff, &U, &f);
+            E += U;
+            if (F) addv(F, k, f, pl);
+        }
+        for (int q = 0; q < P->ncyl; q++) {
+            const double *cy = P->cyl + 3 * q;
+            double d[3] = {min_image(x[0] - cy[0], L->nx, L->periodic[0]),
+                           min_image(x[1] - cy[1], L->ny, L->periodic[1]), 0.0};
+            double rho = norm3(d);
+            if (rho == 0.0) continue; /* on the axis: no direction */
+            double U, f;
+            soft_sphere(P, rho - cy[2] - P->roff, &U, &f);
+            E += U;
+            if (F && f != 0.0) addv(F, k, f / rho, d);
+        }
+    }
+    return E;
+}
+
+double orc_contact_energy(const orc_lattice *L, const orc_mesh *M, const double *X) {
+    return contact(L, M, X, NULL);
+}
+
+void orc_contact_forces(const orc_lattice *L, const orc_mesh *M, const double *X, double *F) {
+    contact(L, M, X, F);
+}
+
+/* ------------------------------------------------------------------------ */
 /* the coupled step                                                          */
 /* ------------------------------------------------------------------------ */
 
 /* Optional per-step diagnostics written by orc_step (NULL to skip). */
 typedef struct {
     double *uk;   /* [nv][3] interpolated velocity */
-    double *Fel;  /* [nv][3] elastic force */
+    double *Fel;  /* [nv][3] elastic force (plus contact forces when enabled) */
     double *Fc;   /* [nv][3] coupling force */
     double *F;    /* [3][N]  total force seen by the collision */
 } orc_trace;
@@ -561,6 +669,12 @@ int orc_step(const orc_lattice *L, const orc_mesh *M, const double *f, double *f
         double *mFc = malloc(sizeof(double) * 3 * nv);
         orc_interpolate(L, uext, nv, X, uk);                 /* step 1 */
         orc_membrane_forces(M, X, Fel);                      /* step 2 */
+        if (M->contact) {                                    /* collisions, Sec. 2.4 */
+            double *Fk = malloc(sizeof(double) * 3 * nv);
+            contact(L, M, X, Fk);
+            for (int i = 0; i < 3 * nv; i++) Fel[i] += Fk[i];
+            free(Fk);
+        }
         for (int i = 0; i < 3 * nv; i++) {
             Fc[i] = M->xi * M->Av[i / 3] * (uk[i] - V[i]);
             mFc[i] = -Fc[i];

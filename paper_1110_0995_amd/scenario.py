@@ -385,6 +385,31 @@ def gap_sweep(nch: int = 64, *, lengths=(64, 128, 192, 256), ny: int = 64, nz: i
     return out
 
 
+# Soft-sphere contact law (a reading: the paper names the potential, not its
+# parameters): U(d) = a d^-n for d in (0, rcut), linear below dmin.
+CONTACT = dict(a=1e-4, n=2.0, rcut=1.0, roff=0.0, dmin=0.05, cell_cell=1)
+
+
+def contact_walls(s: Scenario):
+    """Analytic wall surfaces of a channel scenario for the contact forces:
+    the halfway-bounce-back planes of the solid z layers (z = 1/2 and
+    z = nz - 3/2, unit normals into the fluid) and, for each post, a z-axis
+    cylinder of radius post_radius + 1/2 (the staircase surface of the
+    solid nodes within post_radius).  Returns (planes [np, 4], cyl [nc, 3])."""
+    planes = np.array([[0.0, 0.0, 1.0, 0.5], [0.0, 0.0, -1.0, -(s.nz - 1.5)]])
+    cen = s.meta.get("post_centres", [])
+    r = float(s.meta.get("post_radius", 0)) + 0.5
+    cyl = np.array([[float(cx), float(cy), r] for cx, cy in cen]).reshape(-1, 3)
+    return planes, cyl
+
+
+def contact_params(s: Scenario, **kw) -> dict:
+    planes, cyl = contact_walls(s)
+    d = dict(CONTACT, planes=planes, cyl=cyl)
+    d.update(kw)
+    return d
+
+
 def batch_cells(scenarios: Sequence[Scenario]) -> Tuple[Optional[Cells], np.ndarray]:
     """Concatenate the cell populations of several channels into one (vertex,
     triangle and edge ids renumbered) and give the channel of each cell."""
