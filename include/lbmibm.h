@@ -88,6 +88,27 @@ typedef struct {
     void *stream;            /* hipStream_t to enqueue on (NULL = null stream) */
 } lbm_params;
 
+/* Contact forces between cells and with the walls (Sec. 2.4, collisions: a
+ * soft-sphere potential between IB points of different cells and between
+ * IB points and the walls, cut at an interaction range).  The law is a
+ * reading: U(d) = a d^-n for d = r - roff in (0, rcut), 0 beyond, continued
+ * linearly below dmin (force magnitude n a max(d, dmin)^-(n+1)); r is the
+ * distance between two points (minimum image across periodic axes) or from a
+ * point to a wall surface on the fluid side.  The forces are added to the
+ * membrane force of the step (m->f_el then holds elastic + contact). */
+typedef struct {
+    double a, n;            /* strength and exponent, > 0 */
+    double rcut;            /* interaction range beyond roff, > 0 */
+    double roff;            /* offset, >= 0 */
+    double dmin;            /* 0 < dmin <= rcut */
+    int32_t cell_cell;      /* 1: IB points of different cells of one channel repel each other */
+    int32_t nplanes;        /* wall planes */
+    const double *planes;   /* device [nplanes][4]: unit normal into the fluid, offset (surface n.x = offset) */
+    int32_t ncyl;           /* z-axis cylinders (posts) */
+    const double *cyl;      /* device [ncyl][3]: xc, yc, radius R; fluid outside */
+    const int32_t *cyl_off; /* device [nch+1]: channel k's cylinders are [cyl_off[k], cyl_off[k+1]); NULL: all in every channel */
+} ibm_contact;
+
 /* Membrane population (Sec. 2.2, 2.3).  All pointers are device memory.
  * Topology arrays use global vertex ids; each cell's triangles and edges may
  * only reference that cell's vertices [vert_off[c], vert_off[c+1]). */
@@ -118,6 +139,8 @@ typedef struct {
     double xi;               /* coupling friction per unit membrane area: vertex k feels F_c = xi*avert[k]*(u(X_k) - V_k); > 0 */
     double mass;             /* membrane mass per unit area: vertex k has mass mass*avert[k] (Newton equation of Sec. 2.2); > 0 */
     double dt;               /* IB time step, > 0 */
+    const ibm_contact *contact; /* host struct (its arrays on the device) of contact forces, or NULL for none;
+                                   ibm_rest_shape sizes the pair list for it, so it must not change afterwards */
     /* filled by ibm_rest_shape; the caller must not edit them */
     int32_t max_cell_verts, max_cell_tris, max_cell_edges;
     uint32_t checked;

@@ -29,6 +29,12 @@ class LbmParams(C.Structure):
                 ("gfield", C.c_void_p), ("stream", C.c_void_p)]
 
 
+class IbmContact(C.Structure):
+    _fields_ = [("a", C.c_double), ("n", C.c_double), ("rcut", C.c_double), ("roff", C.c_double),
+                ("dmin", C.c_double), ("cell_cell", C.c_int32), ("nplanes", C.c_int32), ("planes", C.c_void_p),
+                ("ncyl", C.c_int32), ("cyl", C.c_void_p), ("cyl_off", C.c_void_p)]
+
+
 class IbmMesh(C.Structure):
     _fields_ = [("ncells", C.c_int32), ("nverts", C.c_int32), ("ntris", C.c_int32), ("nedges", C.c_int32),
                 ("vert_off", C.c_void_p), ("tri_off", C.c_void_p), ("edge_off", C.c_void_p),
@@ -37,7 +43,7 @@ class IbmMesh(C.Structure):
                 ("l0", C.c_void_p), ("a0", C.c_void_p), ("th0", C.c_void_p), ("a0c", C.c_void_p),
                 ("v0c", C.c_void_p), ("avert", C.c_void_p), ("vtri_off", C.c_void_p), ("vtri", C.c_void_p),
                 ("vedge_off", C.c_void_p), ("vedge", C.c_void_p), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
-                ("max_cell_verts", C.c_int32), ("max_cell_tris", C.c_int32), ("max_cell_edges", C.c_int32),
+                ("contact", C.POINTER(IbmContact)), ("max_cell_verts", C.c_int32), ("max_cell_tris", C.c_int32), ("max_cell_edges", C.c_int32),
                 ("checked", C.c_uint32)]
 
 

@@ -389,6 +389,59 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     }
 }
 
+// Contact law of the collisions (Sec. 2.4; a reading, the paper names the
+// potential only): U(d) = a d^-n for d = r - roff in (0, rcut), 0 beyond,
+// continued linearly below dmin.
+struct ContactLaw {
+    double a, n, rcut, roff, dmin;
+};
+
+// -dU/dd at surface distance d (0 beyond the cut-off)
+__device__ __forceinline__ double contact_force(const ContactLaw &P, double d) {
+    if (d >= P.rcut) return 0.0;
+    return P.n * P.a * pow(d < P.dmin ? P.dmin : d, -P.n - 1.0);
+}
+
+__device__ __forceinline__ double min_image(double d, int L, int periodic) {
+    return periodic ? d - L * floor(d / L + 0.5) : d;
+}
+
+// Walls for the contact law: planes n.x = offset (unit normal into the
+// fluid) and z-axis cylinders (fluid outside), those of channel k being
+// [cyl_off[k], cyl_off[k+1]) (all when cyl_off is null).
+struct WallContact {
+    const double *planes;    // [nplanes][4]
+    const double *cyl;       // [ncyl][3] = xc, yc, R
+    const int32_t *cyl_off;  // [nch+1] or null
+    int nplanes, ncyl;
+    int per[3];
+    ContactLaw law;
+};
+
+// Wall contact force on a point at absolute position (px, py, pz) of
+// channel `chan` (distances with the minimum image across periodic axes).
+__device__ __forceinline__ void wall_force(const WallContact &w, int chan, const Chan &ch, double px, double py,
+                                           double pz, double &fx, double &fy, double &fz) {
+    fx = fy = fz = 0.0;
+    for (int p = 0; p < w.nplanes; p++) {
+        const double *pl = w.planes + 4 * p;
+        const double f = contact_force(w.law, pl[0] * px + pl[1] * py + pl[2] * pz - pl[3] - w.law.roff);
+        fx += f * pl[0];
+        fy += f * pl[1];
+        fz += f * pl[2];
+    }
+    const int c0 = w.cyl_off ? w.cyl_off[chan] : 0, c1 = w.cyl_off ? w.cyl_off[chan + 1] : w.ncyl;
+    for (int q = c0; q < c1; q++) {
+        const double *cy = w.cyl + 3 * q;
+        const double dx = min_image(px - cy[0], ch.nx, w.per[0]), dy = min_image(py - cy[1], ch.ny, w.per[1]);
+        const double rho = sqrt(dx * dx + dy * dy);
+        if (rho == 0.0) continue;
+        const double f = contact_force(w.law, rho - cy[2] - w.law.roff) / rho;
+        fx += f * dx;
+        fy += f * dy;
+    }
+}
+
 // Spread record of one IB point: its stencil's base node, fractional
 // offsets, and the force it exerts on the fluid (-F_c).
 template <class R>
@@ -409,6 +462,7 @@ struct CoupleArgs {
     const double *avert;
     int ncells, nverts;
     double xi, dt_over_m, dt;
+    WallContact wall;  // nplanes = ncyl = 0: no wall contact forces
 };
 
 template <class R>
@@ -455,9 +509,19 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     // step 3 input: the spread record
     SRec<R> *SR = static_cast<SRec<R> *>(a.srec);
     SR[k] = SRec<R>{(uint32_t)(ch.noff + x0 + (int64_t)ch.nx * (y0 + (int64_t)ch.ny * z0)), dx, dy, dz, -fcx, -fcy, -fcz};
-    // step 4 (points): semi-implicit Euler with the vertex's mass
+    // step 4 (points): semi-implicit Euler with the vertex's mass; the
+    // membrane force carries the wall contact force when walls are given
+    R fex = FE[k], fey = FE[NV + k], fez = FE[2 * NV + k];
+    if (a.wall.nplanes + a.wall.ncyl > 0) {
+        double wx_, wy_, wz_;
+        wall_force(a.wall, cell_channel(a.cell_chan, c), ch, a.anchor[c] + ox, a.anchor[a.ncells + c] + oy,
+                   a.anchor[2 * a.ncells + c] + oz, wx_, wy_, wz_);
+        fex += R(wx_);
+        fey += R(wy_);
+        fez += R(wz_);
+    }
     const R h = R(a.dt_over_m / ak);
-    const R nvx = vx + h * (FE[k] + fcx), nvy = vy + h * (FE[NV + k] + fcy), nvz = vz + h * (FE[2 * NV + k] + fcz);
+    const R nvx = vx + h * (fex + fcx), nvy = vy + h * (fey + fcy), nvz = vz + h * (fez + fcz);
     Vv[k] = nvx;
     Vv[NV + k] = nvy;
     Vv[2 * NV + k] = nvz;

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "adjoint_kernels.hpp"
+#include "contact_kernels.hpp"
 #include "ibm_kernels.hpp"
 #include "lattice_kernels.hpp"
 
@@ -73,6 +74,7 @@ uint32_t mesh_tag(const ibm_mesh *m) {
     f.mix((uint64_t)(uintptr_t)m->vtri);
     f.mix((uint64_t)(uintptr_t)m->vedge);
     f.mix((uint64_t)(uintptr_t)m->cell_chan);
+    f.mix((uint64_t)(uintptr_t)m->contact);
     f.mix((uint64_t)m->max_cell_verts);
     return kMeshMagic ^ f.fold();
 }
@@ -89,6 +91,14 @@ uint64_t mesh_launch_key(const ibm_mesh *m) {
     f.mixd(m->xi);
     f.mixd(m->mass);
     f.mixd(m->dt);
+    if (const ibm_contact *k = m->contact) {
+        for (double v : {k->a, k->n, k->rcut, k->roff, k->dmin}) f.mixd(v);
+        f.mix((uint64_t)k->cell_cell);
+        f.mix((uint64_t)k->nplanes);
+        f.mix((uint64_t)k->ncyl);
+        for (const void *p : {(const void *)k->planes, (const void *)k->cyl, (const void *)k->cyl_off})
+            f.mix((uint64_t)(uintptr_t)p);
+    }
     f.mix((uint64_t)m->max_cell_tris);
     f.mix((uint64_t)m->max_cell_edges);
     return f.h | 1ull;
@@ -132,6 +142,11 @@ struct lbm_ctx {
     // launch shape
     int cs_waves = 4;     // tiles (waves) per collide-stream workgroup
     int list_blocks = 0;  // workgroups of the tile-list kernels (0: by lattice size)
+    // contact work buffers, allocated by ibm_rest_shape for a mesh with cell-cell contact
+    double *bounds = nullptr;    // [ncells][4] centroid and radius
+    int2 *pairs = nullptr;       // cell pairs in contact range
+    uint32_t *npairs = nullptr;  // their number this step
+    int bounds_cap = 0, pair_cap = 0;
     // adjoint work buffers, allocated by the first lbm_adjoint_step
     void *lamF = nullptr;  // [N] x 4 real: lambda of the node force at stencil nodes
     void *lamU = nullptr;  // [N] x 4 real: lambda of u_ext at stencil nodes (kept zero between calls)
@@ -241,7 +256,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm,  c->ufield,   c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums, c->ftile,
-                    c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv};
+                    c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -525,6 +540,15 @@ static int check_mesh_ptrs(const lbm_ctx *c, const ibm_mesh *m) {
     if (!(m->xi > 0) || !(m->mass > 0) || !(m->dt > 0) || !std::isfinite(m->xi) || !std::isfinite(m->mass) ||
         !std::isfinite(m->dt))
         return fail(LBM_EINVAL, "xi, mass and dt must be finite and > 0");
+    if (const ibm_contact *k = m->contact) {
+        if (!(k->a > 0) || !(k->n > 0) || !(k->rcut > 0) || !(k->dmin > 0) || !(k->dmin <= k->rcut) ||
+            !(k->roff >= 0) || !std::isfinite(k->a) || !std::isfinite(k->n) || !std::isfinite(k->rcut) ||
+            !std::isfinite(k->roff))
+            return fail(LBM_EINVAL, "contact law needs finite a, n, rcut > 0, 0 < dmin <= rcut and roff >= 0");
+        if (k->nplanes < 0 || k->ncyl < 0 || (k->nplanes && !k->planes) || (k->ncyl && !k->cyl))
+            return fail(LBM_EINVAL, "contact walls: counts must be >= 0 and arrays given when counts are");
+        if (k->cell_cell != 0 && k->cell_cell != 1) return fail(LBM_EINVAL, "contact cell_cell must be 0 or 1");
+    }
     return LBM_OK;
 }
 
@@ -677,6 +701,36 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
         HIPCHK(hipMemsetAsync(c->owner, 0, 4 * c->N, c->s));
         HIPCHK(hipMemsetAsync(c->role, 0, 8 * c->N, c->s));
     }
+    if (const ibm_contact *k = m->contact) {
+        if (k->cyl_off && k->ncyl) {
+            std::vector<int32_t> co(c->nch + 1);
+            HIPCHK(hipMemcpy(co.data(), k->cyl_off, co.size() * 4, hipMemcpyDeviceToHost));
+            if (co[0] != 0 || co[c->nch] != k->ncyl) return fail(LBM_EINVAL, "cyl_off must run from 0 to ncyl");
+            for (int q = 0; q < c->nch; q++)
+                if (co[q + 1] < co[q]) return fail(LBM_EINVAL, "cyl_off must not decrease");
+        }
+        if (k->cell_cell && m->ncells > 1) {
+            const int64_t all = (int64_t)m->ncells * (m->ncells - 1) / 2;
+            if (all > (int64_t(1) << 22))
+                return fail(LBM_EINVAL, "cell-cell contact supports up to %d cells per mesh", 2897);
+            if (3 * (size_t)mv * 8 > kMaxLds)
+                return fail(LBM_EINVAL, "a cell with %d vertices is too large for the contact pass", mv);
+            if (m->ncells > c->bounds_cap || all > c->pair_cap) {
+                drop_graph(c);
+                for (void *b : {(void *)c->bounds, (void *)c->pairs, (void *)c->npairs})
+                    if (b) HIPCHK(hipFree(b));
+                c->bounds = nullptr, c->pairs = nullptr, c->npairs = nullptr;
+                c->bounds_cap = c->pair_cap = 0;
+                if (hipMalloc(&c->bounds, 32 * (size_t)m->ncells) != hipSuccess ||
+                    hipMalloc(&c->pairs, 8 * (size_t)all) != hipSuccess || hipMalloc(&c->npairs, 4) != hipSuccess) {
+                    (void)hipGetLastError();
+                    return fail(LBM_ENOMEM, "allocating the contact pair list failed");
+                }
+                c->bounds_cap = m->ncells;
+                c->pair_cap = (int)all;
+            }
+        }
+    }
     if (c->p.prec == LBM_F64)
         launch_membrane<double>(c, m, true);
     else
@@ -684,6 +738,44 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
     HIPCHK(hipGetLastError());
     m->checked = mesh_tag(m);
     return LBM_OK;
+}
+
+static ContactLaw contact_law(const ibm_contact *k) { return ContactLaw{k->a, k->n, k->rcut, k->roff, k->dmin}; }
+
+// Cell-cell contact forces, added to the membrane force of step n.
+template <class R>
+static void launch_contact(lbm_ctx *c, const ibm_mesh *m) {
+    const ibm_contact *k = m->contact;
+    if (!k || !k->cell_cell || m->ncells < 2) return;
+    BoundsArgs b{m->vert_off, m->anchor, m->x, c->bounds, c->npairs, m->ncells, m->nverts};
+    k_cell_bounds<<<m->ncells, 256, 0, c->s>>>(b);
+    PairArgs p{};
+    p.bounds = c->bounds;
+    p.cell_chan = m->cell_chan;
+    p.chans = c->chans;
+    p.npairs = c->npairs;
+    p.pairs = c->pairs;
+    p.ncells = m->ncells;
+    p.cap = c->pair_cap;
+    for (int d = 0; d < 3; d++) p.per[d] = c->p.periodic[d];
+    p.reach = k->roff + k->rcut;
+    k_contact_pairs<<<dim3((unsigned)cdiv(m->ncells, 256), (unsigned)m->ncells), 256, 0, c->s>>>(p);
+    CellContactArgs a{};
+    a.vert_off = m->vert_off;
+    a.anchor = m->anchor;
+    a.cell_chan = m->cell_chan;
+    a.chans = c->chans;
+    a.x = m->x;
+    a.f_el = m->f_el;
+    a.npairs = c->npairs;
+    a.pairs = c->pairs;
+    a.ncells = m->ncells;
+    a.nverts = m->nverts;
+    a.cap = c->pair_cap;
+    for (int d = 0; d < 3; d++) a.per[d] = c->p.periodic[d];
+    a.law = contact_law(k);
+    const int grid = (int)std::min<int64_t>(c->pair_cap, 1024);
+    k_contact_cells<R><<<grid, kContactThreads, 3 * (size_t)m->max_cell_verts * 8, c->s>>>(a);
 }
 
 template <class S, class R, bool DEV>
@@ -727,6 +819,15 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     a.xi = m->xi;
     a.dt_over_m = m->dt / m->mass;
     a.dt = m->dt;
+    if (const ibm_contact *k = m->contact) {
+        a.wall.planes = k->planes;
+        a.wall.cyl = k->cyl;
+        a.wall.cyl_off = k->cyl_off;
+        a.wall.nplanes = k->nplanes;
+        a.wall.ncyl = k->ncyl;
+        for (int d = 0; d < 3; d++) a.wall.per[d] = c->p.periodic[d];
+        a.wall.law = contact_law(k);
+    }
     dim3 grid((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells);
     k_couple<R><<<grid, 128, 0, c->s>>>(a);
     SpreadArgs sp{};
@@ -759,16 +860,19 @@ static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f) {
     switch (c->p.prec) {
         case LBM_F64:
             launch_membrane<double>(c, m, false);
+            launch_contact<double>(c, m);
             launch_node_velocity<double, double, false>(c, f);
             launch_couple<double>(c, m);
             break;
         case LBM_F32:
             launch_membrane<float>(c, m, false);
+            launch_contact<float>(c, m);
             launch_node_velocity<float, float, false>(c, f);
             launch_couple<float>(c, m);
             break;
         default:
             launch_membrane<float>(c, m, false);
+            launch_contact<float>(c, m);
             launch_node_velocity<float, float, true>(c, f);
             launch_couple<float>(c, m);
             break;
@@ -891,6 +995,7 @@ static int ensure_adjoint(lbm_ctx *c, const ibm_mesh *m) {
 
 static int check_jvp_mesh(const lbm_ctx *c, const ibm_mesh *m) {
     if (int rc = check_mesh_ptrs(c, m)) return rc;
+    if (m->contact) return fail(LBM_EINVAL, "contact forces are not differentiated; use a mesh without contact");
     if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
     if (adj_membrane_lds_bytes(m->max_cell_verts) > kMaxLds)
         return fail(LBM_EINVAL, "a cell with %d vertices is too large for the membrane Jacobian pass",

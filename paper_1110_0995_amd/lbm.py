@@ -202,12 +202,27 @@ class Lattice:
 class Mesh:
     """Membrane population on a lattice's device (SoA arrays, rest shape computed on the GPU)."""
 
-    def __init__(self, lat: Lattice, cells: Cells, cell_chan: Optional[np.ndarray] = None):
+    def __init__(self, lat: Lattice, cells: Cells, cell_chan: Optional[np.ndarray] = None,
+                 contact: Optional[dict] = None):
+        """contact: None, or dict(a, n, rcut, roff, dmin, cell_cell, planes [np, 4], cyl [nc, 3],
+        cyl_off [nch + 1] (optional)) of the soft-sphere contact forces (ibm_contact)."""
         dev, R = lat.device, lat.rdtype
         i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32)).to(dev)
         self.cells = cells
         self.lat = lat
         self.cell_chan = None if cell_chan is None else i32(np.asarray(cell_chan).reshape(-1))
+        self.contact = None
+        if contact is not None:
+            f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.float64)).to(dev)
+            self._planes = f64(np.asarray(contact.get("planes", np.zeros((0, 4)))).reshape(-1, 4))
+            self._cyl = f64(np.asarray(contact.get("cyl", np.zeros((0, 3)))).reshape(-1, 3))
+            self._cyl_off = None if contact.get("cyl_off") is None else i32(contact["cyl_off"])
+            self.contact = _lib.IbmContact(
+                float(contact["a"]), float(contact["n"]), float(contact["rcut"]), float(contact.get("roff", 0.0)),
+                float(contact.get("dmin", 0.05)), int(contact.get("cell_cell", 1)), self._planes.shape[0],
+                self._planes.data_ptr() if self._planes.numel() else None, self._cyl.shape[0],
+                self._cyl.data_ptr() if self._cyl.numel() else None,
+                None if self._cyl_off is None else self._cyl_off.data_ptr())
         self.vert_off = i32(cells.vert_off)
         self.tri_off = i32(cells.tri_off)
         self.edge_off = i32(cells.edge_off)
@@ -234,7 +249,8 @@ class Mesh:
                               None if self.cell_chan is None else p(self.cell_chan), p(self.x), p(self.v), p(self.f_el), p(self.moduli), p(self.l0), p(self.a0),
                               p(self.th0), p(self.a0c), p(self.v0c), p(self.avert), p(self.vtri_off), p(self.vtri),
                               p(self.vedge_off), p(self.vedge), float(cells.xi), float(cells.mass),
-                              float(cells.dt), 0, 0, 0, 0)
+                              float(cells.dt), None if self.contact is None else C.pointer(self.contact),
+                              0, 0, 0, 0)
         _lib.check(lat.lib.ibm_rest_shape(lat.ctx, C.byref(self.s)))
         lat.meshes.append(self)
 

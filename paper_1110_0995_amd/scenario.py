@@ -410,6 +410,20 @@ def contact_params(s: Scenario, **kw) -> dict:
     return d
 
 
+def contact_params_batch(scenarios: Sequence[Scenario], **kw) -> dict:
+    """Contact walls of batched channels: each channel's posts as a run of
+    cylinders (cyl_off [nch + 1]); the z planes are shared, so the channels
+    must have the same nz."""
+    if len({s.nz for s in scenarios}) != 1:
+        raise ValueError("batched contact walls need channels of one height")
+    parts = [contact_walls(s) for s in scenarios]
+    cyl = np.concatenate([c for _, c in parts]).reshape(-1, 3)
+    off = np.concatenate([[0], np.cumsum([len(c) for _, c in parts])]).astype(np.int32)
+    d = dict(CONTACT, planes=parts[0][0], cyl=cyl, cyl_off=off)
+    d.update(kw)
+    return d
+
+
 def batch_cells(scenarios: Sequence[Scenario]) -> Tuple[Optional[Cells], np.ndarray]:
     """Concatenate the cell populations of several channels into one (vertex,
     triangle and edge ids renumbered) and give the channel of each cell."""
