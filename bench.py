@@ -8,7 +8,9 @@ of the whole lattice.  The default workload is the throughput channel:
 tau 0.7, FP32 deviation storage.  A second leg times the batched form: the
 64-channel gap sweep as one batch against the same channels run one after
 another; a third the differentiation form: a checkpointed 300-step run and
-its backward pass against the plain forward run.  Prints ONE JSON line.
+its backward pass against the plain forward run; a fourth the cost of the
+contact forces (collisions) on the main workload; a fifth the gap pass /
+no-pass sweep with those forces.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -254,6 +256,58 @@ def adjoint_leg(lbm_mod) -> dict:
     return out
 
 
+def contact_leg(lbm_mod, steps: int) -> dict:
+    """The throughput workload with the contact forces of the collisions
+    (soft-sphere repulsion between cells and from the walls and posts)
+    switched on, against the same steps without them."""
+    import torch
+    from paper_1110_0995_amd import scenario as S
+    s = S.throughput()
+    out = {"workload": "throughput + contact", "steps": steps, "law": {k: S.CONTACT[k] for k in
+                                                                      ("a", "n", "rcut", "roff", "dmin")}}
+    stream = torch.cuda.current_stream()
+    for name, contact in (("without", None), ("with", S.contact_params(s))):
+        lat = lbm_mod.Lattice.from_scenario(s, prec="f32dev")
+        mesh = lbm_mod.Mesh(lat, s.cells, contact=contact)
+        lat.run(20, mesh, steps_per_graph=10)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        lat.run(steps, mesh, steps_per_graph=10)
+        b.record(stream)
+        torch.cuda.synchronize()
+        out[f"ms_per_step_{name}"] = round(a.elapsed_time(b) / steps, 5)
+        lat.close()
+        del lat, mesh
+        torch.cuda.empty_cache()
+    out["overhead"] = round(out["ms_per_step_with"] / out["ms_per_step_without"] - 1.0, 4)
+    return out
+
+
+def sweep_leg(lbm_mod, steps: int) -> dict:
+    """The gap pass / no-pass experiment on the 64-channel sweep: the batch
+    stepped with the contact forces of the collisions, every cell tracked
+    through its channel's post pair; reports the gaps passed, the smallest
+    one, and the wall-clock rate including the tracking."""
+    import torch
+    from paper_1110_0995_amd import scenario as S
+    from paper_1110_0995_amd import sweep
+    scs = S.gap_sweep()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = sweep.run_sweep(lbm_mod, scs, steps, check_every=100)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    summ = tr.summary()
+    nodes = sum(s.n for s in scs)
+    return {"workload": "gap_sweep + contact", "channels": len(scs), "steps": steps, "check_every": 100,
+            "wall_s": round(dt, 3), "mlups_incl_setup_and_tracking": round(nodes * steps / dt / 1e6, 1),
+            "gaps": sorted({r["gap"] for r in summ}),
+            "passed_gaps": sorted({r["gap"] for r in summ if r["passed"]}),
+            "through": sum(r["through"] for r in summ), "around": sum(r["around"] for r in summ),
+            "min_passing_gap": tr.min_passing_gap()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +319,10 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=200,
                     help="steps of the 64-channel gap sweep, batched and sequential (0 skips the leg)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward leg")
+    ap.add_argument("--sweep-steps", type=int, default=2000,
+                    help="steps of the gap pass / no-pass sweep with contact forces (0 skips the leg)")
+    ap.add_argument("--contact-steps", type=int, default=100,
+                    help="steps of the throughput workload with and without contact forces (0 skips the leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -357,6 +415,10 @@ def main():
         out["batched"] = batched_leg(lbm, args.batched_steps, 20, not args.no_cpu_baseline)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_leg(lbm)
+    if args.contact_steps > 0:
+        out["contact"] = contact_leg(lbm, args.contact_steps)
+    if args.sweep_steps > 0:
+        out["sweep"] = sweep_leg(lbm, args.sweep_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -453,6 +453,22 @@ def batch_cells(scenarios: Sequence[Scenario]) -> Tuple[Optional[Cells], np.ndar
     return cells, np.concatenate(chan)
 
 
+def gap_pair(nx: int = 64, ny: int = 32, nz: int = 24, *, gap: int = 8, post_radius: int = 4,
+             cell_centre=(14.0, None, None), cell_radius: float = 3.0, level: int = 2,
+             moduli: Sequence[float] = MODULI_CTC, tau: float = 0.8, gx: float = 5e-5, steps: int = 1200) -> Scenario:
+    """One channel with a post pair across it at x = nx/2 (centres
+    y = ny/2 -+ (post_radius + gap/2)) and one cell upstream, centred on the
+    gap unless cell_centre says otherwise."""
+    mask = channel_mask(nx, ny, nz)
+    centres = [(nx / 2.0, ny / 2.0 - (post_radius + gap / 2.0)), (nx / 2.0, ny / 2.0 + (post_radius + gap / 2.0))]
+    add_posts(mask, centres, post_radius)
+    c = [cell_centre[0], ny / 2.0 if cell_centre[1] is None else cell_centre[1],
+         (nz - 1) / 2.0 if cell_centre[2] is None else cell_centre[2]]
+    cells = make_cells(np.array([c], np.float64), cell_radius, level, moduli)
+    return Scenario(f"gap{gap}", nx, ny, nz, tau, (gx, 0.0, 0.0), mask, steps, cells=cells,
+                    meta=dict(gap=gap, post_centres=centres, post_radius=post_radius))
+
+
 def adjoint_channel(nx: int = 128, ny: int = 64, nz: int = 32, *, ncells: int = 3,
                     cell_radius: float = 4.0, level: int = 2, tau: float = 0.8, gx: float = 1e-5,
                     steps: int = 300, seed: int = 5, design_x=(32, 96)) -> Scenario:
