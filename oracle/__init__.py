@@ -53,7 +53,7 @@ class _Mesh(C.Structure):
     _fields_ = [("ncells", C.c_int), ("nverts", C.c_int), ("ntris", C.c_int), ("nedges", C.c_int),
                 ("vert_off", _ip), ("tri_off", _ip), ("edge_off", _ip), ("tri", _ip), ("hinge", _ip),
                 ("moduli", _dp), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
-                ("l0", _dp), ("A0", _dp), ("th0", _dp), ("A0c", _dp), ("V0c", _dp), ("Av", _dp),
+                ("stretch_law", C.c_int), ("l0", _dp), ("A0", _dp), ("th0", _dp), ("A0c", _dp), ("V0c", _dp), ("Av", _dp),
                 ("contact", C.POINTER(_Contact))]
 
 
@@ -155,9 +155,10 @@ class Mesh:
     lengths, triangle areas, hinge angles, cell area and volume, and the
     rest area Av carried by each vertex)."""
 
-    def __init__(self, cells, moduli=None, contact=None):
+    def __init__(self, cells, moduli=None, contact=None, stretch_law=None):
         """contact: None, or dict(a, n, rcut, roff, dmin, cell_cell, planes [np, 4], cyl [nc, 3]) of
-        the soft-sphere contact forces (see orc_contact in oracle.c)."""
+        the soft-sphere contact forces (see orc_contact in oracle.c).  stretch_law: 0 linear,
+        1 neo-Hookean (default: the cells' own)."""
         self.cells = cells
         self.vert_off = np.ascontiguousarray(cells.vert_off, np.int32)
         self.tri_off = np.ascontiguousarray(cells.tri_off, np.int32)
@@ -175,6 +176,7 @@ class Mesh:
         self.s = _Mesh(nc, nv, nt, ne, _i(self.vert_off), _i(self.tri_off), _i(self.edge_off),
                        _i(self.tri), _i(self.hinge), _d(self.moduli), float(cells.xi),
                        float(cells.mass), float(cells.dt),
+                       int(getattr(cells, "stretch_law", 0) if stretch_law is None else stretch_law),
                        _d(self.l0), _d(self.A0), _d(self.th0), _d(self.A0c), _d(self.V0c), _d(self.Av),
                        None)
         self.nverts = nv

@@ -96,6 +96,7 @@ typedef struct {
     const int *hinge;    /* [nedges][4] = (p1, p2, qa, qb) */
     const double *moduli;/* [ncells][5] = (k_s, k_b, k_al, k_ag, k_v) */
     double xi, mass, dt; /* friction and mass per unit membrane area, time step */
+    int stretch_law;     /* 0: linear springs, 1: neo-Hookean springs (see membrane_energy) */
     /* rest shape, filled by orc_rest_shape */
     double *l0;  /* [nedges] */
     double *A0;  /* [ntris]  */
@@ -429,8 +430,25 @@ void orc_rest_shape(orc_mesh *M, const double *X) {
         for (int j = 0; j < 3; j++) M->Av[M->tri[3 * t + j]] += M->A0[t] / 3.0;
 }
 
+/* Stretching energy of one edge and -dE/dl.  Reading: linear springs, or
+ * (Sec. 2.3.1: nonlinear, neo-Hookean-like) the uniaxial incompressible
+ * neo-Hookean energy W(lambda) = lambda^2 + 2/lambda - 3 of the stretch
+ * lambda = l/l0, scaled so that both laws agree for small strain:
+ * E = (k_s/6) l0 W(lambda) ~ (k_s/2) (l - l0)^2 / l0.                     */
+static double stretch_energy(int law, double ks, double l, double l0) {
+    if (law == 0) return 0.5 * ks * (l - l0) * (l - l0) / l0;
+    double lam = l / l0;
+    return ks * l0 / 6.0 * (lam * lam + 2.0 / lam - 3.0);
+}
+static double stretch_force(int law, double ks, double l, double l0) {
+    if (law == 0) return -ks * (l - l0) / l0;
+    double lam = l / l0;
+    return -ks / 3.0 * (lam - 1.0 / (lam * lam));
+}
+
 /* Reading of the four moduli as energies (all values from Table 1):
- *   E_s  = sum_edges (k_s/2) (l - l0)^2 / l0          (linear stretching)
+ *   E_s  = sum_edges (k_s/2) (l - l0)^2 / l0          (linear stretching,
+ *          or the neo-Hookean edge energy above)
  *   E_b  = sum_hinges (k_b/2) (theta - theta0)^2      (preferred angle)
  *   E_al = sum_tris (k_al/2) (A - A0)^2 / A0          (local area)
  *   E_ag = (k_ag/2) (A_c - A0_c)^2 / A0_c             (global area)
@@ -454,7 +472,7 @@ double orc_membrane_energy(const orc_mesh *M, const double *X) {
             double d[3];
             sub3(vtx(X, h[1]), vtx(X, h[0]), d);
             double l = norm3(d);
-            E += 0.5 * k[0] * (l - M->l0[e]) * (l - M->l0[e]) / M->l0[e];
+            E += stretch_energy(M->stretch_law, k[0], l, M->l0[e]);
             double th = dihedral(vtx(X, h[0]), vtx(X, h[1]), vtx(X, h[2]), vtx(X, h[3]));
             E += 0.5 * k[1] * (th - M->th0[e]) * (th - M->th0[e]);
         }
@@ -517,8 +535,8 @@ void orc_membrane_forces(const orc_mesh *M, const double *X, double *F) {
             double ev[3];
             sub3(p2, p1, ev);
             double l = norm3(ev);
-            double cs = k[0] * (l - M->l0[e]) / M->l0[e];
-            addv(F, h[0], cs / l, ev);  /* -dE/dp1 = +cs (p2-p1)/l */
+            double cs = -stretch_force(M->stretch_law, k[0], l, M->l0[e]); /* dE/dl */
+            addv(F, h[0], cs / l, ev);  /* -dE/dp1 = +dE/dl (p2-p1)/l */
             addv(F, h[1], -cs / l, ev);
             /* bending */
             double th = dihedral(p1, p2, qa, qb);

@@ -217,6 +217,7 @@ class Cells:
     xi: float = 1.0        # coupling friction per unit membrane area
     mass: float = 2.0      # membrane mass per unit area (IB-point mass = mass * its rest area)
     dt: float = 1.0        # IB time step (one per lattice step)
+    stretch_law: int = 0   # 0: linear edge springs, 1: neo-Hookean edge springs
 
     @property
     def ncells(self) -> int:
@@ -252,14 +253,36 @@ def morton_order(unit: np.ndarray, bits: int = 10) -> np.ndarray:
     return np.argsort(code, kind="stable")
 
 
+# Evans-Fung biconcave profile of a red blood cell (Evans and Fung 1972):
+# half-thickness h(rho) = (R/2) sqrt(1 - rho^2) (C0 + C1 rho^2 + C2 rho^4)
+# at rho = r/R, R the disc radius.
+EVANS_FUNG = (0.207161, 2.002558, -1.122762)
+
+
+def biconcave(unit: np.ndarray) -> np.ndarray:
+    """Map unit-sphere points onto the biconcave disc of radius 1 (axis z):
+    (x, y) kept, z replaced by sign(z) h(rho) with rho^2 = x^2 + y^2."""
+    c0, c1, c2 = EVANS_FUNG
+    rho2 = np.clip(unit[:, 0] ** 2 + unit[:, 1] ** 2, 0.0, 1.0)
+    h = 0.5 * np.sqrt(1.0 - rho2) * (c0 + c1 * rho2 + c2 * rho2 ** 2)
+    return np.stack([unit[:, 0], unit[:, 1], np.sign(unit[:, 2]) * h], axis=1)
+
+
 def make_cells(centres: np.ndarray, radius: float, level: int,
-               moduli: Sequence[float] = MODULI_CTC, xi: float = 1.0) -> Cells:
-    """Icosphere cells of the given radius around ``centres`` [n,3].
+               moduli: Sequence[float] = MODULI_CTC, xi: float = 1.0, shape: str = "sphere",
+               stretch_law: int = 0) -> Cells:
+    """Icosphere cells of the given radius around ``centres`` [n,3]; with
+    shape="rbc" the icosphere is mapped onto the biconcave disc of that
+    radius (red blood cell, Table 1 geometry).
 
     The template's vertices are numbered along a Z-order curve, so
     consecutive vertex ids are neighbours on the surface (and so are the
     lattice nodes their stencils touch)."""
     unit, tris = icosphere(level)
+    if shape == "rbc":
+        unit = biconcave(unit)
+    elif shape != "sphere":
+        raise ValueError(f"unknown cell shape {shape}")
     perm = morton_order(unit)
     inv = np.empty_like(perm)
     inv[perm] = np.arange(len(perm))
@@ -281,7 +304,7 @@ def make_cells(centres: np.ndarray, radius: float, level: int,
         anchor=anchor,
         offset=off.reshape(-1, 3),
         moduli=np.tile(np.asarray(moduli, dtype=np.float64), (n, 1)),
-        xi=xi)
+        xi=xi, stretch_law=int(stretch_law))
 
 
 @dataclasses.dataclass
@@ -444,12 +467,12 @@ def batch_cells(scenarios: Sequence[Scenario]) -> Tuple[Optional[Cells], np.ndar
         chan.append(np.full(c.ncells, k, np.int32))
     c0 = parts[0][1]
     for _, c in parts:
-        if (c.xi, c.mass, c.dt) != (c0.xi, c0.mass, c0.dt):
-            raise ValueError("batched cells must share xi, mass and dt")
+        if (c.xi, c.mass, c.dt, c.stretch_law) != (c0.xi, c0.mass, c0.dt, c0.stretch_law):
+            raise ValueError("batched cells must share xi, mass, dt and the stretching law")
     cells = Cells(np.asarray(vo, np.int32), np.asarray(to, np.int32), np.asarray(eo, np.int32),
                   np.concatenate(tri).astype(np.int32), np.concatenate(hin).astype(np.int32),
                   np.concatenate(anc).astype(np.int32), np.concatenate(off), np.concatenate(mod),
-                  xi=c0.xi, mass=c0.mass, dt=c0.dt)
+                  xi=c0.xi, mass=c0.mass, dt=c0.dt, stretch_law=c0.stretch_law)
     return cells, np.concatenate(chan)
 
 

@@ -1,0 +1,103 @@
+"""Pins of the neo-Hookean stretching law and of the biconcave red-blood-cell
+rest shape (Sec. 2.3.1 and Table 1), CPU only.
+
+  - neo-Hookean edge energy: forces are its negative gradient (central
+    differences), the small-strain limit equals the linear law, and the hand
+    value of a uniform stretch by 2 (energy 2/3 of the linear law's);
+  - the generated biconcave disc converges, at second order in the mesh
+    spacing, to the area and volume of the Evans-Fung surface computed by
+    quadrature of its profile;
+  - at the rest shape the forces vanish; after a deformation they have no
+    net force or torque."""
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_1110_0995_amd import scenario as S
+
+ONLY_KS = (0.01, 0.0, 0.0, 0.0, 0.0)
+
+
+def _mesh(orc, shape="sphere", level=2, law=1, moduli=ONLY_KS, radius=3.0):
+    cells = S.make_cells(np.array([[20.0, 20.0, 20.0]]), radius, level, moduli, shape=shape, stretch_law=law)
+    X0 = cells.positions()
+    M = orc.Mesh(cells)
+    M.rest_shape(X0)
+    return cells, M, X0
+
+
+def test_neo_hookean_force_is_minus_gradient(orc):
+    rng = np.random.default_rng(0)
+    for shape in ("sphere", "rbc"):
+        cells, M, X0 = _mesh(orc, shape, moduli=S.MODULI_RBC)
+        X = X0 + 0.2 * rng.standard_normal(X0.shape)
+        F = M.forces(X)
+        h = 1e-5
+        for k in rng.choice(len(X), 10, replace=False):
+            for a in range(3):
+                Xp, Xm = X.copy(), X.copy()
+                Xp[k, a] += h
+                Xm[k, a] -= h
+                fd = -(M.energy(Xp) - M.energy(Xm)) / (2 * h)
+                # truncation (h^2) and rounding of the differenced energy bound the
+                # agreement to ~1e-8 of the largest force; a wrong term is O(1)
+                assert F[k, a] == pytest.approx(fd, rel=1e-6, abs=1e-8 * np.abs(F).max())
+
+
+def test_neo_hookean_limits_and_hand_value(orc):
+    cells, Mn, X0 = _mesh(orc, law=1)
+    Ml = orc.Mesh(cells, stretch_law=0)
+    Ml.rest_shape(X0)
+    c = X0.mean(0)
+    for lam, ratio, tol in ((1 + 1e-4, 1.0, 1e-3), (2.0, 2.0 / 3.0, 1e-13)):
+        X = c + lam * (X0 - c)  # every edge stretched by lam
+        assert Mn.energy(X) / Ml.energy(X) == pytest.approx(ratio, rel=tol)
+    # compression costs more than in the linear law (the energy diverges as lam -> 0)
+    X = c + 0.5 * (X0 - c)
+    assert Mn.energy(X) > Ml.energy(X)
+
+
+def _evans_fung(R):
+    c0, c1, c2 = S.EVANS_FUNG
+    h = lambda r: 0.5 * R * np.sqrt(max(1 - (r / R) ** 2, 0.0)) * (c0 + c1 * (r / R) ** 2 + c2 * (r / R) ** 4)
+
+    def dh(r):
+        eps = 1e-7 * R
+        return (h(r + eps) - h(r - eps)) / (2 * eps)
+
+    V = 2 * integrate.quad(lambda r: 2 * np.pi * r * h(r), 0, R, limit=200)[0]
+    # area: the two faces, parametrised by r up to the rim where h' diverges
+    # (integrable: use t = sqrt(1 - r/R) near the rim)
+    A = 2 * integrate.quad(lambda r: 2 * np.pi * r * np.sqrt(1 + dh(r) ** 2), 0, R * (1 - 1e-12), limit=400)[0]
+    return A, V
+
+
+def test_biconcave_disc_converges_to_evans_fung(orc):
+    R = 3.91
+    A_ex, V_ex = _evans_fung(R)
+    # the well-known red-cell numbers for R = 3.91 um: about 135 um^2 and 94 um^3
+    assert 130 < A_ex < 140 and 90 < V_ex < 98
+    errs = []
+    for level in (3, 4, 5):
+        cells = S.make_cells(np.array([[20.0, 20.0, 20.0]]), R, level, S.MODULI_RBC, shape="rbc")
+        M = orc.Mesh(cells)
+        A, V = M.area_volume(cells.positions())
+        errs.append((abs(A[0] - A_ex) / A_ex, abs(V[0] - V_ex) / V_ex))
+    errs = np.array(errs)
+    assert errs[-1].max() < 2e-3
+    # halving the mesh spacing divides the error by about 4
+    assert np.all(errs[1] / errs[2] > 3.0) and np.all(errs[0] / errs[1] > 3.0)
+
+
+def test_rbc_rest_and_invariances(orc):
+    rng = np.random.default_rng(3)
+    cells, M, X0 = _mesh(orc, "rbc", level=3, moduli=S.MODULI_RBC, radius=3.91)
+    F0 = M.forces(X0)
+    assert np.abs(F0).max() < 1e-12
+    # the dimple: rest hinge angles are not all of one sign
+    assert M.th0.min() < -1e-3 and M.th0.max() > 1e-3
+    X = X0 + 0.1 * rng.standard_normal(X0.shape)
+    F = M.forces(X)
+    assert np.abs(F.sum(0)).max() <= 1e-12 * np.abs(F).max() * len(F)
+    tq = np.cross(X - X.mean(0), F).sum(0)
+    assert np.abs(tq).max() <= 1e-11 * np.abs(F).max() * len(F)
