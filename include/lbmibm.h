@@ -141,6 +141,8 @@ typedef struct {
     double dt;               /* IB time step, > 0 */
     const ibm_contact *contact; /* host struct (its arrays on the device) of contact forces, or NULL for none;
                                    ibm_rest_shape sizes the pair list for it, so it must not change afterwards */
+    int32_t stretch_law;     /* edge stretching (Sec. 2.3.1): 0 = linear springs (k_s/2)(l - l0)^2/l0;
+                                1 = neo-Hookean (k_s/6) l0 (lam^2 + 2/lam - 3), lam = l/l0 (same small-strain limit) */
     /* filled by ibm_rest_shape; the caller must not edit them */
     int32_t max_cell_verts, max_cell_tris, max_cell_edges;
     uint32_t checked;

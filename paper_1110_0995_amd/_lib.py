@@ -43,7 +43,7 @@ class IbmMesh(C.Structure):
                 ("l0", C.c_void_p), ("a0", C.c_void_p), ("th0", C.c_void_p), ("a0c", C.c_void_p),
                 ("v0c", C.c_void_p), ("avert", C.c_void_p), ("vtri_off", C.c_void_p), ("vtri", C.c_void_p),
                 ("vedge_off", C.c_void_p), ("vedge", C.c_void_p), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
-                ("contact", C.POINTER(IbmContact)), ("max_cell_verts", C.c_int32), ("max_cell_tris", C.c_int32), ("max_cell_edges", C.c_int32),
+                ("contact", C.POINTER(IbmContact)), ("stretch_law", C.c_int32), ("max_cell_verts", C.c_int32), ("max_cell_tris", C.c_int32), ("max_cell_edges", C.c_int32),
                 ("checked", C.c_uint32)]
 
 

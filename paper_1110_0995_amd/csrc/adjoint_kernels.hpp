@@ -218,6 +218,7 @@ struct JvpArgs {
     const void *moduli;
     const double *l0, *a0, *th0, *a0c, *v0c, *avert;
     int ncells, nverts, ntris, nedges, maxv;
+    int stretch_law;
     double *f_out;    // [3][nverts] F_el(X) in FP64, or null
     double *jvp_out;  // [3][nverts] (dF_el/dX) w
 };
@@ -296,7 +297,8 @@ __global__ __launch_bounds__(kMembThreads) void k_adj_membrane(JvpArgs a) {
             const Dual l2 = dotd(ev, ev), l = dsqrt(l2);
             const Dual th = datan2(dotd(cross(na, nb), ev) / l, dotd(na, nb));
             const double ref = a.l0[e];
-            const Dual cs = (ks / ref) * (l - mk(ref)) / l;
+            const Dual lam = l / ref;
+            const Dual cs = (a.stretch_law ? (ks / 3.0) * (lam - mk(1.0) / (lam * lam)) : (ks / ref) * (l - mk(ref))) / l;
             const Dual cb = kb * (th - mk(a.th0[e]));
             const DV3 ga = (-(l / dotd(na, na))) * na, gb = (-(l / dotd(nb, nb))) * nb;
             DV3 gth;

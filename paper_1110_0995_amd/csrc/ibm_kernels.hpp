@@ -98,6 +98,7 @@ struct MembArgs {
     const void *moduli;
     double *l0, *a0, *th0, *a0c, *v0c, *avert;
     int ncells, nverts, ntris, nedges, maxv, maxt, maxe;
+    int stretch_law;  // 0: linear edge springs, 1: neo-Hookean edge springs
     uint8_t *need;   // [N] stencil-node marks
     uint8_t *tneed;  // [ntiles] tile marks
 };
@@ -220,7 +221,10 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
             continue;
         }
         const double ref = a.l0[e0 + e];
-        eco[2 * e] = R(ks * (l - ref) / ref / l);     // force on p1 = cs (p2 - p1)
+        // dE/dl / l; neo-Hookean: E = (k_s/6) l0 (lam^2 + 2/lam - 3), lam = l/l0
+        const double lam = l / ref;
+        const double dEdl = a.stretch_law ? ks / 3.0 * (lam - 1.0 / (lam * lam)) : ks * (l - ref) / ref;
+        eco[2 * e] = R(dEdl / l);                      // force on p1 = cs (p2 - p1)
         eco[2 * e + 1] = R(kb * (th - a.th0[e0 + e]));  // force = -cb grad theta
     }
     __syncthreads();

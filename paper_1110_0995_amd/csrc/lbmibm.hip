@@ -91,6 +91,7 @@ uint64_t mesh_launch_key(const ibm_mesh *m) {
     f.mixd(m->xi);
     f.mixd(m->mass);
     f.mixd(m->dt);
+    f.mix((uint64_t)m->stretch_law);
     if (const ibm_contact *k = m->contact) {
         for (double v : {k->a, k->n, k->rcut, k->roff, k->dmin}) f.mixd(v);
         f.mix((uint64_t)k->cell_cell);
@@ -540,6 +541,7 @@ static int check_mesh_ptrs(const lbm_ctx *c, const ibm_mesh *m) {
     if (!(m->xi > 0) || !(m->mass > 0) || !(m->dt > 0) || !std::isfinite(m->xi) || !std::isfinite(m->mass) ||
         !std::isfinite(m->dt))
         return fail(LBM_EINVAL, "xi, mass and dt must be finite and > 0");
+    if (m->stretch_law != 0 && m->stretch_law != 1) return fail(LBM_EINVAL, "stretch_law must be 0 or 1");
     if (const ibm_contact *k = m->contact) {
         if (!(k->a > 0) || !(k->n > 0) || !(k->rcut > 0) || !(k->dmin > 0) || !(k->dmin <= k->rcut) ||
             !(k->roff >= 0) || !std::isfinite(k->a) || !std::isfinite(k->n) || !std::isfinite(k->rcut) ||
@@ -595,6 +597,7 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.ntris = m->ntris;
     a.nedges = m->nedges;
     a.maxv = m->max_cell_verts;
+    a.stretch_law = m->stretch_law;
     a.need = c->need;
     a.tneed = c->tneed;
     const size_t sm = membrane_lds_bytes<R>(m->max_cell_verts, m->max_cell_tris, m->max_cell_edges);
@@ -1034,6 +1037,7 @@ static void launch_jvp(lbm_ctx *c, const ibm_mesh *m, const double *x, const dou
     a.ntris = m->ntris;
     a.nedges = m->nedges;
     a.maxv = m->max_cell_verts;
+    a.stretch_law = m->stretch_law;
     a.f_out = f_out;
     a.jvp_out = jvp_out;
     k_adj_membrane<R><<<m->ncells, kMembThreads, adj_membrane_lds_bytes(m->max_cell_verts), c->s>>>(a);

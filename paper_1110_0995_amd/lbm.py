@@ -250,7 +250,7 @@ class Mesh:
                               p(self.th0), p(self.a0c), p(self.v0c), p(self.avert), p(self.vtri_off), p(self.vtri),
                               p(self.vedge_off), p(self.vedge), float(cells.xi), float(cells.mass),
                               float(cells.dt), None if self.contact is None else C.pointer(self.contact),
-                              0, 0, 0, 0)
+                              int(getattr(cells, "stretch_law", 0)), 0, 0, 0, 0)
         _lib.check(lat.lib.ibm_rest_shape(lat.ctx, C.byref(self.s)))
         lat.meshes.append(self)
 

@@ -40,6 +40,14 @@ import numpy as np
 # as lattice-unit values.
 MODULI_CTC = (0.0023, 0.000464, 0.0029, 0.29, 2.9)
 MODULI_RBC = (0.008, 0.0016, 0.01, 1.0, 10.0)
+# Membrane mass per unit area for red cells.  The explicit point update is
+# linearly stable while the stiffest membrane mode satisfies
+# lambda_max(H / m) < 2 + 2 (1 - xi/mass) (H the energy Hessian, friction xi
+# per area); with the red-cell moduli on the biconcave disc lambda_max is
+# about 14 / mass (the volume term dominates), so mass 2 is unstable and 8
+# leaves a wide margin.  Tumour cells (sphere, CTC moduli: about 2.2 / mass)
+# keep mass 2.
+MASS_RBC = 8.0
 
 
 # ---------------------------------------------------------------------------
@@ -270,7 +278,7 @@ def biconcave(unit: np.ndarray) -> np.ndarray:
 
 def make_cells(centres: np.ndarray, radius: float, level: int,
                moduli: Sequence[float] = MODULI_CTC, xi: float = 1.0, shape: str = "sphere",
-               stretch_law: int = 0) -> Cells:
+               stretch_law: int = 0, mass: float = 2.0) -> Cells:
     """Icosphere cells of the given radius around ``centres`` [n,3]; with
     shape="rbc" the icosphere is mapped onto the biconcave disc of that
     radius (red blood cell, Table 1 geometry).
@@ -304,7 +312,7 @@ def make_cells(centres: np.ndarray, radius: float, level: int,
         anchor=anchor,
         offset=off.reshape(-1, 3),
         moduli=np.tile(np.asarray(moduli, dtype=np.float64), (n, 1)),
-        xi=xi, stretch_law=int(stretch_law))
+        xi=xi, mass=float(mass), stretch_law=int(stretch_law))
 
 
 @dataclasses.dataclass
@@ -447,12 +455,22 @@ def contact_params_batch(scenarios: Sequence[Scenario], **kw) -> dict:
     return d
 
 
+def concat_cells(populations: Sequence[Cells]) -> Cells:
+    """One population from several (vertex, triangle and edge ids renumbered)."""
+    cells, _ = _concat([(0, c) for c in populations])
+    return cells
+
+
 def batch_cells(scenarios: Sequence[Scenario]) -> Tuple[Optional[Cells], np.ndarray]:
     """Concatenate the cell populations of several channels into one (vertex,
     triangle and edge ids renumbered) and give the channel of each cell."""
     parts = [(k, s.cells) for k, s in enumerate(scenarios) if s.cells is not None]
     if not parts:
         return None, np.zeros(0, np.int32)
+    return _concat(parts)
+
+
+def _concat(parts) -> Tuple[Cells, np.ndarray]:
     vo, to, eo = [0], [0], [0]
     tri, hin, anc, off, mod, chan = [], [], [], [], [], []
     for k, c in parts:

@@ -101,3 +101,39 @@ def test_rbc_rest_and_invariances(orc):
     assert np.abs(F.sum(0)).max() <= 1e-12 * np.abs(F).max() * len(F)
     tq = np.cross(X - X.mean(0), F).sum(0)
     assert np.abs(tq).max() <= 1e-11 * np.abs(F).max() * len(F)
+
+
+def test_red_cell_mass_keeps_the_point_update_stable(orc):
+    """The linear stability bound of the explicit point update,
+    lambda_max(H/m) < 2 + 2 (1 - xi/mass), by power iteration on the
+    oracle's force Jacobian (central differences): red-cell moduli on the
+    biconcave disc violate it at mass 2 and satisfy it at MASS_RBC; a coupled
+    run confirms both."""
+    def lam_max(cells):
+        M = orc.Mesh(cells)
+        X = cells.positions()
+        M.rest_shape(X)
+        m = M.point_mass()[:, None]
+        v = np.random.default_rng(0).standard_normal(X.shape)
+        lam = 0.0
+        for _ in range(150):
+            v /= np.linalg.norm(v)
+            w = -(M.forces(X + 1e-6 * v) - M.forces(X - 1e-6 * v)) / 2e-6 / m
+            lam = float((v * w).sum())
+            v = w
+        return lam
+
+    for mass, stable in ((2.0, False), (S.MASS_RBC, True)):
+        cells = S.make_cells(np.array([[12.0, 12.0, 11.5]]), 3.91, 2, S.MODULI_RBC, shape="rbc", stretch_law=1,
+                             mass=mass)
+        bound = 2 + 2 * (1 - cells.xi / mass)
+        assert (lam_max(cells) < bound) == stable
+        L = orc.Lattice(24, 24, 24, tau=0.8, g=(5e-5, 0, 0), solid=S.channel_mask(24, 24, 24))
+        M = orc.Mesh(cells)
+        X = cells.positions()
+        M.rest_shape(X)
+        X += 1e-3 * np.random.default_rng(1).standard_normal(X.shape)
+        V = np.zeros_like(X)
+        orc.run(L, M, L.rest(), X, V, nsteps=60)
+        grew = not np.isfinite(X).all() or np.abs(X - cells.positions()).max() > 1.0
+        assert grew != stable
