@@ -71,6 +71,7 @@ def lib():
         L = C.CDLL(_SO)
         L.orc_membrane_energy.restype = C.c_double
         L.orc_contact_energy.restype = C.c_double
+        L.orc_dipole_energy.restype = C.c_double
         L.orc_step.restype = C.c_int
         L.orc_run.restype = C.c_int
         _lib = L
@@ -288,3 +289,63 @@ def run(L: Lattice, M: Optional[Mesh], f: np.ndarray, X=None, V=None, nsteps: in
     if rc:
         raise MemoryError("orc_run failed")
     return f
+
+
+# ---------------------------------------------------------------------------
+# magnetic bead stage
+
+class _Mag(C.Structure):
+    _fields_ = [("nsheets", C.c_int), ("sheets", _dp), ("bias", C.c_double * 3), ("a", C.c_double),
+                ("chi", C.c_double), ("eta", C.c_double), ("dt", C.c_double), ("rep_a", C.c_double),
+                ("rep_n", C.c_double), ("rep_cut", C.c_double), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("periodic", C.c_int * 3), ("walls_z", C.c_int), ("quad", C.c_int)]
+
+
+class Magnet:
+    """Bead-stage parameters (see orc_mag in oracle.c).  sheets [ns, 6] =
+    (z, x0, x1, y0, y1, sigma); positions are [n, 3] arrays."""
+
+    def __init__(self, sheets, bias, a, chi, eta, dt, rep=(1e-3, 2.0, 0.5), dims=(64, 64, 32),
+                 periodic=(1, 1, 0), walls_z=True, quad=16):
+        self.sheets = np.ascontiguousarray(np.asarray(sheets, np.float64).reshape(-1, 6))
+        self.s = _Mag(len(self.sheets), _d(self.sheets) if len(self.sheets) else _dp(), (C.c_double * 3)(*bias),
+                      float(a), float(chi), float(eta), float(dt), float(rep[0]), float(rep[1]), float(rep[2]),
+                      int(dims[0]), int(dims[1]), int(dims[2]), (C.c_int * 3)(*periodic), int(bool(walls_z)),
+                      int(quad))
+
+    def field(self, p) -> np.ndarray:
+        p = np.ascontiguousarray(np.asarray(p, np.float64).reshape(-1, 3))
+        B = np.zeros_like(p)
+        lib().orc_mag_field(C.byref(self.s), _d(p), C.c_int(len(p)), _d(B))
+        return B
+
+    def forces(self, x):
+        x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1, 3))
+        m, F = np.zeros_like(x), np.zeros_like(x)
+        lib().orc_mag_forces(C.byref(self.s), _d(x), C.c_int(len(x)), _d(m), _d(F))
+        return m, F
+
+    def run(self, x, nsteps: int) -> np.ndarray:
+        """nsteps overdamped steps; x [n, 3] advanced in place and returned."""
+        if lib().orc_mag_run(C.byref(self.s), _d(x), C.c_int(len(x)), C.c_int(nsteps)):
+            raise MemoryError("orc_mag_run failed")
+        return x
+
+    def freeze(self, x, solid) -> np.ndarray:
+        """OR the nodes within a bead radius of a bead centre into solid (uint8 [N])."""
+        x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1, 3))
+        lib().orc_mag_freeze(C.byref(self.s), _d(x), C.c_int(len(x)),
+                             solid.ctypes.data_as(C.POINTER(C.c_uint8)))
+        return solid
+
+
+def dipole_force(m1, m2, r) -> np.ndarray:
+    F = np.zeros(3)
+    lib().orc_dipole_force(_d(np.ascontiguousarray(m1, np.float64)), _d(np.ascontiguousarray(m2, np.float64)),
+                           _d(np.ascontiguousarray(r, np.float64)), _d(F))
+    return F
+
+
+def dipole_energy(m1, m2, r) -> float:
+    return lib().orc_dipole_energy(_d(np.ascontiguousarray(m1, np.float64)), _d(np.ascontiguousarray(m2, np.float64)),
+                                   _d(np.ascontiguousarray(r, np.float64)))

@@ -44,6 +44,7 @@
 #endif
 
 #define Q 19
+#define PI_ 3.14159265358979323846
 
 /* D3Q19 velocities: rest, 6 faces, 12 edges; the opposite of odd i is i+1. */
 static const int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
@@ -732,4 +733,173 @@ int orc_run(const orc_lattice *L, const orc_mesh *M, double *f, double *X, doubl
     if (a != f) memcpy(f, a, sizeof(double) * Q * N);
     free(g);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* magnetic bead stage (the chain-forming part of the filter, Sec. 2.5)      */
+/* ------------------------------------------------------------------------ */
+
+/* Units: lattice lengths and steps, magnetic constant mu0 = 1, so B = H
+ * outside the magnets.  Readings: the magnets are planar sheets of uniform
+ * magnetic surface charge sigma (z = const, rectangle [x0,x1] x [y0,y1]),
+ * whose field is H(r) = sigma/(4 pi) * integral (r - r')/|r - r'|^3 dA';
+ * plus a uniform bias field.  A soft-magnetic bead of radius a and
+ * susceptibility chi takes the induced moment m = 4 pi a^3 chi/(chi + 3) B
+ * (a sphere in a uniform field; the beads' fields on each other are not fed
+ * back into the moments).  Forces: the gradient force F_g = grad(m.B) at
+ * fixed m; the dipole interaction of two beads (the paper's interaction
+ * equation); a soft-sphere repulsion between beads (surface distance
+ * r - 2a) and from the walls z = 1/2, nz - 3/2 (distance z - 1/2 - a);
+ * overdamped motion against Stokes drag, x += dt F / (6 pi eta a). */
+typedef struct {
+    int nsheets;
+    const double *sheets; /* [nsheets][6] = (z, x0, x1, y0, y1, sigma) */
+    double bias[3];
+    double a, chi, eta, dt;
+    double rep_a, rep_n, rep_cut; /* repulsion U(d) = rep_a d^-rep_n for d in (0, rep_cut), linear below rep_cut/100 */
+    int nx, ny, nz;
+    int periodic[3];
+    int walls_z;                  /* 1: walls at z = 1/2 and nz - 3/2 */
+    int quad;                     /* Gauss-Legendre panels per side of a sheet (8 points per panel) */
+} orc_mag;
+
+/* 8-point Gauss-Legendre nodes and weights on [-1, 1] */
+static const double GLX[8] = {-0.9602898564975363, -0.7966664774136267, -0.5255324099163290, -0.1834346424956498,
+                              0.1834346424956498,  0.5255324099163290,  0.7966664774136267,  0.9602898564975363};
+static const double GLW[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873, 0.3626837833783620,
+                              0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
+
+/* field of the sheets and the bias at p, by composite Gauss-Legendre quadrature */
+static void mag_field_at(const orc_mag *G, const double p[3], double B[3]) {
+    for (int d = 0; d < 3; d++) B[d] = G->bias[d];
+    for (int s = 0; s < G->nsheets; s++) {
+        const double *S = G->sheets + 6 * s;
+        /* panels no wider than half the point's distance from the sheet plane */
+        double L = fmax(S[2] - S[1], S[4] - S[3]), dz = fabs(p[2] - S[0]);
+        int np = G->quad > 0 ? G->quad : 16;
+        double need = dz > 0 ? ceil(2.0 * L / dz) : 512.0;
+        if (need > np) np = need > 512.0 ? 512 : (int)need;
+        double hx = (S[2] - S[1]) / np, hy = (S[4] - S[3]) / np;
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < np; i++)
+            for (int j = 0; j < np; j++)
+                for (int a = 0; a < 8; a++)
+                    for (int b = 0; b < 8; b++) {
+                        double xq = S[1] + hx * (i + 0.5 + 0.5 * GLX[a]);
+                        double yq = S[3] + hy * (j + 0.5 + 0.5 * GLX[b]);
+                        double r[3] = {p[0] - xq, p[1] - yq, p[2] - S[0]};
+                        double R = norm3(r);
+                        double w = GLW[a] * GLW[b] * 0.25 * hx * hy / (R * R * R);
+                        for (int d = 0; d < 3; d++) acc[d] += w * r[d];
+                    }
+        for (int d = 0; d < 3; d++) B[d] += S[5] / (4.0 * PI_) * acc[d];
+    }
+}
+
+void orc_mag_field(const orc_mag *G, const double *p, int n, double *B) {
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; k++) mag_field_at(G, p + 3 * k, B + 3 * k);
+}
+
+/* dipole-dipole force on bead 2 from bead 1, r = x2 - x1 (the paper's
+ * interaction equation with mu0 = 1) */
+static void dipole_force(const double *m1, const double *m2, const double *r, double *F) {
+    double r2 = dot3(r, r), rn = sqrt(r2);
+    double m1r = dot3(m1, r), m2r = dot3(m2, r), mm = dot3(m1, m2);
+    double c = 3.0 / (4.0 * PI_ * r2 * r2 * rn);
+    for (int d = 0; d < 3; d++) F[d] = c * (m1r * m2[d] + m2r * m1[d] + mm * r[d] - 5.0 * m1r * m2r * r[d] / r2);
+}
+
+/* dipole-dipole energy, for the gradient pin: U = (m1.m2 - 3 (m1.rh)(m2.rh)) / (4 pi r^3) */
+double orc_dipole_energy(const double *m1, const double *m2, const double *r) {
+    double r2 = dot3(r, r), rn = sqrt(r2);
+    return (dot3(m1, m2) - 3.0 * dot3(m1, r) * dot3(m2, r) / r2) / (4.0 * PI_ * r2 * rn);
+}
+
+void orc_dipole_force(const double *m1, const double *m2, const double *r, double *F) { dipole_force(m1, m2, r, F); }
+
+static double rep_force(const orc_mag *G, double d) {
+    if (d >= G->rep_cut) return 0.0;
+    double dmin = G->rep_cut / 100.0;
+    return G->rep_n * G->rep_a * pow(d < dmin ? dmin : d, -G->rep_n - 1.0);
+}
+
+/* moments m [n][3] and total forces F [n][3] on beads at x [n][3] */
+void orc_mag_forces(const orc_mag *G, const double *x, int n, double *m, double *F) {
+    const double alpha = 4.0 * PI_ * G->a * G->a * G->a * G->chi / (G->chi + 3.0);
+    const int dims[3] = {G->nx, G->ny, G->nz};
+    /* moments and gradient forces F_j = sum_i m_i dB_i/dx_j (central differences) */
+    for (int k = 0; k < n; k++) {
+        double B[3];
+        mag_field_at(G, x + 3 * k, B);
+        for (int d = 0; d < 3; d++) m[3 * k + d] = alpha * B[d];
+    }
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < n; k++) {
+        double h = 1e-4 * G->a;
+        for (int j = 0; j < 3; j++) {
+            double pp[3] = {x[3 * k], x[3 * k + 1], x[3 * k + 2]}, pm[3] = {pp[0], pp[1], pp[2]};
+            pp[j] += h;
+            pm[j] -= h;
+            double Bp[3], Bm[3];
+            mag_field_at(G, pp, Bp);
+            mag_field_at(G, pm, Bm);
+            double s = 0.0;
+            for (int i = 0; i < 3; i++) s += m[3 * k + i] * (Bp[i] - Bm[i]) / (2 * h);
+            F[3 * k + j] = s;
+        }
+    }
+    /* bead-bead dipole forces and repulsion (all pairs, minimum image) */
+    for (int k = 0; k < n; k++)
+        for (int l = 0; l < n; l++) {
+            if (l == k) continue;
+            double r[3];
+            for (int d = 0; d < 3; d++) r[d] = min_image(x[3 * k + d] - x[3 * l + d], dims[d], G->periodic[d]);
+            double Fd[3];
+            dipole_force(m + 3 * l, m + 3 * k, r, Fd); /* on k from l */
+            double rn = norm3(r);
+            double fr = rep_force(G, rn - 2.0 * G->a) / rn;
+            for (int d = 0; d < 3; d++) F[3 * k + d] += Fd[d] + fr * r[d];
+        }
+    if (G->walls_z)
+        for (int k = 0; k < n; k++) {
+            double z = x[3 * k + 2];
+            F[3 * k + 2] += rep_force(G, z - 0.5 - G->a) - rep_force(G, (G->nz - 1.5) - z - G->a);
+        }
+}
+
+/* nsteps overdamped steps of the beads, x [n][3] in place */
+int orc_mag_run(const orc_mag *G, double *x, int n, int nsteps) {
+    double *m = malloc(sizeof(double) * 3 * n), *F = malloc(sizeof(double) * 3 * n);
+    if (!m || !F) { free(m); free(F); return -1; }
+    const double mob = G->dt / (6.0 * PI_ * G->eta * G->a);
+    for (int s = 0; s < nsteps; s++) {
+        orc_mag_forces(G, x, n, m, F);
+        for (int i = 0; i < 3 * n; i++) x[i] += mob * F[i];
+    }
+    free(m);
+    free(F);
+    return 0;
+}
+
+/* the chains fixed in space: node (x, y, z) is solid if its centre lies
+ * within a of a bead centre (minimum image); solid is OR-ed in */
+void orc_mag_freeze(const orc_mag *G, const double *x, int n, uint8_t *solid) {
+    const int dims[3] = {G->nx, G->ny, G->nz};
+    for (int z = 0; z < G->nz; z++)
+        for (int y = 0; y < G->ny; y++)
+            for (int xx = 0; xx < G->nx; xx++) {
+                const double p[3] = {xx, y, z};
+                for (int k = 0; k < n; k++) {
+                    double r2 = 0.0;
+                    for (int d = 0; d < 3; d++) {
+                        double dd = min_image(p[d] - x[3 * k + d], dims[d], G->periodic[d]);
+                        r2 += dd * dd;
+                    }
+                    if (r2 <= G->a * G->a) {
+                        solid[xx + (long)G->nx * (y + (long)G->ny * z)] = 1;
+                        break;
+                    }
+                }
+            }
 }
