@@ -313,11 +313,14 @@ class Magnet:
                       int(dims[0]), int(dims[1]), int(dims[2]), (C.c_int * 3)(*periodic), int(bool(walls_z)),
                       int(quad))
 
-    def field(self, p) -> np.ndarray:
+    def field(self, p, jacobian: bool = False):
+        """B [n, 3] at points p [n, 3]; with jacobian=True also
+        J [n, 3, 3], J[k, i, j] = dB_i/dx_j."""
         p = np.ascontiguousarray(np.asarray(p, np.float64).reshape(-1, 3))
         B = np.zeros_like(p)
-        lib().orc_mag_field(C.byref(self.s), _d(p), C.c_int(len(p)), _d(B))
-        return B
+        J = np.zeros((len(p), 3, 3)) if jacobian else None
+        lib().orc_mag_field(C.byref(self.s), _d(p), C.c_int(len(p)), _d(B), _d(J) if jacobian else None)
+        return (B, J) if jacobian else B
 
     def forces(self, x):
         x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1, 3))

@@ -769,18 +769,23 @@ static const double GLX[8] = {-0.9602898564975363, -0.7966664774136267, -0.52553
 static const double GLW[8] = {0.1012285362903763, 0.2223810344533745, 0.3137066458778873, 0.3626837833783620,
                               0.3626837833783620, 0.3137066458778873, 0.2223810344533745, 0.1012285362903763};
 
-/* field of the sheets and the bias at p, by composite Gauss-Legendre quadrature */
-static void mag_field_at(const orc_mag *G, const double p[3], double B[3]) {
+/* field of the sheets and the bias at p, and (if J is not NULL) its
+ * gradient J[i][j] = dB_i/dx_j, by composite Gauss-Legendre quadrature of
+ * the Coulomb kernel r/|r|^3 and of its gradient delta_ij/|r|^3 -
+ * 3 r_i r_j/|r|^5 (differentiation under the integral sign) */
+static void mag_field_at(const orc_mag *G, const double p[3], double B[3], double J[9]) {
     for (int d = 0; d < 3; d++) B[d] = G->bias[d];
+    if (J)
+        for (int d = 0; d < 9; d++) J[d] = 0.0;
     for (int s = 0; s < G->nsheets; s++) {
         const double *S = G->sheets + 6 * s;
-        /* panels no wider than half the point's distance from the sheet plane */
+        /* panels no wider than a third of the point's distance from the sheet plane */
         double L = fmax(S[2] - S[1], S[4] - S[3]), dz = fabs(p[2] - S[0]);
         int np = G->quad > 0 ? G->quad : 16;
-        double need = dz > 0 ? ceil(2.0 * L / dz) : 512.0;
-        if (need > np) np = need > 512.0 ? 512 : (int)need;
+        double need = dz > 0 ? ceil(3.0 * L / dz) : 1024.0;
+        if (need > np) np = need > 1024.0 ? 1024 : (int)need;
         double hx = (S[2] - S[1]) / np, hy = (S[4] - S[3]) / np;
-        double acc[3] = {0.0, 0.0, 0.0};
+        double acc[3] = {0.0, 0.0, 0.0}, jac[9] = {0.0};
         for (int i = 0; i < np; i++)
             for (int j = 0; j < np; j++)
                 for (int a = 0; a < 8; a++)
@@ -788,17 +793,23 @@ static void mag_field_at(const orc_mag *G, const double p[3], double B[3]) {
                         double xq = S[1] + hx * (i + 0.5 + 0.5 * GLX[a]);
                         double yq = S[3] + hy * (j + 0.5 + 0.5 * GLX[b]);
                         double r[3] = {p[0] - xq, p[1] - yq, p[2] - S[0]};
-                        double R = norm3(r);
-                        double w = GLW[a] * GLW[b] * 0.25 * hx * hy / (R * R * R);
+                        double R2 = dot3(r, r), R = sqrt(R2);
+                        double w = GLW[a] * GLW[b] * 0.25 * hx * hy / (R2 * R);
                         for (int d = 0; d < 3; d++) acc[d] += w * r[d];
+                        if (J)
+                            for (int d = 0; d < 3; d++)
+                                for (int e = 0; e < 3; e++)
+                                    jac[3 * d + e] += w * ((d == e ? 1.0 : 0.0) - 3.0 * r[d] * r[e] / R2);
                     }
         for (int d = 0; d < 3; d++) B[d] += S[5] / (4.0 * PI_) * acc[d];
+        if (J)
+            for (int d = 0; d < 9; d++) J[d] += S[5] / (4.0 * PI_) * jac[d];
     }
 }
 
-void orc_mag_field(const orc_mag *G, const double *p, int n, double *B) {
+void orc_mag_field(const orc_mag *G, const double *p, int n, double *B, double *J) {
 #pragma omp parallel for schedule(static)
-    for (int k = 0; k < n; k++) mag_field_at(G, p + 3 * k, B + 3 * k);
+    for (int k = 0; k < n; k++) mag_field_at(G, p + 3 * k, B + 3 * k, J ? J + 9 * k : NULL);
 }
 
 /* dipole-dipole force on bead 2 from bead 1, r = x2 - x1 (the paper's
@@ -828,24 +839,15 @@ static double rep_force(const orc_mag *G, double d) {
 void orc_mag_forces(const orc_mag *G, const double *x, int n, double *m, double *F) {
     const double alpha = 4.0 * PI_ * G->a * G->a * G->a * G->chi / (G->chi + 3.0);
     const int dims[3] = {G->nx, G->ny, G->nz};
-    /* moments and gradient forces F_j = sum_i m_i dB_i/dx_j (central differences) */
-    for (int k = 0; k < n; k++) {
-        double B[3];
-        mag_field_at(G, x + 3 * k, B);
-        for (int d = 0; d < 3; d++) m[3 * k + d] = alpha * B[d];
-    }
+    /* moments and gradient forces F_j = sum_i m_i dB_i/dx_j */
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < n; k++) {
-        double h = 1e-4 * G->a;
+        double B[3], J[9];
+        mag_field_at(G, x + 3 * k, B, J);
+        for (int d = 0; d < 3; d++) m[3 * k + d] = alpha * B[d];
         for (int j = 0; j < 3; j++) {
-            double pp[3] = {x[3 * k], x[3 * k + 1], x[3 * k + 2]}, pm[3] = {pp[0], pp[1], pp[2]};
-            pp[j] += h;
-            pm[j] -= h;
-            double Bp[3], Bm[3];
-            mag_field_at(G, pp, Bp);
-            mag_field_at(G, pm, Bm);
             double s = 0.0;
-            for (int i = 0; i < 3; i++) s += m[3 * k + i] * (Bp[i] - Bm[i]) / (2 * h);
+            for (int i = 0; i < 3; i++) s += m[3 * k + i] * J[3 * i + j];
             F[3 * k + j] = s;
         }
     }

@@ -4,7 +4,8 @@ CPU only.
 
   - the charge-sheet field: on the axis of a rectangle it equals sigma times
     the solid angle over 4 pi (closed form), far away it is the monopole
-    field, and it is divergence- and curl-free;
+    field; off the axis field and gradient equal the corner closed form of a
+    charged rectangle; the gradient is symmetric and traceless;
   - the dipole interaction equation: hand values for two aligned and two
     side-by-side moments, the negative gradient of the dipole energy, and
     Newton's third law;
@@ -38,18 +39,56 @@ def test_sheet_field_closed_forms(orc):
         assert Bf == pytest.approx(2.0 * 4 * A * B / (4 * np.pi * r * r) * u, rel=2e-3, abs=1e-12)
 
 
+def _rect_field(sheet, p):
+    """Closed form of the field of a uniformly charged rectangle and of its
+    gradient: sums over the four corners of log and arctangent terms (the
+    antiderivatives of the Coulomb kernel over the rectangle)."""
+    z, x0, x1, y0, y1, sig = sheet
+    w = p[2] - z
+    B, J = np.zeros(3), np.zeros((3, 3))
+    for i, xc in enumerate((x0, x1)):
+        for j, yc in enumerate((y0, y1)):
+            s = (-1) ** (i + j)
+            X, Y = xc - p[0], yc - p[1]
+            R = np.sqrt(X * X + Y * Y + w * w)
+            B += s * np.array([np.log(Y + R), np.log(X + R), np.arctan(X * Y / (w * R))])
+            J[0, 0] -= s * X / (R * (Y + R))
+            J[1, 1] -= s * Y / (R * (X + R))
+            J[0, 1] -= s / R
+            J[0, 2] += s * w / (R * (Y + R))
+            J[1, 2] += s * w / (R * (X + R))
+    J[1, 0], J[2, 0], J[2, 1] = J[0, 1], J[0, 2], J[1, 2]
+    J[2, 2] = -J[0, 0] - J[1, 1]
+    return sig / (4 * np.pi) * B, sig / (4 * np.pi) * J
+
+
+def test_sheet_field_and_gradient_off_axis(orc):
+    """Away from the axis: the quadrature equals the corner closed form for
+    the field and its gradient, and the gradient equals central differences
+    of the field (a check on the closed form's derivative terms too)."""
+    sh = [3.0, -10.0, 30.0, -5.0, 25.0, 1.3]
+    G = orc.Magnet([sh], (0, 0, 0), 1.0, 1.0, 1.0, 1.0)
+    rng = np.random.default_rng(0)
+    P = rng.uniform(-15, 35, (8, 3))
+    P[:, 2] = np.where(np.abs(P[:, 2] - 3.0) < 1.0, 5.0, P[:, 2])
+    Bo, Jo = G.field(P, jacobian=True)
+    for p, bo, jo in zip(P, Bo, Jo):
+        b, j = _rect_field(sh, p)
+        assert np.abs(bo - b).max() <= 1e-13 * np.abs(b).max()
+        assert np.abs(jo - j).max() <= 1e-12 * np.abs(j).max()
+        h = 1e-4
+        fd = np.array([(_rect_field(sh, p + h * e)[0] - _rect_field(sh, p - h * e)[0]) / (2 * h) for e in np.eye(3)]).T
+        assert np.abs(j - fd).max() <= 1e-7 * np.abs(j).max()
+
+
 def test_sheet_field_divergence_and_curl_free(orc):
     G = orc.Magnet([[0.0, -6, 6, -4, 4, 1.0], [8.0, -6, 6, -4, 4, -1.0]], (0.1, 0.0, 0.2), 1.0, 1.0, 1.0, 1.0)
-    h = 1e-4
-    for p in ([1.0, 2.0, 3.0], [-4.5, 1.5, 1.0], [7.0, -5.0, 6.5]):
-        J = np.zeros((3, 3))
-        for j in range(3):
-            e = np.zeros(3)
-            e[j] = h
-            J[:, j] = (G.field([np.add(p, e)])[0] - G.field([np.subtract(p, e)])[0]) / (2 * h)
-        scale = np.abs(J).max()
-        assert abs(np.trace(J)) <= 1e-6 * scale
-        assert np.abs(J - J.T).max() <= 1e-6 * scale
+    P = np.array([[1.0, 2.0, 3.0], [-4.5, 1.5, 1.0], [7.0, -5.0, 6.5]])
+    _, J = G.field(P, jacobian=True)
+    for j in J:
+        scale = np.abs(j).max()
+        assert abs(np.trace(j)) <= 1e-12 * scale
+        assert np.abs(j - j.T).max() <= 1e-12 * scale
 
 
 def test_dipole_interaction(orc):
@@ -87,13 +126,13 @@ def test_gradient_force(orc):
                    dims=(64, 64, 64), periodic=(0, 0, 0), walls_z=False, quad=8)
     m, F = G.forces([[0.0, 0.0, d]])
     bz = _axis_bz(sig, A, B, d)
-    h = 1e-5
-    dbz = (_axis_bz(sig, A, B, d + h) - _axis_bz(sig, A, B, d - h)) / (2 * h)
-    assert m[0, 2] == pytest.approx(alpha * bz, rel=1e-9)
-    assert F[0, 2] == pytest.approx(alpha * bz * dbz, rel=1e-6)
-    # the lateral components vanish by symmetry: what is left is the rounding
-    # of the central differences (step 1e-4 a)
-    assert np.abs(F[0, :2]).max() < 1e-8 * abs(F[0, 2])
+    # d/dd of (sigma/pi) atan(f), f = AB / (d R), R = sqrt(A^2 + B^2 + d^2)
+    R = np.sqrt(A * A + B * B + d * d)
+    f = A * B / (d * R)
+    dbz = sig / np.pi * (-A * B * (R * R + d * d) / (d * d * R ** 3)) / (1 + f * f)
+    assert m[0, 2] == pytest.approx(alpha * bz, rel=1e-12)
+    assert F[0, 2] == pytest.approx(alpha * bz * dbz, rel=1e-12)
+    assert np.abs(F[0, :2]).max() < 1e-13 * abs(F[0, 2])
 
 
 def test_bead_pair_settles_along_the_field(orc):
