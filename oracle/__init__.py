@@ -328,6 +328,16 @@ class Magnet:
         lib().orc_mag_forces(C.byref(self.s), _d(x), C.c_int(len(x)), _d(m), _d(F))
         return m, F
 
+    def forces_sample(self, x, idx) -> np.ndarray:
+        """Total forces [len(idx), 3] on the beads idx only."""
+        x = np.ascontiguousarray(np.asarray(x, np.float64).reshape(-1, 3))
+        idx = np.ascontiguousarray(idx, np.int32)
+        F = np.zeros((len(idx), 3))
+        if lib().orc_mag_forces_sample(C.byref(self.s), _d(x), C.c_int(len(x)),
+                                       idx.ctypes.data_as(C.POINTER(C.c_int)), C.c_int(len(idx)), _d(F)):
+            raise ValueError("orc_mag_forces_sample: bad index or no memory")
+        return F
+
     def run(self, x, nsteps: int) -> np.ndarray:
         """nsteps overdamped steps; x [n, 3] advanced in place and returned."""
         if lib().orc_mag_run(C.byref(self.s), _d(x), C.c_int(len(x)), C.c_int(nsteps)):

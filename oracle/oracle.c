@@ -835,39 +835,64 @@ static double rep_force(const orc_mag *G, double d) {
     return G->rep_n * G->rep_a * pow(d < dmin ? dmin : d, -G->rep_n - 1.0);
 }
 
+/* induced moments m [n][3] of beads at x [n][3] */
+void orc_mag_moments(const orc_mag *G, const double *x, int n, double *m) {
+    const double alpha = 4.0 * PI_ * G->a * G->a * G->a * G->chi / (G->chi + 3.0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < n; k++) {
+        double B[3];
+        mag_field_at(G, x + 3 * k, B, NULL);
+        for (int d = 0; d < 3; d++) m[3 * k + d] = alpha * B[d];
+    }
+}
+
+/* total force on bead k given every bead's moment: gradient force
+ * F_j = sum_i m_i dB_i/dx_j, then the dipole force and repulsion of every
+ * other bead (minimum image), then the walls */
+static void force_on(const orc_mag *G, const double *x, int n, const double *m, int k, double F[3]) {
+    const int dims[3] = {G->nx, G->ny, G->nz};
+    double B[3], J[9];
+    mag_field_at(G, x + 3 * k, B, J);
+    for (int j = 0; j < 3; j++) {
+        double s = 0.0;
+        for (int i = 0; i < 3; i++) s += m[3 * k + i] * J[3 * i + j];
+        F[j] = s;
+    }
+    for (int l = 0; l < n; l++) {
+        if (l == k) continue;
+        double r[3];
+        for (int d = 0; d < 3; d++) r[d] = min_image(x[3 * k + d] - x[3 * l + d], dims[d], G->periodic[d]);
+        double Fd[3];
+        dipole_force(m + 3 * l, m + 3 * k, r, Fd); /* on k from l */
+        double rn = norm3(r);
+        double fr = rep_force(G, rn - 2.0 * G->a) / rn;
+        for (int d = 0; d < 3; d++) F[d] += Fd[d] + fr * r[d];
+    }
+    if (G->walls_z) {
+        double z = x[3 * k + 2];
+        F[2] += rep_force(G, z - 0.5 - G->a) - rep_force(G, (G->nz - 1.5) - z - G->a);
+    }
+}
+
 /* moments m [n][3] and total forces F [n][3] on beads at x [n][3] */
 void orc_mag_forces(const orc_mag *G, const double *x, int n, double *m, double *F) {
-    const double alpha = 4.0 * PI_ * G->a * G->a * G->a * G->chi / (G->chi + 3.0);
-    const int dims[3] = {G->nx, G->ny, G->nz};
-    /* moments and gradient forces F_j = sum_i m_i dB_i/dx_j */
-#pragma omp parallel for schedule(static)
-    for (int k = 0; k < n; k++) {
-        double B[3], J[9];
-        mag_field_at(G, x + 3 * k, B, J);
-        for (int d = 0; d < 3; d++) m[3 * k + d] = alpha * B[d];
-        for (int j = 0; j < 3; j++) {
-            double s = 0.0;
-            for (int i = 0; i < 3; i++) s += m[3 * k + i] * J[3 * i + j];
-            F[3 * k + j] = s;
-        }
-    }
-    /* bead-bead dipole forces and repulsion (all pairs, minimum image) */
-    for (int k = 0; k < n; k++)
-        for (int l = 0; l < n; l++) {
-            if (l == k) continue;
-            double r[3];
-            for (int d = 0; d < 3; d++) r[d] = min_image(x[3 * k + d] - x[3 * l + d], dims[d], G->periodic[d]);
-            double Fd[3];
-            dipole_force(m + 3 * l, m + 3 * k, r, Fd); /* on k from l */
-            double rn = norm3(r);
-            double fr = rep_force(G, rn - 2.0 * G->a) / rn;
-            for (int d = 0; d < 3; d++) F[3 * k + d] += Fd[d] + fr * r[d];
-        }
-    if (G->walls_z)
-        for (int k = 0; k < n; k++) {
-            double z = x[3 * k + 2];
-            F[3 * k + 2] += rep_force(G, z - 0.5 - G->a) - rep_force(G, (G->nz - 1.5) - z - G->a);
-        }
+    orc_mag_moments(G, x, n, m);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int k = 0; k < n; k++) force_on(G, x, n, m, k, F + 3 * k);
+}
+
+/* total forces F [nidx][3] on the beads idx [nidx] only (every bead's
+ * moment is still needed); returns -1 on a bad index or no memory */
+int orc_mag_forces_sample(const orc_mag *G, const double *x, int n, const int *idx, int nidx, double *F) {
+    for (int i = 0; i < nidx; i++)
+        if (idx[i] < 0 || idx[i] >= n) return -1;
+    double *m = malloc(sizeof(double) * 3 * (size_t)n);
+    if (!m) return -1;
+    orc_mag_moments(G, x, n, m);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < nidx; i++) force_on(G, x, n, m, idx[i], F + 3 * i);
+    free(m);
+    return 0;
 }
 
 /* nsteps overdamped steps of the beads, x [n][3] in place */

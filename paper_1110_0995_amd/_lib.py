@@ -1,4 +1,5 @@
-"""ctypes view of the C ABI declared in include/lbmibm.h (argument marshalling only)."""
+"""ctypes view of the C ABI declared in include/lbmibm.h and include/magnet.h
+(argument marshalling only)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -15,11 +16,13 @@ PRECISIONS = {"f64": LBM_F64, "f32": LBM_F32, "f32dev": LBM_F32_DEV}
 ERRORS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EHIP: "EHIP", LBM_ENONFINITE: "ENONFINITE",
           LBM_ESTATE: "ESTATE"}
 
-# every symbol include/lbmibm.h declares
+# every symbol include/*.h declares
 EXPORTS = ("lbm_plane_stride", "lbm_workspace_bytes", "lbm_init", "lbm_init_channels",
            "lbm_workspace_bytes_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape", "ibm_couple",
            "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp", "lbm_adjoint_step",
-           "lbm_run_record", "lbm_adjoint_run", "lbm_destroy", "lbm_last_error")
+           "lbm_run_record", "lbm_adjoint_run", "lbm_destroy", "lbm_last_error",
+           "mag_workspace_bytes", "mag_field", "mag_forces", "mag_run", "mag_freeze")
+MAG_MAX_SHEETS = 8
 
 
 class LbmParams(C.Structure):
@@ -45,6 +48,14 @@ class IbmMesh(C.Structure):
                 ("vedge_off", C.c_void_p), ("vedge", C.c_void_p), ("xi", C.c_double), ("mass", C.c_double), ("dt", C.c_double),
                 ("contact", C.POINTER(IbmContact)), ("stretch_law", C.c_int32), ("max_cell_verts", C.c_int32), ("max_cell_tris", C.c_int32), ("max_cell_edges", C.c_int32),
                 ("checked", C.c_uint32)]
+
+
+class MagParams(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nsheets", C.c_int32), ("sheets", (C.c_double * 6) * MAG_MAX_SHEETS),
+                ("bias", C.c_double * 3), ("a", C.c_double), ("chi", C.c_double), ("eta", C.c_double),
+                ("dt", C.c_double), ("rep_a", C.c_double), ("rep_n", C.c_double), ("rep_cut", C.c_double),
+                ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("periodic", C.c_int32 * 3),
+                ("walls_z", C.c_int32), ("stream", C.c_void_p)]
 
 
 class LbmError(RuntimeError):
@@ -88,11 +99,19 @@ def load() -> C.CDLL:
     L.lbm_adjoint_run.argtypes = [vp, C.POINTER(IbmMesh), C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, C.c_int32]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_destroy.restype = None
+    mp = C.POINTER(MagParams)
+    L.mag_workspace_bytes.argtypes = [mp]
+    L.mag_workspace_bytes.restype = C.c_int64
+    L.mag_field.argtypes = [mp, vp, C.c_int32, vp, vp]
+    L.mag_forces.argtypes = [mp, vp, vp, vp, vp]
+    L.mag_run.argtypes = [mp, vp, C.c_int32, vp]
+    L.mag_freeze.argtypes = [mp, vp, vp]
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_init", "lbm_init_channels", "lbm_set_launch", "lbm_run", "lbm_step", "ibm_rest_shape",
                  "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp",
-                 "lbm_adjoint_step", "lbm_run_record", "lbm_adjoint_run"):
+                 "lbm_adjoint_step", "lbm_run_record", "lbm_adjoint_run", "mag_field", "mag_forces", "mag_run",
+                 "mag_freeze"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

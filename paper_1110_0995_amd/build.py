@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbmibm.so")
-SOURCES = ["lbmibm.hip"]
+SOURCES = ["lbmibm.hip", "magnet.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

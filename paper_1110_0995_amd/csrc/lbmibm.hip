@@ -176,6 +176,11 @@ static void drop_graph(lbm_ctx *c) {
 
 LBM_API const char *lbm_last_error(void) { return g_err.c_str(); }
 
+// the error slot shared with the magnetic-stage entry points
+namespace lbm {
+void set_error(const char *msg) { g_err = msg; }
+}  // namespace lbm
+
 LBM_API int64_t lbm_plane_stride(int64_t n, int32_t prec) {
     if (n <= 0) return 0;
     const int64_t es = prec == LBM_F64 ? 8 : 4;

@@ -549,3 +549,101 @@ def to_json(s: Scenario) -> str:
              periodic=list(s.periodic), ncells=(s.cells.ncells if s.cells else 0),
              nverts=(s.cells.nverts if s.cells else 0), meta=s.meta)
     return json.dumps(d, default=float)
+
+
+# ---------------------------------------------------------------------------
+# magnetic bead stage (Sec. 2.5): the inputs of the chain-forming stage
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class BeadStage:
+    """Inputs of the bead stage: bead centres x [n, 3] (float64), charge
+    sheets [ns, 6] = (z, x0, x1, y0, y1, sigma), homogeneous bias field,
+    bead radius a, susceptibility chi, viscosity eta, time step dt, bead
+    repulsion rep = (A, n, cut), lattice dims, periodic axes, walls at
+    z = 1/2 and nz - 3/2."""
+    x: np.ndarray
+    sheets: np.ndarray
+    bias: Tuple[float, float, float]
+    a: float
+    chi: float
+    eta: float
+    dt: float
+    rep: Tuple[float, float, float]
+    dims: Tuple[int, int, int]
+    periodic: Tuple[int, int, int] = (1, 1, 0)
+    walls_z: bool = True
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return len(self.x)
+
+
+def place_beads(rng: np.random.Generator, n: int, a: float, dims: Tuple[int, int, int], zlim: Tuple[float, float],
+                min_gap: float) -> np.ndarray:
+    """Random sequential addition of n bead centres in [0, nx) x [0, ny) x
+    zlim, pairwise centre distances > 2a + min_gap (minimum image in x and
+    y), using a uniform grid of bins no smaller than that distance."""
+    nx, ny, _ = dims
+    dmin = 2 * a + min_gap
+    nbx, nby = max(1, int(nx // dmin)), max(1, int(ny // dmin))
+    nbz = max(1, int((zlim[1] - zlim[0]) // dmin))
+    bins: dict = {}
+    out = np.zeros((n, 3))
+    k = tries = 0
+    while k < n:
+        tries += 1
+        if tries > 200 * n + 10000:
+            raise RuntimeError(f"could not place {n} beads (placed {k})")
+        p = np.array([rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(*zlim)])
+        b = (int(p[0] / nx * nbx) % nbx, int(p[1] / ny * nby) % nby,
+             min(nbz - 1, int((p[2] - zlim[0]) / (zlim[1] - zlim[0]) * nbz)))
+        ok = True
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    for q in bins.get(((b[0] + dx) % nbx, (b[1] + dy) % nby, b[2] + dz), ()):
+                        d = p - out[q]
+                        d[0] -= nx * np.floor(d[0] / nx + 0.5)
+                        d[1] -= ny * np.floor(d[1] / ny + 0.5)
+                        if d @ d <= dmin * dmin:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            out[k] = p
+            bins.setdefault(b, []).append(k)
+            k += 1
+    return out
+
+
+def bead_stage(nx: int = 512, ny: int = 256, nz: int = 128, *, n: int = 16384, a: float = 1.5, chi: float = 4.0,
+               sigma: float = 1.0, bias: float = 0.5, sheet_gap: float = 6.0, eta: float = 0.1, dt: float = 0.012,
+               rep: Tuple[float, float, float] = (0.5, 2.0, 1.0), seed: int = 0) -> BeadStage:
+    """Beads between two charge sheets above and below the channel with
+    opposite charge (bottom +sigma, top -sigma: the field inside points
+    along +z), each 1/8 of the channel wider than it on every side, plus a
+    bias field along +z.  eta is the lattice fluid's dynamic viscosity at
+    tau = 0.8 ((tau - 1/2)/3).  rep balances the contact attraction of two
+    beads in the mid-channel field (about 8 force units) at a surface gap of
+    about 0.5; dt keeps the explicit overdamped update stable for a chain:
+    its fastest mode has stiffness 4k (k = n (n + 1) A g^-(n+2) at that gap,
+    about 44), and mobility * 4k = dt/(6 pi eta a) * 176 is about 0.75,
+    well below 2.
+    Defaults: the 512 x 256 x 128 channel with 16384 beads of radius 1.5
+    (about 1.4 % volume fraction)."""
+    rng = np.random.default_rng(seed)
+    zlo, zhi = 0.5 + a + 0.5, nz - 1.5 - a - 0.5
+    x = place_beads(rng, n, a, (nx, ny, nz), (zlo, zhi), 1.0)
+    mx, my = nx / 8, ny / 8
+    sheets = np.array([[0.5 - sheet_gap, -mx, nx + mx, -my, ny + my, sigma],
+                       [nz - 1.5 + sheet_gap, -mx, nx + mx, -my, ny + my, -sigma]])
+    return BeadStage(x=x, sheets=sheets, bias=(0.0, 0.0, bias), a=a, chi=chi, eta=eta, dt=dt, rep=tuple(rep),
+                     dims=(nx, ny, nz), periodic=(1, 1, 0), walls_z=True,
+                     meta=dict(seed=seed, sigma=sigma, bias=bias, sheet_gap=sheet_gap))
