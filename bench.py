@@ -308,6 +308,50 @@ def sweep_leg(lbm_mod, steps: int) -> dict:
             "min_passing_gap": tr.min_passing_gap()}
 
 
+# FP64 operations of one dipole pair (Eq. interaction) plus the repulsion
+# test, counting a square root or a division as one: separation 3, |r|^2 5,
+# |r| 1, 3/(4 pi |r|^5) 3, the three dot products 15, 5 (m1.r)(m2.r)/|r|^2 3,
+# the bracket and scale 19, accumulation 3, surface gap 1
+FLOPS_PER_PAIR = 53
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def magnet_leg(steps: int) -> dict:
+    """The magnetic bead stage (Sec. 2.5): 16384 beads between two charge
+    sheets in the 512 x 256 x 128 channel, FP64, all-pairs dipole
+    interaction; the chains it forms are then fixed into the solid mask
+    (timed separately)."""
+    import torch
+    from paper_1110_0995_amd import magnet
+    from paper_1110_0995_amd import scenario as S
+    st = S.bead_stage()
+    b = magnet.Beads(st)
+    stream = torch.cuda.current_stream()
+    b.run(20)
+    torch.cuda.synchronize()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    b.run(steps)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ms = a0.elapsed_time(a1) / steps
+    solid = torch.zeros(st.dims[0] * st.dims[1] * st.dims[2], dtype=torch.uint8, device="cuda")
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(stream)
+    b.freeze(solid)
+    f1.record(stream)
+    torch.cuda.synchronize()
+    x = b.positions()
+    pairs = st.n * (st.n - 1)
+    tflops = pairs * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12
+    return {"workload": "bead_stage 512x256x128, 16384 beads a=1.5, 2 sheets + bias, f64", "steps": steps,
+            "ms_per_step": round(ms, 5), "pair_interactions_per_s": round(pairs / (ms * 1e-3), 1),
+            "fp64_tflops_step": round(tflops, 2), "frac_of_fp64_vector_peak": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "flops_per_pair": FLOPS_PER_PAIR, "freeze_ms": round(f0.elapsed_time(f1), 4),
+            "solid_fraction_after_freeze": round(float(solid.float().mean().item()), 5),
+            "finite": bool(np.isfinite(x).all())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -323,6 +367,8 @@ def main():
                     help="steps of the gap pass / no-pass sweep with contact forces (0 skips the leg)")
     ap.add_argument("--contact-steps", type=int, default=100,
                     help="steps of the throughput workload with and without contact forces (0 skips the leg)")
+    ap.add_argument("--magnet-steps", type=int, default=200,
+                    help="steps of the magnetic bead stage, 16384 beads (0 skips the leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -419,6 +465,8 @@ def main():
         out["contact"] = contact_leg(lbm, args.contact_steps)
     if args.sweep_steps > 0:
         out["sweep"] = sweep_leg(lbm, args.sweep_steps)
+    if args.magnet_steps > 0:
+        out["magnet"] = magnet_leg(args.magnet_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -108,6 +108,8 @@ MagArgs make_args(const mag_params *p, double *x, void *work) {
     A.rep_n = p->rep_n;
     A.rep_cut = p->rep_cut;
     A.rep_dmin = p->rep_cut / 100.0;
+    const double e = p->rep_n + 1.0;
+    A.rep_pow = (e == std::floor(e) && e >= 1.0 && e <= 16.0) ? (int)e : 0;
     A.L[0] = p->nx;
     A.L[1] = p->ny;
     A.L[2] = p->nz;
@@ -133,8 +135,26 @@ int launch_self(const MagArgs &A, int mode, hipStream_t s) {
 }
 
 int launch_pairs(const MagArgs &A, hipStream_t s) {
-    hipLaunchKernelGGL(k_mag_pairs, dim3((unsigned)cdiv(A.n, kPairThreads), (unsigned)A.nslice), dim3(kPairThreads),
-                       0, s, A);
+    const dim3 grid((unsigned)cdiv(A.n, kPairThreads), (unsigned)A.nslice), block(kPairThreads);
+    const int per = A.per[0] | (A.per[1] << 1) | (A.per[2] << 2);
+#define MAG_PAIRS(P)                                                                                \
+    case P:                                                                                       \
+        if (A.rep_pow)                                                                            \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mag_pairs<true, P>), grid, block, 0, s, A);      \
+        else                                                                                      \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mag_pairs<false, P>), grid, block, 0, s, A);     \
+        break;
+    switch (per) {
+        MAG_PAIRS(0)
+        MAG_PAIRS(1)
+        MAG_PAIRS(2)
+        MAG_PAIRS(3)
+        MAG_PAIRS(4)
+        MAG_PAIRS(5)
+        MAG_PAIRS(6)
+        MAG_PAIRS(7)
+    }
+#undef MAG_PAIRS
     MAGCHK(hipGetLastError());
     return LBM_OK;
 }

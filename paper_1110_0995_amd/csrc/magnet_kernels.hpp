@@ -22,6 +22,7 @@ struct MagArgs {
     double mob;        // dt/(6 pi eta a)
     double a;
     double rep_a, rep_n, rep_cut, rep_dmin;
+    int rep_pow;       // n + 1 when that is an integer in [1, 16] (the force by products), else 0
     double L[3];       // periodic lengths
     double ztop;       // nz - 3/2
     int per[3];
@@ -155,11 +156,37 @@ __global__ void k_mag_self(MagArgs A, int mode) {
     }
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton-Raphson
+// steps y <- y (3 - x y^2)/2, each of which squares the relative error
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * (1.5 - (0.5 * x * y) * y);
+    y = y * (1.5 - (0.5 * x * y) * y);
+    return y;
+}
+
+// repulsion magnitude over |r| for g < cut; an integer power n + 1 is taken
+// by repeated products (within a few roundings of pow), any other by pow
+template <bool kIntPow>
+__device__ __forceinline__ double rep_over_r(const MagArgs &A, double g, double rn) {
+    if (!kIntPow) return rep_force(A, g) / rn;
+    const double ig = 1.0 / (g < A.rep_dmin ? A.rep_dmin : g);
+    double p = ig;
+    for (int e = 1; e < A.rep_pow; e++) p *= ig;
+    return A.rep_n * A.rep_a * p / rn;
+}
+
 // All pairs: block (bx, q) takes targets [bx*256, +256) against the sources
-// of slice q, staged through LDS a tile of 256 at a time (every lane reads
-// the same source: broadcast).  Writes the slice's force on each target.
+// of slice q, staged through LDS a tile of 256 at a time as three 16-byte
+// records per bead (every lane reads the same record: broadcast).  Writes
+// the slice's force on each target.  kPer is the mask of periodic axes
+// (bit d = axis d).  The minimum image rounds r/L to nearest by a product
+// with 1/L, which can differ from d - L floor(d/L + 1/2) only at
+// separations of half a period.  A lane's own bead gets |r|^2 = 1e300,
+// whose force underflows to exactly zero.
+template <bool kIntPow, int kPer>
 __global__ __launch_bounds__(kPairThreads) void k_mag_pairs(MagArgs A) {
-    __shared__ double sx[3][kPairThreads], sm[3][kPairThreads];
+    __shared__ double2 sa[kPairThreads], sb[kPairThreads], sc[kPairThreads];  // (x0,x1) (x2,m0) (m1,m2)
     const int n = A.n, t = threadIdx.x;
     const int k = blockIdx.x * kPairThreads + t;
     const bool valid = k < n;
@@ -168,38 +195,46 @@ __global__ __launch_bounds__(kPairThreads) void k_mag_pairs(MagArgs A) {
     const double mk0 = A.m[kk], mk1 = A.m[n + kk], mk2 = A.m[2 * n + kk];
     const int l0 = blockIdx.y * A.slice_len;
     const int l1 = min(n, l0 + A.slice_len);
-    const double twoa = 2.0 * A.a;
+    const double twoa = 2.0 * A.a, c0 = 3.0 / (4.0 * kPi);
+    const double L0 = A.L[0], L1 = A.L[1], L2 = A.L[2];
+    const double i0 = 1.0 / L0, i1 = 1.0 / L1, i2 = 1.0 / L2;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     for (int base = l0; base < l1; base += kPairThreads) {
         const int l = base + t;
         if (l < l1) {
-            sx[0][t] = A.x[l];
-            sx[1][t] = A.x[n + l];
-            sx[2][t] = A.x[2 * n + l];
-            sm[0][t] = A.m[l];
-            sm[1][t] = A.m[n + l];
-            sm[2][t] = A.m[2 * n + l];
+            sa[t] = make_double2(A.x[l], A.x[n + l]);
+            sb[t] = make_double2(A.x[2 * n + l], A.m[l]);
+            sc[t] = make_double2(A.m[n + l], A.m[2 * n + l]);
         }
         __syncthreads();
         const int cnt = min(kPairThreads, l1 - base);
+        const int self = k - base;  // this lane's own index in the tile, if there
         for (int j = 0; j < cnt; j++) {
-            if (base + j == k) continue;
-            const double r0 = min_image(xk0 - sx[0][j], A.L[0], A.per[0]);
-            const double r1 = min_image(xk1 - sx[1][j], A.L[1], A.per[1]);
-            const double r2 = min_image(xk2 - sx[2][j], A.L[2], A.per[2]);
-            const double ml0 = sm[0][j], ml1 = sm[1][j], ml2 = sm[2][j];
-            const double rr = r0 * r0 + r1 * r1 + r2 * r2, rn = sqrt(rr);
-            const double c = 3.0 / (4.0 * kPi * rr * rr * rn);
+            const double2 pa = sa[j], pb = sb[j], pc = sc[j];
+            double r0 = xk0 - pa.x, r1 = xk1 - pa.y, r2 = xk2 - pb.x;
+            if (kPer & 1) r0 -= L0 * rint(r0 * i0);
+            if (kPer & 2) r1 -= L1 * rint(r1 * i1);
+            if (kPer & 4) r2 -= L2 * rint(r2 * i2);
+            const double ml0 = pb.y, ml1 = pc.x, ml2 = pc.y;
+            double rr = r0 * r0 + r1 * r1 + r2 * r2;
+            rr = j == self ? 1e300 : rr;
+            const double ir = rsqrt_nr(rr), ir2 = ir * ir;
+            const double c = c0 * ir2 * ir2 * ir;
             const double m1r = ml0 * r0 + ml1 * r1 + ml2 * r2;  // source moment . r
             const double m2r = mk0 * r0 + mk1 * r1 + mk2 * r2;  // target moment . r
             const double mm = ml0 * mk0 + ml1 * mk1 + ml2 * mk2;
-            const double q = mm - 5.0 * m1r * m2r / rr;
-            double fr = 0.0;
+            const double q = mm - 5.0 * m1r * m2r * ir2;
+            a0 += c * (m1r * mk0 + m2r * ml0 + q * r0);
+            a1 += c * (m1r * mk1 + m2r * ml1 + q * r1);
+            a2 += c * (m1r * mk2 + m2r * ml2 + q * r2);
+            const double rn = rr * ir;
             const double g = rn - twoa;
-            if (g < A.rep_cut) fr = rep_force(A, g) / rn;
-            a0 += c * (m1r * mk0 + m2r * ml0 + q * r0) + fr * r0;
-            a1 += c * (m1r * mk1 + m2r * ml1 + q * r1) + fr * r1;
-            a2 += c * (m1r * mk2 + m2r * ml2 + q * r2) + fr * r2;
+            if (g < A.rep_cut) {
+                const double fr = rep_over_r<kIntPow>(A, g, rn);
+                a0 += fr * r0;
+                a1 += fr * r1;
+                a2 += fr * r2;
+            }
         }
         __syncthreads();
     }

@@ -95,9 +95,11 @@ def test_field_and_gradient(orc, mag):
         assert np.abs(J[k] - Jo[k]).max() <= 1e-12 * np.abs(Jo[k]).max(), P[k]
 
 
-@pytest.mark.parametrize("n", [1, 257, 300, 700])
-def test_forces(orc, mag, n):
+@pytest.mark.parametrize("n,rep_n", [(1, 2.0), (257, 2.0), (300, 2.0), (700, 2.0), (300, 2.5)])
+def test_forces(orc, mag, n, rep_n):
+    """rep_n = 2 takes the integer-power repulsion, 2.5 the general one."""
     st = _small(n=n, seed=n)
+    st.rep = (st.rep[0], rep_n, st.rep[2])
     rng = np.random.default_rng(n)
     if n >= 40:
         st.x = _touching(st, rng)
