@@ -46,7 +46,7 @@ class _Lat(C.Structure):
 class _Contact(C.Structure):
     _fields_ = [("a", C.c_double), ("n", C.c_double), ("rcut", C.c_double), ("roff", C.c_double),
                 ("dmin", C.c_double), ("cell_cell", C.c_int), ("nplanes", C.c_int), ("planes", _dp),
-                ("ncyl", C.c_int), ("cyl", _dp)]
+                ("ncyl", C.c_int), ("cyl", _dp), ("nsph", C.c_int), ("sph", _dp)]
 
 
 class _Mesh(C.Structure):
@@ -185,11 +185,13 @@ class Mesh:
         if contact is not None:
             self.planes = np.ascontiguousarray(np.asarray(contact.get("planes", np.zeros((0, 4))), np.float64))
             self.cyl = np.ascontiguousarray(np.asarray(contact.get("cyl", np.zeros((0, 3))), np.float64))
+            self.sph = np.ascontiguousarray(np.asarray(contact.get("spheres", np.zeros((0, 4))), np.float64))
             self._contact = _Contact(float(contact["a"]), float(contact["n"]), float(contact["rcut"]),
                                      float(contact.get("roff", 0.0)), float(contact.get("dmin", 0.05)),
                                      int(contact.get("cell_cell", 1)), len(self.planes),
                                      _d(self.planes) if len(self.planes) else _dp(),
-                                     len(self.cyl), _d(self.cyl) if len(self.cyl) else _dp())
+                                     len(self.cyl), _d(self.cyl) if len(self.cyl) else _dp(),
+                                     len(self.sph), _d(self.sph) if len(self.sph) else _dp())
             self.s.contact = C.pointer(self._contact)
 
     def contact_energy(self, L, X) -> float:

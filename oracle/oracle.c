@@ -76,9 +76,10 @@ typedef struct {
  * interaction range.  Reading: U(d) = a d^-n for d = r - roff in (0, rcut),
  * zero beyond; below dmin the potential continues linearly with the slope
  * it has at dmin (a finite force for overlapping points).  Walls are
- * analytic surfaces: planes n.x = offset (unit normal n into the fluid) and
- * z-axis cylinders of radius R (fluid outside); r is then the distance to
- * the surface on the fluid side. */
+ * analytic surfaces: planes n.x = offset (unit normal n into the fluid),
+ * z-axis cylinders of radius R and fixed spheres of radius R (the beads of
+ * the frozen chains; fluid outside both); r is then the distance to the
+ * surface on the fluid side (minimum image across periodic axes). */
 typedef struct {
     double a, n, rcut, roff, dmin;
     int cell_cell;          /* 1: points of different cells repel each other */
@@ -86,6 +87,8 @@ typedef struct {
     const double *planes;   /* [nplanes][4] = (nx, ny, nz, offset) */
     int ncyl;
     const double *cyl;      /* [ncyl][3] = (xc, yc, R) */
+    int nsph;
+    const double *sph;      /* [nsph][4] = (xc, yc, zc, R): fixed spheres (the beads of frozen chains), fluid outside */
 } orc_contact;
 
 typedef struct {
@@ -642,6 +645,17 @@ static double contact(const orc_lattice *L, const orc_mesh *M, const double *X, 
             soft_sphere(P, rho - cy[2] - P->roff, &U, &f);
             E += U;
             if (F && f != 0.0) addv(F, k, f / rho, d);
+        }
+        for (int q = 0; q < P->nsph; q++) {
+            const double *sp = P->sph + 4 * q;
+            double d[3];
+            for (int a = 0; a < 3; a++) d[a] = min_image(x[a] - sp[a], dims[a], L->periodic[a]);
+            double r = norm3(d);
+            if (r == 0.0) continue; /* at the centre: no direction */
+            double U, f;
+            soft_sphere(P, r - sp[3] - P->roff, &U, &f);
+            E += U;
+            if (F && f != 0.0) addv(F, k, f / r, d);
         }
     }
     return E;

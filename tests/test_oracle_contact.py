@@ -4,7 +4,8 @@ from the walls; Sec. 2.4, collisions), CPU only.
 Hand values of the law U(d) = a d^-n (a = 1, n = 2 unless said), the force
 as the negative gradient of the energy (central differences), Newton's third
 law for the cell-cell part, the cut-off, exclusion of pairs within one cell,
-the periodic minimum image, the linear continuation below dmin, and momentum
+the periodic minimum image, hand values for planes, posts and fixed spheres,
+the linear continuation below dmin, and momentum
 conservation of a coupled step with contact forces on."""
 import numpy as np
 import pytest
@@ -71,10 +72,13 @@ def test_force_is_minus_energy_gradient(orc):
     rng = np.random.default_rng(0)
     lat, M, cells = _two_cells(orc, 0.3, contact=_law(a=1e-3, n=1.5, rcut=1.2, roff=0.1, dmin=0.01,
                                                       planes=np.array([[0.0, 0.0, 1.0, 7.6]]),
-                                                      cyl=np.array([[10.0, 7.3, 0.5]])))
+                                                      cyl=np.array([[10.0, 7.3, 0.5]]),
+                                                      spheres=np.array([[13.0, 10.4, 12.9, 0.6]])))
     X = cells.positions() + 0.05 * rng.standard_normal(cells.positions().shape)
     F = M.contact_forces(lat, X)
     assert np.abs(F).max() > 0
+    # the sphere is within range of some vertices
+    assert (np.linalg.norm(X - [13.0, 10.4, 12.9], axis=1) - 0.7 < 1.2).any()
     h = 1e-6
     for k in rng.choice(len(X), 12, replace=False).tolist() + list(np.nonzero(np.abs(F).sum(1))[0][:8]):
         for a in range(3):
@@ -136,6 +140,30 @@ def test_walls_hand_values(orc):
     # through the periodic y boundary: the same post shifted by ny acts the same
     M3 = orc.Mesh(cells, contact=_law(cyl=cyl + np.array([[0.0, 20.0, 0.0]])))
     assert np.abs(M3.contact_forces(lat, X) - F2).max() <= 1e-9
+
+
+def test_sphere_hand_values(orc):
+    """A fixed sphere (a bead of a frozen chain) whose surface is 0.4 from
+    the vertex furthest along +x: force 2 * 0.4^-3 along the line from the
+    centre; the same sphere seen through the periodic x boundary acts the
+    same; with the axis not periodic its image is out of range."""
+    cells = S.make_cells(np.array([[10.0, 10.0, 10.0]]), 2.0, 1)
+    X = cells.positions()
+    east = np.argmax(X[:, 0])
+    R = 1.5
+    u = np.array([1.0, 0.3, -0.2])
+    u /= np.linalg.norm(u)
+    c = X[east] + (R + 0.4) * u
+    lat = orc.Lattice(40, 20, 20, tau=0.8, periodic=(1, 1, 0))
+    F = orc.Mesh(cells, contact=_law(spheres=np.array([[*c, R]]))).contact_forces(lat, X)
+    assert F[east] == pytest.approx(-2 * 0.4 ** -3 * u, rel=1e-12)
+    near = np.linalg.norm(X - c, axis=1) - R < 1.0
+    assert np.abs(F[~near]).max() == 0.0 and (np.abs(F[near]).sum(1) > 0).all()
+    Fp = orc.Mesh(cells, contact=_law(spheres=np.array([[c[0] + 40.0, c[1], c[2], R]]))).contact_forces(lat, X)
+    assert np.abs(Fp - F).max() <= 1e-9
+    lat0 = orc.Lattice(40, 20, 20, tau=0.8, periodic=(0, 1, 0))
+    F0 = orc.Mesh(cells, contact=_law(spheres=np.array([[c[0] + 40.0, c[1], c[2], R]]))).contact_forces(lat0, X)
+    assert np.abs(F0).max() == 0.0
 
 
 def test_linear_continuation_below_dmin(orc):
