@@ -94,8 +94,10 @@ typedef struct {
  * reading: U(d) = a d^-n for d = r - roff in (0, rcut), 0 beyond, continued
  * linearly below dmin (force magnitude n a max(d, dmin)^-(n+1)); r is the
  * distance between two points (minimum image across periodic axes) or from a
- * point to a wall surface on the fluid side.  The forces are added to the
- * membrane force of the step (m->f_el then holds elastic + contact). */
+ * point to a wall surface on the fluid side (planes, z-axis cylinders and
+ * fixed spheres).  Cell-cell forces are added to the membrane force of the
+ * step (m->f_el then holds elastic + contact); the wall forces act in the
+ * point update of the same step. */
 typedef struct {
     double a, n;            /* strength and exponent, > 0 */
     double rcut;            /* interaction range beyond roff, > 0 */
@@ -107,6 +109,11 @@ typedef struct {
     int32_t ncyl;           /* z-axis cylinders (posts) */
     const double *cyl;      /* device [ncyl][3]: xc, yc, radius R; fluid outside */
     const int32_t *cyl_off; /* device [nch+1]: channel k's cylinders are [cyl_off[k], cyl_off[k+1]); NULL: all in every channel */
+    int32_t nspheres;       /* fixed spheres (Sec. 2.5: the beads of the chains fixed in space), 0 .. 2^22;
+                               only in a one-channel context */
+    const double *spheres;  /* device [nspheres][4]: xc, yc, zc, R > 0; fluid outside.  Read by ibm_rest_shape,
+                               which sorts them into a uniform grid of cells no smaller than R_max + roff + rcut;
+                               after changing them call ibm_rest_shape again */
 } ibm_contact;
 
 /* Membrane population (Sec. 2.2, 2.3).  All pointers are device memory.

@@ -35,7 +35,8 @@ class LbmParams(C.Structure):
 class IbmContact(C.Structure):
     _fields_ = [("a", C.c_double), ("n", C.c_double), ("rcut", C.c_double), ("roff", C.c_double),
                 ("dmin", C.c_double), ("cell_cell", C.c_int32), ("nplanes", C.c_int32), ("planes", C.c_void_p),
-                ("ncyl", C.c_int32), ("cyl", C.c_void_p), ("cyl_off", C.c_void_p)]
+                ("ncyl", C.c_int32), ("cyl", C.c_void_p), ("cyl_off", C.c_void_p), ("nspheres", C.c_int32),
+                ("spheres", C.c_void_p)]
 
 
 class IbmMesh(C.Structure):

@@ -417,10 +417,24 @@ struct WallContact {
     const double *planes;    // [nplanes][4]
     const double *cyl;       // [ncyl][3] = xc, yc, R
     const int32_t *cyl_off;  // [nch+1] or null
-    int nplanes, ncyl;
+    const double *sph;       // [nsph][4] = xc, yc, zc, R
+    const int32_t *sph_start, *sph_items;  // uniform grid of the spheres: cell c holds items [start[c], start[c+1])
+    int nplanes, ncyl, nsph;
+    int sg[3];               // grid cells per axis
+    double sinv[3];          // 1 / grid cell size per axis
     int per[3];
     ContactLaw law;
 };
+
+// Grid cell of coordinate v along an axis of length L: wrapped into
+// [0, L) along a periodic axis, clamped to the grid at the faces of a
+// non-periodic one (so a cell's neighbours still hold every sphere within
+// one cell size).
+__device__ __forceinline__ int grid_cell(double v, double L, int per, double inv, int g) {
+    if (per) v -= L * floor(v / L);
+    const double q = floor(v * inv);
+    return q < 0.0 ? 0 : (q >= (double)g ? g - 1 : (int)q);
+}
 
 // Wall contact force on a point at absolute position (px, py, pz) of
 // channel `chan` (distances with the minimum image across periodic axes).
@@ -443,6 +457,47 @@ __device__ __forceinline__ void wall_force(const WallContact &w, int chan, const
         const double f = contact_force(w.law, rho - cy[2] - w.law.roff) / rho;
         fx += f * dx;
         fy += f * dy;
+    }
+    if (w.nsph == 0) return;
+    // spheres in the 3 x 3 x 3 grid cells around the point (every cell once
+    // along an axis of fewer than 3 cells)
+    const double Ld[3] = {(double)ch.nx, (double)ch.ny, (double)ch.nz};
+    const double pv[3] = {px, py, pz};
+    int lo[3], cnt[3], ci[3];
+    for (int d = 0; d < 3; d++) {
+        ci[d] = grid_cell(pv[d], Ld[d], w.per[d], w.sinv[d], w.sg[d]);
+        if (w.sg[d] < 3) {
+            lo[d] = 0;
+            cnt[d] = w.sg[d];
+        } else if (w.per[d]) {
+            lo[d] = ci[d] - 1;
+            cnt[d] = 3;
+        } else {
+            lo[d] = ci[d] > 0 ? ci[d] - 1 : 0;
+            cnt[d] = min(ci[d] + 1, w.sg[d] - 1) - lo[d] + 1;
+        }
+    }
+    for (int a = 0; a < cnt[2]; a++) {
+        const int cz = (lo[2] + a + w.sg[2]) % w.sg[2];
+        for (int b = 0; b < cnt[1]; b++) {
+            const int cyy = (lo[1] + b + w.sg[1]) % w.sg[1];
+            for (int e = 0; e < cnt[0]; e++) {
+                const int cx = (lo[0] + e + w.sg[0]) % w.sg[0];
+                const int cell = cx + w.sg[0] * (cyy + w.sg[1] * cz);
+                for (int it = w.sph_start[cell]; it < w.sph_start[cell + 1]; it++) {
+                    const double *sp = w.sph + 4 * w.sph_items[it];
+                    const double dx = min_image(px - sp[0], ch.nx, w.per[0]);
+                    const double dy = min_image(py - sp[1], ch.ny, w.per[1]);
+                    const double dz = min_image(pz - sp[2], ch.nz, w.per[2]);
+                    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                    if (r == 0.0) continue;
+                    const double f = contact_force(w.law, r - sp[3] - w.law.roff) / r;
+                    fx += f * dx;
+                    fy += f * dy;
+                    fz += f * dz;
+                }
+            }
+        }
     }
 }
 

@@ -75,6 +75,10 @@ uint32_t mesh_tag(const ibm_mesh *m) {
     f.mix((uint64_t)(uintptr_t)m->vedge);
     f.mix((uint64_t)(uintptr_t)m->cell_chan);
     f.mix((uint64_t)(uintptr_t)m->contact);
+    if (m->contact) {
+        f.mix((uint64_t)m->contact->nspheres);
+        f.mix((uint64_t)(uintptr_t)m->contact->spheres);
+    }
     f.mix((uint64_t)m->max_cell_verts);
     return kMeshMagic ^ f.fold();
 }
@@ -97,8 +101,10 @@ uint64_t mesh_launch_key(const ibm_mesh *m) {
         f.mix((uint64_t)k->cell_cell);
         f.mix((uint64_t)k->nplanes);
         f.mix((uint64_t)k->ncyl);
-        for (const void *p : {(const void *)k->planes, (const void *)k->cyl, (const void *)k->cyl_off})
+        for (const void *p : {(const void *)k->planes, (const void *)k->cyl, (const void *)k->cyl_off,
+                              (const void *)k->spheres})
             f.mix((uint64_t)(uintptr_t)p);
+        f.mix((uint64_t)k->nspheres);
     }
     f.mix((uint64_t)m->max_cell_tris);
     f.mix((uint64_t)m->max_cell_edges);
@@ -148,6 +154,14 @@ struct lbm_ctx {
     int2 *pairs = nullptr;       // cell pairs in contact range
     uint32_t *npairs = nullptr;  // their number this step
     int bounds_cap = 0, pair_cap = 0;
+    // uniform grid of the fixed contact spheres, built by ibm_rest_shape
+    int32_t *sph_start = nullptr;  // [cells + 1]
+    int32_t *sph_items = nullptr;  // [nspheres] sphere ids, by cell
+    int sph_cap_cells = 0, sph_cap_items = 0;
+    const double *sph_src = nullptr;  // the spheres the grid was built from
+    int sph_n = 0;
+    int sph_g[3] = {1, 1, 1};
+    double sph_inv[3] = {0.0, 0.0, 0.0};
     // adjoint work buffers, allocated by the first lbm_adjoint_step
     void *lamF = nullptr;  // [N] x 4 real: lambda of the node force at stencil nodes
     void *lamU = nullptr;  // [N] x 4 real: lambda of u_ext at stencil nodes (kept zero between calls)
@@ -262,7 +276,8 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm,  c->ufield,   c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums, c->ftile,
-                    c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs};
+                    c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
+                    c->sph_start, c->sph_items};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -555,6 +570,9 @@ static int check_mesh_ptrs(const lbm_ctx *c, const ibm_mesh *m) {
         if (k->nplanes < 0 || k->ncyl < 0 || (k->nplanes && !k->planes) || (k->ncyl && !k->cyl))
             return fail(LBM_EINVAL, "contact walls: counts must be >= 0 and arrays given when counts are");
         if (k->cell_cell != 0 && k->cell_cell != 1) return fail(LBM_EINVAL, "contact cell_cell must be 0 or 1");
+        if (k->nspheres < 0 || k->nspheres > (1 << 22) || (k->nspheres && !k->spheres))
+            return fail(LBM_EINVAL, "contact spheres: 0 <= nspheres <= 2^22, and the array given when nspheres > 0");
+        if (k->nspheres && c->nch > 1) return fail(LBM_EINVAL, "contact spheres need a one-channel context");
     }
     return LBM_OK;
 }
@@ -610,6 +628,72 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
         k_membrane<R, true><<<m->ncells, kMembThreads, sm, c->s>>>(a);
     else
         k_membrane<R, false><<<m->ncells, kMembThreads, sm, c->s>>>(a);
+}
+
+// Sort the fixed contact spheres into a uniform grid over the lattice (one
+// channel) whose cells are no smaller than the reach R_max + roff + rcut
+// of a sphere, so that the 27 cells around a point hold every sphere that
+// can act on it.  Synchronous: reads the spheres back.
+static int build_sphere_grid(lbm_ctx *c, const ibm_contact *k) {
+    c->sph_src = nullptr;
+    c->sph_n = 0;
+    if (k->nspheres == 0) return LBM_OK;
+    const int ns = k->nspheres;
+    std::vector<double> sp(4 * (size_t)ns);
+    HIPCHK(hipStreamSynchronize(c->s));
+    HIPCHK(hipMemcpy(sp.data(), k->spheres, sp.size() * 8, hipMemcpyDeviceToHost));
+    double rmax = 0.0;
+    for (int q = 0; q < ns; q++) {
+        for (int d = 0; d < 4; d++)
+            if (!std::isfinite(sp[4 * q + d])) return fail(LBM_EINVAL, "contact sphere %d is not finite", q);
+        if (!(sp[4 * q + 3] > 0)) return fail(LBM_EINVAL, "contact sphere %d needs R > 0", q);
+        rmax = std::max(rmax, sp[4 * q + 3]);
+    }
+    const double reach = (rmax + k->roff + k->rcut) * (1.0 + 1e-9);
+    const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
+    int g[3];
+    int64_t ncell = 1;
+    for (int d = 0; d < 3; d++) {
+        g[d] = (int)std::max(1.0, std::min(1024.0, std::floor(dims[d] / reach)));
+        c->sph_g[d] = g[d];
+        c->sph_inv[d] = g[d] / (double)dims[d];
+        ncell *= g[d];
+    }
+    // the cell of each sphere as the kernel computes it for a point
+    std::vector<int32_t> cell(ns), start(ncell + 1, 0), items(ns);
+    for (int q = 0; q < ns; q++) {
+        int id[3];
+        for (int d = 0; d < 3; d++) {
+            double v = sp[4 * q + d];
+            if (c->p.periodic[d]) v -= dims[d] * std::floor(v / dims[d]);
+            const double qd = std::floor(v * c->sph_inv[d]);
+            id[d] = qd < 0.0 ? 0 : (qd >= g[d] ? g[d] - 1 : (int)qd);
+        }
+        cell[q] = id[0] + g[0] * (id[1] + g[1] * id[2]);
+        start[cell[q] + 1]++;
+    }
+    for (int64_t i = 0; i < ncell; i++) start[i + 1] += start[i];
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (int q = 0; q < ns; q++) items[fill[cell[q]]++] = q;  // ascending ids within a cell
+    drop_graph(c);  // captured steps hold the grid's shape in their kernel arguments
+    if (ncell + 1 > c->sph_cap_cells || ns > c->sph_cap_items) {
+        for (void *b : {(void *)c->sph_start, (void *)c->sph_items})
+            if (b) HIPCHK(hipFree(b));
+        c->sph_start = c->sph_items = nullptr;
+        c->sph_cap_cells = c->sph_cap_items = 0;
+        if (hipMalloc(&c->sph_start, 4 * (size_t)(ncell + 1)) != hipSuccess ||
+            hipMalloc(&c->sph_items, 4 * (size_t)ns) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "allocating the contact sphere grid failed");
+        }
+        c->sph_cap_cells = (int)(ncell + 1);
+        c->sph_cap_items = ns;
+    }
+    HIPCHK(hipMemcpy(c->sph_start, start.data(), 4 * (size_t)(ncell + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->sph_items, items.data(), 4 * (size_t)ns, hipMemcpyHostToDevice));
+    c->sph_src = k->spheres;
+    c->sph_n = ns;
+    return LBM_OK;
 }
 
 LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
@@ -710,6 +794,7 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
         HIPCHK(hipMemsetAsync(c->role, 0, 8 * c->N, c->s));
     }
     if (const ibm_contact *k = m->contact) {
+        if (int rc = build_sphere_grid(c, k)) return rc;
         if (k->cyl_off && k->ncyl) {
             std::vector<int32_t> co(c->nch + 1);
             HIPCHK(hipMemcpy(co.data(), k->cyl_off, co.size() * 4, hipMemcpyDeviceToHost));
@@ -835,6 +920,16 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
         a.wall.ncyl = k->ncyl;
         for (int d = 0; d < 3; d++) a.wall.per[d] = c->p.periodic[d];
         a.wall.law = contact_law(k);
+        if (k->nspheres) {  // the grid matches: the mesh tag (checked before) covers the spheres
+            a.wall.sph = k->spheres;
+            a.wall.sph_start = c->sph_start;
+            a.wall.sph_items = c->sph_items;
+            a.wall.nsph = k->nspheres;
+            for (int d = 0; d < 3; d++) {
+                a.wall.sg[d] = c->sph_g[d];
+                a.wall.sinv[d] = c->sph_inv[d];
+            }
+        }
     }
     dim3 grid((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells);
     k_couple<R><<<grid, 128, 0, c->s>>>(a);
@@ -888,10 +983,20 @@ static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f) {
 }
 static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m) { enqueue_couple(c, m, cur_f(c)); }
 
+// A mesh is ready for coupled steps when ibm_rest_shape has seen it in its
+// current form and the context's sphere grid is the one of its spheres.
+static int check_mesh_ready(const lbm_ctx *c, const ibm_mesh *m) {
+    if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
+    const ibm_contact *k = m->contact;
+    if (k && k->nspheres && (c->sph_src != k->spheres || c->sph_n != k->nspheres))
+        return fail(LBM_ESTATE, "the context's sphere grid belongs to another mesh: call ibm_rest_shape again");
+    return LBM_OK;
+}
+
 LBM_API int ibm_couple(lbm_ctx *c, const ibm_mesh *m) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
     if (int rc = check_mesh_ptrs(c, m)) return rc;
-    if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
+    if (int rc = check_mesh_ready(c, m)) return rc;
     enqueue_couple(c, m);
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -943,7 +1048,7 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
         return fail(LBM_EINVAL, "steps_per_graph must be 0 or even and at most 4096 (got %d)", steps_per_graph);
     if (m) {
         if (int rc = check_mesh_ptrs(c, m)) return rc;
-        if (m->checked != mesh_tag(m)) return fail(LBM_ESTATE, "call ibm_rest_shape on this mesh first");
+        if (int rc = check_mesh_ready(c, m)) return rc;
     }
     int32_t left = nsteps;
     if (steps_per_graph > 0 && nsteps >= steps_per_graph) {

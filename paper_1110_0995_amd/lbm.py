@@ -205,7 +205,8 @@ class Mesh:
     def __init__(self, lat: Lattice, cells: Cells, cell_chan: Optional[np.ndarray] = None,
                  contact: Optional[dict] = None):
         """contact: None, or dict(a, n, rcut, roff, dmin, cell_cell, planes [np, 4], cyl [nc, 3],
-        cyl_off [nch + 1] (optional)) of the soft-sphere contact forces (ibm_contact)."""
+        cyl_off [nch + 1] (optional), spheres [ns, 4] (optional)) of the soft-sphere contact forces
+        (ibm_contact)."""
         dev, R = lat.device, lat.rdtype
         i32 = lambda a: torch.as_tensor(np.ascontiguousarray(a, np.int32)).to(dev)
         self.cells = cells
@@ -217,12 +218,14 @@ class Mesh:
             self._planes = f64(np.asarray(contact.get("planes", np.zeros((0, 4)))).reshape(-1, 4))
             self._cyl = f64(np.asarray(contact.get("cyl", np.zeros((0, 3)))).reshape(-1, 3))
             self._cyl_off = None if contact.get("cyl_off") is None else i32(contact["cyl_off"])
+            self._sph = f64(np.asarray(contact.get("spheres", np.zeros((0, 4)))).reshape(-1, 4))
             self.contact = _lib.IbmContact(
                 float(contact["a"]), float(contact["n"]), float(contact["rcut"]), float(contact.get("roff", 0.0)),
                 float(contact.get("dmin", 0.05)), int(contact.get("cell_cell", 1)), self._planes.shape[0],
                 self._planes.data_ptr() if self._planes.numel() else None, self._cyl.shape[0],
                 self._cyl.data_ptr() if self._cyl.numel() else None,
-                None if self._cyl_off is None else self._cyl_off.data_ptr())
+                None if self._cyl_off is None else self._cyl_off.data_ptr(), self._sph.shape[0],
+                self._sph.data_ptr() if self._sph.numel() else None)
         self.vert_off = i32(cells.vert_off)
         self.tri_off = i32(cells.tri_off)
         self.edge_off = i32(cells.edge_off)

@@ -441,6 +441,14 @@ def contact_params(s: Scenario, **kw) -> dict:
     return d
 
 
+def bead_spheres(x: np.ndarray, a: float) -> np.ndarray:
+    """Contact spheres [n, 4] of frozen beads: centre and radius a + 1/2
+    (the staircase surface of the solid nodes within a of the centre), as
+    for the posts."""
+    x = np.asarray(x, np.float64).reshape(-1, 3)
+    return np.column_stack([x, np.full(len(x), a + 0.5)])
+
+
 def contact_params_batch(scenarios: Sequence[Scenario], **kw) -> dict:
     """Contact walls of batched channels: each channel's posts as a run of
     cylinders (cyl_off [nch + 1]); the z planes are shared, so the channels
@@ -581,11 +589,13 @@ class BeadStage:
 
 
 def place_beads(rng: np.random.Generator, n: int, a: float, dims: Tuple[int, int, int], zlim: Tuple[float, float],
-                min_gap: float) -> np.ndarray:
-    """Random sequential addition of n bead centres in [0, nx) x [0, ny) x
-    zlim, pairwise centre distances > 2a + min_gap (minimum image in x and
-    y), using a uniform grid of bins no smaller than that distance."""
+                min_gap: float, xlim: Optional[Tuple[float, float]] = None) -> np.ndarray:
+    """Random sequential addition of n bead centres in xlim (default
+    [0, nx)) x [0, ny) x zlim, pairwise centre distances > 2a + min_gap
+    (minimum image in x and y), using a uniform grid of bins no smaller than
+    that distance."""
     nx, ny, _ = dims
+    xlo, xhi = xlim if xlim is not None else (0.0, float(nx))
     dmin = 2 * a + min_gap
     nbx, nby = max(1, int(nx // dmin)), max(1, int(ny // dmin))
     nbz = max(1, int((zlim[1] - zlim[0]) // dmin))
@@ -596,7 +606,7 @@ def place_beads(rng: np.random.Generator, n: int, a: float, dims: Tuple[int, int
         tries += 1
         if tries > 200 * n + 10000:
             raise RuntimeError(f"could not place {n} beads (placed {k})")
-        p = np.array([rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(*zlim)])
+        p = np.array([rng.uniform(xlo, xhi), rng.uniform(0, ny), rng.uniform(*zlim)])
         b = (int(p[0] / nx * nbx) % nbx, int(p[1] / ny * nby) % nby,
              min(nbz - 1, int((p[2] - zlim[0]) / (zlim[1] - zlim[0]) * nbz)))
         ok = True
@@ -625,7 +635,8 @@ def place_beads(rng: np.random.Generator, n: int, a: float, dims: Tuple[int, int
 
 def bead_stage(nx: int = 512, ny: int = 256, nz: int = 128, *, n: int = 16384, a: float = 1.5, chi: float = 4.0,
                sigma: float = 1.0, bias: float = 0.5, sheet_gap: float = 6.0, eta: float = 0.1, dt: float = 0.012,
-               rep: Tuple[float, float, float] = (0.5, 2.0, 1.0), seed: int = 0) -> BeadStage:
+               rep: Tuple[float, float, float] = (0.5, 2.0, 1.0), seed: int = 0,
+               xband: Optional[Tuple[float, float]] = None, sheets: bool = True) -> BeadStage:
     """Beads between two charge sheets above and below the channel with
     opposite charge (bottom +sigma, top -sigma: the field inside points
     along +z), each 1/8 of the channel wider than it on every side, plus a
@@ -637,13 +648,15 @@ def bead_stage(nx: int = 512, ny: int = 256, nz: int = 128, *, n: int = 16384, a
     about 44), and mobility * 4k = dt/(6 pi eta a) * 176 is about 0.75,
     well below 2.
     Defaults: the 512 x 256 x 128 channel with 16384 beads of radius 1.5
-    (about 1.4 % volume fraction)."""
+    (about 1.4 % volume fraction).  xband limits the beads to a band of x
+    (a filter section of the channel); sheets=False leaves the bias field
+    alone (its field then equals the mid-channel one only roughly)."""
     rng = np.random.default_rng(seed)
     zlo, zhi = 0.5 + a + 0.5, nz - 1.5 - a - 0.5
-    x = place_beads(rng, n, a, (nx, ny, nz), (zlo, zhi), 1.0)
+    x = place_beads(rng, n, a, (nx, ny, nz), (zlo, zhi), 1.0, xband)
     mx, my = nx / 8, ny / 8
-    sheets = np.array([[0.5 - sheet_gap, -mx, nx + mx, -my, ny + my, sigma],
-                       [nz - 1.5 + sheet_gap, -mx, nx + mx, -my, ny + my, -sigma]])
-    return BeadStage(x=x, sheets=sheets, bias=(0.0, 0.0, bias), a=a, chi=chi, eta=eta, dt=dt, rep=tuple(rep),
+    sh = np.array([[0.5 - sheet_gap, -mx, nx + mx, -my, ny + my, sigma],
+                   [nz - 1.5 + sheet_gap, -mx, nx + mx, -my, ny + my, -sigma]]) if sheets else np.zeros((0, 6))
+    return BeadStage(x=x, sheets=sh, bias=(0.0, 0.0, bias), a=a, chi=chi, eta=eta, dt=dt, rep=tuple(rep),
                      dims=(nx, ny, nz), periodic=(1, 1, 0), walls_z=True,
-                     meta=dict(seed=seed, sigma=sigma, bias=bias, sheet_gap=sheet_gap))
+                     meta=dict(seed=seed, sigma=sigma if sheets else 0.0, bias=bias, sheet_gap=sheet_gap, xband=xband))
