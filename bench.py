@@ -352,6 +352,46 @@ def magnet_leg(steps: int) -> dict:
             "finite": bool(np.isfinite(x).all())}
 
 
+def chain_filter_leg(bead_steps: int, steps: int) -> dict:
+    """The staged filter run at the throughput channel's size: the bead
+    stage (4096 beads in a band between the sheets) forms chains, they are
+    fixed into the solid mask and as contact spheres, then 400 cells and the
+    fluid run through them (FP32 deviation storage); the coupled steps are
+    timed with and without the contact forces."""
+    import torch
+    from paper_1110_0995_amd import lbm, pipeline
+    from paper_1110_0995_amd import scenario as S
+    st, cells = S.chain_filter_inputs()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cf = pipeline.chain_filter(st, bead_steps, cells, gx=1e-5, steps=steps)
+    torch.cuda.synchronize()
+    stage_s = time.perf_counter() - t0
+    s = cf.scenario
+    out = {"workload": "chain_filter 512x256x128, 4096 beads in x [192, 320), 400 cells x 642 vertices, f32dev",
+           "bead_steps": bead_steps, "stage_and_freeze_s": round(stage_s, 3), "steps": steps,
+           "solid_fraction": round(float(s.solid.mean()), 5), "spheres": len(cf.beads)}
+    stream = torch.cuda.current_stream()
+    for name, contact in (("without", None), ("with", cf.contact)):
+        lat = lbm.Lattice.from_scenario(s, prec="f32dev")
+        mesh = lbm.Mesh(lat, cells, contact=contact)
+        lat.run(20, mesh, steps_per_graph=10)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        lat.run(steps, mesh, steps_per_graph=10)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[f"ms_per_step_{name}_contact"] = round(ms, 5)
+        out[f"mlups_{name}_contact"] = round(s.n / (ms * 1e-3) / 1e6, 1)
+        out[f"finite_{name}_contact"] = bool(np.isfinite(mesh.positions()).all())
+        lat.close()
+        del lat, mesh
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -369,6 +409,8 @@ def main():
                     help="steps of the throughput workload with and without contact forces (0 skips the leg)")
     ap.add_argument("--magnet-steps", type=int, default=200,
                     help="steps of the magnetic bead stage, 16384 beads (0 skips the leg)")
+    ap.add_argument("--chain-filter-steps", type=int, default=100,
+                    help="coupled steps of the staged filter run through frozen bead chains (0 skips the leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -467,6 +509,8 @@ def main():
         out["sweep"] = sweep_leg(lbm, args.sweep_steps)
     if args.magnet_steps > 0:
         out["magnet"] = magnet_leg(args.magnet_steps)
+    if args.chain_filter_steps > 0:
+        out["chain_filter"] = chain_filter_leg(5000, args.chain_filter_steps)
     print(json.dumps(out), flush=True)
 
 

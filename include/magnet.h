@@ -55,7 +55,7 @@ extern "C" {
 #endif
 
 #define MAG_MAX_SHEETS 8
-#define MAG_MAX_BEADS (1 << 22)
+#define MAG_MAX_BEADS (1 << 17)
 
 typedef struct {
     int32_t n;                           /* beads, 1 .. MAG_MAX_BEADS */
@@ -73,9 +73,12 @@ typedef struct {
     void *stream;                        /* hipStream_t (NULL = null stream) */
 } mag_params;
 
-/* Bytes of device workspace mag_forces and mag_run need for p->n beads
- * (moments, one-bead forces and per-slice partial pair forces); 0 if p is
- * invalid (lbm_last_error() says why). */
+/* Bytes of device workspace mag_forces and mag_run need for p->n beads:
+ * moments, one-bead forces and the pair forces from each block of b beads,
+ * (2 + ceil(n/b)) arrays of 3n doubles, each rounded up to 256 bytes; b is
+ * the largest of 256, 128, 64 for which the ceil(n/b) blocks form at least
+ * 2048 block pairs (counting a block with itself), else 64 (1.6 GB at the
+ * largest n); 0 if p is invalid (lbm_last_error() says why). */
 int64_t mag_workspace_bytes(const mag_params *p);
 
 /* Field of the sheets plus the bias (Sec. 2.5 set-up) at npts points:

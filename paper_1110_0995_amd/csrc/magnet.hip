@@ -73,21 +73,22 @@ int check_params(const mag_params *p) {
     return LBM_OK;
 }
 
-// Source slices of the pair kernel: enough blocks to fill the chip
-// (about 2048 of 256 threads), each slice a whole number of LDS tiles.
-void slices(int n, int *nslice, int *slice_len) {
-    const int64_t tb = cdiv(n, kPairThreads);
-    int64_t s = std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, tb), tb));
-    int64_t len = cdiv(cdiv(n, s), kPairThreads) * kPairThreads;
-    *slice_len = (int)len;
-    *nslice = (int)cdiv(n, len);
+// Waves per workgroup of the pair kernel (blocks of 64 of them beads): the
+// largest of 4, 2, 1 that still gives about 2048 workgroups (block pairs),
+// so that small bead counts fill the chip too.  Its partial sums hold one
+// [3][n] array per block.
+int pair_waves(int n) {
+    for (int w : {4, 2}) {
+        const int64_t nb = cdiv(n, 64 * w);
+        if (nb * (nb + 1) / 2 >= 2048) return w;
+    }
+    return 1;
 }
+int blocks(int n) { return (int)cdiv(n, 64 * pair_waves(n)); }
 
 int64_t work_bytes(int n) {
-    int ns, len;
-    slices(n, &ns, &len);
     const int64_t plane = cdiv((int64_t)3 * n * 8, 256) * 256;  // one [3][n] double array, 256-aligned
-    return plane * (2 + ns);
+    return plane * (2 + blocks(n));
 }
 
 void fill_common(const mag_params *p, double sheet[kMaxSheets][6], double bias[3], int *nsheets) {
@@ -117,7 +118,7 @@ MagArgs make_args(const mag_params *p, double *x, void *work) {
     for (int d = 0; d < 3; d++) A.per[d] = p->periodic[d];
     A.walls = p->walls_z;
     A.n = p->n;
-    slices(p->n, &A.nslice, &A.slice_len);
+    A.nslice = blocks(p->n);
     const int64_t plane = cdiv((int64_t)3 * p->n * 8, 256) * 256;
     char *w = (char *)work;
     A.x = x;
@@ -129,20 +130,28 @@ MagArgs make_args(const mag_params *p, double *x, void *work) {
 }
 
 int launch_self(const MagArgs &A, int mode, hipStream_t s) {
-    hipLaunchKernelGGL(k_mag_self, dim3((unsigned)cdiv(A.n, 256)), dim3(256), 0, s, A, mode);
+    hipLaunchKernelGGL(k_mag_self, dim3((unsigned)cdiv((int64_t)A.n * kLanesPerBead, 256)), dim3(256), 0, s, A, mode);
     MAGCHK(hipGetLastError());
     return LBM_OK;
 }
 
 int launch_pairs(const MagArgs &A, hipStream_t s) {
-    const dim3 grid((unsigned)cdiv(A.n, kPairThreads), (unsigned)A.nslice), block(kPairThreads);
+    const int64_t nb = A.nslice;
+    const int waves = pair_waves(A.n);
+    const dim3 grid((unsigned)(nb * (nb + 1) / 2)), block(64 * waves);
     const int per = A.per[0] | (A.per[1] << 1) | (A.per[2] << 2);
-#define MAG_PAIRS(P)                                                                                \
-    case P:                                                                                       \
-        if (A.rep_pow)                                                                            \
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mag_pairs<true, P>), grid, block, 0, s, A);      \
-        else                                                                                      \
-            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mag_pairs<false, P>), grid, block, 0, s, A);     \
+#define MAG_PAIRS_W(P, W)                                                                        \
+    if (waves == W) {                                                                            \
+        if (A.rep_pow)                                                                           \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mag_pairs<true, P, W>), grid, block, 0, s, A);  \
+        else                                                                                     \
+            hipLaunchKernelGGL(HIP_KERNEL_NAME(k_mag_pairs<false, P, W>), grid, block, 0, s, A); \
+    }
+#define MAG_PAIRS(P)        \
+    case P:                 \
+        MAG_PAIRS_W(P, 1)   \
+        MAG_PAIRS_W(P, 2)   \
+        MAG_PAIRS_W(P, 4)   \
         break;
     switch (per) {
         MAG_PAIRS(0)
@@ -154,6 +163,7 @@ int launch_pairs(const MagArgs &A, hipStream_t s) {
         MAG_PAIRS(6)
         MAG_PAIRS(7)
     }
+#undef MAG_PAIRS_W
 #undef MAG_PAIRS
     MAGCHK(hipGetLastError());
     return LBM_OK;

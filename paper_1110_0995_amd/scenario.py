@@ -660,3 +660,16 @@ def bead_stage(nx: int = 512, ny: int = 256, nz: int = 128, *, n: int = 16384, a
     return BeadStage(x=x, sheets=sh, bias=(0.0, 0.0, bias), a=a, chi=chi, eta=eta, dt=dt, rep=tuple(rep),
                      dims=(nx, ny, nz), periodic=(1, 1, 0), walls_z=True,
                      meta=dict(seed=seed, sigma=sigma if sheets else 0.0, bias=bias, sheet_gap=sheet_gap, xband=xband))
+
+
+def chain_filter_inputs(nx: int = 512, ny: int = 256, nz: int = 128, *, nbeads: int = 4096,
+                        band: Tuple[float, float] = (192.0, 320.0), ncells: int = 400, cell_radius: float = 4.0,
+                        level: int = 3, seed: int = 5) -> Tuple[BeadStage, Cells]:
+    """Inputs of the staged filter run at the throughput channel's size:
+    beads in a band of x between the charge sheets (they form the chains of
+    the filter), and cells (642 vertices, tumour-cell moduli) seeded
+    upstream of the band, at least 16 lattice units from it."""
+    st = bead_stage(nx, ny, nz, n=nbeads, seed=seed, xband=band)
+    rng = np.random.default_rng(seed + 1)
+    cen = place_cells(rng, ncells, cell_radius, (int(band[0]) - 16, ny, nz))
+    return st, make_cells(cen, cell_radius, level, MODULI_CTC)

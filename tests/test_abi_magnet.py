@@ -53,20 +53,26 @@ def test_struct_layout_matches_header(tmp_path):
 
 
 def test_workspace_bytes(L):
-    # moments and one-bead forces, then one [3][n] force array per source
-    # slice of 256-bead tiles (about 2048 pair blocks), each 256-byte aligned
+    # moments and one-bead forces, then one [3][n] force array per block of
+    # b beads, each 256-byte aligned; b = 256, 128 or 64: the largest giving
+    # at least 2048 block pairs (else 64)
     def expect(n):
-        tb = -(-n // 256)
-        s = max(1, min(-(-2048 // tb), tb))
-        length = -(-(-(-n // s)) // 256) * 256
-        ns = -(-n // length)
+        b = 64
+        for bb in (256, 128):
+            nb = -(-n // bb)
+            if nb * (nb + 1) // 2 >= 2048:
+                b = bb
+                break
         plane = -(-(24 * n) // 256) * 256
-        return plane * (2 + ns)
+        return plane * (2 + -(-n // b))
 
-    for n in (1, 255, 256, 1000, 16384, 100000):
+    for n in (1, 255, 256, 1000, 4096, 8191, 8192, 16384, 100000, 1 << 17):
         p = _params(n)
         assert L.mag_workspace_bytes(C.byref(p)) == expect(n), n
-    assert expect(1) == 256 * 3 and expect(16384) == 24 * 16384 * (2 + 32)
+    assert expect(1) == 256 * 3 and expect(16384) == 24 * 16384 * (2 + 64)
+    assert expect(4096) == 24 * 4096 * (2 + 64)  # blocks of 64: 2080 block pairs
+    p = _params((1 << 17) + 1)
+    assert L.mag_workspace_bytes(C.byref(p)) == 0
 
 
 @pytest.mark.parametrize("kw,msg", [
