@@ -108,7 +108,7 @@ __global__ void k_mag_field(FieldArgs A) {
 constexpr int kLanesPerBead = 8;  // lanes sharing one bead's sheet corners in k_mag_self
 
 // Eight consecutive lanes per bead (a group inside one wave).  M_APPLY /
-// M_TOTAL: total force f = fs + the pair partials (blocks in order); M_TOTAL
+// M_TOTAL: total force f = the pair partials of all blocks + fs; M_TOTAL
 // writes it to fout, M_APPLY moves the bead by mob f.  M_MOMENTS: field and
 // gradient at the (moved) position -- the lanes split the sheets' corners
 // and add their terms with a butterfly over the group -- then the moment
@@ -120,12 +120,14 @@ __global__ __launch_bounds__(256) void k_mag_self(MagArgs A, int mode) {
     const int n = A.n;
     double p[3] = {A.x[k], A.x[n + k], A.x[2 * n + k]};
     if (mode & (M_APPLY | M_TOTAL)) {
-        double f[3];
-        for (int d = 0; d < 3; d++) {
-            double s = 0.0;
-            for (int q = 0; q < A.nslice; q++) s += A.part[((int64_t)q * 3 + d) * n + k];
-            f[d] = A.fs[d * n + k] + s;
-        }
+        // the partial sums of the blocks, split over the group's lanes and
+        // added with a butterfly (every lane ends with the total)
+        double f[3] = {0.0, 0.0, 0.0};
+        for (int q = sub; q < A.nslice; q += kLanesPerBead)
+            for (int d = 0; d < 3; d++) f[d] += A.part[((int64_t)q * 3 + d) * n + k];
+        for (int off = kLanesPerBead / 2; off > 0; off >>= 1)
+            for (int d = 0; d < 3; d++) f[d] += __shfl_xor(f[d], off, kLanesPerBead);
+        for (int d = 0; d < 3; d++) f[d] += A.fs[d * n + k];
         if ((mode & M_TOTAL) && sub == 0)
             for (int d = 0; d < 3; d++) A.fout[d * n + k] = f[d];
         if (mode & M_APPLY)
