@@ -80,7 +80,7 @@ struct AdjStepArgs {
     int64_t stride;
     const uint8_t *cls;
     const uint32_t *links;
-    void *fibm;            // spread force of step n at the marked nodes (read and cleared)
+    const void *fibm;      // spread force of step n, valid at the marked nodes
     const uint8_t *need;   // stencil-node marks (left set for k_adj_nodes)
     const uint8_t *tneed;  // tile marks
     void *lamF;            // [N] Vec4: lambda_F at marked nodes (written)
@@ -89,16 +89,18 @@ struct AdjStepArgs {
     const Chan *chans;
     const uint16_t *tile_chan;
     int ntiles;
+    int remap;             // as in StepArgs
     int64_t N;
     double g[3];
     double omega, kf;
 };
 
 template <class S, class R, bool DEV, bool HAS_G>
-__global__ __launch_bounds__(256) void k_adj_collide_stream(AdjStepArgs a) {
+__global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
     using R4 = typename Vec4<R>::T;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
+    const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tile = blk * (blockDim.x >> 6) + wave;
     if (tile >= a.ntiles) return;
     const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
     const int lt = tile - ch.toff, row = lt / ch.tpr;
@@ -115,13 +117,12 @@ __global__ __launch_bounds__(256) void k_adj_collide_stream(AdjStepArgs a) {
         Fz += G[2 * N + n];
     }
     const bool marked = a.tneed[tile] && a.need[n];
-    R4 *FI = static_cast<R4 *>(a.fibm);
+    const R4 *FI = static_cast<const R4 *>(a.fibm);
     if (marked) {
         const R4 fi = FI[n];
         Fx += fi.x;
         Fy += fi.y;
         Fz += fi.z;
-        FI[n] = R4{R(0), R(0), R(0), R(0)};
     }
     R *L = static_cast<R *>(a.lam);
     R4 *LF = static_cast<R4 *>(a.lamF);

@@ -35,6 +35,9 @@ __host__ __device__ constexpr R wgt(int i) {
 // b % 8).  Renumber them so each XCD walks one contiguous range of tiles:
 // neighbouring tiles then share an L2 (their partial-line stores of the
 // x-shifted populations merge there) and each L2 sees a compact footprint.
+// Where a workgroup holds whole x rows the natural order is faster (one
+// compact address range for the whole chip), and the collide-stream passes
+// skip the renumbering.
 __device__ __forceinline__ int xcd_block(int b, int nb) {
     const int q = nb >> 3, r = nb & 7, k = b & 7, i = b >> 3;
     return (k < r) ? k * (q + 1) + i : r * (q + 1) + (k - r) * q + i;

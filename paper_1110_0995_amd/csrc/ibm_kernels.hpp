@@ -33,19 +33,21 @@
 //   contributions, and writes them to that base node's slot after claiming
 //   it with one compare-and-swap of the call's epoch (a base node already
 //   claimed by another cell in this call falls back to float atomics into
-//   the force accumulator; that needs two membranes inside one lattice
-//   cell).  The owner also sets, at each of the 8 corner nodes, the byte
+//   a separate accumulator, kept zero between steps; that needs two
+//   membranes inside one lattice cell).  The owner also sets, at each of the 8 corner nodes, the byte
 //   that says "base node in role q has a slot for you".
 // k_gather_nodes (one wave per listed tile) reads its node's 8 role bytes
-//   with one load, adds the flagged slots in a fixed order and clears the
-//   bytes; the fallback path flags its tiles so that only those read the
-//   accumulated atomics back.
+//   with one load, adds the flagged slots in a fixed order, clears the
+//   bytes and writes the node's spread force at every marked node; the
+//   fallback path flags its tiles so that only those read the accumulated
+//   atomics back (and clear them).
 // All sums except the fallback are in a fixed order, so the spread is
 // bit-reproducible.
 //
 // The node and tile marks stay set until the collide-stream pass: they are
-// exactly the nodes that received spread force, so that pass reads (and
-// clears) the force record of marked nodes only, then clears the marks.
+// exactly the nodes whose spread force the gather wrote this step, so that
+// pass reads the force record of marked nodes only (a record elsewhere may
+// hold an earlier step's force) and clears the marks.
 #pragma once
 
 #include "d3q19.hpp"
@@ -101,6 +103,8 @@ struct MembArgs {
     int stretch_law;  // 0: linear edge springs, 1: neo-Hookean edge springs
     uint8_t *need;   // [N] stencil-node marks
     uint8_t *tneed;  // [ntiles] tile marks
+    void *fibm;      // [N] Vec4 spread force: zeroed at newly marked nodes when `accumulate`
+    int accumulate;  // 1: another membrane was coupled earlier in this step (its force stays)
 };
 
 constexpr int kMembThreads = 512;
@@ -164,10 +168,21 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int row = ys[q & 1] + ch.ny * zs[q >> 1];
-                a.need[ch.noff + (int64_t)row * ch.nx + xs[0]] = 1;
-                a.need[ch.noff + (int64_t)row * ch.nx + xs[1]] = 1;
-                a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[0] >> 6)] = 1;
-                a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[1] >> 6)] = 1;
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    const int64_t nn = ch.noff + (int64_t)row * ch.nx + xs[e];
+                    if (a.accumulate) {
+                        // a node first marked now starts from zero force; one
+                        // marked by an earlier membrane of the step keeps its force
+                        if (!a.need[nn]) {
+                            a.need[nn] = 1;
+                            static_cast<typename Vec4<R>::T *>(a.fibm)[nn] = typename Vec4<R>::T{R(0), R(0), R(0), R(0)};
+                        }
+                    } else {
+                        a.need[nn] = 1;
+                    }
+                    a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[e] >> 6)] = 1;
+                }
             }
         }
     }
@@ -598,7 +613,7 @@ struct SpreadArgs {
     uint32_t *owner;   // [N] epoch of the call that last claimed the base node's slot
     void *cslot;       // [N][8] Vec4: corner contributions of a base node
     uint8_t *role;     // [N][8] role[n][q] = 1: base node of n in role q holds a slot
-    void *fibm;        // [N] Vec4 (fallback)
+    void *facc;        // [N] Vec4: accumulator of the fallback (zero between steps)
     uint8_t *ftile;    // [ntiles] 1: a node of the tile got fallback atomics this call
     const uint32_t *epoch;
     const Chan *chans;
@@ -678,7 +693,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
                 a.role[n * 8 + q] = 1;
             }
         } else {
-            R4 *FI = static_cast<R4 *>(a.fibm);
+            R4 *FI = static_cast<R4 *>(a.facc);
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 const int ys_ = ys[(q >> 1) & 1], zs_ = zs[q >> 2];
@@ -699,17 +714,23 @@ struct GatherArgs {
     const void *cslot;
     const uint8_t *need;
     uint8_t *ftile;  // [ntiles] fallback flags, cleared here
-    void *fibm;      // [N] Vec4
+    void *fibm;      // [N] Vec4: spread force, written (or, with `accumulate`, added) at the nodes this call spreads to
+    void *facc;      // [N] Vec4: fallback accumulator, read and cleared in flagged tiles
+    int accumulate;  // as in MembArgs
     const Chan *chans;
     const uint16_t *tile_chan;
 };
 
 // Each listed tile: every lane reads its node's 8 role bytes with one load
 // (zero away from the stencils), adds the flagged slots in a fixed order and
-// stores the sum as the node's spread force.  Only in a tile that the
-// fallback path flagged does the sum go on top of the accumulated atomics
-// (read-modify-write of the marked nodes), so the common chain is list ->
-// role word -> slots -> store.
+// stores the sum as the node's spread force.  Every node marked by the
+// call's membrane gets a slot role or sits in a tile the fallback path
+// flagged, so the force is written at every marked node and the
+// collide-stream pass never needs the record cleared.  Only in a flagged tile
+// does the sum go on top of the accumulated atomics, which are read and
+// cleared; with `accumulate` (a second membrane coupled in the same step)
+// it is added to the force already there.  The common chain is list -> role
+// word -> slots -> store.
 template <class R>
 __global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
     using R4 = typename Vec4<R>::T;
@@ -750,14 +771,22 @@ __global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
         }
         if (fallback) {
             if (!a.need[n]) continue;
-            R4 f = FI[n];
-            f.x += Fx;
-            f.y += Fy;
-            f.z += Fz;
-            FI[n] = f;
-        } else if (roles) {
-            FI[n] = R4{Fx, Fy, Fz, R(0)};  // the accumulator is zero here
+            R4 *FA = static_cast<R4 *>(a.facc);
+            const R4 f = FA[n];
+            FA[n] = R4{R(0), R(0), R(0), R(0)};
+            Fx += f.x;
+            Fy += f.y;
+            Fz += f.z;
+        } else if (!roles) {
+            continue;
         }
+        if (a.accumulate) {
+            const R4 f = FI[n];
+            Fx = f.x + Fx;
+            Fy = f.y + Fy;
+            Fz = f.z + Fz;
+        }
+        FI[n] = R4{Fx, Fy, Fz, R(0)};
     }
 }
 

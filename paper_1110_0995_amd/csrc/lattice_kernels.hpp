@@ -129,13 +129,14 @@ struct StepArgs {
     int64_t stride;
     const uint8_t *cls;
     const uint32_t *links;
-    void *fibm;           // [N] x 4 immersed-boundary force accumulator (x, y, z, unused)
+    const void *fibm;     // [N] x 4 immersed-boundary force (x, y, z, unused), valid at marked nodes
     uint8_t *need;        // [N] 1: the node received spread force this step
     uint8_t *tneed;       // [ntiles] 1: the tile holds such a node
     const void *gfield;   // [3][N] or null
     const Chan *chans;
     const uint16_t *tile_chan;  // null for a single channel
     int ntiles;
+    int remap;            // 1: renumber workgroups so each XCD walks one contiguous tile range
     int64_t N;
     double g[3];
     double omega, kf;
@@ -146,15 +147,21 @@ struct StepArgs {
 // coalesced, collides in registers and writes every post-collision value
 // straight to its destination slot (neighbour along c_i, or the opposite
 // slot of the same node when that link is a wall link).  The spread force is
-// read, and cleared, only at nodes marked as stencil nodes of this step.
+// read only at nodes marked as stencil nodes of this step (where the gather
+// pass wrote it), and the marks are cleared.
 // A workgroup is blockDim/64 consecutive tiles (the tile shape is a launch
-// parameter).  IDX is the index type of element offsets from the buffer
+// parameter); when it holds whole x rows, the partial cache lines of the
+// x-shifted stores of a row meet in one L2 whatever XCD runs it and the
+// workgroups keep their natural order (the chip then streams through one
+// compact address range), otherwise they are renumbered by XCD (`remap`) so
+// that neighbouring tiles share an L2.  IDX is the index type of element offsets from the buffer
 // base: uint32_t when 19 planes fit in 4 GiB (single 64-bit base + 32-bit
 // lane offsets), int64_t otherwise.
 template <class S, class R, bool DEV, bool HAS_G, class IDX>
 __global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * (blockDim.x >> 6) + wave;
+    const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+    const int tile = blk * (blockDim.x >> 6) + wave;
     if (tile >= a.ntiles) return;
     const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
     const int lt = tile - ch.toff;
@@ -175,13 +182,10 @@ __global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
     }
     if (a.tneed[tile]) {
         if (at(a.need, n)) {
-            R *fi = static_cast<R *>(a.fibm);
+            const R *fi = static_cast<const R *>(a.fibm);
             Fx += at(fi, 4 * n);
             Fy += at(fi, 4 * n + 1);
             Fz += at(fi, 4 * n + 2);
-            at(fi, 4 * n) = R(0);
-            at(fi, 4 * n + 1) = R(0);
-            at(fi, 4 * n + 2) = R(0);
             at(a.need, n) = 0;
         }
         if (lane == 0) a.tneed[tile] = 0;

@@ -125,7 +125,8 @@ struct lbm_ctx {
     size_t rsize = 4;  // sizeof(real)
     uint8_t *cls = nullptr;
     uint32_t *links = nullptr;
-    void *fibm = nullptr;        // [N] x 4 real: spread force accumulator
+    void *fibm = nullptr;        // [N] x 4 real: spread force of the step, valid at the nodes marked this step
+    void *facc = nullptr;        // [N] x 4 real: accumulator of the atomic fallback spread, zero between steps
     void *ufield = nullptr;      // [N] x 4 real: fluid velocity of the marked nodes
     uint8_t *need = nullptr;     // [N] 1 = node under some IB stencil this step
     uint8_t *tneed = nullptr;    // [ntiles] 1 = tile holds a marked node
@@ -147,13 +148,15 @@ struct lbm_ctx {
     int cur = 0;  // 0: state in f_a, 1: in f_b
     int64_t steps = 0;
     // launch shape
-    int cs_waves = 4;     // tiles (waves) per collide-stream workgroup
+    int cs_waves = 0;     // tiles (waves) per collide-stream workgroup; 0 = by the lattice (cs_shape)
     int list_blocks = 0;  // workgroups of the tile-list kernels (0: by lattice size)
     // contact work buffers, allocated by ibm_rest_shape for a mesh with cell-cell contact
     double *bounds = nullptr;    // [ncells][4] centroid and radius
     int2 *pairs = nullptr;       // cell pairs in contact range
     uint32_t *npairs = nullptr;  // their number this step
     int bounds_cap = 0, pair_cap = 0;
+    int couples = 0;  // membranes coupled since the last collide-stream pass
+    int acc = 0;      // the membrane being coupled adds to the force of an earlier one
     // uniform grid of the fixed contact spheres, built by ibm_rest_shape
     int32_t *sph_start = nullptr;  // [cells + 1]
     int32_t *sph_items = nullptr;  // [nspheres] sphere ids, by cell
@@ -250,7 +253,7 @@ static int make_channels(int32_t nch, const int32_t *dims, std::vector<Chan> &ou
 }
 
 static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch) {
-    return N + 4 * N + 8 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
+    return N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
            (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
 }
 
@@ -274,7 +277,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->cap_s) (void)hipStreamSynchronize(c->cap_s);
     drop_graph(c);
     if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
-    void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm,  c->ufield,   c->need, c->tneed, c->tlist,
+    void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
                     c->sph_start, c->sph_items};
@@ -299,6 +302,7 @@ static int init_ctx(lbm_ctx *c) {
     const size_t tpad = (size_t)cdiv((int64_t)tn, 16) * 16;
     if (hipMalloc(&c->chans, sizeof(Chan) * c->nch) != hipSuccess || hipMalloc(&c->cls, c->N) != hipSuccess ||
         hipMalloc(&c->links, 4 * c->N) != hipSuccess || hipMalloc(&c->fibm, 4 * c->N * c->rsize) != hipSuccess ||
+        hipMalloc(&c->facc, 4 * c->N * c->rsize) != hipSuccess ||
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
         hipMalloc(&c->tneed, tpad) != hipSuccess || hipMalloc(&c->tlist, 4 * tn) != hipSuccess ||
         hipMalloc(&c->tcount, 4) != hipSuccess || hipMalloc(&c->epoch, 4) != hipSuccess ||
@@ -323,6 +327,7 @@ static int init_ctx(lbm_ctx *c) {
     k_classify<<<(int)cdiv(c->ntiles, 4), 256, 0, c->s>>>(c->chans, c->tile_chan, c->ntiles, p->periodic[0],
                                                            p->periodic[1], p->periodic[2], p->solid, c->cls, c->links);
     HIPCHK(hipMemsetAsync(c->fibm, 0, 4 * c->N * c->rsize, c->s));
+    HIPCHK(hipMemsetAsync(c->facc, 0, 4 * c->N * c->rsize, c->s));
     HIPCHK(hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s));
     HIPCHK(hipMemsetAsync(c->need, 0, c->N, c->s));
     HIPCHK(hipMemsetAsync(c->tneed, 0, tpad, c->s));
@@ -387,7 +392,7 @@ LBM_API int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t 
     if (w != 0 && w != 1 && w != 2 && w != 4 && w != 8)
         return fail(LBM_EINVAL, "collide_waves_per_block must be 0, 1, 2, 4 or 8 (got %d)", w);
     if (list_blocks < 0 || list_blocks > 65536) return fail(LBM_EINVAL, "list_blocks must be in [0, 65536]");
-    c->cs_waves = w ? w : 4;
+    c->cs_waves = w;
     c->list_blocks = list_blocks;
     drop_graph(c);  // a captured graph holds the old launch shape
     return LBM_OK;
@@ -396,10 +401,29 @@ LBM_API int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t 
 static const void *cur_f(const lbm_ctx *c) { return c->cur ? c->p.f_b : c->p.f_a; }
 static void *nxt_f(const lbm_ctx *c) { return c->cur ? c->p.f_a : c->p.f_b; }
 
+// Workgroup shape of the collide-stream passes.  One channel whose x rows
+// are at most 8 tiles: whole rows per workgroup (as many as fit in 8 waves),
+// in natural order; otherwise 4 tiles per workgroup renumbered by XCD.  An
+// explicit shape (lbm_set_launch) skips the renumbering only when it holds
+// whole rows of a one-channel lattice.
+struct CsShape {
+    int waves, remap;
+};
+static CsShape cs_shape(const lbm_ctx *c) {
+    const int tpr = c->nch == 1 ? c->hchans[0].tpr : 0;
+    if (c->cs_waves == 0) {
+        if (tpr >= 1 && tpr <= 8) return {(8 / tpr) * tpr, 0};
+        return {4, 1};
+    }
+    return {c->cs_waves, (tpr >= 1 && c->cs_waves % tpr == 0) ? 0 : 1};
+}
+
 template <class S, class R, bool DEV>
-static void launch_step(lbm_ctx *c, const StepArgs &a) {
-    const int nb = (int)cdiv(c->ntiles, c->cs_waves);
-    const int bs = 64 * c->cs_waves;
+static void launch_step(lbm_ctx *c, StepArgs a) {
+    const CsShape sh = cs_shape(c);
+    a.remap = sh.remap;
+    const int nb = (int)cdiv(c->ntiles, sh.waves);
+    const int bs = 64 * sh.waves;
     if (c->off32) {
         if (c->p.gfield)
             k_collide_stream<S, R, DEV, true, uint32_t><<<nb, bs, 0, c->s>>>(a);
@@ -450,6 +474,7 @@ static StepArgs step_args(const lbm_ctx *c) {
 
 // One collide-stream pass from fa into fb (the context's parity is untouched).
 static void enqueue_step_into(lbm_ctx *c, const void *fa, void *fb) {
+    c->couples = 0;  // this pass consumes the spread force
     StepArgs a = step_args(c);
     a.fa = fa;
     a.fb = fb;
@@ -590,6 +615,8 @@ static int waves_grid(const lbm_ctx *c) {
 template <class R>
 static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     MembArgs a{};
+    a.fibm = c->fibm;
+    a.accumulate = rest ? 0 : c->acc;
     a.tcount = c->tcount;
     a.epoch = c->epoch;
     a.chans = c->chans;
@@ -939,7 +966,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.owner = c->owner;
     sp.cslot = c->cslot;
     sp.role = c->role;
-    sp.fibm = c->fibm;
+    sp.facc = c->facc;
     sp.ftile = c->ftile;
     sp.epoch = c->epoch;
     sp.chans = c->chans;
@@ -953,6 +980,8 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     g.need = c->need;
     g.ftile = c->ftile;
     g.fibm = c->fibm;
+    g.facc = c->facc;
+    g.accumulate = c->acc;
     g.chans = c->chans;
     g.tile_chan = c->tile_chan;
     k_gather_nodes<R><<<waves_grid(c), 256, 0, c->s>>>(g);
@@ -960,6 +989,8 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
 
 // The immersed-boundary half of a coupled step with the populations f.
 static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f) {
+    c->acc = c->couples > 0;  // read by the membrane and gather launches below
+    c->couples++;
     switch (c->p.prec) {
         case LBM_F64:
             launch_membrane<double>(c, m, false);
@@ -1180,8 +1211,10 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
         mm.f_el = c->fels;
         enqueue_copy(c, c->xs, x_n, 3 * (size_t)m->nverts * 8);
         enqueue_copy(c, c->vs, v_n, 3 * (size_t)m->nverts * sizeof(R));
+        c->couples = 0;
         enqueue_couple(c, &mm, f_n);
     }
+    c->couples = 0;  // the adjoint pass below consumes the recomputed force
     AdjStepArgs a{};
     a.f = f_n;
     a.lam_next = lam_next;
@@ -1202,11 +1235,13 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
     a.omega = 1.0 / c->p.tau;
     a.kf = 1.0 - 0.5 / c->p.tau;
-    const int nb = (int)cdiv(c->ntiles, 4);
+    const CsShape sh = cs_shape(c);
+    a.remap = sh.remap;
+    const int nb = (int)cdiv(c->ntiles, sh.waves);
     if (c->p.gfield)
-        k_adj_collide_stream<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
+        k_adj_collide_stream<S, R, DEV, true><<<nb, 64 * sh.waves, 0, c->s>>>(a);
     else
-        k_adj_collide_stream<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
+        k_adj_collide_stream<S, R, DEV, false><<<nb, 64 * sh.waves, 0, c->s>>>(a);
     if (!m) return;
     launch_jvp<R>(c, m, x_n, nullptr, lam_x, lam_v, nullptr, c->hv);
     AdjPointArgs p{};

@@ -102,11 +102,11 @@ def test_workspace_bytes(L):
     p = _params()
     n = 512
     tiles = 8 * 8  # one 64-wide tile per x-row
-    # node class + link mask + force accumulator and velocity field (4 floats
-    # each) + node marks + tile marks and tile fallback flags (each padded to
+    # node class + link mask + spread force, fallback accumulator and velocity
+    # field (4 floats each) + node marks + tile marks and tile fallback flags (each padded to
     # 16) and tile list (4 bytes each) + list length + claim epoch +
     # reduction partials + sums + the channel record
-    one = n + 4 * n + 8 * n * 4 + n + 2 * tiles + 4 * tiles + 4 + 4 + 2 * 32 + 32 + CHAN_BYTES
+    one = n + 4 * n + 12 * n * 4 + n + 2 * tiles + 4 * tiles + 4 + 4 + 2 * 32 + 32 + CHAN_BYTES
     assert L.lbm_workspace_bytes(C.byref(p)) == one
     dims = (C.c_int32 * 3)(8, 8, 8)
     assert L.lbm_workspace_bytes_channels(C.byref(p), 1, dims) == one
@@ -118,7 +118,7 @@ def test_workspace_bytes_channels(L):
     n = 600 + 512
     tiles = 2 * 3 * 2 + 8 * 8
     # as for one channel, plus a 2-byte channel id per tile
-    expect = (n + 4 * n + 8 * n * 4 + n + 2 * 80 + 4 * tiles + 4 + 4 + 5 * 32 + 32 + 2 * CHAN_BYTES + 2 * tiles)
+    expect = (n + 4 * n + 12 * n * 4 + n + 2 * 80 + 4 * tiles + 4 + 4 + 5 * 32 + 32 + 2 * CHAN_BYTES + 2 * tiles)
     assert L.lbm_workspace_bytes_channels(C.byref(p), 2, dims) == expect
 
 

@@ -258,6 +258,38 @@ def test_overlapping_cells_share_base_nodes_f64(orc, lbm):
     assert np.abs(mesh.positions() - X).max() < 1e-12
 
 
+def test_two_meshes_sharing_stencil_nodes_f64(orc, lbm):
+    """The overlapping pair of cells split into two membrane populations,
+    each coupled before the same collide-stream pass: nodes under both
+    stencils receive the force of both (the second coupling adds to the
+    first, including at base nodes the second population claims anew)."""
+    nx, ny, nz = 32, 24, 20
+    cen = np.array([[12.2, 11.7, 9.6], [14.9, 12.3, 10.1]])
+    mod = (0.01, 0.002, 0.005, 0.05, 0.2)
+    both = S.make_cells(cen, 3.0, 2, moduli=mod)
+    a, b = S.make_cells(cen[:1], 3.0, 2, moduli=mod), S.make_cells(cen[1:], 3.0, 2, moduli=mod)
+    s = S.Scenario("overlap2", nx, ny, nz, 0.8, (1e-4, 0, 0), S.channel_mask(nx, ny, nz), 10, cells=both)
+    # the two stencils share nodes
+    stencil = lambda X: {tuple(int(v) for v in np.floor(p) + d) for p in X for d in np.ndindex(2, 2, 2)}
+    assert len(stencil(a.positions()) & stencil(b.positions())) > 0
+    lat = lbm.Lattice.from_scenario(s, prec="f64")
+    ma, mb = lbm.Mesh(lat, a), lbm.Mesh(lat, b)
+    L = orc.Lattice.from_scenario(s)
+    M = orc.Mesh(both)
+    X = both.positions()
+    M.rest_shape(X)
+    V = np.zeros_like(X)
+    f = L.rest()
+    for _ in range(6):
+        lat.couple(ma)
+        lat.couple(mb)
+        lat.step(1)
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    assert np.abs(lat.populations_f64().cpu().numpy()[:, fl] - f[:, fl]).max() < 1e-14
+    assert np.abs(np.concatenate([ma.positions(), mb.positions()]) - X).max() < 1e-12
+
+
 def test_coupled_step_is_bit_reproducible(lbm):
     """Two identical runs give identical populations, positions and forces:
     membrane forces are gathered per vertex in a fixed order and the spread
