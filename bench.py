@@ -392,6 +392,40 @@ def chain_filter_leg(bead_steps: int, steps: int) -> dict:
     return out
 
 
+def red_cells_leg(steps: int) -> dict:
+    """Red blood cells in the throughput channel: 1000 randomly oriented
+    biconcave discs (red-cell moduli) and 40 tumour cells, 642 vertices each,
+    neo-Hookean stretching, contact forces on, FP32 deviation storage; the
+    same cells with the linear stretching law for comparison."""
+    import dataclasses
+    import torch
+    from paper_1110_0995_amd import lbm
+    from paper_1110_0995_amd import scenario as S
+    s = S.red_cell_suspension()
+    out = {"workload": "red_cells 512x256x128, 1000 red + 40 tumour cells x 642 vertices, neo-Hookean, contact, "
+                       "f32dev", "ib_points": int(s.cells.nverts), "steps": steps}
+    stream = torch.cuda.current_stream()
+    for name, law in (("neo_hookean", 1), ("linear", 0)):
+        cells = dataclasses.replace(s.cells, stretch_law=law)
+        lat = lbm.Lattice.from_scenario(s, prec="f32dev")
+        mesh = lbm.Mesh(lat, cells, contact=S.contact_params(s))
+        lat.run(20, mesh, steps_per_graph=10)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        lat.run(steps, mesh, steps_per_graph=10)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[f"ms_per_step_{name}"] = round(ms, 5)
+        out[f"mlups_{name}"] = round(s.n / (ms * 1e-3) / 1e6, 1)
+        out[f"finite_{name}"] = bool(np.isfinite(mesh.positions()).all())
+        lat.close()
+        del lat, mesh
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -411,6 +445,8 @@ def main():
                     help="steps of the magnetic bead stage, 16384 beads (0 skips the leg)")
     ap.add_argument("--chain-filter-steps", type=int, default=100,
                     help="coupled steps of the staged filter run through frozen bead chains (0 skips the leg)")
+    ap.add_argument("--red-cells-steps", type=int, default=100,
+                    help="coupled steps of the red-cell suspension, neo-Hookean and linear (0 skips the leg)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -511,6 +547,8 @@ def main():
         out["magnet"] = magnet_leg(args.magnet_steps)
     if args.chain_filter_steps > 0:
         out["chain_filter"] = chain_filter_leg(5000, args.chain_filter_steps)
+    if args.red_cells_steps > 0:
+        out["red_cells"] = red_cells_leg(args.red_cells_steps)
     print(json.dumps(out), flush=True)
 
 

@@ -278,10 +278,11 @@ def biconcave(unit: np.ndarray) -> np.ndarray:
 
 def make_cells(centres: np.ndarray, radius: float, level: int,
                moduli: Sequence[float] = MODULI_CTC, xi: float = 1.0, shape: str = "sphere",
-               stretch_law: int = 0, mass: float = 2.0) -> Cells:
+               stretch_law: int = 0, mass: float = 2.0, rotations: Optional[np.ndarray] = None) -> Cells:
     """Icosphere cells of the given radius around ``centres`` [n,3]; with
     shape="rbc" the icosphere is mapped onto the biconcave disc of that
-    radius (red blood cell, Table 1 geometry).
+    radius (red blood cell, Table 1 geometry); ``rotations`` [n,3,3]
+    optionally turns each cell's template.
 
     The template's vertices are numbered along a Z-order curve, so
     consecutive vertex ids are neighbours on the surface (and so are the
@@ -301,7 +302,10 @@ def make_cells(centres: np.ndarray, radius: float, level: int,
     nv, nt, ne = len(unit), len(tris), len(hin)
     n = len(centres)
     anchor = np.floor(centres).astype(np.int32)
-    off = (radius * unit[None, :, :] + (centres - anchor)[:, None, :]).astype(np.float32)
+    shaped = radius * unit[None, :, :]
+    if rotations is not None:
+        shaped = np.einsum("cij,vj->cvi", np.asarray(rotations, np.float64), radius * unit)
+    off = (shaped + (centres - anchor)[:, None, :]).astype(np.float32)
     base = (np.arange(n) * nv)[:, None, None]
     return Cells(
         vert_off=(np.arange(n + 1) * nv).astype(np.int32),
@@ -673,3 +677,61 @@ def chain_filter_inputs(nx: int = 512, ny: int = 256, nz: int = 128, *, nbeads: 
     rng = np.random.default_rng(seed + 1)
     cen = place_cells(rng, ncells, cell_radius, (int(band[0]) - 16, ny, nz))
     return st, make_cells(cen, cell_radius, level, MODULI_CTC)
+
+
+def random_rotations(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n rotation matrices, uniform over the rotation group (QR of Gaussian
+    matrices with the sign fixed)."""
+    q, r = np.linalg.qr(rng.standard_normal((n, 3, 3)))
+    q = q * np.sign(np.diagonal(r, axis1=1, axis2=2))[:, None, :]
+    det = np.linalg.det(q)
+    q[det < 0, :, 0] *= -1.0
+    return q
+
+
+def red_cell_suspension(nx: int = 512, ny: int = 256, nz: int = 128, *, posts_x: int = 8, posts_y: int = 4,
+                        post_radius: int = 8, gap_range=(6, 14), nred: int = 1000, red_radius: float = 5.0,
+                        ntumour: int = 40, tumour_radius: float = 10.0, level: int = 3, tau: float = 0.7,
+                        gx: float = 1e-5, steps: int = 1000, seed: int = 6) -> Scenario:
+    """The throughput channel (8x4 posts, gaps U{6..14}) with a suspension of
+    red cells (biconcave discs of radius 5, randomly oriented, red-cell
+    moduli) and tumour cells (spheres of radius 10, tumour-cell moduli), all
+    642 vertices, neo-Hookean stretching, membrane mass 8 (the red cells'
+    stability bound); placed by random sequential addition of bounding
+    spheres, tumour cells first, 1 LU apart and clear of posts and walls."""
+    rng = np.random.default_rng(seed)
+    mask = channel_mask(nx, ny, nz)
+    gx_ = rng.integers(gap_range[0], gap_range[1] + 1, size=posts_x - 1)
+    gy_ = rng.integers(gap_range[0], gap_range[1] + 1, size=posts_y - 1)
+    posts = post_array_centres(nx, ny, gx_, gy_, post_radius)
+    add_posts(mask, posts, post_radius)
+    radii = np.concatenate([np.full(ntumour, tumour_radius), np.full(nred, red_radius)])
+    placed: List[np.ndarray] = []
+    prad: List[float] = []
+    pc = np.asarray(posts, np.float64).reshape(-1, 2)
+    for r in radii:
+        for _ in range(200000):
+            p = np.array([rng.uniform(0, nx), rng.uniform(0, ny), rng.uniform(0.5 + r + 1.0, nz - 1.5 - r - 1.0)])
+            if len(pc):
+                d = pc - p[:2]
+                d -= np.array([nx, ny]) * np.floor(d / [nx, ny] + 0.5)
+                if (np.hypot(d[:, 0], d[:, 1]) < post_radius + 0.5 + r + 1.0).any():
+                    continue
+            if placed:
+                d = np.asarray(placed) - p
+                d[:, 0] -= nx * np.floor(d[:, 0] / nx + 0.5)
+                d[:, 1] -= ny * np.floor(d[:, 1] / ny + 0.5)
+                if (np.linalg.norm(d, axis=1) < np.asarray(prad) + r + 1.0).any():
+                    continue
+            placed.append(p)
+            prad.append(r)
+            break
+        else:
+            raise RuntimeError(f"could only place {len(placed)} of {len(radii)} cells")
+    cen = np.asarray(placed)
+    tum = make_cells(cen[:ntumour], tumour_radius, level, MODULI_CTC, stretch_law=1, mass=MASS_RBC)
+    red = make_cells(cen[ntumour:], red_radius, level, MODULI_RBC, shape="rbc", stretch_law=1, mass=MASS_RBC,
+                     rotations=random_rotations(rng, nred))
+    cells = concat_cells([tum, red])
+    return Scenario("red_cells", nx, ny, nz, tau, (gx, 0.0, 0.0), mask, steps, cells=cells,
+                    meta=dict(post_centres=posts, post_radius=post_radius, seed=seed, nred=nred, ntumour=ntumour))
