@@ -679,9 +679,15 @@ static int build_sphere_grid(lbm_ctx *c, const ibm_contact *k) {
     const double reach = (rmax + k->roff + k->rcut) * (1.0 + 1e-9);
     const int dims[3] = {c->p.nx, c->p.ny, c->p.nz};
     int g[3];
+    for (int d = 0; d < 3; d++) g[d] = (int)std::max(1.0, std::min(1024.0, std::floor(dims[d] / reach)));
+    // at most 2^22 cells (16 MB of offsets): halve the finest axis until it fits
+    // (larger cells still hold every sphere in reach)
+    while ((int64_t)g[0] * g[1] * g[2] > (int64_t(1) << 22)) {
+        const int d = (g[0] >= g[1] && g[0] >= g[2]) ? 0 : (g[1] >= g[2] ? 1 : 2);
+        g[d] = std::max(1, g[d] / 2);
+    }
     int64_t ncell = 1;
     for (int d = 0; d < 3; d++) {
-        g[d] = (int)std::max(1.0, std::min(1024.0, std::floor(dims[d] / reach)));
         c->sph_g[d] = g[d];
         c->sph_inv[d] = g[d] / (double)dims[d];
         ncell *= g[d];
