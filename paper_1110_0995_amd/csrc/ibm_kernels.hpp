@@ -108,6 +108,7 @@ struct MembArgs {
 };
 
 constexpr int kMembThreads = 512;
+constexpr int kInc = 4;  // incident elements whose indices a vertex loads together
 
 __device__ __forceinline__ int cell_channel(const int32_t *cell_chan, int c) { return cell_chan ? cell_chan[c] : 0; }
 
@@ -254,44 +255,78 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
             continue;
         }
         double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (int i = a.vtri_off[vg]; i < a.vtri_off[vg + 1]; i++) {
-            const int code = a.vtri[i], t = (code >> 2) - t0, r = code & 3;
-            const V3 A = P(a.tri[t0 + t] - v0), B = P(a.tri[NT + t0 + t] - v0), C = P(a.tri[2 * NT + t0 + t] - v0);
-            const V3 n = crs(sub(B, A), sub(C, A));
-            // role r: grad of area ~ (next - prev) x n, of volume (next x prev)/6
-            const V3 nx_ = r == 0 ? B : (r == 1 ? C : A), pv = r == 0 ? C : (r == 1 ? A : B);
-            const V3 g = crs(sub(nx_, pv), n), vg3 = crs(nx_, pv);
-            const double h = (double)tco[t];
-            fx += h * g.x - cv6 * vg3.x;
-            fy += h * g.y - cv6 * vg3.y;
-            fz += h * g.z - cv6 * vg3.z;
-        }
-        for (int i = a.vedge_off[vg]; i < a.vedge_off[vg + 1]; i++) {
-            const int code = a.vedge[i], e = (code >> 2) - e0, r = code & 3;
-            const V3 p1 = P(a.hinge[e0 + e] - v0), p2 = P(a.hinge[NE + e0 + e] - v0);
-            const V3 qa = P(a.hinge[2 * NE + e0 + e] - v0), qb = P(a.hinge[3 * NE + e0 + e] - v0);
-            const V3 ev = sub(p2, p1);
-            const V3 na = crs(ev, sub(qa, p1)), nb = crs(sub(p1, p2), sub(qb, p2));
-            const double l2 = dot(ev, ev), l = sqrt(l2);
-            const double cs = (double)eco[2 * e], cb = (double)eco[2 * e + 1];
-            // d theta/d qa = -|e| na/|na|^2, d theta/d qb = -|e| nb/|nb|^2; the edge ends
-            // take the combinations that keep net force and torque zero.
-            const V3 ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
-            V3 g;
-            double s = 0.0;
-            if (r == 2) {
-                g = ga;
-            } else if (r == 3) {
-                g = gb;
-            } else {
-                const double sa = dot(sub(qa, p1), ev) / l2, sb = dot(sub(qb, p1), ev) / l2;
-                const double ca_ = r == 0 ? -(1.0 - sa) : -sa, cb_ = r == 0 ? -(1.0 - sb) : -sb;
-                g = V3{ca_ * ga.x + cb_ * gb.x, ca_ * ga.y + cb_ * gb.y, ca_ * ga.z + cb_ * gb.z};
-                s = r == 0 ? cs : -cs;
+        // The incident elements are taken kInc at a time: their codes and
+        // vertex indices are loaded first (independent loads in flight
+        // together), then the terms are added in list order.
+        const int ti0 = a.vtri_off[vg], ti1 = a.vtri_off[vg + 1];
+        for (int base = ti0; base < ti1; base += kInc) {
+            int tv[kInc][3], tt[kInc], tr[kInc];
+#pragma unroll
+            for (int j = 0; j < kInc; j++) {
+                const int code = base + j < ti1 ? a.vtri[base + j] : a.vtri[ti0];
+                tt[j] = (code >> 2) - t0;
+                tr[j] = code & 3;
             }
-            fx += s * ev.x - cb * g.x;
-            fy += s * ev.y - cb * g.y;
-            fz += s * ev.z - cb * g.z;
+#pragma unroll
+            for (int j = 0; j < kInc; j++)
+#pragma unroll
+                for (int q = 0; q < 3; q++) tv[j][q] = a.tri[q * NT + t0 + tt[j]] - v0;
+#pragma unroll
+            for (int j = 0; j < kInc; j++) {
+                if (base + j >= ti1) break;
+                const int t = tt[j], r = tr[j];
+                const V3 A = P(tv[j][0]), B = P(tv[j][1]), C = P(tv[j][2]);
+                const V3 n = crs(sub(B, A), sub(C, A));
+                // role r: grad of area ~ (next - prev) x n, of volume (next x prev)/6
+                const V3 nx_ = r == 0 ? B : (r == 1 ? C : A), pv = r == 0 ? C : (r == 1 ? A : B);
+                const V3 g = crs(sub(nx_, pv), n), vg3 = crs(nx_, pv);
+                const double h = (double)tco[t];
+                fx += h * g.x - cv6 * vg3.x;
+                fy += h * g.y - cv6 * vg3.y;
+                fz += h * g.z - cv6 * vg3.z;
+            }
+        }
+        const int ei0 = a.vedge_off[vg], ei1 = a.vedge_off[vg + 1];
+        for (int base = ei0; base < ei1; base += kInc) {
+            int ev4[kInc][4], ee[kInc], er[kInc];
+#pragma unroll
+            for (int j = 0; j < kInc; j++) {
+                const int code = base + j < ei1 ? a.vedge[base + j] : a.vedge[ei0];
+                ee[j] = (code >> 2) - e0;
+                er[j] = code & 3;
+            }
+#pragma unroll
+            for (int j = 0; j < kInc; j++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) ev4[j][q] = a.hinge[q * NE + e0 + ee[j]] - v0;
+#pragma unroll
+            for (int j = 0; j < kInc; j++) {
+                if (base + j >= ei1) break;
+                const int e = ee[j], r = er[j];
+                const V3 p1 = P(ev4[j][0]), p2 = P(ev4[j][1]), qa = P(ev4[j][2]), qb = P(ev4[j][3]);
+                const V3 ev = sub(p2, p1);
+                const V3 na = crs(ev, sub(qa, p1)), nb = crs(sub(p1, p2), sub(qb, p2));
+                const double l2 = dot(ev, ev), l = sqrt(l2);
+                const double cs = (double)eco[2 * e], cb = (double)eco[2 * e + 1];
+                // d theta/d qa = -|e| na/|na|^2, d theta/d qb = -|e| nb/|nb|^2; the edge ends
+                // take the combinations that keep net force and torque zero.
+                const V3 ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
+                V3 g;
+                double s = 0.0;
+                if (r == 2) {
+                    g = ga;
+                } else if (r == 3) {
+                    g = gb;
+                } else {
+                    const double sa = dot(sub(qa, p1), ev) / l2, sb = dot(sub(qb, p1), ev) / l2;
+                    const double ca_ = r == 0 ? -(1.0 - sa) : -sa, cb_ = r == 0 ? -(1.0 - sb) : -sb;
+                    g = V3{ca_ * ga.x + cb_ * gb.x, ca_ * ga.y + cb_ * gb.y, ca_ * ga.z + cb_ * gb.z};
+                    s = r == 0 ? cs : -cs;
+                }
+                fx += s * ev.x - cb * g.x;
+                fy += s * ev.y - cb * g.y;
+                fz += s * ev.z - cb * g.z;
+            }
         }
         R *FE = static_cast<R *>(a.f_el);
         FE[vg] = R(fx);
