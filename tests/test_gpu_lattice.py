@@ -171,3 +171,28 @@ def test_periodic_box_momentum_f64(orc, lbm):
     Ftot = np.array(g) * nx * ny * nz + G.reshape(3, -1).sum(1)
     assert abs(p1[0] - p0[0]) < 1e-12 * p0[0]
     assert np.allclose(p1[1:], p0[1:] + 50 * Ftot, rtol=0, atol=1e-12 * p0[0])
+
+
+@pytest.mark.parametrize("nx", [150, 700])
+def test_row_workgroups_match_other_shapes(lbm, nx):
+    """One channel: the automatic collide-stream shape (whole x rows per
+    workgroup in natural order when a row is at most 8 tiles: nx = 150, 3
+    tiles; 4 renumbered tiles otherwise: nx = 700, 11 tiles) gives bitwise
+    the results of explicit shapes, with cells, posts and a ragged last
+    tile."""
+    import torch
+    from paper_1110_0995_amd import scenario as S
+    s = S.posts_and_cells(nx, 24, 16, posts_x=1, posts_y=1, post_radius=3, gap=6, ncells=2, cell_radius=3.0, level=2,
+                          gx=1e-4, seed=5)
+    out = []
+    for waves in (0, 1, 4, 8):
+        lat = lbm.Lattice.from_scenario(s, prec="f32dev")
+        mesh = lbm.Mesh(lat, s.cells)
+        lat.set_launch(waves, 0)
+        lat.run(10, mesh, steps_per_graph=0)
+        lat.run(10, mesh, steps_per_graph=10)
+        torch.cuda.synchronize()
+        out.append((lat.current().cpu().numpy(), mesh.positions()))
+        lat.close()
+    for f, x in out[1:]:
+        assert np.array_equal(f, out[0][0]) and np.array_equal(x, out[0][1])
