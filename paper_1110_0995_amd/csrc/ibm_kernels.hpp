@@ -120,6 +120,46 @@ __host__ __device__ inline size_t membrane_lds_bytes(int maxv, int maxt, int max
            ((size_t)maxt + 2 * (size_t)maxe) * sizeof(R);
 }
 
+// Force on a vertex in role r of triangle (A, B, C) with area coefficient h
+// and volume coefficient cv6: grad of area ~ (next - prev) x n, of volume
+// (next x prev)/6.
+__device__ __forceinline__ void tri_term(const V3 &A, const V3 &B, const V3 &C, int r, double h, double cv6,
+                                         double &fx, double &fy, double &fz) {
+    const V3 n = crs(sub(B, A), sub(C, A));
+    const V3 nx_ = r == 0 ? B : (r == 1 ? C : A), pv = r == 0 ? C : (r == 1 ? A : B);
+    const V3 g = crs(sub(nx_, pv), n), vg3 = crs(nx_, pv);
+    fx += h * g.x - cv6 * vg3.x;
+    fy += h * g.y - cv6 * vg3.y;
+    fz += h * g.z - cv6 * vg3.z;
+}
+
+// Force on a vertex in role r (0: p1, 1: p2, 2: qa, 3: qb) of hinge
+// (p1, p2, qa, qb) with stretch coefficient cs and bend coefficient cb.
+// d theta/d qa = -|e| na/|na|^2, d theta/d qb = -|e| nb/|nb|^2; the edge ends
+// take the combinations that keep net force and torque zero.
+__device__ __forceinline__ void edge_term(const V3 &p1, const V3 &p2, const V3 &qa, const V3 &qb, int r, double cs,
+                                          double cb, double &fx, double &fy, double &fz) {
+    const V3 ev = sub(p2, p1);
+    const V3 na = crs(ev, sub(qa, p1)), nb = crs(sub(p1, p2), sub(qb, p2));
+    const double l2 = dot(ev, ev), l = sqrt(l2);
+    const V3 ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
+    V3 g;
+    double s = 0.0;
+    if (r == 2) {
+        g = ga;
+    } else if (r == 3) {
+        g = gb;
+    } else {
+        const double sa = dot(sub(qa, p1), ev) / l2, sb = dot(sub(qb, p1), ev) / l2;
+        const double ca_ = r == 0 ? -(1.0 - sa) : -sa, cb_ = r == 0 ? -(1.0 - sb) : -sb;
+        g = V3{ca_ * ga.x + cb_ * gb.x, ca_ * ga.y + cb_ * gb.y, ca_ * ga.z + cb_ * gb.z};
+        s = r == 0 ? cs : -cs;
+    }
+    fx += s * ev.x - cb * g.x;
+    fy += s * ev.y - cb * g.y;
+    fz += s * ev.z - cb * g.z;
+}
+
 // REST = true: write the rest shape; false: elastic forces + stencil marks.
 //
 // Forces are the exact gradients of the energies written element by
@@ -246,6 +286,7 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     __syncthreads();
 
     // vertex pass
+    R *FE = static_cast<R *>(a.f_el);
     for (int k = threadIdx.x; k < nv; k += blockDim.x) {
         const int vg = v0 + k;
         if (REST) {  // each vertex carries a third of its triangles' rest area
@@ -274,16 +315,7 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
 #pragma unroll
             for (int j = 0; j < kInc; j++) {
                 if (base + j >= ti1) break;
-                const int t = tt[j], r = tr[j];
-                const V3 A = P(tv[j][0]), B = P(tv[j][1]), C = P(tv[j][2]);
-                const V3 n = crs(sub(B, A), sub(C, A));
-                // role r: grad of area ~ (next - prev) x n, of volume (next x prev)/6
-                const V3 nx_ = r == 0 ? B : (r == 1 ? C : A), pv = r == 0 ? C : (r == 1 ? A : B);
-                const V3 g = crs(sub(nx_, pv), n), vg3 = crs(nx_, pv);
-                const double h = (double)tco[t];
-                fx += h * g.x - cv6 * vg3.x;
-                fy += h * g.y - cv6 * vg3.y;
-                fz += h * g.z - cv6 * vg3.z;
+                tri_term(P(tv[j][0]), P(tv[j][1]), P(tv[j][2]), tr[j], (double)tco[tt[j]], cv6, fx, fy, fz);
             }
         }
         const int ei0 = a.vedge_off[vg], ei1 = a.vedge_off[vg + 1];
@@ -302,33 +334,11 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
 #pragma unroll
             for (int j = 0; j < kInc; j++) {
                 if (base + j >= ei1) break;
-                const int e = ee[j], r = er[j];
-                const V3 p1 = P(ev4[j][0]), p2 = P(ev4[j][1]), qa = P(ev4[j][2]), qb = P(ev4[j][3]);
-                const V3 ev = sub(p2, p1);
-                const V3 na = crs(ev, sub(qa, p1)), nb = crs(sub(p1, p2), sub(qb, p2));
-                const double l2 = dot(ev, ev), l = sqrt(l2);
-                const double cs = (double)eco[2 * e], cb = (double)eco[2 * e + 1];
-                // d theta/d qa = -|e| na/|na|^2, d theta/d qb = -|e| nb/|nb|^2; the edge ends
-                // take the combinations that keep net force and torque zero.
-                const V3 ga = scl(-l / dot(na, na), na), gb = scl(-l / dot(nb, nb), nb);
-                V3 g;
-                double s = 0.0;
-                if (r == 2) {
-                    g = ga;
-                } else if (r == 3) {
-                    g = gb;
-                } else {
-                    const double sa = dot(sub(qa, p1), ev) / l2, sb = dot(sub(qb, p1), ev) / l2;
-                    const double ca_ = r == 0 ? -(1.0 - sa) : -sa, cb_ = r == 0 ? -(1.0 - sb) : -sb;
-                    g = V3{ca_ * ga.x + cb_ * gb.x, ca_ * ga.y + cb_ * gb.y, ca_ * ga.z + cb_ * gb.z};
-                    s = r == 0 ? cs : -cs;
-                }
-                fx += s * ev.x - cb * g.x;
-                fy += s * ev.y - cb * g.y;
-                fz += s * ev.z - cb * g.z;
+                const int e = ee[j];
+                edge_term(P(ev4[j][0]), P(ev4[j][1]), P(ev4[j][2]), P(ev4[j][3]), er[j], (double)eco[2 * e],
+                          (double)eco[2 * e + 1], fx, fy, fz);
             }
         }
-        R *FE = static_cast<R *>(a.f_el);
         FE[vg] = R(fx);
         FE[NV + vg] = R(fy);
         FE[2 * NV + vg] = R(fz);
