@@ -184,11 +184,11 @@ int lbm_init_channels(const lbm_params *p, int32_t nch, const int32_t *dims, lbm
 int64_t lbm_workspace_bytes_channels(const lbm_params *p, int32_t nch, const int32_t *dims);
 
 /* Launch shape, results unchanged: collide_waves_per_block = 64-node tiles
- * per collide-stream workgroup (1, 2, 4 or 8; 0 = by the lattice: whole x
- * rows, as many as fit in 8 tiles, for a one-channel lattice whose rows are
- * at most 8 tiles, else 4), list_blocks = workgroups of the kernels that
- * walk the list of tiles under a membrane stencil (0 = by lattice size, at
- * most 65536).  Drops a captured graph. */
+ * per collide-stream workgroup (1, 2, 4 or 8; 0 = by the channels: each
+ * workgroup takes whole x rows of one channel, as many as fit in 8 tiles,
+ * or a piece of 8 tiles of a longer row), list_blocks = workgroups of the
+ * kernels that walk the list of tiles under a membrane stencil (0 = by
+ * lattice size, at most 65536).  Drops a captured graph. */
 int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t list_blocks);
 
 /* nsteps >= 0 coupled steps: for each, ibm_couple(c, m) (skipped when m is

@@ -2,7 +2,9 @@
 
 Three knobs change speed but never results (the kernels compute the same
 values in the same order whatever the launch shape):
-  - collide_waves_per_block: 64-node tiles per collide-stream workgroup;
+  - collide_waves_per_block: 64-node tiles per collide-stream workgroup
+    (0: whole x rows of one channel per workgroup, the row groups chosen
+    per channel length);
   - list_blocks: workgroups of the kernels that walk the list of tiles
     under a membrane stencil (0 = sized from the lattice);
   - steps_per_graph: coupled steps captured in one HIP graph launch.
@@ -22,7 +24,7 @@ from typing import Dict, Optional
 
 import torch
 
-WAVES = (1, 2, 4, 8)
+WAVES = (0, 1, 2, 4, 8)
 LIST_BLOCKS = (0, 256, 1024, 4096)
 GRAPH_STEPS = (2, 10, 50)
 
@@ -81,7 +83,7 @@ def tune(lat, mesh=None, steps: int = 20, cache: Optional[str] = None, force: bo
     saved = [t.clone() for t in (lat.f_a, lat.f_b)]
     msaved = [t.clone() for t in (mesh.x, mesh.v, mesh.f_el)] if mesh is not None else []
     # even step counts only: the state buffers end where they started
-    w, lb, g = 4, 0, 10
+    w, lb, g = 0, 0, 10
     ms = {}
     for cand in WAVES:
         ms[("w", cand)] = _time(lat, mesh, cand, lb, g, steps)

@@ -90,6 +90,7 @@ struct AdjStepArgs {
     const uint16_t *tile_chan;
     int ntiles;
     int remap;             // as in StepArgs
+    const uint32_t *wgtab; // [gridDim.x] workgroup table (first tile << 3 | tiles - 1), or null
     int64_t N;
     double g[3];
     double omega, kf;
@@ -99,8 +100,15 @@ template <class S, class R, bool DEV, bool HAS_G>
 __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
     using R4 = typename Vec4<R>::T;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int tile = blk * (blockDim.x >> 6) + wave;
+    int tile;
+    if (a.wgtab) {
+        const uint32_t e = a.wgtab[blockIdx.x];
+        if (wave > (int)(e & 7u)) return;
+        tile = (int)(e >> 3) + wave;
+    } else {
+        const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+        tile = blk * (blockDim.x >> 6) + wave;
+    }
     if (tile >= a.ntiles) return;
     const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
     const int lt = tile - ch.toff, row = lt / ch.tpr;

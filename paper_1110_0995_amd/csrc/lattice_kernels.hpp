@@ -137,6 +137,7 @@ struct StepArgs {
     const uint16_t *tile_chan;  // null for a single channel
     int ntiles;
     int remap;            // 1: renumber workgroups so each XCD walks one contiguous tile range
+    const uint32_t *wgtab; // [gridDim.x] workgroup table (first tile << 3 | tiles - 1), or null
     int64_t N;
     double g[3];
     double omega, kf;
@@ -160,8 +161,15 @@ struct StepArgs {
 template <class S, class R, bool DEV, bool HAS_G, class IDX>
 __global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-    const int tile = blk * (blockDim.x >> 6) + wave;
+    int tile;
+    if (a.wgtab) {
+        const uint32_t e = a.wgtab[blockIdx.x];
+        if (wave > (int)(e & 7u)) return;
+        tile = (int)(e >> 3) + wave;
+    } else {
+        const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+        tile = blk * (blockDim.x >> 6) + wave;
+    }
     if (tile >= a.ntiles) return;
     const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
     const int lt = tile - ch.toff;

@@ -120,6 +120,8 @@ struct lbm_ctx {
     std::vector<Chan> hchans;
     Chan *chans = nullptr;          // device copy of hchans
     uint16_t *tile_chan = nullptr;  // [ntiles] channel of each tile, null for one channel
+    uint32_t *wgtab = nullptr;      // [nwg] collide-stream workgroups: first tile << 3 | (tiles - 1)
+    int nwg = 0;
     int64_t N = 0, stride = 0;
     int ntiles = 0;
     size_t rsize = 4;  // sizeof(real)
@@ -252,15 +254,43 @@ static int make_channels(int32_t nch, const int32_t *dims, std::vector<Chan> &ou
     return LBM_OK;
 }
 
-static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch) {
-    return N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
+// Collide-stream workgroups of whole x rows: a channel whose rows are at
+// most 8 tiles gets workgroups of floor(8 / tiles per row) rows (the last
+// one of the channel may hold fewer); a longer row is cut into pieces of 8
+// tiles.  A workgroup never spans two channels.  Entry: first tile << 3 |
+// (tiles - 1).
+static int64_t row_groups(int tpr, int64_t rows) {
+    return tpr <= 8 ? cdiv(rows, 8 / tpr) : rows * cdiv(tpr, 8);
+}
+static void build_row_groups(const std::vector<Chan> &chs, std::vector<uint32_t> &tab) {
+    tab.clear();
+    for (const Chan &ch : chs) {
+        const int64_t rows = (int64_t)ch.ny * ch.nz;
+        if (ch.tpr <= 8) {
+            const int rpw = 8 / ch.tpr;
+            for (int64_t r0 = 0; r0 < rows; r0 += rpw) {
+                const int64_t nr = std::min<int64_t>(rpw, rows - r0);
+                tab.push_back((uint32_t)((ch.toff + r0 * ch.tpr) << 3) | (uint32_t)(nr * ch.tpr - 1));
+            }
+        } else {
+            for (int64_t r = 0; r < rows; r++)
+                for (int c0 = 0; c0 < ch.tpr; c0 += 8)
+                    tab.push_back((uint32_t)((ch.toff + r * ch.tpr + c0) << 3) | (uint32_t)(std::min(8, ch.tpr - c0) - 1));
+        }
+    }
+}
+
+static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch, int64_t nwg) {
+    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
            (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
 }
 
 LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {
     if (check_params(p)) return -1;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
-    return workspace(N, cdiv(p->nx, 64) * (int64_t)p->ny * p->nz, p->prec == LBM_F64 ? 8 : 4, 1);
+    const int tpr = (int)cdiv(p->nx, 64);
+    return workspace(N, tpr * (int64_t)p->ny * p->nz, p->prec == LBM_F64 ? 8 : 4, 1,
+                     row_groups(tpr, (int64_t)p->ny * p->nz));
 }
 
 LBM_API int64_t lbm_workspace_bytes_channels(const lbm_params *p, int32_t nch, const int32_t *dims) {
@@ -268,7 +298,9 @@ LBM_API int64_t lbm_workspace_bytes_channels(const lbm_params *p, int32_t nch, c
     std::vector<Chan> chs;
     int64_t N, T;
     if (make_channels(nch, dims, chs, N, T) || check_common(p, N)) return -1;
-    return workspace(N, T, p->prec == LBM_F64 ? 8 : 4, nch);
+    int64_t nwg = 0;
+    for (const Chan &ch : chs) nwg += row_groups(ch.tpr, (int64_t)ch.ny * ch.nz);
+    return workspace(N, T, p->prec == LBM_F64 ? 8 : 4, nch, nwg);
 }
 
 LBM_API void lbm_destroy(lbm_ctx *c) {
@@ -280,7 +312,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
-                    c->sph_start, c->sph_items};
+                    c->sph_start, c->sph_items, c->wgtab};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -315,6 +347,16 @@ static int init_ctx(lbm_ctx *c) {
         return fail(LBM_ENOMEM, "device allocation of the context work buffers failed");
     }
     HIPCHK(hipMemcpy(c->chans, c->hchans.data(), sizeof(Chan) * c->nch, hipMemcpyHostToDevice));
+    {
+        std::vector<uint32_t> tab;
+        build_row_groups(c->hchans, tab);
+        c->nwg = (int)tab.size();
+        if (hipMalloc(&c->wgtab, 4 * tab.size()) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "device allocation of the workgroup table failed");
+        }
+        HIPCHK(hipMemcpy(c->wgtab, tab.data(), 4 * tab.size(), hipMemcpyHostToDevice));
+    }
     if (c->nch > 1) {
         std::vector<uint16_t> tc(tn);
         for (int k = 0; k < c->nch; k++) {
@@ -401,28 +443,28 @@ LBM_API int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t 
 static const void *cur_f(const lbm_ctx *c) { return c->cur ? c->p.f_b : c->p.f_a; }
 static void *nxt_f(const lbm_ctx *c) { return c->cur ? c->p.f_a : c->p.f_b; }
 
-// Workgroup shape of the collide-stream passes.  One channel whose x rows
-// are at most 8 tiles: whole rows per workgroup (as many as fit in 8 waves),
-// in natural order; otherwise 4 tiles per workgroup renumbered by XCD.  An
-// explicit shape (lbm_set_launch) skips the renumbering only when it holds
+// Workgroup shape of the collide-stream passes.  By default (cs_waves = 0)
+// workgroups of 8 waves take the row groups of the workgroup table (whole x
+// rows of one channel, as many as fit in 8 tiles; pieces of 8 tiles of a
+// longer row) in natural order.  An explicit shape (lbm_set_launch) cuts
+// the tile range into equal workgroups, renumbered by XCD unless they hold
 // whole rows of a one-channel lattice.
 struct CsShape {
-    int waves, remap;
+    int waves, remap, nb;
+    const uint32_t *tab;
 };
 static CsShape cs_shape(const lbm_ctx *c) {
+    if (c->cs_waves == 0) return {8, 0, c->nwg, c->wgtab};
     const int tpr = c->nch == 1 ? c->hchans[0].tpr : 0;
-    if (c->cs_waves == 0) {
-        if (tpr >= 1 && tpr <= 8) return {(8 / tpr) * tpr, 0};
-        return {4, 1};
-    }
-    return {c->cs_waves, (tpr >= 1 && c->cs_waves % tpr == 0) ? 0 : 1};
+    return {c->cs_waves, (tpr >= 1 && c->cs_waves % tpr == 0) ? 0 : 1, (int)cdiv(c->ntiles, c->cs_waves), nullptr};
 }
 
 template <class S, class R, bool DEV>
 static void launch_step(lbm_ctx *c, StepArgs a) {
     const CsShape sh = cs_shape(c);
     a.remap = sh.remap;
-    const int nb = (int)cdiv(c->ntiles, sh.waves);
+    a.wgtab = sh.tab;
+    const int nb = sh.nb;
     const int bs = 64 * sh.waves;
     if (c->off32) {
         if (c->p.gfield)
@@ -1243,7 +1285,8 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     a.kf = 1.0 - 0.5 / c->p.tau;
     const CsShape sh = cs_shape(c);
     a.remap = sh.remap;
-    const int nb = (int)cdiv(c->ntiles, sh.waves);
+    a.wgtab = sh.tab;
+    const int nb = sh.nb;
     if (c->p.gfield)
         k_adj_collide_stream<S, R, DEV, true><<<nb, 64 * sh.waves, 0, c->s>>>(a);
     else
