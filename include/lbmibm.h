@@ -39,8 +39,9 @@
  *   - Ownership: the caller allocates every buffer passed in (device
  *     memory unless stated) and keeps it alive until lbm_destroy; the
  *     library only borrows them.  The context owns its own work buffers
- *     (node classes, immersed-boundary force accumulator, reduction
- *     partials), allocated in lbm_init and freed in lbm_destroy.
+ *     (node classes, immersed-boundary spread force and fallback
+ *     accumulator, reduction partials, collide-stream workgroup table),
+ *     allocated in lbm_init and freed in lbm_destroy.
  *   - Streams: every call enqueues on params.stream and returns without
  *     waiting, except lbm_read_fields with a non-NULL host_sums,
  *     ibm_rest_shape (reads the mesh topology back to check it) and
@@ -224,7 +225,9 @@ int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m);
  * surrounding nodes for the next lbm_step, then V += dt/m_k (F_el + F_c),
  * X += dt V.  Lengths, areas, angles, cell area and volume are evaluated in
  * FP64 from the stored positions in every precision, so their small
- * departures from the rest shape are not lost to rounding. */
+ * departures from the rest shape are not lost to rounding.  Several meshes
+ * may be coupled before one lbm_step: their spread forces add up (the
+ * next lbm_step consumes the sum). */
 int ibm_couple(lbm_ctx *c, const ibm_mesh *m);
 
 /* rho [N] and u [3][N] (real, device, either may be NULL) of the current
