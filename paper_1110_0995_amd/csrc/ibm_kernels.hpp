@@ -631,7 +631,7 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     // step 4 (points): semi-implicit Euler with the vertex's mass; the
     // membrane force carries the wall contact force when walls are given
     R fex = FE[k], fey = FE[NV + k], fez = FE[2 * NV + k];
-    if (a.wall.nplanes + a.wall.ncyl > 0) {
+    if (a.wall.nplanes + a.wall.ncyl + a.wall.nsph > 0) {
         double wx_, wy_, wz_;
         wall_force(a.wall, cell_channel(a.cell_chan, c), ch, a.anchor[c] + ox, a.anchor[a.ncells + c] + oy,
                    a.anchor[2 * a.ncells + c] + oz, wx_, wy_, wz_);

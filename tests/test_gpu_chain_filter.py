@@ -150,3 +150,39 @@ def test_pipeline_small(orc, gpu):
     ug = ug.double().cpu().numpy()
     assert np.linalg.norm(ug[:, fl] - uo[:, fl]) / np.linalg.norm(uo[:, fl]) < 1e-5
     assert np.abs(mesh.positions() - X).max() < 1e-4
+
+
+def test_sphere_outside_the_lattice_f64(orc, gpu):
+    """A contact sphere centred below z = 0 (outside the lattice along its
+    non-periodic axis; the grid clamps it into the bottom cells) and one
+    far above the top, with a cell resting just above the first: coupled
+    FP64 steps equal the oracle's, and the sphere acts."""
+    lbm, _, _ = gpu
+    nx, ny, nz = 40, 32, 24
+    unit, _ = S.icosphere(2)
+    R = 3.0
+    low = R * -unit[:, 2].min()
+    cen = np.array([20.0, 16.0, 0.0])
+    sph = np.array([[20.0, 16.0, -0.4, 2.0], [7.0, 9.0, nz + 5.0, 2.0]])
+    cen[2] = sph[0, 2] + sph[0, 3] + 0.3 + low  # lowest vertex 0.3 above the sphere's top
+    cells = S.make_cells(cen[None], R, 2, moduli=(0.02, 0.005, 0.01, 0.1, 0.5))
+    s = S.Scenario("below", nx, ny, nz, 0.8, (1e-4, 0.0, 0.0), S.channel_mask(nx, ny, nz), 4, cells=cells,
+                   periodic=(1, 1, 0))
+    contact = S.contact_params(s, a=1e-4, planes=np.zeros((0, 4)), spheres=sph)
+    L = orc.Lattice.from_scenario(s)
+    M = orc.Mesh(cells, contact=contact)
+    X = cells.positions()
+    M.rest_shape(X)
+    Fs = M.contact_forces(L, X)
+    assert np.abs(Fs).max() > 1e-3
+    lat = lbm.Lattice.from_scenario(s, prec="f64")
+    mesh = lbm.Mesh(lat, cells, contact=contact)
+    lat.run(4, mesh)
+    V = np.zeros_like(X)
+    f = L.rest()
+    for _ in range(4):
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    assert np.abs(lat.populations_f64().cpu().numpy()[:, fl] - f[:, fl]).max() < 3e-14
+    assert np.abs(mesh.velocities() - V).max() < 1e-13
+    assert np.abs(mesh.positions() - X).max() < 1e-12
