@@ -192,6 +192,19 @@ int64_t lbm_workspace_bytes_channels(const lbm_params *p, int32_t nch, const int
  * lattice size, at most 65536).  Drops a captured graph. */
 int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t list_blocks);
 
+/* Schedule of a coupled step's immersed-boundary kernels, results unchanged
+ * (bitwise): with overlap, the membrane forces (Sec. 2.3) run on a second
+ * stream owned by the context while the velocities at the stencil nodes
+ * (Sec. 2.2 step 1) are evaluated on p->stream, and both are joined into
+ * p->stream before the point update; without it they run in order.  Either
+ * way every call's work is on p->stream when it returns.  mode = 1: always,
+ * 0: never, -1 (the default): when the mesh has at least
+ * LBM_OVERLAP_MIN_POINTS IB points (below that the join costs more than the
+ * overlap saves).  The adjoint's recomputed steps never overlap.  Drops a
+ * captured graph; LBM_EINVAL for another mode. */
+#define LBM_OVERLAP_MIN_POINTS 16384
+int lbm_set_ibm_overlap(lbm_ctx *c, int32_t mode);
+
 /* nsteps >= 0 coupled steps: for each, ibm_couple(c, m) (skipped when m is
  * NULL) then lbm_step(c, 1).  With steps_per_graph > 0 (even, at most
  * 4096) the steps are taken in groups of steps_per_graph, captured once into

@@ -1,18 +1,22 @@
 // Immersed-boundary kernels (Sec. 2.2) and membrane forces (Sec. 2.3).
 //
-// One coupled step runs four kernels before the collide-stream pass:
+// One coupled step runs these kernels before the collide-stream pass:
 //
-// k_membrane (one workgroup per cell): the cell's vertex positions are
-//   staged in LDS; the cell's total area and volume (the global constraints
+// k_mark (one thread per IB point) marks, with plain byte stores, every
+//   lattice node of every point's 2x2x2 stencil and the 64-node tile
+//   holding it.
+//
+// k_membrane (one workgroup per cell; on a second stream, beside the
+//   compaction and velocity passes, which do not need its forces): the
+//   cell's vertex positions are staged in LDS; the cell's total area and
+//   volume (the global constraints
 //   that need every vertex of the cell, Sec. 2.3.3) are reduced first, then
 //   each triangle and each edge/hinge stores its scalar force coefficient in
 //   LDS, and each vertex sums its incident elements' gradients in a fixed
 //   order and writes its force once.
 //   Lengths, areas, angles and volumes are evaluated in FP64 from the FP64
 //   positions, so their small departures from the (FP64) rest shape keep
-//   full accuracy in every storage precision.  The same pass marks, with
-//   plain byte stores, every lattice node of every vertex's 2x2x2 stencil
-//   and the 64-node tile holding it.
+//   full accuracy in every storage precision.
 //
 // k_compact: the marked tiles become a dense list.
 //
@@ -87,12 +91,79 @@ __device__ __forceinline__ double hinge_angle(V3 p1, V3 p2, V3 qa, V3 qb, V3 &na
     return atan2(dot(crs(na, nb), e) / sqrt(dot(e, e)), dot(na, nb));
 }
 
-struct MembArgs {
+__device__ __forceinline__ int cell_channel(const int32_t *cell_chan, int c) { return cell_chan ? cell_chan[c] : 0; }
+
+struct MarkArgs {
     uint32_t *tcount;  // tile-list length, reset here for this step
     uint32_t *epoch;   // spreading-claim epoch, advanced here for this step
     const Chan *chans;
     const int32_t *cell_chan;  // [ncells] channel of each cell, null for a single channel
-    const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge, *anchor;
+    const int32_t *vert_off, *anchor;
+    const double *x;  // [3][nverts] offsets
+    int ncells, nverts;
+    uint8_t *need;   // [N] stencil-node marks
+    uint8_t *tneed;  // [ntiles] tile marks
+    void *fibm;      // [N] Vec4 spread force: zeroed at newly marked nodes when `accumulate`
+    int accumulate;  // 1: another membrane was coupled earlier in this step (its force stays)
+};
+
+// Mark the 2x2x2 stencil of a point at offset (px, py, pz) from anchor
+// (ax, ay, az) in channel ch: every node, and the 64-node tile holding it,
+// with plain byte stores.
+template <class R>
+__device__ __forceinline__ void mark_stencil(const MarkArgs &a, const Chan &ch, int ax, int ay, int az, double px,
+                                             double py, double pz) {
+    const int x0 = pmod(ax + (int)floor(px), ch.nx);
+    const int y0 = pmod(ay + (int)floor(py), ch.ny);
+    const int z0 = pmod(az + (int)floor(pz), ch.nz);
+    const int xs[2] = {x0, x0 + 1 == ch.nx ? 0 : x0 + 1};
+    const int ys[2] = {y0, y0 + 1 == ch.ny ? 0 : y0 + 1};
+    const int zs[2] = {z0, z0 + 1 == ch.nz ? 0 : z0 + 1};
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int row = ys[q & 1] + ch.ny * zs[q >> 1];
+#pragma unroll
+        for (int e = 0; e < 2; e++) {
+            const int64_t nn = ch.noff + (int64_t)row * ch.nx + xs[e];
+            if (a.accumulate) {
+                // a node first marked now starts from zero force; one
+                // marked by an earlier membrane of the step keeps its force
+                if (!a.need[nn]) {
+                    a.need[nn] = 1;
+                    static_cast<typename Vec4<R>::T *>(a.fibm)[nn] = typename Vec4<R>::T{R(0), R(0), R(0), R(0)};
+                }
+            } else {
+                a.need[nn] = 1;
+            }
+            // the two x of a row share a tile unless the pair crosses a tile edge
+            if (e == 0 || (xs[1] >> 6) != (xs[0] >> 6)) a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[e] >> 6)] = 1;
+        }
+    }
+}
+
+// Reset of the tile-list length and advance of the claim epoch for a step.
+__device__ __forceinline__ void start_marks(const MarkArgs &a) {
+    *a.tcount = 0;
+    *a.epoch += 1u;
+}
+
+// The stencil marks of every point (positions of this step) on their own:
+// one thread per point, blockIdx.y = cell.  Independent of the membrane
+// forces, so the velocity pass that reads the marks can run beside the
+// membrane kernel.
+template <class R>
+__global__ __launch_bounds__(128) void k_mark(MarkArgs a) {
+    const int c = blockIdx.y;
+    if (c == 0 && blockIdx.x == 0 && threadIdx.x == 0) start_marks(a);
+    const int v0 = a.vert_off[c], k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.vert_off[c + 1] - v0) return;
+    const int NV = a.nverts;
+    mark_stencil<R>(a, a.chans[cell_channel(a.cell_chan, c)], a.anchor[c], a.anchor[a.ncells + c],
+                    a.anchor[2 * a.ncells + c], a.x[v0 + k], a.x[NV + v0 + k], a.x[2 * NV + v0 + k]);
+}
+
+struct MembArgs {
+    const int32_t *vert_off, *tri_off, *edge_off, *tri, *hinge;
     // per-vertex incidence (global vertex ids; entries are element*4 + role)
     const int32_t *vtri_off, *vtri, *vedge_off, *vedge;
     const double *x;  // [3][nverts] offsets
@@ -101,16 +172,12 @@ struct MembArgs {
     double *l0, *a0, *th0, *a0c, *v0c, *avert;
     int ncells, nverts, ntris, nedges, maxv, maxt, maxe;
     int stretch_law;  // 0: linear edge springs, 1: neo-Hookean edge springs
-    uint8_t *need;   // [N] stencil-node marks
-    uint8_t *tneed;  // [ntiles] tile marks
-    void *fibm;      // [N] Vec4 spread force: zeroed at newly marked nodes when `accumulate`
-    int accumulate;  // 1: another membrane was coupled earlier in this step (its force stays)
+    MarkArgs mark;    // the stencil marks, when the kernel also sets them (MARK)
 };
 
 constexpr int kMembThreads = 512;
 constexpr int kInc = 4;  // incident elements whose indices a vertex loads together
 
-__device__ __forceinline__ int cell_channel(const int32_t *cell_chan, int c) { return cell_chan ? cell_chan[c] : 0; }
 
 // LDS layout: reduction scratch (2 doubles per wave), x, y, z positions
 // (double), then one coefficient per triangle and two per edge (R).
@@ -160,7 +227,9 @@ __device__ __forceinline__ void edge_term(const V3 &p1, const V3 &p2, const V3 &
     fz += s * ev.z - cb * g.z;
 }
 
-// REST = true: write the rest shape; false: elastic forces + stencil marks.
+// REST = true: write the rest shape; false: elastic forces, and with MARK
+// the stencil marks of the cell's points as well (the coupled step that does
+// not run the membrane beside the velocity pass).
 //
 // Forces are the exact gradients of the energies written element by
 // element.  A first pass computes each element's scalar coefficient (a
@@ -169,7 +238,7 @@ __device__ __forceinline__ void edge_term(const V3 &p1, const V3 &p2, const V3 &
 // sum over its incident elements, walked in a fixed order from the
 // incidence lists, of coefficient times the element's gradient with respect
 // to that vertex.  No atomics, so the forces are bit-reproducible.
-template <class R, bool REST>
+template <class R, bool REST, bool MARK>
 __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     extern __shared__ double smem_d[];
     const int c = blockIdx.x;
@@ -190,42 +259,12 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     __syncthreads();
     auto P = [&](int k) { return V3{px[k], py[k], pz[k]}; };
     const int NT = a.ntris, NE = a.nedges;
-
-    if (!REST) {
-        if (c == 0 && threadIdx.x == 0) {
-            *a.tcount = 0;
-            *a.epoch += 1u;
-        }
-        // mark every node of every vertex's stencil (positions of this step)
-        const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
-        const int ax = a.anchor[c], ay = a.anchor[a.ncells + c], az = a.anchor[2 * a.ncells + c];
-        for (int k = threadIdx.x; k < nv; k += blockDim.x) {
-            const int x0 = pmod(ax + (int)floor(px[k]), ch.nx);
-            const int y0 = pmod(ay + (int)floor(py[k]), ch.ny);
-            const int z0 = pmod(az + (int)floor(pz[k]), ch.nz);
-            const int xs[2] = {x0, x0 + 1 == ch.nx ? 0 : x0 + 1};
-            const int ys[2] = {y0, y0 + 1 == ch.ny ? 0 : y0 + 1};
-            const int zs[2] = {z0, z0 + 1 == ch.nz ? 0 : z0 + 1};
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                const int row = ys[q & 1] + ch.ny * zs[q >> 1];
-#pragma unroll
-                for (int e = 0; e < 2; e++) {
-                    const int64_t nn = ch.noff + (int64_t)row * ch.nx + xs[e];
-                    if (a.accumulate) {
-                        // a node first marked now starts from zero force; one
-                        // marked by an earlier membrane of the step keeps its force
-                        if (!a.need[nn]) {
-                            a.need[nn] = 1;
-                            static_cast<typename Vec4<R>::T *>(a.fibm)[nn] = typename Vec4<R>::T{R(0), R(0), R(0), R(0)};
-                        }
-                    } else {
-                        a.need[nn] = 1;
-                    }
-                    a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[e] >> 6)] = 1;
-                }
-            }
-        }
+    if (MARK) {
+        const MarkArgs &mk = a.mark;
+        if (c == 0 && threadIdx.x == 0) start_marks(mk);
+        const Chan ch = mk.chans[cell_channel(mk.cell_chan, c)];
+        const int ax = mk.anchor[c], ay = mk.anchor[mk.ncells + c], az = mk.anchor[2 * mk.ncells + c];
+        for (int k = threadIdx.x; k < nv; k += blockDim.x) mark_stencil<R>(mk, ch, ax, ay, az, px[k], py[k], pz[k]);
     }
 
     // cell area and volume (FP64 sums of FP64 per-triangle values, fixed order)

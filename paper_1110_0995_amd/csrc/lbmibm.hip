@@ -175,6 +175,11 @@ struct lbm_ctx {
     void *vs = nullptr;    // [3][nv] real velocities, likewise
     void *fels = nullptr;  // [3][nv] real elastic forces, likewise
     double *hv = nullptr;  // [3][nv] membrane Jacobian times direction
+    // second stream of a coupled step: the membrane forces run on it beside
+    // the compaction and velocity passes; ev_fork / ev_join order the two
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int ibm_overlap = -1;  // lbm_set_ibm_overlap mode
     // captured graphs: plain coupled steps, recorded steps, reverse sweep
     hipStream_t cap_s = nullptr;
     hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
@@ -307,8 +312,12 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->s);
     if (c->cap_s) (void)hipStreamSynchronize(c->cap_s);
+    if (c->side) (void)hipStreamSynchronize(c->side);
     drop_graph(c);
     if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    for (hipEvent_t e : {c->ev_fork, c->ev_join})
+        if (e) (void)hipEventDestroy(e);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
@@ -346,6 +355,9 @@ static int init_ctx(lbm_ctx *c) {
         (void)hipGetLastError();
         return fail(LBM_ENOMEM, "device allocation of the context work buffers failed");
     }
+    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     HIPCHK(hipMemcpy(c->chans, c->hchans.data(), sizeof(Chan) * c->nch, hipMemcpyHostToDevice));
     {
         std::vector<uint32_t> tab;
@@ -437,6 +449,14 @@ LBM_API int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t 
     c->cs_waves = w;
     c->list_blocks = list_blocks;
     drop_graph(c);  // a captured graph holds the old launch shape
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_ibm_overlap(lbm_ctx *c, int32_t mode) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (mode < -1 || mode > 1) return fail(LBM_EINVAL, "overlap mode must be -1, 0 or 1 (got %d)", mode);
+    if (mode != c->ibm_overlap) drop_graph(c);
+    c->ibm_overlap = mode;
     return LBM_OK;
 }
 
@@ -654,15 +674,29 @@ static int waves_grid(const lbm_ctx *c) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
 }
 
-template <class R>
-static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
-    MembArgs a{};
-    a.fibm = c->fibm;
-    a.accumulate = rest ? 0 : c->acc;
+static MarkArgs mark_args(const lbm_ctx *c, const ibm_mesh *m) {
+    MarkArgs a{};
     a.tcount = c->tcount;
     a.epoch = c->epoch;
     a.chans = c->chans;
     a.cell_chan = m->cell_chan;
+    a.vert_off = m->vert_off;
+    a.anchor = m->anchor;
+    a.x = m->x;
+    a.ncells = m->ncells;
+    a.nverts = m->nverts;
+    a.need = c->need;
+    a.tneed = c->tneed;
+    a.fibm = c->fibm;
+    a.accumulate = c->acc;
+    return a;
+}
+
+// Membrane forces (rest: the rest shape); with `mark` the same kernel sets
+// the stencil marks.
+template <class R>
+static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest, bool mark = false) {
+    MembArgs a{};
     a.vtri_off = m->vtri_off;
     a.vtri = m->vtri;
     a.vedge_off = m->vedge_off;
@@ -674,7 +708,6 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.edge_off = m->edge_off;
     a.tri = m->tri;
     a.hinge = m->hinge;
-    a.anchor = m->anchor;
     a.x = m->x;
     a.f_el = m->f_el;
     a.moduli = m->moduli;
@@ -690,13 +723,22 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest) {
     a.nedges = m->nedges;
     a.maxv = m->max_cell_verts;
     a.stretch_law = m->stretch_law;
-    a.need = c->need;
-    a.tneed = c->tneed;
     const size_t sm = membrane_lds_bytes<R>(m->max_cell_verts, m->max_cell_tris, m->max_cell_edges);
-    if (rest)
-        k_membrane<R, true><<<m->ncells, kMembThreads, sm, c->s>>>(a);
-    else
-        k_membrane<R, false><<<m->ncells, kMembThreads, sm, c->s>>>(a);
+    if (rest) {
+        k_membrane<R, true, false><<<m->ncells, kMembThreads, sm, c->s>>>(a);
+    } else if (mark) {
+        a.mark = mark_args(c, m);
+        k_membrane<R, false, true><<<m->ncells, kMembThreads, sm, c->s>>>(a);
+    } else {
+        k_membrane<R, false, false><<<m->ncells, kMembThreads, sm, c->s>>>(a);
+    }
+}
+
+// Stencil marks of this step's positions on their own (with the list length
+// and claim epoch reset for the step).
+template <class R>
+static void launch_mark(lbm_ctx *c, const ibm_mesh *m) {
+    k_mark<R><<<dim3((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells), 128, 0, c->s>>>(mark_args(c, m));
 }
 
 // Sort the fixed contact spheres into a uniform grid over the lattice (one
@@ -946,10 +988,13 @@ static void launch_contact(lbm_ctx *c, const ibm_mesh *m) {
     k_contact_cells<R><<<grid, kContactThreads, 3 * (size_t)m->max_cell_verts * 8, c->s>>>(a);
 }
 
-template <class S, class R, bool DEV>
-static void launch_node_velocity(lbm_ctx *c, const void *f) {
+static void launch_compact(lbm_ctx *c) {
     k_compact<<<(int)cdiv(c->ntiles, kCompactThreads * kCompactPerThread), kCompactThreads, 0, c->s>>>(
         c->tneed, c->ntiles, c->tlist, c->tcount);
+}
+
+template <class S, class R, bool DEV>
+static void launch_node_velocity(lbm_ctx *c, const void *f) {
     NodeVelArgs a{};
     a.f = f;
     a.stride = c->stride;
@@ -1036,28 +1081,48 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
 }
 
 // The immersed-boundary half of a coupled step with the populations f.
-static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f) {
-    c->acc = c->couples > 0;  // read by the membrane and gather launches below
+// With `overlap`, the membrane (and cell-cell contact) forces run on the
+// side stream while the stencil nodes are marked, the marked tiles listed
+// and their nodes' velocities evaluated; the point update waits for both.
+// The membrane is launched first: its workgroups (a few per compute unit,
+// each holding its cell in LDS) then hold their slots before the velocity
+// pass fills the chip.  Without it (the adjoint's recomputed steps, small
+// and bound by launch latency) the membrane kernel also sets the marks and
+// everything runs in order on the caller's stream.  Everything is joined back into the caller's
+// stream before the call returns.
+template <class S, class R, bool DEV>
+static void enqueue_couple_as(lbm_ctx *c, const ibm_mesh *m, const void *f, bool overlap) {
+    c->acc = c->couples > 0;  // read by the mark and gather launches below
     c->couples++;
+    if (!overlap) {
+        launch_membrane<R>(c, m, false, true);
+        launch_contact<R>(c, m);
+        launch_compact(c);
+        launch_node_velocity<S, R, DEV>(c, f);
+        launch_couple<R>(c, m);
+        return;
+    }
+    const hipStream_t user = c->s;
+    (void)hipEventRecord(c->ev_fork, user);
+    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    c->s = c->side;
+    launch_membrane<R>(c, m, false);
+    launch_contact<R>(c, m);
+    (void)hipEventRecord(c->ev_join, c->side);
+    c->s = user;
+    launch_mark<R>(c, m);
+    launch_compact(c);
+    launch_node_velocity<S, R, DEV>(c, f);
+    (void)hipStreamWaitEvent(user, c->ev_join, 0);
+    launch_couple<R>(c, m);
+}
+static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f, bool may_overlap = true) {
+    const bool overlap =
+        may_overlap && (c->ibm_overlap == 1 || (c->ibm_overlap == -1 && m->nverts >= LBM_OVERLAP_MIN_POINTS));
     switch (c->p.prec) {
-        case LBM_F64:
-            launch_membrane<double>(c, m, false);
-            launch_contact<double>(c, m);
-            launch_node_velocity<double, double, false>(c, f);
-            launch_couple<double>(c, m);
-            break;
-        case LBM_F32:
-            launch_membrane<float>(c, m, false);
-            launch_contact<float>(c, m);
-            launch_node_velocity<float, float, false>(c, f);
-            launch_couple<float>(c, m);
-            break;
-        default:
-            launch_membrane<float>(c, m, false);
-            launch_contact<float>(c, m);
-            launch_node_velocity<float, float, true>(c, f);
-            launch_couple<float>(c, m);
-            break;
+        case LBM_F64: enqueue_couple_as<double, double, false>(c, m, f, overlap); break;
+        case LBM_F32: enqueue_couple_as<float, float, false>(c, m, f, overlap); break;
+        default: enqueue_couple_as<float, float, true>(c, m, f, overlap); break;
     }
 }
 static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m) { enqueue_couple(c, m, cur_f(c)); }
@@ -1260,7 +1325,7 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
         enqueue_copy(c, c->xs, x_n, 3 * (size_t)m->nverts * 8);
         enqueue_copy(c, c->vs, v_n, 3 * (size_t)m->nverts * sizeof(R));
         c->couples = 0;
-        enqueue_couple(c, &mm, f_n);
+        enqueue_couple(c, &mm, f_n, false);
     }
     c->couples = 0;  // the adjoint pass below consumes the recomputed force
     AdjStepArgs a{};

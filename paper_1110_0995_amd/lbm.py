@@ -91,6 +91,10 @@ class Lattice:
     def set_launch(self, collide_waves_per_block: int = 0, list_blocks: int = 0) -> None:
         _lib.check(self.lib.lbm_set_launch(self.ctx, int(collide_waves_per_block), int(list_blocks)))
 
+    def set_ibm_overlap(self, mode: int = -1) -> None:
+        """1: membrane forces beside the velocity pass, 0: in order, -1: by mesh size."""
+        _lib.check(self.lib.lbm_set_ibm_overlap(self.ctx, int(mode)))
+
     # -- the four calls of the path --------------------------------------
     def step(self, nsteps: int = 1) -> None:
         _lib.check(self.lib.lbm_step(self.ctx, int(nsteps)))

@@ -90,6 +90,7 @@ def test_null_context_calls(L):
     assert L.lbm_init(None, None) == _lib.LBM_EINVAL
     assert L.lbm_init_channels(None, 1, None, None) == _lib.LBM_EINVAL
     assert L.lbm_set_launch(None, 4, 0) == _lib.LBM_EINVAL
+    assert L.lbm_set_ibm_overlap(None, 1) == _lib.LBM_EINVAL
     assert L.lbm_run(None, None, 1, 0) == _lib.LBM_EINVAL
     L.lbm_destroy(None)
     assert b"NULL" in L.lbm_last_error()

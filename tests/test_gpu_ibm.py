@@ -306,6 +306,62 @@ def test_coupled_step_is_bit_reproducible(lbm):
         assert np.array_equal(a, b)
 
 
+def test_overlapped_schedule_f64(orc, lbm):
+    """The membrane kernels on the context's second stream beside the
+    velocity pass (forced on for a small mesh) give the same bits as the
+    in-order schedule, eager and in captured graphs, with one membrane per
+    step and with two, and match the oracle."""
+    s = _small(ncells=2, seed=31)
+    law = S.contact_params(s)
+    out = {}
+    off = (s.cells.offset.astype(np.float64)
+           + 0.05 * np.random.default_rng(2).standard_normal(s.cells.offset.shape)).astype(np.float32)
+    for mode in (0, 1):
+        lat = lbm.Lattice.from_scenario(s, prec="f64")
+        lat.set_ibm_overlap(mode)
+        mesh = lbm.Mesh(lat, s.cells, contact=law)
+        mesh.set_offsets(off)
+        for _ in range(5):
+            lat.couple(mesh)
+            lat.step(1)
+        lat.run(8, mesh, steps_per_graph=4)
+        out[mode] = (lat.populations_f64().cpu().numpy(), mesh.positions(), mesh.velocities())
+        lat.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f64", deform=0.05, seed=1, vel=1e-3)
+    lat.set_ibm_overlap(1)
+    f = L.rest()
+    for _ in range(10):
+        lat.couple(mesh)
+        lat.step(1)
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    assert np.abs(lat.populations_f64().cpu().numpy()[:, fl] - f[:, fl]).max() < 1e-14
+    assert np.abs(mesh.positions() - X).max() < 1e-12
+    lat.close()
+    # two membranes per step: the second marks on its own and adds its force
+    nx, ny, nz = 32, 24, 20
+    cen = np.array([[12.2, 11.7, 9.6], [14.9, 12.3, 10.1]])
+    mod = (0.01, 0.002, 0.005, 0.05, 0.2)
+    a, b = S.make_cells(cen[:1], 3.0, 2, moduli=mod), S.make_cells(cen[1:], 3.0, 2, moduli=mod)
+    s2 = S.Scenario("overlap2", nx, ny, nz, 0.8, (1e-4, 0, 0), S.channel_mask(nx, ny, nz), 10,
+                    cells=S.make_cells(cen, 3.0, 2, moduli=mod))
+    res = {}
+    for mode in (0, 1):
+        lat = lbm.Lattice.from_scenario(s2, prec="f64")
+        lat.set_ibm_overlap(mode)
+        ma, mb = lbm.Mesh(lat, a), lbm.Mesh(lat, b)
+        for _ in range(6):
+            lat.couple(ma)
+            lat.couple(mb)
+            lat.step(1)
+        res[mode] = (lat.populations_f64().cpu().numpy(), ma.positions(), mb.positions())
+        lat.close()
+    for u, w in zip(res[0], res[1]):
+        assert np.array_equal(u, w)
+
+
 def test_couple_requires_rest_shape(lbm):
     from paper_1110_0995_amd import _lib
     s = _small(posts=False, ncells=1)
