@@ -162,8 +162,8 @@ typedef struct {
 int64_t lbm_plane_stride(int64_t n_nodes, int32_t prec);
 
 /* Bytes lbm_init allocates on the device for this lattice (the first
- * ibm_rest_shape adds (12 + 32*s)*N bytes of spreading slots, s = sizeof(real),
- * plus one spread record per IB point). */
+ * ibm_rest_shape adds 4*N bytes of spreading claims, plus one spread record
+ * per IB point). */
 int64_t lbm_workspace_bytes(const lbm_params *p);
 
 /* Validate p, create a context and set both state buffers to the fluid at

@@ -33,23 +33,20 @@
 // Spreading (step 3) avoids per-contribution float atomics, which run at a
 // small fraction of store throughput on this GPU:
 // k_spread_cells (one workgroup per cell) sorts the cell's records by base
-//   node in LDS, sums each base node's points into its 8 corner
-//   contributions, and writes them to that base node's slot after claiming
-//   it with one compare-and-swap of the call's epoch (a base node already
-//   claimed by another cell in this call falls back to float atomics into
-//   a separate accumulator, kept zero between steps; that needs two
-//   membranes inside one lattice cell).  The owner also sets, at each of the 8 corner nodes, the byte
-//   that says "base node in role q has a slot for you".
-// k_gather_nodes (one wave per listed tile) reads its node's 8 role bytes
-//   with one load, adds the flagged slots in a fixed order, clears the
-//   bytes and writes the node's spread force at every marked node; the
-//   fallback path flags its tiles so that only those read the accumulated
-//   atomics back (and clear them).
-// All sums except the fallback are in a fixed order, so the spread is
+//   node in LDS, finds the cell's stencil nodes in a bitmap over the box of
+//   its base nodes and, one thread per node, sums the node's contributions
+//   in a fixed order, claims the node with one atomic exchange of the
+//   call's epoch and writes the sum as the node's spread force.  A node
+//   already claimed by another cell in this call (two membranes within a
+//   lattice spacing) falls back to float atomics into a separate
+//   accumulator, kept zero between steps, and flags its tile;
+// k_spread_fixup adds that accumulator at the flagged tiles' marked nodes
+//   (and returns at once when no node took the fallback).
+// All sums except the fallback's are in a fixed order, so the spread is
 // bit-reproducible.
 //
 // The node and tile marks stay set until the collide-stream pass: they are
-// exactly the nodes whose spread force the gather wrote this step, so that
+// exactly the nodes whose spread force the call wrote this step, so that
 // pass reads the force record of marked nodes only (a record elsewhere may
 // hold an earlier step's force) and clears the marks.
 #pragma once
@@ -96,6 +93,7 @@ __device__ __forceinline__ int cell_channel(const int32_t *cell_chan, int c) { r
 struct MarkArgs {
     uint32_t *tcount;  // tile-list length, reset here for this step
     uint32_t *epoch;   // spreading-claim epoch, advanced here for this step
+    uint32_t *nfall;   // count of the spread's fallback nodes, reset here for this step
     const Chan *chans;
     const int32_t *cell_chan;  // [ncells] channel of each cell, null for a single channel
     const int32_t *vert_off, *anchor;
@@ -141,9 +139,11 @@ __device__ __forceinline__ void mark_stencil(const MarkArgs &a, const Chan &ch, 
     }
 }
 
-// Reset of the tile-list length and advance of the claim epoch for a step.
+// Reset of the tile-list length and fallback count and advance of the claim
+// epoch for a step.
 __device__ __forceinline__ void start_marks(const MarkArgs &a) {
     *a.tcount = 0;
+    *a.nfall = 0;
     *a.epoch += 1u;
 }
 
@@ -690,41 +690,191 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
 
 constexpr int kSpreadThreads = 512;
 constexpr int kSpreadMaxPoints = 2048;  // per cell (bounded by the membrane pass's LDS anyway)
+constexpr int kSpreadBox = 16384;       // nodes of the largest per-cell box of base nodes kept in LDS
 
 struct SpreadArgs {
     const int32_t *vert_off;
     const void *srec;
-    uint32_t *owner;   // [N] epoch of the call that last claimed the base node's slot
-    void *cslot;       // [N][8] Vec4: corner contributions of a base node
-    uint8_t *role;     // [N][8] role[n][q] = 1: base node of n in role q holds a slot
+    uint32_t *owner;   // [N] epoch of the call that last claimed the node
+    void *fibm;        // [N] Vec4: spread force, written (with `accumulate`, added) at the nodes a cell claims
     void *facc;        // [N] Vec4: accumulator of the fallback (zero between steps)
     uint8_t *ftile;    // [ntiles] 1: a node of the tile got fallback atomics this call
+    uint32_t *nfall;   // nodes spread through the fallback in this call
     const uint32_t *epoch;
     const Chan *chans;
     const int32_t *cell_chan;
+    int accumulate;    // as in MarkArgs
+    int pmax;          // power of two >= the largest cell's point count (>= 64)
+    int maxv;          // the largest cell's point count
 };
 
+// A point's offsets and force, staged in LDS by the spread.
+template <class R>
+struct SPoint {
+    R dx, dy, dz, fx, fy, fz;
+};
+
+// LDS of k_spread_cells: sort keys [pmax] (u32), staged points [maxv], run
+// table over the box [kSpreadBox] (u16), node bitmap [kSpreadBox/32] (u32),
+// node list [8 maxv] (u16), and a few scalars.
+template <class R>
+__host__ __device__ inline size_t spread_lds_bytes(int pmax, int maxv) {
+    return 4 * (size_t)pmax + sizeof(SPoint<R>) * (size_t)maxv + 2 * (size_t)kSpreadBox + kSpreadBox / 8 +
+           16 * (size_t)maxv + 256;
+}
+
+// Block-wide exclusive prefix sum of one int per thread (blockDim.x <= 1024);
+// `wsum` holds one int per wave.  Returns the prefix; `total` gets the sum.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *wsum, int &total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+    for (int w = 0; w < nw; w++) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    __syncthreads();
+    return before + inc - v;
+}
+
+// Spreading, one workgroup per cell (Sec. 2.2 step 3: every point exerts
+// -F_c on its 2x2x2 stencil with the trilinear weights).  The cell's base
+// nodes, unwrapped around its first point, span a small box; the points
+// are sorted by (base node in the box, point) in LDS, and a table over the
+// box gives each base node's run of points.  The stencil nodes are the set
+// bits of a bitmap over the box; each is summed by one thread, corner by
+// corner and within a corner in sorted point order, claimed for this call
+// with one atomic exchange of the call's epoch, and its sum written as the
+// node's spread force.  A node already claimed by another cell in this
+// call (membranes within a lattice spacing of each other) takes the sum as
+// float atomics into a separate accumulator, kept zero between steps, and
+// flags its tile for k_spread_fixup; so does every node of a cell whose box
+// exceeds kSpreadBox nodes (point by point, after its claim has set the
+// node's force to zero, or kept it with `accumulate`).  Every stencil node of
+// the call is written, so the collide-stream pass reads the force at the
+// marked nodes without clearing.
 template <class R>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     using R4 = typename Vec4<R>::T;
-    __shared__ unsigned long long key[kSpreadMaxPoints];
+    extern __shared__ uint32_t smem_u32[];
+    uint32_t *key = smem_u32;                                                  // [pmax]
+    SPoint<R> *pts = reinterpret_cast<SPoint<R> *>(key + a.pmax);             // [maxv]
+    uint16_t *table = reinterpret_cast<uint16_t *>(pts + a.maxv);             // [kSpreadBox]
+    uint32_t *bits = reinterpret_cast<uint32_t *>(table + kSpreadBox);        // [kSpreadBox / 32]
+    uint16_t *nodes = reinterpret_cast<uint16_t *>(bits + kSpreadBox / 32);  // [8 maxv]
+    int *sc = reinterpret_cast<int *>(nodes + 8 * a.maxv);                    // scalars and scan scratch
     const int c = blockIdx.x;
     const int v0 = a.vert_off[c], nv = a.vert_off[c + 1] - v0;
+    if (nv <= 0) return;
+    const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
+    const SRec<R> *SR = static_cast<const SRec<R> *>(a.srec) + v0;
+    const uint32_t epoch = *a.epoch;
+    R4 *FI = static_cast<R4 *>(a.fibm);
+    R4 *FA = static_cast<R4 *>(a.facc);
+    auto decode = [&](uint32_t b, int &x, int &y, int &z) {
+        const int64_t lb = (int64_t)b - ch.noff;
+        x = (int)(lb % ch.nx);
+        y = (int)((lb / ch.nx) % ch.ny);
+        z = (int)(lb / ((int64_t)ch.nx * ch.ny));
+    };
+    auto unwrap = [](int d, int L) {  // d mod L in (-L/2, L/2]
+        d %= L;
+        if (d < 0) d += L;
+        return 2 * d > L ? d - L : d;
+    };
+    auto fallback_add = [&](uint32_t y, int gx, int gy, int gz, R fx, R fy, R fz) {
+        R *rec = reinterpret_cast<R *>(&FA[y]);
+        atomicAdd(rec + 0, fx);
+        atomicAdd(rec + 1, fy);
+        atomicAdd(rec + 2, fz);
+        a.ftile[ch.toff + (int64_t)(gy + ch.ny * gz) * ch.tpr + (gx >> 6)] = 1;
+        atomicAdd(a.nfall, 1u);
+    };
+    // base nodes unwrapped around the first point's; their bounding box
+    int rx, ry, rz;
+    decode(SR[0].base, rx, ry, rz);
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const SRec<R> r = SR[i];
+        int x, y, z;
+        decode(r.base, x, y, z);
+        const int u[3] = {unwrap(x - rx, ch.nx), unwrap(y - ry, ch.ny), unwrap(z - rz, ch.nz)};
+        for (int d = 0; d < 3; d++) {
+            lo[d] = min(lo[d], u[d]);
+            hi[d] = max(hi[d], u[d]);
+        }
+        pts[i] = SPoint<R>{r.dx, r.dy, r.dz, r.fx, r.fy, r.fz};
+    }
+    for (int d = 0; d < 3; d++) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[d] = min(lo[d], __shfl_xor(lo[d], o, 64));
+            hi[d] = max(hi[d], __shfl_xor(hi[d], o, 64));
+        }
+    }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 6; d++) sc[d] = d < 3 ? INT32_MAX : INT32_MIN;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        for (int d = 0; d < 3; d++) {
+            atomicMin(&sc[d], lo[d]);
+            atomicMax(&sc[3 + d], hi[d]);
+        }
+    __syncthreads();
+    const int mx = sc[0], my = sc[1], mz = sc[2];
+    const int64_t Bx = (int64_t)sc[3] - mx + 2, By = (int64_t)sc[4] - my + 2, Bz = (int64_t)sc[5] - mz + 2;
+    const bool boxed = Bx * By * Bz <= kSpreadBox;
+    if (!boxed) {
+        // a cell too large for the box: point by point through the fallback
+        for (int t = threadIdx.x; t < 8 * nv; t += blockDim.x) {
+            const int i = t >> 3, q = t & 7;
+            const SRec<R> r = SR[i];
+            int x, y, z;
+            decode(r.base, x, y, z);
+            const int gx = (q & 1) ? (x + 1 == ch.nx ? 0 : x + 1) : x;
+            const int gy = ((q >> 1) & 1) ? (y + 1 == ch.ny ? 0 : y + 1) : y;
+            const int gz = (q >> 2) ? (z + 1 == ch.nz ? 0 : z + 1) : z;
+            const uint32_t n = (uint32_t)(ch.noff + gx + (int64_t)ch.nx * (gy + (int64_t)ch.ny * gz));
+            if (atomicExch(&a.owner[n], epoch) != epoch && !a.accumulate) FI[n] = R4{R(0), R(0), R(0), R(0)};
+            const R wx = (q & 1) ? r.dx : R(1) - r.dx, wy = ((q >> 1) & 1) ? r.dy : R(1) - r.dy;
+            const R wz = (q >> 2) ? r.dz : R(1) - r.dz;
+            const R wt = wx * wy * wz;
+            fallback_add(n, gx, gy, gz, wt * r.fx, wt * r.fy, wt * r.fz);
+        }
+        return;
+    }
+    const int bx_ = (int)Bx, by_ = (int)By, V = (int)(Bx * By * Bz);
+    // sort (box index of the base node, point)
     int P = 64;
     while (P < nv) P <<= 1;
-    const SRec<R> *SR = static_cast<const SRec<R> *>(a.srec) + v0;
-    for (int i = threadIdx.x; i < P; i += blockDim.x)
-        key[i] = i < nv ? ((unsigned long long)SR[i].base << 32) | (unsigned)i : ~0ull;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        uint32_t k = 0xffffffffu;
+        if (i < nv) {
+            int x, y, z;
+            decode(SR[i].base, x, y, z);
+            const int li = (unwrap(x - rx, ch.nx) - mx) + bx_ * ((unwrap(y - ry, ch.ny) - my) + by_ * (unwrap(z - rz, ch.nz) - mz));
+            k = ((uint32_t)li << 11) | (uint32_t)i;
+        }
+        key[i] = k;
+    }
+    for (int i = threadIdx.x; i < V; i += blockDim.x) table[i] = 0;
+    for (int i = threadIdx.x; i < (V + 31) / 32; i += blockDim.x) bits[i] = 0;
     __syncthreads();
-    // bitonic sort of (base node, point) keys
     for (int kk = 2; kk <= P; kk <<= 1)
         for (int j = kk >> 1; j > 0; j >>= 1) {
             for (int i = threadIdx.x; i < P; i += blockDim.x) {
                 const int l = i ^ j;
                 if (l > i) {
-                    const unsigned long long ki = key[i], kl = key[l];
-                    const bool up = (i & kk) == 0;
-                    if ((ki > kl) == up) {
+                    const uint32_t ki = key[i], kl = key[l];
+                    if ((ki > kl) == ((i & kk) == 0)) {
                         key[i] = kl;
                         key[l] = ki;
                     }
@@ -732,145 +882,123 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
             }
             __syncthreads();
         }
-    // one thread per run of equal base nodes
-    R4 *CS = static_cast<R4 *>(a.cslot);
-    const uint32_t epoch = *a.epoch;
-    const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
+    // run table and stencil-node bitmap
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-        const uint32_t b = (uint32_t)(key[i] >> 32);
-        if (i > 0 && (uint32_t)(key[i - 1] >> 32) == b) continue;
-        R F[8][3];
+        const uint32_t li = key[i] >> 11;
+        if (i == 0 || (key[i - 1] >> 11) != li) table[li] = (uint16_t)(i + 1);
+        const int lx = (int)(li % bx_), ly = (int)((li / bx_) % by_), lz = (int)(li / (bx_ * by_));
 #pragma unroll
-        for (int q = 0; q < 8; q++) F[q][0] = F[q][1] = F[q][2] = R(0);
-        for (int j = i; j < nv && (uint32_t)(key[j] >> 32) == b; j++) {
-            const SRec<R> r = SR[(uint32_t)key[j]];
-            const R wx[2] = {R(1) - r.dx, r.dx}, wy[2] = {R(1) - r.dy, r.dy}, wz[2] = {R(1) - r.dz, r.dz};
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const R wt = wx[q & 1] * wy[(q >> 1) & 1] * wz[q >> 2];
-                F[q][0] += wt * r.fx;
-                F[q][1] += wt * r.fy;
-                F[q][2] += wt * r.fz;
-            }
+        for (int q = 0; q < 8; q++) {
+            const int nn = (lx + (q & 1)) + bx_ * ((ly + ((q >> 1) & 1)) + by_ * (lz + (q >> 2)));
+            atomicOr(&bits[nn >> 5], 1u << (nn & 31));
         }
-        // claim the base node's slot for this call
-        uint32_t old = a.owner[b];
-        bool won = false;
-        while (old != epoch) {
-            const uint32_t seen = atomicCAS(&a.owner[b], old, epoch);
-            if (seen == old) {
-                won = true;
-                break;
-            }
-            old = seen;
+    }
+    __syncthreads();
+    // node list (box indices, ascending)
+    const int nwords = (V + 31) / 32;
+    int total = 0;
+    for (int w0 = 0; w0 < nwords; w0 += blockDim.x) {
+        const int w = w0 + threadIdx.x;
+        uint32_t m = w < nwords ? bits[w] : 0u;
+        int tot;
+        int off = total + block_exclusive_scan(__popc(m), sc + 8, tot);
+        while (m) {
+            const int b = __builtin_ctz(m);
+            m &= m - 1;
+            nodes[off++] = (uint16_t)(w * 32 + b);
         }
-        const int64_t lb = (int64_t)b - ch.noff;
-        const int bx = (int)(lb % ch.nx), by = (int)((lb / ch.nx) % ch.ny), bz = (int)(lb / ((int64_t)ch.nx * ch.ny));
-        const int xs[2] = {bx, bx + 1 == ch.nx ? 0 : bx + 1};
-        const int ys[2] = {by, by + 1 == ch.ny ? 0 : by + 1};
-        const int zs[2] = {bz, bz + 1 == ch.nz ? 0 : bz + 1};
-        if (won) {
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                CS[(size_t)b * 8 + q] = R4{F[q][0], F[q][1], F[q][2], R(0)};
-                const int64_t n = ch.noff + xs[q & 1] + (int64_t)ch.nx * (ys[(q >> 1) & 1] + (int64_t)ch.ny * zs[q >> 2]);
-                a.role[n * 8 + q] = 1;
+        total += tot;
+    }
+    __syncthreads();
+    // one thread per stencil node
+    for (int k = threadIdx.x; k < total; k += blockDim.x) {
+        const int li = nodes[k];
+        const int lx = li % bx_, ly = (li / bx_) % by_, lz = li / (bx_ * by_);
+        R Fx = R(0), Fy = R(0), Fz = R(0);
+#pragma unroll 1
+        for (int q = 0; q < 8; q++) {
+            const int ex = lx - (q & 1), ey = ly - ((q >> 1) & 1), ez = lz - (q >> 2);
+            if (ex < 0 || ey < 0 || ez < 0) continue;
+            const uint32_t bi = (uint32_t)(ex + bx_ * (ey + by_ * ez));
+            const int s0 = table[bi];
+            if (!s0) continue;
+            R Sx = R(0), Sy = R(0), Sz = R(0);
+            for (int j = s0 - 1; j < nv && (key[j] >> 11) == bi; j++) {
+                const SPoint<R> r = pts[key[j] & 0x7ffu];
+                const R wx = (q & 1) ? r.dx : R(1) - r.dx, wy = ((q >> 1) & 1) ? r.dy : R(1) - r.dy;
+                const R wz = (q >> 2) ? r.dz : R(1) - r.dz;
+                const R wt = wx * wy * wz;
+                Sx += wt * r.fx;
+                Sy += wt * r.fy;
+                Sz += wt * r.fz;
             }
+            Fx += Sx;
+            Fy += Sy;
+            Fz += Sz;
+        }
+        int gx = (rx + mx + lx) % ch.nx, gy = (ry + my + ly) % ch.ny, gz = (rz + mz + lz) % ch.nz;
+        gx += gx < 0 ? ch.nx : 0;
+        gy += gy < 0 ? ch.ny : 0;
+        gz += gz < 0 ? ch.nz : 0;
+        const uint32_t n = (uint32_t)(ch.noff + gx + (int64_t)ch.nx * (gy + (int64_t)ch.ny * gz));
+        if (atomicExch(&a.owner[n], epoch) != epoch) {
+            if (a.accumulate) {
+                const R4 f = FI[n];
+                Fx = f.x + Fx;
+                Fy = f.y + Fy;
+                Fz = f.z + Fz;
+            }
+            FI[n] = R4{Fx, Fy, Fz, R(0)};
         } else {
-            R4 *FI = static_cast<R4 *>(a.facc);
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                const int ys_ = ys[(q >> 1) & 1], zs_ = zs[q >> 2];
-                const int64_t n = ch.noff + xs[q & 1] + (int64_t)ch.nx * (ys_ + (int64_t)ch.ny * zs_);
-                R *rec = reinterpret_cast<R *>(&FI[n]);
-                atomicAdd(rec + 0, F[q][0]);
-                atomicAdd(rec + 1, F[q][1]);
-                atomicAdd(rec + 2, F[q][2]);
-                a.ftile[ch.toff + (int64_t)(ys_ + ch.ny * zs_) * ch.tpr + (xs[q & 1] >> 6)] = 1;
-            }
+            fallback_add(n, gx, gy, gz, Fx, Fy, Fz);
         }
     }
 }
 
-struct GatherArgs {
+struct FixupArgs {
     const uint32_t *tlist, *tcount;
-    uint8_t *role;   // [N][8], cleared here
-    const void *cslot;
+    const uint32_t *nfall;
     const uint8_t *need;
     uint8_t *ftile;  // [ntiles] fallback flags, cleared here
-    void *fibm;      // [N] Vec4: spread force, written (or, with `accumulate`, added) at the nodes this call spreads to
-    void *facc;      // [N] Vec4: fallback accumulator, read and cleared in flagged tiles
-    int accumulate;  // as in MembArgs
+    void *fibm;      // [N] Vec4 spread force
+    void *facc;      // [N] Vec4 fallback accumulator, read and cleared here
     const Chan *chans;
     const uint16_t *tile_chan;
 };
 
-// Each listed tile: every lane reads its node's 8 role bytes with one load
-// (zero away from the stencils), adds the flagged slots in a fixed order and
-// stores the sum as the node's spread force.  Every node marked by the
-// call's membrane gets a slot role or sits in a tile the fallback path
-// flagged, so the force is written at every marked node and the
-// collide-stream pass never needs the record cleared.  Only in a flagged tile
-// does the sum go on top of the accumulated atomics, which are read and
-// cleared; with `accumulate` (a second membrane coupled in the same step)
-// it is added to the force already there.  The common chain is list -> role
-// word -> slots -> store.
+// The fallback's atomics onto the spread force: in every listed tile the
+// spread flagged, each marked node adds the accumulator and clears it.  A
+// wave checks 64 list entries with one ballot and works through the flagged
+// ones; the kernel returns at once when no node of the call took the
+// fallback.
 template <class R>
-__global__ __launch_bounds__(256) void k_gather_nodes(GatherArgs a) {
+__global__ __launch_bounds__(256) void k_spread_fixup(FixupArgs a) {
     using R4 = typename Vec4<R>::T;
+    if (*a.nfall == 0) return;
     const int lane = threadIdx.x & 63;
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     const uint32_t count = *a.tcount;
-    const R4 *CS = static_cast<const R4 *>(a.cslot);
     R4 *FI = static_cast<R4 *>(a.fibm);
-    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
-        const int tile = __builtin_amdgcn_readfirstlane((int)a.tlist[w]);
-        const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
-        const bool fallback = __builtin_amdgcn_readfirstlane((int)a.ftile[tile]) != 0;
-        const int lt = tile - ch.toff, row = lt / ch.tpr;
-        const int x = (lt - row * ch.tpr) * 64 + lane;
-        if (fallback && lane == 0) a.ftile[tile] = 0;
-        if (x >= ch.nx) continue;
-        const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
-        unsigned long long *rp = reinterpret_cast<unsigned long long *>(a.role) + n;
-        const unsigned long long roles = *rp;
-        R Fx = R(0), Fy = R(0), Fz = R(0);
-        if (roles) {
-            *rp = 0ull;
-            const int y = row % ch.ny, z = row / ch.ny;
-            const int xb[2] = {x, x == 0 ? ch.nx - 1 : x - 1};
-            const int yb[2] = {y, y == 0 ? ch.ny - 1 : y - 1};
-            const int zb[2] = {z, z == 0 ? ch.nz - 1 : z - 1};
-            // node n is corner q of base node (x - qx, y - qy, z - qz)
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                if (!((roles >> (8 * q)) & 0xffull)) continue;
-                const int64_t b =
-                    ch.noff + xb[q & 1] + (int64_t)ch.nx * (yb[(q >> 1) & 1] + (int64_t)ch.ny * zb[q >> 2]);
-                const R4 f = CS[b * 8 + q];
-                Fx += f.x;
-                Fy += f.y;
-                Fz += f.z;
-            }
-        }
-        if (fallback) {
+    R4 *FA = static_cast<R4 *>(a.facc);
+    for (uint32_t w0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u; w0 < count; w0 += nwaves * 64u) {
+        const uint32_t w = w0 + lane;
+        const int mine = w < count ? (int)a.tlist[w] : -1;
+        unsigned long long flagged = __ballot(mine >= 0 && a.ftile[mine]);
+        while (flagged) {
+            const int j = __builtin_ctzll(flagged);
+            flagged &= flagged - 1;
+            const int tile = __builtin_amdgcn_readlane(mine, j);
+            const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
+            const int lt = tile - ch.toff, row = lt / ch.tpr;
+            const int x = (lt - row * ch.tpr) * 64 + lane;
+            if (lane == 0) a.ftile[tile] = 0;
+            if (x >= ch.nx) continue;
+            const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
             if (!a.need[n]) continue;
-            R4 *FA = static_cast<R4 *>(a.facc);
-            const R4 f = FA[n];
+            const R4 f = FA[n], g = FI[n];
             FA[n] = R4{R(0), R(0), R(0), R(0)};
-            Fx += f.x;
-            Fy += f.y;
-            Fz += f.z;
-        } else if (!roles) {
-            continue;
+            FI[n] = R4{g.x + f.x, g.y + f.y, g.z + f.z, R(0)};
         }
-        if (a.accumulate) {
-            const R4 f = FI[n];
-            Fx = f.x + Fx;
-            Fy = f.y + Fy;
-            Fz = f.z + Fz;
-        }
-        FI[n] = R4{Fx, Fy, Fz, R(0)};
     }
 }
 

@@ -139,9 +139,8 @@ struct lbm_ctx {
     // spreading workspace, allocated by the first ibm_rest_shape
     void *srec = nullptr;        // spread records, one per IB point of the largest mesh
     int64_t srec_cap = 0;
-    uint32_t *owner = nullptr;   // [N] epoch of the last claim of each base node's slot
-    void *cslot = nullptr;       // [N][8] x 4 real: corner contributions per base node
-    uint8_t *role = nullptr;     // [N][8] slot flags read by the node gather
+    uint32_t *owner = nullptr;   // [N] epoch of the last spreading claim of each node
+    uint32_t *nfall = nullptr;   // nodes spread through the fallback in the current call
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
     int64_t nparts = 0;
@@ -286,7 +285,7 @@ static void build_row_groups(const std::vector<Chan> &chs, std::vector<uint32_t>
 }
 
 static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch, int64_t nwg) {
-    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
+    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + 4 + cdiv(N, 256) * 32 + 32 +
            (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
 }
 
@@ -319,7 +318,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     for (hipEvent_t e : {c->ev_fork, c->ev_join})
         if (e) (void)hipEventDestroy(e);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
-                    c->tcount, c->epoch,    c->srec, c->owner, c->cslot, c->role, c->partials, c->sums, c->ftile,
+                    c->tcount, c->epoch,    c->srec, c->owner, c->nfall, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
                     c->sph_start, c->sph_items, c->wgtab};
     for (void *b : bufs)
@@ -347,6 +346,7 @@ static int init_ctx(lbm_ctx *c) {
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
         hipMalloc(&c->tneed, tpad) != hipSuccess || hipMalloc(&c->tlist, 4 * tn) != hipSuccess ||
         hipMalloc(&c->tcount, 4) != hipSuccess || hipMalloc(&c->epoch, 4) != hipSuccess ||
+        hipMalloc(&c->nfall, 4) != hipSuccess ||
         hipMalloc(&c->ftile, tpad) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
@@ -388,6 +388,7 @@ static int init_ctx(lbm_ctx *c) {
     HIPCHK(hipMemsetAsync(c->ftile, 0, tpad, c->s));
     HIPCHK(hipMemsetAsync(c->tcount, 0, 4, c->s));
     HIPCHK(hipMemsetAsync(c->epoch, 0, 4, c->s));
+    HIPCHK(hipMemsetAsync(c->nfall, 0, 4, c->s));
     const int nb = (int)cdiv(c->N, 256);
     for (void *f : {p->f_a, p->f_b}) {
         switch (p->prec) {
@@ -665,6 +666,14 @@ static int check_mesh_ptrs(const lbm_ctx *c, const ibm_mesh *m) {
 }
 
 static constexpr size_t kMaxLds = 64 * 1024;
+static constexpr size_t kMaxSpreadLds = 160 * 1024;  // the spread's workgroups may take a compute unit's whole LDS
+
+// Power of two >= a cell's point count (at least 64): the spread's sort size.
+static int spread_pmax(int maxv) {
+    int p = 64;
+    while (p < maxv) p <<= 1;
+    return p;
+}
 
 // Workgroups of the kernels that walk the compacted tile list.
 static int waves_grid(const lbm_ctx *c) {
@@ -678,6 +687,7 @@ static MarkArgs mark_args(const lbm_ctx *c, const ibm_mesh *m) {
     MarkArgs a{};
     a.tcount = c->tcount;
     a.epoch = c->epoch;
+    a.nfall = c->nfall;
     a.chans = c->chans;
     a.cell_chan = m->cell_chan;
     a.vert_off = m->vert_off;
@@ -901,14 +911,23 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
         c->srec_cap = need_rec;
     }
     if (!c->owner) {
-        if (hipMalloc(&c->owner, 4 * c->N) != hipSuccess || hipMalloc(&c->cslot, 8 * 4 * c->rsize * c->N) != hipSuccess ||
-            hipMalloc(&c->role, 8 * c->N) != hipSuccess) {
+        if (hipMalloc(&c->owner, 4 * c->N) != hipSuccess) {
             (void)hipGetLastError();
-            return fail(LBM_ENOMEM, "allocating the spreading slots (%lld bytes) failed",
-                        (long long)((12 + 32 * c->rsize) * c->N));
+            return fail(LBM_ENOMEM, "allocating the spreading claims (%lld bytes) failed", (long long)(4 * c->N));
         }
         HIPCHK(hipMemsetAsync(c->owner, 0, 4 * c->N, c->s));
-        HIPCHK(hipMemsetAsync(c->role, 0, 8 * c->N, c->s));
+    }
+    {
+        const size_t sl = c->rsize == 8 ? spread_lds_bytes<double>(spread_pmax(mv), mv)
+                                        : spread_lds_bytes<float>(spread_pmax(mv), mv);
+        if (sl > kMaxSpreadLds) return fail(LBM_EINVAL, "a cell with %d vertices does not fit the spread's LDS", mv);
+        const hipError_t e = c->rsize == 8
+            ? hipFuncSetAttribute((const void *)k_spread_cells<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sl)
+            : hipFuncSetAttribute((const void *)k_spread_cells<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sl);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_EHIP, "the spread's LDS (%zu bytes) was refused: %s", sl, hipGetErrorString(e));
+        }
     }
     if (const ibm_contact *k = m->contact) {
         if (int rc = build_sphere_grid(c, k)) return rc;
@@ -1057,27 +1076,29 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.vert_off = m->vert_off;
     sp.srec = c->srec;
     sp.owner = c->owner;
-    sp.cslot = c->cslot;
-    sp.role = c->role;
+    sp.fibm = c->fibm;
     sp.facc = c->facc;
     sp.ftile = c->ftile;
+    sp.nfall = c->nfall;
     sp.epoch = c->epoch;
     sp.chans = c->chans;
     sp.cell_chan = m->cell_chan;
-    k_spread_cells<R><<<m->ncells, kSpreadThreads, 0, c->s>>>(sp);
-    GatherArgs g{};
-    g.tlist = c->tlist;
-    g.tcount = c->tcount;
-    g.role = c->role;
-    g.cslot = c->cslot;
-    g.need = c->need;
-    g.ftile = c->ftile;
-    g.fibm = c->fibm;
-    g.facc = c->facc;
-    g.accumulate = c->acc;
-    g.chans = c->chans;
-    g.tile_chan = c->tile_chan;
-    k_gather_nodes<R><<<waves_grid(c), 256, 0, c->s>>>(g);
+    sp.accumulate = c->acc;
+    sp.pmax = spread_pmax(m->max_cell_verts);
+    sp.maxv = m->max_cell_verts;
+    k_spread_cells<R><<<m->ncells, kSpreadThreads, spread_lds_bytes<R>(sp.pmax, sp.maxv), c->s>>>(sp);
+    FixupArgs fx{};
+    fx.tlist = c->tlist;
+    fx.tcount = c->tcount;
+    fx.nfall = c->nfall;
+    fx.need = c->need;
+    fx.ftile = c->ftile;
+    fx.fibm = c->fibm;
+    fx.facc = c->facc;
+    fx.chans = c->chans;
+    fx.tile_chan = c->tile_chan;
+    // four waves per workgroup, 64 list entries per wave
+    k_spread_fixup<R><<<(int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 256), 4096)), 256, 0, c->s>>>(fx);
 }
 
 // The immersed-boundary half of a coupled step with the populations f.
@@ -1092,7 +1113,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
 // stream before the call returns.
 template <class S, class R, bool DEV>
 static void enqueue_couple_as(lbm_ctx *c, const ibm_mesh *m, const void *f, bool overlap) {
-    c->acc = c->couples > 0;  // read by the mark and gather launches below
+    c->acc = c->couples > 0;  // read by the mark and spread launches below
     c->couples++;
     if (!overlap) {
         launch_membrane<R>(c, m, false, true);

@@ -235,10 +235,31 @@ def test_dense_cell_f64(orc, lbm):
     assert np.abs(mesh.positions() - X).max() < 1e-12
 
 
+def test_large_cell_spread_fallback_f64(orc, lbm):
+    """A cell of radius 14: the box of its stencil base nodes holds more than
+    16384 nodes, so the spread takes it point by point through the atomic
+    fallback.  The coupled FP64 steps still match the oracle."""
+    nx, ny, nz = 44, 40, 40
+    cells = S.make_cells(np.array([[21.4, 19.7, 19.3]]), 14.0, 3, moduli=(0.02, 0.005, 0.01, 0.1, 0.5))
+    b = np.floor(cells.positions()).astype(int)
+    assert np.prod(b.max(0) - b.min(0) + 2) > 16384
+    s = S.Scenario("large", nx, ny, nz, 0.8, (1e-4, 0, 0), S.channel_mask(nx, ny, nz), 4, cells=cells)
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f64", deform=0.05, seed=12, vel=1e-3)
+    f = L.rest()
+    for _ in range(4):
+        lat.couple(mesh)
+        lat.step(1)
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    assert np.abs(lat.populations_f64().cpu().numpy()[:, fl] - f[:, fl]).max() < 1e-14
+    assert np.abs(mesh.positions() - X).max() < 1e-12
+    assert np.abs(mesh.velocities() - V).max() < 1e-13
+
+
 def test_overlapping_cells_share_base_nodes_f64(orc, lbm):
-    """Two cells of one population overlap, so some stencil base nodes hold
-    points of both: the second cell to claim such a node spreads through the
-    fallback path.  Results must still match the oracle."""
+    """Two cells of one population overlap, so some stencil nodes (and base
+    nodes) hold points of both: the second cell to claim such a node spreads
+    through the fallback path.  Results must still match the oracle."""
     nx, ny, nz = 32, 24, 20
     cells = S.make_cells(np.array([[12.2, 11.7, 9.6], [14.9, 12.3, 10.1]]), 3.0, 2,
                          moduli=(0.01, 0.002, 0.005, 0.05, 0.2))
