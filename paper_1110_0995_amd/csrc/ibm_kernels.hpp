@@ -691,6 +691,7 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
 constexpr int kSpreadThreads = 512;
 constexpr int kSpreadMaxPoints = 2048;  // per cell (bounded by the membrane pass's LDS anyway)
 constexpr int kSpreadBox = 16384;       // nodes of the largest per-cell box of base nodes kept in LDS
+static_assert(kSpreadBox / 32 <= kSpreadThreads, "the spread scans one bitmap word per thread");
 
 struct SpreadArgs {
     const int32_t *vert_off;
@@ -714,13 +715,14 @@ struct SPoint {
     R dx, dy, dz, fx, fy, fz;
 };
 
-// LDS of k_spread_cells: sort keys [pmax] (u32), staged points [maxv], run
-// table over the box [kSpreadBox] (u16), node bitmap [kSpreadBox/32] (u32),
-// node list [8 maxv] (u16), and a few scalars.
+// LDS of k_spread_cells: sort keys [pmax] (u32), staged points [maxv],
+// base-node and stencil-node bitmaps over the box [kSpreadBox/32] (u32 each),
+// prefix counts of the base bitmap's words [kSpreadBox/32] (u16), run starts
+// [maxv] and node list [8 maxv] (u16), and a few scalars.
 template <class R>
 __host__ __device__ inline size_t spread_lds_bytes(int pmax, int maxv) {
-    return 4 * (size_t)pmax + sizeof(SPoint<R>) * (size_t)maxv + 2 * (size_t)kSpreadBox + kSpreadBox / 8 +
-           16 * (size_t)maxv + 256;
+    return 4 * (size_t)pmax + sizeof(SPoint<R>) * (size_t)maxv + 2 * (kSpreadBox / 32) * 4 + (kSpreadBox / 32) * 2 +
+           18 * (size_t)maxv + 256;
 }
 
 // Block-wide exclusive prefix sum of one int per thread (blockDim.x <= 1024);
@@ -748,9 +750,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wsum, int &total
 // Spreading, one workgroup per cell (Sec. 2.2 step 3: every point exerts
 // -F_c on its 2x2x2 stencil with the trilinear weights).  The cell's base
 // nodes, unwrapped around its first point, span a small box; the points
-// are sorted by (base node in the box, point) in LDS, and a table over the
-// box gives each base node's run of points.  The stencil nodes are the set
-// bits of a bitmap over the box; each is summed by one thread, corner by
+// are sorted by (base node in the box, point) in LDS; a bitmap of the base
+// nodes over the box with per-word prefix counts gives each base node's
+// run of points.  The stencil nodes are the set bits of a second bitmap
+// over the box; each is summed by one thread, corner by
 // corner and within a corner in sorted point order, claimed for this call
 // with one atomic exchange of the call's epoch, and its sum written as the
 // node's spread force.  A node already claimed by another cell in this
@@ -764,13 +767,16 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wsum, int &total
 template <class R>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     using R4 = typename Vec4<R>::T;
+    constexpr int kWords = kSpreadBox / 32;
     extern __shared__ uint32_t smem_u32[];
-    uint32_t *key = smem_u32;                                                  // [pmax]
-    SPoint<R> *pts = reinterpret_cast<SPoint<R> *>(key + a.pmax);             // [maxv]
-    uint16_t *table = reinterpret_cast<uint16_t *>(pts + a.maxv);             // [kSpreadBox]
-    uint32_t *bits = reinterpret_cast<uint32_t *>(table + kSpreadBox);        // [kSpreadBox / 32]
-    uint16_t *nodes = reinterpret_cast<uint16_t *>(bits + kSpreadBox / 32);  // [8 maxv]
-    int *sc = reinterpret_cast<int *>(nodes + 8 * a.maxv);                    // scalars and scan scratch
+    uint32_t *key = smem_u32;                                          // [pmax]
+    SPoint<R> *pts = reinterpret_cast<SPoint<R> *>(key + a.pmax);     // [maxv]
+    uint32_t *bbits = reinterpret_cast<uint32_t *>(pts + a.maxv);     // [kWords] base nodes of the cell
+    uint32_t *bits = bbits + kWords;                                   // [kWords] stencil nodes
+    uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + kWords);     // [kWords] base bits in earlier words
+    uint16_t *rstart = wpre + kWords;                                  // [maxv] first sorted index of each run
+    uint16_t *nodes = rstart + a.maxv;                                 // [8 maxv]
+    int *sc = reinterpret_cast<int *>(nodes + 8 * a.maxv + (a.maxv & 1));  // scalars and scan scratch
     const int c = blockIdx.x;
     const int v0 = a.vert_off[c], nv = a.vert_off[c + 1] - v0;
     if (nv <= 0) return;
@@ -865,8 +871,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         }
         key[i] = k;
     }
-    for (int i = threadIdx.x; i < V; i += blockDim.x) table[i] = 0;
-    for (int i = threadIdx.x; i < (V + 31) / 32; i += blockDim.x) bits[i] = 0;
+    const int nwords = (V + 31) / 32;
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) bbits[i] = bits[i] = 0;
     __syncthreads();
     for (int kk = 2; kk <= P; kk <<= 1)
         for (int j = kk >> 1; j > 0; j >>= 1) {
@@ -882,10 +888,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
             }
             __syncthreads();
         }
-    // run table and stencil-node bitmap
+    // base-node and stencil-node bitmaps; runs are in ascending box order, so
+    // a base node's run is its rank among the set base bits
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
         const uint32_t li = key[i] >> 11;
-        if (i == 0 || (key[i - 1] >> 11) != li) table[li] = (uint16_t)(i + 1);
+        if (i == 0 || (key[i - 1] >> 11) != li) atomicOr(&bbits[li >> 5], 1u << (li & 31));
         const int lx = (int)(li % bx_), ly = (int)((li / bx_) % by_), lz = (int)(li / (bx_ * by_));
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -894,8 +901,20 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         }
     }
     __syncthreads();
+    {
+        const int w = threadIdx.x;  // nwords <= kWords = blockDim.x
+        int tot;
+        const int pre = block_exclusive_scan(w < nwords ? __popc(bbits[w]) : 0, sc + 8, tot);
+        if (w < nwords) wpre[w] = (uint16_t)pre;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const uint32_t li = key[i] >> 11;
+        if (i == 0 || (key[i - 1] >> 11) != li)
+            rstart[wpre[li >> 5] + __popc(bbits[li >> 5] & ((1u << (li & 31)) - 1u))] = (uint16_t)i;
+    }
+    __syncthreads();
     // node list (box indices, ascending)
-    const int nwords = (V + 31) / 32;
     int total = 0;
     for (int w0 = 0; w0 < nwords; w0 += blockDim.x) {
         const int w = w0 + threadIdx.x;
@@ -920,10 +939,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
             const int ex = lx - (q & 1), ey = ly - ((q >> 1) & 1), ez = lz - (q >> 2);
             if (ex < 0 || ey < 0 || ez < 0) continue;
             const uint32_t bi = (uint32_t)(ex + bx_ * (ey + by_ * ez));
-            const int s0 = table[bi];
-            if (!s0) continue;
+            const uint32_t m = bbits[bi >> 5], bit = 1u << (bi & 31);
+            if (!(m & bit)) continue;
+            const int s0 = rstart[wpre[bi >> 5] + __popc(m & (bit - 1u))];
             R Sx = R(0), Sy = R(0), Sz = R(0);
-            for (int j = s0 - 1; j < nv && (key[j] >> 11) == bi; j++) {
+            for (int j = s0; j < nv && (key[j] >> 11) == bi; j++) {
                 const SPoint<R> r = pts[key[j] & 0x7ffu];
                 const R wx = (q & 1) ? r.dx : R(1) - r.dx, wy = ((q >> 1) & 1) ? r.dy : R(1) - r.dy;
                 const R wz = (q >> 2) ? r.dz : R(1) - r.dz;
