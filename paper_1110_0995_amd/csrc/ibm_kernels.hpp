@@ -40,8 +40,8 @@
 //   already claimed by another cell in this call (two membranes within a
 //   lattice spacing) falls back to float atomics into a separate
 //   accumulator, kept zero between steps, and flags its tile;
-// k_spread_fixup adds that accumulator at the flagged tiles' marked nodes
-//   (and returns at once when no node took the fallback).
+// k_spread_fixup adds that accumulator at the marked nodes of the flagged
+//   tiles, which the spread lists once each.
 // All sums except the fallback's are in a fixed order, so the spread is
 // bit-reproducible.
 //
@@ -93,7 +93,7 @@ __device__ __forceinline__ int cell_channel(const int32_t *cell_chan, int c) { r
 struct MarkArgs {
     uint32_t *tcount;  // tile-list length, reset here for this step
     uint32_t *epoch;   // spreading-claim epoch, advanced here for this step
-    uint32_t *nfall;   // count of the spread's fallback nodes, reset here for this step
+    uint32_t *nfall;   // length of the spread's list of fallback tiles, reset here for this step
     const Chan *chans;
     const int32_t *cell_chan;  // [ncells] channel of each cell, null for a single channel
     const int32_t *vert_off, *anchor;
@@ -699,8 +699,9 @@ struct SpreadArgs {
     uint32_t *owner;   // [N] epoch of the call that last claimed the node
     void *fibm;        // [N] Vec4: spread force, written (with `accumulate`, added) at the nodes a cell claims
     void *facc;        // [N] Vec4: accumulator of the fallback (zero between steps)
-    uint8_t *ftile;    // [ntiles] 1: a node of the tile got fallback atomics this call
-    uint32_t *nfall;   // nodes spread through the fallback in this call
+    uint8_t *ftile;    // [ntiles] (padded to 16) 1: a node of the tile got fallback atomics this call
+    uint32_t *flist;   // [ntiles] the flagged tiles, each listed once
+    uint32_t *nfall;   // length of that list
     const uint32_t *epoch;
     const Chan *chans;
     const int32_t *cell_chan;
@@ -801,8 +802,11 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         atomicAdd(rec + 0, fx);
         atomicAdd(rec + 1, fy);
         atomicAdd(rec + 2, fz);
-        a.ftile[ch.toff + (int64_t)(gy + ch.ny * gz) * ch.tpr + (gx >> 6)] = 1;
-        atomicAdd(a.nfall, 1u);
+        // flag the tile; the call that sets its byte lists it
+        const int64_t t = ch.toff + (int64_t)(gy + ch.ny * gz) * ch.tpr + (gx >> 6);
+        const uint32_t sh = 8u * (uint32_t)(t & 3);
+        const uint32_t old = atomicOr(reinterpret_cast<uint32_t *>(a.ftile) + (t >> 2), 1u << sh);
+        if (((old >> sh) & 0xffu) == 0u) a.flist[atomicAdd(a.nfall, 1u)] = (uint32_t)t;
     };
     // base nodes unwrapped around the first point's; their bounding box
     int rx, ry, rz;
@@ -976,8 +980,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
 }
 
 struct FixupArgs {
-    const uint32_t *tlist, *tcount;
-    const uint32_t *nfall;
+    const uint32_t *flist, *nfall;  // tiles the spread flagged this call
     const uint8_t *need;
     uint8_t *ftile;  // [ntiles] fallback flags, cleared here
     void *fibm;      // [N] Vec4 spread force
@@ -986,39 +989,28 @@ struct FixupArgs {
     const uint16_t *tile_chan;
 };
 
-// The fallback's atomics onto the spread force: in every listed tile the
-// spread flagged, each marked node adds the accumulator and clears it.  A
-// wave checks 64 list entries with one ballot and works through the flagged
-// ones; the kernel returns at once when no node of the call took the
-// fallback.
+// The fallback's atomics onto the spread force: one wave per tile the spread
+// flagged; each marked node adds the accumulator and clears it.
 template <class R>
 __global__ __launch_bounds__(256) void k_spread_fixup(FixupArgs a) {
     using R4 = typename Vec4<R>::T;
-    if (*a.nfall == 0) return;
+    const uint32_t count = *a.nfall;
     const int lane = threadIdx.x & 63;
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    const uint32_t count = *a.tcount;
     R4 *FI = static_cast<R4 *>(a.fibm);
     R4 *FA = static_cast<R4 *>(a.facc);
-    for (uint32_t w0 = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 64u; w0 < count; w0 += nwaves * 64u) {
-        const uint32_t w = w0 + lane;
-        const int mine = w < count ? (int)a.tlist[w] : -1;
-        unsigned long long flagged = __ballot(mine >= 0 && a.ftile[mine]);
-        while (flagged) {
-            const int j = __builtin_ctzll(flagged);
-            flagged &= flagged - 1;
-            const int tile = __builtin_amdgcn_readlane(mine, j);
-            const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
-            const int lt = tile - ch.toff, row = lt / ch.tpr;
-            const int x = (lt - row * ch.tpr) * 64 + lane;
-            if (lane == 0) a.ftile[tile] = 0;
-            if (x >= ch.nx) continue;
-            const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
-            if (!a.need[n]) continue;
-            const R4 f = FA[n], g = FI[n];
-            FA[n] = R4{R(0), R(0), R(0), R(0)};
-            FI[n] = R4{g.x + f.x, g.y + f.y, g.z + f.z, R(0)};
-        }
+    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
+        const int tile = __builtin_amdgcn_readfirstlane((int)a.flist[w]);
+        const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
+        const int lt = tile - ch.toff, row = lt / ch.tpr;
+        const int x = (lt - row * ch.tpr) * 64 + lane;
+        if (lane == 0) a.ftile[tile] = 0;
+        if (x >= ch.nx) continue;
+        const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
+        if (!a.need[n]) continue;
+        const R4 f = FA[n], g = FI[n];
+        FA[n] = R4{R(0), R(0), R(0), R(0)};
+        FI[n] = R4{g.x + f.x, g.y + f.y, g.z + f.z, R(0)};
     }
 }
 

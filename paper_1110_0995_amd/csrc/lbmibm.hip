@@ -140,7 +140,8 @@ struct lbm_ctx {
     void *srec = nullptr;        // spread records, one per IB point of the largest mesh
     int64_t srec_cap = 0;
     uint32_t *owner = nullptr;   // [N] epoch of the last spreading claim of each node
-    uint32_t *nfall = nullptr;   // nodes spread through the fallback in the current call
+    uint32_t *nfall = nullptr;   // tiles the spread's fallback flagged in the current call
+    uint32_t *flist = nullptr;   // [ntiles] those tiles
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
     int64_t nparts = 0;
@@ -285,7 +286,7 @@ static void build_row_groups(const std::vector<Chan> &chs, std::vector<uint32_t>
 }
 
 static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch, int64_t nwg) {
-    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + 4 + cdiv(N, 256) * 32 + 32 +
+    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 8 * tiles + 4 + 4 + 4 + cdiv(N, 256) * 32 + 32 +
            (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
 }
 
@@ -318,7 +319,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     for (hipEvent_t e : {c->ev_fork, c->ev_join})
         if (e) (void)hipEventDestroy(e);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
-                    c->tcount, c->epoch,    c->srec, c->owner, c->nfall, c->partials, c->sums, c->ftile,
+                    c->tcount, c->epoch,    c->srec, c->owner, c->nfall, c->flist, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
                     c->sph_start, c->sph_items, c->wgtab};
     for (void *b : bufs)
@@ -346,7 +347,7 @@ static int init_ctx(lbm_ctx *c) {
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
         hipMalloc(&c->tneed, tpad) != hipSuccess || hipMalloc(&c->tlist, 4 * tn) != hipSuccess ||
         hipMalloc(&c->tcount, 4) != hipSuccess || hipMalloc(&c->epoch, 4) != hipSuccess ||
-        hipMalloc(&c->nfall, 4) != hipSuccess ||
+        hipMalloc(&c->nfall, 4) != hipSuccess || hipMalloc(&c->flist, 4 * tn) != hipSuccess ||
         hipMalloc(&c->ftile, tpad) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
@@ -1080,6 +1081,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.facc = c->facc;
     sp.ftile = c->ftile;
     sp.nfall = c->nfall;
+    sp.flist = c->flist;
     sp.epoch = c->epoch;
     sp.chans = c->chans;
     sp.cell_chan = m->cell_chan;
@@ -1088,8 +1090,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.maxv = m->max_cell_verts;
     k_spread_cells<R><<<m->ncells, kSpreadThreads, spread_lds_bytes<R>(sp.pmax, sp.maxv), c->s>>>(sp);
     FixupArgs fx{};
-    fx.tlist = c->tlist;
-    fx.tcount = c->tcount;
+    fx.flist = c->flist;
     fx.nfall = c->nfall;
     fx.need = c->need;
     fx.ftile = c->ftile;
@@ -1097,8 +1098,7 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     fx.facc = c->facc;
     fx.chans = c->chans;
     fx.tile_chan = c->tile_chan;
-    // four waves per workgroup, 64 list entries per wave
-    k_spread_fixup<R><<<(int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 256), 4096)), 256, 0, c->s>>>(fx);
+    k_spread_fixup<R><<<(int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4), 256)), 256, 0, c->s>>>(fx);
 }
 
 // The immersed-boundary half of a coupled step with the populations f.
