@@ -235,6 +235,28 @@ def test_dense_cell_f64(orc, lbm):
     assert np.abs(mesh.positions() - X).max() < 1e-12
 
 
+def test_cell_across_periodic_faces_f64(orc, lbm):
+    """A cell centred on the corner where the periodic x and y faces meet:
+    its stencils wrap across both faces (the spread sums it in a box
+    unwrapped around one of its points).  Coupled FP64 steps equal the
+    oracle's."""
+    nx, ny, nz = 36, 32, 24
+    cells = S.make_cells(np.array([[0.3, 31.6, 11.4]]), 4.0, 2, moduli=(0.02, 0.005, 0.01, 0.1, 0.5))
+    X = cells.positions()
+    assert (X[:, 0] < 0).any() and (X[:, 0] > 0).any() and (X[:, 1] > ny - 1).any()
+    s = S.Scenario("corner", nx, ny, nz, 0.8, (1e-4, 0, 0), S.channel_mask(nx, ny, nz), 6, cells=cells)
+    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f64", deform=0.05, seed=14, vel=1e-3)
+    f = L.rest()
+    for _ in range(6):
+        lat.couple(mesh)
+        lat.step(1)
+        f = orc.step(L, M, f, X, V)
+    fl = s.solid.reshape(-1) == 0
+    assert np.abs(lat.populations_f64().cpu().numpy()[:, fl] - f[:, fl]).max() < 1e-14
+    assert np.abs(mesh.positions() - X).max() < 1e-12
+    assert np.abs(mesh.velocities() - V).max() < 1e-13
+
+
 def test_large_cell_spread_fallback_f64(orc, lbm):
     """A cell of radius 14: the box of its stencil base nodes holds more than
     16384 nodes, so the spread takes it point by point through the atomic
