@@ -138,6 +138,7 @@ struct StepArgs {
     int ntiles;
     int remap;            // 1: renumber workgroups so each XCD walks one contiguous tile range
     const uint32_t *wgtab; // [gridDim.x] workgroup table (first tile << 3 | tiles - 1), or null
+    int reverse;          // 1: take the table's entries in reverse order
     int64_t N;
     double g[3];
     double omega, kf;
@@ -155,7 +156,9 @@ struct StepArgs {
 // x-shifted stores of a row meet in one L2 whatever XCD runs it and the
 // workgroups keep their natural order (the chip then streams through one
 // compact address range), otherwise they are renumbered by XCD (`remap`) so
-// that neighbouring tiles share an L2.  IDX is the index type of element offsets from the buffer
+// that neighbouring tiles share an L2.  Every other pass takes the table in
+// reverse order, so that it starts on the rows the previous pass wrote last
+// (still held by the memory-side cache).  IDX is the index type of element offsets from the buffer
 // base: uint32_t when 19 planes fit in 4 GiB (single 64-bit base + 32-bit
 // lane offsets), int64_t otherwise.
 template <class S, class R, bool DEV, bool HAS_G, class IDX>
@@ -163,7 +166,7 @@ __global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int tile;
     if (a.wgtab) {
-        const uint32_t e = a.wgtab[blockIdx.x];
+        const uint32_t e = a.wgtab[a.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
         if (wave > (int)(e & 7u)) return;
         tile = (int)(e >> 3) + wave;
     } else {

@@ -486,6 +486,7 @@ static void launch_step(lbm_ctx *c, StepArgs a) {
     const CsShape sh = cs_shape(c);
     a.remap = sh.remap;
     a.wgtab = sh.tab;
+    a.reverse = (int)(c->steps & 1);  // every other pass walks the table backwards
     const int nb = sh.nb;
     const int bs = 64 * sh.waves;
     if (c->off32) {
