@@ -81,6 +81,8 @@ struct AdjStepArgs {
     const uint8_t *cls;
     const uint32_t *links;
     const void *fibm;      // spread force of step n, valid at the marked nodes
+    void *facc;            // the spread's fallback accumulator: added and cleared in flagged tiles
+    uint8_t *ftile;        // tiles holding fallback sums (cleared here)
     const uint8_t *need;   // stencil-node marks (left set for k_adj_nodes)
     const uint8_t *tneed;  // tile marks
     void *lamF;            // [N] Vec4: lambda_F at marked nodes (written)
@@ -124,14 +126,23 @@ __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
         Fy += G[N + n];
         Fz += G[2 * N + n];
     }
-    const bool marked = a.tneed[tile] && a.need[n];
+    const bool tmark = a.tneed[tile] != 0;
+    const bool marked = tmark && a.need[n];
+    const bool fl = tmark && a.ftile[tile] != 0;
     const R4 *FI = static_cast<const R4 *>(a.fibm);
     if (marked) {
-        const R4 fi = FI[n];
+        R4 fi = FI[n];
+        if (fl) {  // the spread's fallback sums, taken once
+            R4 *FA = static_cast<R4 *>(a.facc);
+            const R4 fa = FA[n];
+            fi = R4{fi.x + fa.x, fi.y + fa.y, fi.z + fa.z, R(0)};
+            FA[n] = R4{R(0), R(0), R(0), R(0)};
+        }
         Fx += fi.x;
         Fy += fi.y;
         Fz += fi.z;
     }
+    if (fl && lane == 0) a.ftile[tile] = 0;
     R *L = static_cast<R *>(a.lam);
     R4 *LF = static_cast<R4 *>(a.lamF);
     if (a.cls[n] == CLS_SOLID) {

@@ -39,9 +39,9 @@
 //   call's epoch and writes the sum as the node's spread force.  A node
 //   already claimed by another cell in this call (two membranes within a
 //   lattice spacing) falls back to float atomics into a separate
-//   accumulator, kept zero between steps, and flags its tile;
-// k_spread_fixup adds that accumulator at the marked nodes of the flagged
-//   tiles, which the spread lists once each.
+//   accumulator, kept zero between steps, and flags its tile; the
+//   collide-stream pass adds that accumulator at the flagged tiles' marked
+//   nodes and clears it.
 // All sums except the fallback's are in a fixed order, so the spread is
 // bit-reproducible.
 //
@@ -93,7 +93,6 @@ __device__ __forceinline__ int cell_channel(const int32_t *cell_chan, int c) { r
 struct MarkArgs {
     uint32_t *tcount;  // tile-list length, reset here for this step
     uint32_t *epoch;   // spreading-claim epoch, advanced here for this step
-    uint32_t *nfall;   // length of the spread's list of fallback tiles, reset here for this step
     const Chan *chans;
     const int32_t *cell_chan;  // [ncells] channel of each cell, null for a single channel
     const int32_t *vert_off, *anchor;
@@ -139,11 +138,9 @@ __device__ __forceinline__ void mark_stencil(const MarkArgs &a, const Chan &ch, 
     }
 }
 
-// Reset of the tile-list length and fallback count and advance of the claim
-// epoch for a step.
+// Reset of the tile-list length and advance of the claim epoch for a step.
 __device__ __forceinline__ void start_marks(const MarkArgs &a) {
     *a.tcount = 0;
-    *a.nfall = 0;
     *a.epoch += 1u;
 }
 
@@ -699,9 +696,7 @@ struct SpreadArgs {
     uint32_t *owner;   // [N] epoch of the call that last claimed the node
     void *fibm;        // [N] Vec4: spread force, written (with `accumulate`, added) at the nodes a cell claims
     void *facc;        // [N] Vec4: accumulator of the fallback (zero between steps)
-    uint8_t *ftile;    // [ntiles] (padded to 16) 1: a node of the tile got fallback atomics this call
-    uint32_t *flist;   // [ntiles] the flagged tiles, each listed once
-    uint32_t *nfall;   // length of that list
+    uint8_t *ftile;    // [ntiles] 1: a node of the tile got fallback atomics (cleared by the collide-stream pass)
     const uint32_t *epoch;
     const Chan *chans;
     const int32_t *cell_chan;
@@ -760,7 +755,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *wsum, int &total
 // node's spread force.  A node already claimed by another cell in this
 // call (membranes within a lattice spacing of each other) takes the sum as
 // float atomics into a separate accumulator, kept zero between steps, and
-// flags its tile for k_spread_fixup; so does every node of a cell whose box
+// flags its tile for the collide-stream pass, which adds the accumulator
+// at the flagged tiles' marked nodes and clears it; so does every node of a cell whose box
 // exceeds kSpreadBox nodes (point by point, after its claim has set the
 // node's force to zero, or kept it with `accumulate`).  Every stencil node of
 // the call is written, so the collide-stream pass reads the force at the
@@ -802,11 +798,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         atomicAdd(rec + 0, fx);
         atomicAdd(rec + 1, fy);
         atomicAdd(rec + 2, fz);
-        // flag the tile; the call that sets its byte lists it
-        const int64_t t = ch.toff + (int64_t)(gy + ch.ny * gz) * ch.tpr + (gx >> 6);
-        const uint32_t sh = 8u * (uint32_t)(t & 3);
-        const uint32_t old = atomicOr(reinterpret_cast<uint32_t *>(a.ftile) + (t >> 2), 1u << sh);
-        if (((old >> sh) & 0xffu) == 0u) a.flist[atomicAdd(a.nfall, 1u)] = (uint32_t)t;
+        a.ftile[ch.toff + (int64_t)(gy + ch.ny * gz) * ch.tpr + (gx >> 6)] = 1;
     };
     // base nodes unwrapped around the first point's; their bounding box
     int rx, ry, rz;
@@ -976,41 +968,6 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         } else {
             fallback_add(n, gx, gy, gz, Fx, Fy, Fz);
         }
-    }
-}
-
-struct FixupArgs {
-    const uint32_t *flist, *nfall;  // tiles the spread flagged this call
-    const uint8_t *need;
-    uint8_t *ftile;  // [ntiles] fallback flags, cleared here
-    void *fibm;      // [N] Vec4 spread force
-    void *facc;      // [N] Vec4 fallback accumulator, read and cleared here
-    const Chan *chans;
-    const uint16_t *tile_chan;
-};
-
-// The fallback's atomics onto the spread force: one wave per tile the spread
-// flagged; each marked node adds the accumulator and clears it.
-template <class R>
-__global__ __launch_bounds__(256) void k_spread_fixup(FixupArgs a) {
-    using R4 = typename Vec4<R>::T;
-    const uint32_t count = *a.nfall;
-    const int lane = threadIdx.x & 63;
-    const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
-    R4 *FI = static_cast<R4 *>(a.fibm);
-    R4 *FA = static_cast<R4 *>(a.facc);
-    for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
-        const int tile = __builtin_amdgcn_readfirstlane((int)a.flist[w]);
-        const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
-        const int lt = tile - ch.toff, row = lt / ch.tpr;
-        const int x = (lt - row * ch.tpr) * 64 + lane;
-        if (lane == 0) a.ftile[tile] = 0;
-        if (x >= ch.nx) continue;
-        const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
-        if (!a.need[n]) continue;
-        const R4 f = FA[n], g = FI[n];
-        FA[n] = R4{R(0), R(0), R(0), R(0)};
-        FI[n] = R4{g.x + f.x, g.y + f.y, g.z + f.z, R(0)};
     }
 }
 

@@ -130,6 +130,8 @@ struct StepArgs {
     const uint8_t *cls;
     const uint32_t *links;
     const void *fibm;     // [N] x 4 immersed-boundary force (x, y, z, unused), valid at marked nodes
+    void *facc;           // [N] x 4 the spread's fallback accumulator: added and cleared in flagged tiles
+    uint8_t *ftile;       // [ntiles] 1: the tile holds fallback sums (cleared here)
     uint8_t *need;        // [N] 1: the node received spread force this step
     uint8_t *tneed;       // [ntiles] 1: the tile holds such a node
     const void *gfield;   // [3][N] or null
@@ -149,8 +151,9 @@ struct StepArgs {
 // coalesced, collides in registers and writes every post-collision value
 // straight to its destination slot (neighbour along c_i, or the opposite
 // slot of the same node when that link is a wall link).  The spread force is
-// read only at nodes marked as stencil nodes of this step (where the gather
-// pass wrote it), and the marks are cleared.
+// read only at nodes marked as stencil nodes of this step (where the spread
+// wrote it; in a tile the spread flagged, plus its fallback accumulator,
+// which is cleared), and the marks are cleared.
 // A workgroup is blockDim/64 consecutive tiles (the tile shape is a launch
 // parameter); when it holds whole x rows, the partial cache lines of the
 // x-shifted stores of a row meet in one L2 whatever XCD runs it and the
@@ -192,14 +195,28 @@ __global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
         Fz += at(G, 2 * N + n);
     }
     if (a.tneed[tile]) {
+        const bool fl = a.ftile[tile] != 0;
         if (at(a.need, n)) {
             const R *fi = static_cast<const R *>(a.fibm);
-            Fx += at(fi, 4 * n);
-            Fy += at(fi, 4 * n + 1);
-            Fz += at(fi, 4 * n + 2);
+            R fx = at(fi, 4 * n), fy = at(fi, 4 * n + 1), fz = at(fi, 4 * n + 2);
+            if (fl) {  // the spread's fallback sums, taken once
+                R *fa = static_cast<R *>(a.facc);
+                fx = fx + at(fa, 4 * n);
+                fy = fy + at(fa, 4 * n + 1);
+                fz = fz + at(fa, 4 * n + 2);
+                at(fa, 4 * n) = R(0);
+                at(fa, 4 * n + 1) = R(0);
+                at(fa, 4 * n + 2) = R(0);
+            }
+            Fx += fx;
+            Fy += fy;
+            Fz += fz;
             at(a.need, n) = 0;
         }
-        if (lane == 0) a.tneed[tile] = 0;
+        if (lane == 0) {
+            a.tneed[tile] = 0;
+            if (fl) a.ftile[tile] = 0;
+        }
     }
     const uint8_t cl = at(a.cls, n);
     if (cl == CLS_SOLID) return;

@@ -140,8 +140,6 @@ struct lbm_ctx {
     void *srec = nullptr;        // spread records, one per IB point of the largest mesh
     int64_t srec_cap = 0;
     uint32_t *owner = nullptr;   // [N] epoch of the last spreading claim of each node
-    uint32_t *nfall = nullptr;   // tiles the spread's fallback flagged in the current call
-    uint32_t *flist = nullptr;   // [ntiles] those tiles
     bool off32 = false;          // every lattice buffer below 4 GiB
     double *partials = nullptr;
     int64_t nparts = 0;
@@ -286,7 +284,7 @@ static void build_row_groups(const std::vector<Chan> &chs, std::vector<uint32_t>
 }
 
 static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch, int64_t nwg) {
-    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 8 * tiles + 4 + 4 + 4 + cdiv(N, 256) * 32 + 32 +
+    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
            (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
 }
 
@@ -319,7 +317,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     for (hipEvent_t e : {c->ev_fork, c->ev_join})
         if (e) (void)hipEventDestroy(e);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
-                    c->tcount, c->epoch,    c->srec, c->owner, c->nfall, c->flist, c->partials, c->sums, c->ftile,
+                    c->tcount, c->epoch,    c->srec, c->owner, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
                     c->sph_start, c->sph_items, c->wgtab};
     for (void *b : bufs)
@@ -347,7 +345,6 @@ static int init_ctx(lbm_ctx *c) {
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
         hipMalloc(&c->tneed, tpad) != hipSuccess || hipMalloc(&c->tlist, 4 * tn) != hipSuccess ||
         hipMalloc(&c->tcount, 4) != hipSuccess || hipMalloc(&c->epoch, 4) != hipSuccess ||
-        hipMalloc(&c->nfall, 4) != hipSuccess || hipMalloc(&c->flist, 4 * tn) != hipSuccess ||
         hipMalloc(&c->ftile, tpad) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
         hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
@@ -389,7 +386,6 @@ static int init_ctx(lbm_ctx *c) {
     HIPCHK(hipMemsetAsync(c->ftile, 0, tpad, c->s));
     HIPCHK(hipMemsetAsync(c->tcount, 0, 4, c->s));
     HIPCHK(hipMemsetAsync(c->epoch, 0, 4, c->s));
-    HIPCHK(hipMemsetAsync(c->nfall, 0, 4, c->s));
     const int nb = (int)cdiv(c->N, 256);
     for (void *f : {p->f_a, p->f_b}) {
         switch (p->prec) {
@@ -524,6 +520,8 @@ static StepArgs step_args(const lbm_ctx *c) {
     a.cls = c->cls;
     a.links = c->links;
     a.fibm = c->fibm;
+    a.facc = c->facc;
+    a.ftile = c->ftile;
     a.need = c->need;
     a.tneed = c->tneed;
     a.gfield = c->p.gfield;
@@ -689,7 +687,6 @@ static MarkArgs mark_args(const lbm_ctx *c, const ibm_mesh *m) {
     MarkArgs a{};
     a.tcount = c->tcount;
     a.epoch = c->epoch;
-    a.nfall = c->nfall;
     a.chans = c->chans;
     a.cell_chan = m->cell_chan;
     a.vert_off = m->vert_off;
@@ -1081,8 +1078,6 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.fibm = c->fibm;
     sp.facc = c->facc;
     sp.ftile = c->ftile;
-    sp.nfall = c->nfall;
-    sp.flist = c->flist;
     sp.epoch = c->epoch;
     sp.chans = c->chans;
     sp.cell_chan = m->cell_chan;
@@ -1090,16 +1085,6 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     sp.pmax = spread_pmax(m->max_cell_verts);
     sp.maxv = m->max_cell_verts;
     k_spread_cells<R><<<m->ncells, kSpreadThreads, spread_lds_bytes<R>(sp.pmax, sp.maxv), c->s>>>(sp);
-    FixupArgs fx{};
-    fx.flist = c->flist;
-    fx.nfall = c->nfall;
-    fx.need = c->need;
-    fx.ftile = c->ftile;
-    fx.fibm = c->fibm;
-    fx.facc = c->facc;
-    fx.chans = c->chans;
-    fx.tile_chan = c->tile_chan;
-    k_spread_fixup<R><<<(int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4), 256)), 256, 0, c->s>>>(fx);
 }
 
 // The immersed-boundary half of a coupled step with the populations f.
@@ -1338,6 +1323,17 @@ template <class S, class R, bool DEV>
 static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const double *x_n, const void *v_n,
                            const void *lam_next, void *lam, double *lam_x, double *lam_v, void *dgrad) {
     if (m) {
+        // the membrane Jacobian-vector product needs only X_n and the
+        // incoming adjoints: it runs on the side stream while the forward
+        // half is recomputed and the collide-stream pass is transposed, and
+        // the point pass waits for it
+        const hipStream_t user = c->s;
+        (void)hipEventRecord(c->ev_fork, user);
+        (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+        c->s = c->side;
+        launch_jvp<R>(c, m, x_n, nullptr, lam_x, lam_v, nullptr, c->hv);
+        (void)hipEventRecord(c->ev_join, c->side);
+        c->s = user;
         // recompute the forward immersed-boundary half of step n: stencil
         // marks, u_ext and rho at the marked nodes, the spread force
         ibm_mesh mm = *m;
@@ -1358,6 +1354,8 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     a.cls = c->cls;
     a.links = c->links;
     a.fibm = c->fibm;
+    a.facc = c->facc;
+    a.ftile = c->ftile;
     a.need = c->need;
     a.tneed = c->tneed;
     a.lamF = c->lamF;
@@ -1379,7 +1377,7 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     else
         k_adj_collide_stream<S, R, DEV, false><<<nb, 64 * sh.waves, 0, c->s>>>(a);
     if (!m) return;
-    launch_jvp<R>(c, m, x_n, nullptr, lam_x, lam_v, nullptr, c->hv);
+    (void)hipStreamWaitEvent(c->s, c->ev_join, 0);
     AdjPointArgs p{};
     p.ufield = c->ufield;
     p.lamF = c->lamF;
