@@ -34,6 +34,19 @@
 
 namespace lbm {
 
+// Two plain copies in one launch (4-byte words): elements [0, n0) of the
+// first pair, then [0, n1) of the second.
+__global__ __launch_bounds__(256) void k_copy_pair(const uint32_t *__restrict__ s0, uint32_t *__restrict__ d0,
+                                                   int64_t n0, const uint32_t *__restrict__ s1,
+                                                   uint32_t *__restrict__ d1, int64_t n1) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n0 + n1; i += (int64_t)gridDim.x * 256) {
+        if (i < n0)
+            d0[i] = s0[i];
+        else
+            d1[i - n0] = s1[i - n0];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // forward-mode dual numbers (value, directional derivative)
 

@@ -1340,8 +1340,12 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
         mm.x = c->xs;
         mm.v = c->vs;
         mm.f_el = c->fels;
-        enqueue_copy(c, c->xs, x_n, 3 * (size_t)m->nverts * 8);
-        enqueue_copy(c, c->vs, v_n, 3 * (size_t)m->nverts * sizeof(R));
+        {  // X_n and V_n into the scratch the recomputed step advances (one launch)
+            const int64_t n0 = 3 * (int64_t)m->nverts * 2, n1 = 3 * (int64_t)m->nverts * (int64_t)(sizeof(R) / 4);
+            k_copy_pair<<<(int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n0 + n1, 256), 4096)), 256, 0, c->s>>>(
+                reinterpret_cast<const uint32_t *>(x_n), reinterpret_cast<uint32_t *>(c->xs), n0,
+                static_cast<const uint32_t *>(v_n), static_cast<uint32_t *>(c->vs), n1);
+        }
         c->couples = 0;
         enqueue_couple(c, &mm, f_n, false);
     }
