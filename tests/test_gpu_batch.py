@@ -8,7 +8,8 @@ a captured HIP graph.
     gap sweep in the launch shape the benchmark times;
   - every replay of a captured graph equals the eager loop bitwise, with
     eager work and synchronisations between the replays, across a change of
-    state-buffer parity and of launch shape;
+    state-buffer parity and of launch shape, also when the captured steps run
+    the membrane kernels on the context's second stream;
   - each channel of an FP64 batch matches the FP64 oracle run on that
     channel alone;
   - the launch shape (tiles per workgroup, tile-list workgroups) does not
@@ -68,6 +69,13 @@ def test_batch_channels_equal_alone_bitwise(lbm):
     lat, mesh, cells, chan = _batch(lbm, scs)
     lat.run(30, mesh)
     fb, xb, vb = _state(lat, mesh)
+    # the membrane kernels beside the velocity pass: the same bits
+    lo, mo, _, _ = _batch(lbm, scs)
+    lo.set_ibm_overlap(1)
+    lo.run(30, mo)
+    fo, xo, vo = _state(lo, mo)
+    assert np.array_equal(fo, fb) and np.array_equal(xo, xb) and np.array_equal(vo, vb)
+    lo.close()
     for k, s in enumerate(scs):
         la, ma = _alone(lbm, s)
         la.run(30, ma)
@@ -85,6 +93,7 @@ def test_graph_replays_equal_eager(lbm):
     scs = _small_batch(seed=8)
     A, MA, _, _ = _batch(lbm, scs)
     B, MB, _, _ = _batch(lbm, scs)
+    B.set_ibm_overlap(1)  # the captured steps fork and join the second stream
     S_ = 4
     for r in range(4):
         A.run(S_, MA)
