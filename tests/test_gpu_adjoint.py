@@ -257,7 +257,8 @@ def test_coupled_run_leaves_final_state(lbm):
 
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_run_record_matches_plain_steps(lbm, use_graph):
-    """Recording steps (graph or not) gives bitwise the plain run's states:
+    """Recording steps (graph or not, with the membrane kernels on the
+    second stream) gives bitwise the plain run's states:
     record k equals the state after k steps on every fluid node (records
     after the first are written by the streaming pass, which never writes
     the slots of solid nodes, and nothing reads them), and the final state
@@ -268,6 +269,7 @@ def test_run_record_matches_plain_steps(lbm, use_graph):
     MA = lbm.Mesh(A, s.cells)
     B = lbm.Lattice.from_scenario(s, prec="f32dev")
     MB = lbm.Mesh(B, s.cells)
+    B.set_ibm_overlap(1)  # the recorded steps run the membrane on the second stream
     n = 6
     rec = B.record_buffers(n, MB)
     for rep in range(2):  # the second call replays the captured graph
