@@ -929,6 +929,13 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     for (int k = threadIdx.x; k < total; k += blockDim.x) {
         const int li = nodes[k];
         const int lx = li % bx_, ly = (li / bx_) % by_, lz = li / (bx_ * by_);
+        int gx = (rx + mx + lx) % ch.nx, gy = (ry + my + ly) % ch.ny, gz = (rz + mz + lz) % ch.nz;
+        gx += gx < 0 ? ch.nx : 0;
+        gy += gy < 0 ? ch.ny : 0;
+        gz += gz < 0 ? ch.nz : 0;
+        const uint32_t n = (uint32_t)(ch.noff + gx + (int64_t)ch.nx * (gy + (int64_t)ch.ny * gz));
+        // the claim goes out first, so that its round trip overlaps the sum
+        const uint32_t prev = atomicExch(&a.owner[n], epoch);
         R Fx = R(0), Fy = R(0), Fz = R(0);
 #pragma unroll 1
         for (int q = 0; q < 8; q++) {
@@ -952,12 +959,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
             Fy += Sy;
             Fz += Sz;
         }
-        int gx = (rx + mx + lx) % ch.nx, gy = (ry + my + ly) % ch.ny, gz = (rz + mz + lz) % ch.nz;
-        gx += gx < 0 ? ch.nx : 0;
-        gy += gy < 0 ? ch.ny : 0;
-        gz += gz < 0 ? ch.nz : 0;
-        const uint32_t n = (uint32_t)(ch.noff + gx + (int64_t)ch.nx * (gy + (int64_t)ch.ny * gz));
-        if (atomicExch(&a.owner[n], epoch) != epoch) {
+        if (prev != epoch) {
             if (a.accumulate) {
                 const R4 f = FI[n];
                 Fx = f.x + Fx;
