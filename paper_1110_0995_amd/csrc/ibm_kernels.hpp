@@ -854,41 +854,35 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         return;
     }
     const int bx_ = (int)Bx, by_ = (int)By, V = (int)(Bx * By * Bz);
-    // sort (box index of the base node, point)
-    int P = 64;
-    while (P < nv) P <<= 1;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        uint32_t k = 0xffffffffu;
+    const int nwords = (V + 31) / 32;
+    // Counting sort of the points by (box index of the base node, point).  A
+    // run of points with one base node is numbered by that node's rank among
+    // the set base bits; a point's place is its run's start plus the number
+    // of the run's points with a smaller index.
+    constexpr int kPer = kSpreadMaxPoints / kSpreadThreads;  // points per thread at most
+    int *cnt = reinterpret_cast<int *>(nodes + (a.maxv & 1));     // [maxv] points per run (the node list comes later)
+    uint16_t *memb = reinterpret_cast<uint16_t *>(cnt + a.maxv);  // [maxv] the runs' points, unordered
+    uint32_t lis[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        const int i = threadIdx.x + m * kSpreadThreads;
+        lis[m] = 0;
         if (i < nv) {
             int x, y, z;
             decode(SR[i].base, x, y, z);
-            const int li = (unwrap(x - rx, ch.nx) - mx) + bx_ * ((unwrap(y - ry, ch.ny) - my) + by_ * (unwrap(z - rz, ch.nz) - mz));
-            k = ((uint32_t)li << 11) | (uint32_t)i;
+            lis[m] = (uint32_t)((unwrap(x - rx, ch.nx) - mx) +
+                                bx_ * ((unwrap(y - ry, ch.ny) - my) + by_ * (unwrap(z - rz, ch.nz) - mz)));
         }
-        key[i] = k;
+        if (i < a.maxv) cnt[i] = 0;
     }
-    const int nwords = (V + 31) / 32;
     for (int i = threadIdx.x; i < nwords; i += blockDim.x) bbits[i] = bits[i] = 0;
     __syncthreads();
-    for (int kk = 2; kk <= P; kk <<= 1)
-        for (int j = kk >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < P; i += blockDim.x) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t ki = key[i], kl = key[l];
-                    if ((ki > kl) == ((i & kk) == 0)) {
-                        key[i] = kl;
-                        key[l] = ki;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    // base-node and stencil-node bitmaps; runs are in ascending box order, so
-    // a base node's run is its rank among the set base bits
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-        const uint32_t li = key[i] >> 11;
-        if (i == 0 || (key[i - 1] >> 11) != li) atomicOr(&bbits[li >> 5], 1u << (li & 31));
+    // base-node and stencil-node bitmaps
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        if (threadIdx.x + m * kSpreadThreads >= nv) continue;
+        const uint32_t li = lis[m];
+        atomicOr(&bbits[li >> 5], 1u << (li & 31));
         const int lx = (int)(li % bx_), ly = (int)((li / bx_) % by_), lz = (int)(li / (bx_ * by_));
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -897,18 +891,55 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         }
     }
     __syncthreads();
+    int nruns;
     {
         const int w = threadIdx.x;  // nwords <= kWords = blockDim.x
-        int tot;
-        const int pre = block_exclusive_scan(w < nwords ? __popc(bbits[w]) : 0, sc + 8, tot);
+        const int pre = block_exclusive_scan(w < nwords ? __popc(bbits[w]) : 0, sc + 8, nruns);
         if (w < nwords) wpre[w] = (uint16_t)pre;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-        const uint32_t li = key[i] >> 11;
-        if (i == 0 || (key[i - 1] >> 11) != li)
-            rstart[wpre[li >> 5] + __popc(bbits[li >> 5] & ((1u << (li & 31)) - 1u))] = (uint16_t)i;
+    int run[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; m++) {
+        run[m] = -1;
+        if (threadIdx.x + m * kSpreadThreads < nv) {
+            const uint32_t li = lis[m];
+            run[m] = wpre[li >> 5] + __popc(bbits[li >> 5] & ((1u << (li & 31)) - 1u));
+            atomicAdd(&cnt[run[m]], 1);
+        }
     }
+    __syncthreads();
+    {
+        // run starts: exclusive scan of the counts, kPer consecutive runs per thread
+        const int r0 = threadIdx.x * kPer;
+        int c4[kPer], sum = 0;
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            c4[m] = r0 + m < nruns ? cnt[r0 + m] : 0;
+            sum += c4[m];
+        }
+        int tot;
+        int pre = block_exclusive_scan(sum, sc + 8, tot);
+#pragma unroll
+        for (int m = 0; m < kPer; m++) {
+            if (r0 + m < nruns) rstart[r0 + m] = (uint16_t)pre;
+            pre += c4[m];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPer; m++)
+        if (run[m] >= 0) memb[rstart[run[m]] + atomicSub(&cnt[run[m]], 1) - 1] = (uint16_t)(threadIdx.x + m * kSpreadThreads);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < kPer; m++)
+        if (run[m] >= 0) {
+            const int i = threadIdx.x + m * kSpreadThreads, r = run[m];
+            const int s0 = rstart[r], s1 = r + 1 < nruns ? (int)rstart[r + 1] : nv;
+            int rank = 0;
+            for (int j = s0; j < s1; j++) rank += memb[j] < i;
+            key[s0 + rank] = (lis[m] << 11) | (uint32_t)i;
+        }
     __syncthreads();
     // node list (box indices, ascending)
     int total = 0;
