@@ -145,14 +145,21 @@ __device__ __forceinline__ void start_marks(const MarkArgs &a) {
 }
 
 // The stencil marks of every point (positions of this step) on their own:
-// one thread per point, blockIdx.y = cell.  Independent of the membrane
+// one thread per point (cell and chunk from the workgroup index as below).  Independent of the membrane
 // forces, so the velocity pass that reads the marks can run beside the
 // membrane kernel.
+// Workgroups go to the 8 XCDs round-robin by index; the mapping below keeps
+// all nb chunks of a cell on one XCD, so that the cell's partially written
+// mark lines are dirty in one L2 only: workgroup L takes cell
+// 8 (L / 8nb) + L % 8 and chunk (L / 8) % nb (grid: nb * ncells rounded up
+// to 8).
 template <class R>
-__global__ __launch_bounds__(128) void k_mark(MarkArgs a) {
-    const int c = blockIdx.y;
-    if (c == 0 && blockIdx.x == 0 && threadIdx.x == 0) start_marks(a);
-    const int v0 = a.vert_off[c], k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(128) void k_mark(MarkArgs a, int nb) {
+    const int L = blockIdx.x;
+    const int c = (L / (8 * nb)) * 8 + (L & 7), chunk = (L >> 3) % nb;
+    if (L == 0 && threadIdx.x == 0) start_marks(a);
+    if (c >= a.ncells) return;
+    const int v0 = a.vert_off[c], k = chunk * blockDim.x + threadIdx.x;
     if (k >= a.vert_off[c + 1] - v0) return;
     const int NV = a.nverts;
     mark_stencil<R>(a, a.chans[cell_channel(a.cell_chan, c)], a.anchor[c], a.anchor[a.ncells + c],

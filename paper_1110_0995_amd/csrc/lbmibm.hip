@@ -747,7 +747,8 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest, bool mark 
 // and claim epoch reset for the step).
 template <class R>
 static void launch_mark(lbm_ctx *c, const ibm_mesh *m) {
-    k_mark<R><<<dim3((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells), 128, 0, c->s>>>(mark_args(c, m));
+    const int nb = (int)cdiv(m->max_cell_verts, 128);
+    k_mark<R><<<(unsigned)(nb * cdiv(m->ncells, 8) * 8), 128, 0, c->s>>>(mark_args(c, m), nb);
 }
 
 // Sort the fixed contact spheres into a uniform grid over the lattice (one
