@@ -148,15 +148,21 @@ __device__ __forceinline__ void start_marks(const MarkArgs &a) {
 // one thread per point (cell and chunk from the workgroup index as below).  Independent of the membrane
 // forces, so the velocity pass that reads the marks can run beside the
 // membrane kernel.
-// Workgroups go to the 8 XCDs round-robin by index; the mapping below keeps
-// all nb chunks of a cell on one XCD, so that the cell's partially written
-// mark lines are dirty in one L2 only: workgroup L takes cell
-// 8 (L / 8nb) + L % 8 and chunk (L / 8) % nb (grid: nb * ncells rounded up
-// to 8).
+// Workgroups go to the 8 XCDs round-robin by index.  For the per-point
+// kernels this mapping keeps all nb chunks of a cell on one XCD, so that
+// the lines the cell's points share (partially written marks, gathered
+// velocities) live in one L2: workgroup L takes cell 8 (L / 8nb) + L % 8
+// and chunk (L / 8) % nb (grid: nb * ncells rounded up to 8).
+__device__ __forceinline__ void xcd_cell_chunk(int L, int nb, int &c, int &chunk) {
+    c = (L / (8 * nb)) * 8 + (L & 7);
+    chunk = (L >> 3) % nb;
+}
+
 template <class R>
 __global__ __launch_bounds__(128) void k_mark(MarkArgs a, int nb) {
     const int L = blockIdx.x;
-    const int c = (L / (8 * nb)) * 8 + (L & 7), chunk = (L >> 3) % nb;
+    int c, chunk;
+    xcd_cell_chunk(L, nb, c, chunk);
     if (L == 0 && threadIdx.x == 0) start_marks(a);
     if (c >= a.ncells) return;
     const int v0 = a.vert_off[c], k = chunk * blockDim.x + threadIdx.x;
@@ -625,14 +631,17 @@ struct CoupleArgs {
     int ncells, nverts;
     double xi, dt_over_m, dt;
     WallContact wall;  // nplanes = ncyl = 0: no wall contact forces
+    int nb;            // point chunks of 128 per cell (workgroup mapping as for k_mark)
 };
 
 template <class R>
 __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     using R4 = typename Vec4<R>::T;
-    const int c = blockIdx.y;
+    int c, chunk;
+    xcd_cell_chunk(blockIdx.x, a.nb, c, chunk);
+    if (c >= a.ncells) return;
     const int vb = a.vert_off[c], ve = a.vert_off[c + 1];
-    const int k = vb + blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = vb + chunk * blockDim.x + threadIdx.x;
     if (k >= ve) return;
     const int NV = a.nverts;
     double *X = a.x;

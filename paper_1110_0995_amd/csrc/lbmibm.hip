@@ -1070,8 +1070,8 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
             }
         }
     }
-    dim3 grid((unsigned)cdiv(m->max_cell_verts, 128), (unsigned)m->ncells);
-    k_couple<R><<<grid, 128, 0, c->s>>>(a);
+    a.nb = (int)cdiv(m->max_cell_verts, 128);
+    k_couple<R><<<(unsigned)(a.nb * cdiv(m->ncells, 8) * 8), 128, 0, c->s>>>(a);
     SpreadArgs sp{};
     sp.vert_off = m->vert_off;
     sp.srec = c->srec;
