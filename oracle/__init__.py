@@ -20,8 +20,13 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
+# ORACLE_SANITIZE=1 selects a build with AddressSanitizer and
+# UndefinedBehaviorSanitizer (host code only; load it with libasan preloaded)
+_SANITIZE = os.environ.get("ORACLE_SANITIZE") == "1"
+_SO = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
+_SAN_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+              "-fno-sanitize-recover=undefined"]
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int)
@@ -30,7 +35,8 @@ _ip = C.POINTER(C.c_int)
 def build(force: bool = False) -> str:
     """Compile oracle.c into liboracle.so (gcc, -O2, OpenMP, no contraction)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+        opt = _SAN_FLAGS if _SANITIZE else ["-O2"]
+        cmd = ["gcc", *opt, "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
                "-shared", "-fPIC", "-o", _SO + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_SO + ".tmp", _SO)
@@ -74,6 +80,7 @@ def lib():
         L.orc_dipole_energy.restype = C.c_double
         L.orc_step.restype = C.c_int
         L.orc_run.restype = C.c_int
+        L.orc_objective.restype = C.c_double
         _lib = L
     return _lib
 
@@ -291,6 +298,15 @@ def run(L: Lattice, M: Optional[Mesh], f: np.ndarray, X=None, V=None, nsteps: in
     if rc:
         raise MemoryError("orc_run failed")
     return f
+
+
+def objective(L: Lattice, M: Optional[Mesh], f: np.ndarray, X=None, X0=None) -> float:
+    """Outflow through the plane x = nx-1 (sum of j_x + (g_x + G_x)/2 over
+    its fluid nodes) plus each cell's squared centroid displacement X vs X0."""
+    if M is None:
+        return lib().orc_objective(C.byref(L.s), None, _d(f), _dp(), _dp())
+    return lib().orc_objective(C.byref(L.s), C.byref(M.s), _d(f), _d(np.ascontiguousarray(X, np.float64)),
+                               _d(np.ascontiguousarray(X0, np.float64)))
 
 
 # ---------------------------------------------------------------------------

@@ -749,6 +749,41 @@ int orc_run(const orc_lattice *L, const orc_mesh *M, double *f, double *X, doubl
     return 0;
 }
 
+/* Objective of the differentiation workload (the paper has none; reading):
+ * the outflow through the last x plane, sum over its fluid nodes of
+ * j_x + (g_x + G_x)/2 (the x-momentum carried by the populations f, with
+ * the half-force shift of the velocity), plus for every cell of M the
+ * squared distance between the vertex centroid of X and that of X0 (both
+ * [nv][3] absolute positions).  M may be NULL (no cell term). */
+double orc_objective(const orc_lattice *L, const orc_mesh *M, const double *f, const double *X, const double *X0) {
+    long N = nnodes(L);
+    ksum J = {0, 0};
+    for (int z = 0; z < L->nz; z++)
+        for (int y = 0; y < L->ny; y++) {
+            long n = (L->nx - 1) + (long)L->nx * (y + (long)L->ny * z);
+            if (L->solid[n]) continue;
+            double jx = 0.0;
+            for (int i = 0; i < Q; i++) jx += f[i * N + n] * CX[i];
+            kadd(&J, jx + 0.5 * (L->g[0] + (L->G ? L->G[n] : 0.0)));
+        }
+    if (M)
+        for (int c = 0; c < M->ncells; c++) {
+            int a = M->vert_off[c], b = M->vert_off[c + 1];
+            double d2 = 0.0;
+            for (int d = 0; d < 3; d++) {
+                double s1 = 0.0, s0 = 0.0;
+                for (int k = a; k < b; k++) {
+                    s1 += X[3 * k + d];
+                    s0 += X0[3 * k + d];
+                }
+                double dd = (s1 - s0) / (b - a);
+                d2 += dd * dd;
+            }
+            kadd(&J, d2);
+        }
+    return J.s + J.c;
+}
+
 /* ------------------------------------------------------------------------ */
 /* magnetic bead stage (the chain-forming part of the filter, Sec. 2.5)      */
 /* ------------------------------------------------------------------------ */

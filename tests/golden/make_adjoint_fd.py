@@ -11,7 +11,8 @@ nodes of the plane x = 127 at step 300, plus the squared displacement of
 each cell's vertex centroid.
 The derivative along unit direction d is (J(eps d) - J(-eps d)) / (2 eps)
 at G = 0; two directions are repeated at 2 eps to show the truncation error
-is negligible.  Only the oracle and the seeded input generator are used.
+is negligible.  Every value comes from the oracle (its stepper and its
+objective); the seeded input generator supplies the workload.
 
 Run from the repository root:  python tests/golden/make_adjoint_fd.py
 """
@@ -30,21 +31,6 @@ from paper_1110_0995_amd import scenario as S  # noqa: E402
 
 EPS = 1e-4
 NDIR = 16
-CX = np.array([0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0], np.float64)
-
-
-def objective(s, f, G, X, X0):
-    nx, ny, nz = s.nx, s.ny, s.nz
-    idx = np.arange(ny * nz) * nx + (nx - 1)
-    idx = idx[s.solid.reshape(-1)[idx] == 0]
-    Gx = G.reshape(3, -1)[0, idx]
-    J = float(((CX[:, None] * f[:, idx]).sum(0) + 0.5 * (s.g[0] + Gx)).sum())
-    off = s.cells.vert_off
-    for c in range(len(off) - 1):
-        a, b = int(off[c]), int(off[c + 1])
-        d = X[a:b].mean(0) - X0[a:b].mean(0)
-        J += float(d @ d)
-    return J
 
 
 def run(s, G):
@@ -55,7 +41,7 @@ def run(s, G):
     M.rest_shape(X)
     V = np.zeros_like(X)
     f = oracle.run(L, M, L.rest(), X, V, nsteps=s.steps)
-    return objective(s, f, G, X, X0)
+    return oracle.objective(L, M, f, X, X0)
 
 
 def embed(s, d):
