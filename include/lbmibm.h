@@ -213,7 +213,10 @@ int lbm_set_ibm_overlap(lbm_ctx *c, int32_t mode);
  * captured again when the mesh (its buffers, xi, mass or dt), the group
  * length, the launch shape or the parity of the state buffer changes.
  * Graph and ordinary launches run the same kernels on the same data, so
- * the results are bitwise those of the eager loop. */
+ * the results are bitwise those of the eager loop.  When a mesh was
+ * coupled (ibm_couple) before the call, its spread force is still pending:
+ * the first step then runs as ordinary launches, adding m's force to it as
+ * the eager loop does, and the graph groups follow. */
 int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps_per_graph);
 
 /* Advance the lattice nsteps >= 0 times: fused BGK collision with Guo

@@ -1203,7 +1203,15 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
         if (int rc = check_mesh_ready(c, m)) return rc;
     }
     int32_t left = nsteps;
-    if (steps_per_graph > 0 && nsteps >= steps_per_graph) {
+    if (c->couples > 0 && left > 0 && steps_per_graph > 0) {
+        // a mesh coupled before this call left its spread force pending: the
+        // first step adds to it (every captured step starts from none), so it
+        // runs as ordinary launches
+        if (m) enqueue_couple(c, m);
+        enqueue_steps(c, 1);
+        left--;
+    }
+    if (steps_per_graph > 0 && left >= steps_per_graph) {
         Fnv key;
         key.mix(G_RUN);
         key.mix((uint64_t)steps_per_graph);
@@ -1500,6 +1508,7 @@ LBM_API int lbm_run_record(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, void *
         key.mix(G_REC);
         key.mix((uint64_t)nsteps);
         key.mix((uint64_t)c->cur);
+        key.mix((uint64_t)(c->couples > 0));  // baked into the first step's spread, as in lbm_run
         key.mix(mesh_launch_key(m));
         for (const void *p : {(const void *)f_rec, (const void *)x_rec, (const void *)v_rec}) key.mix((uint64_t)(uintptr_t)p);
         if (int rc = capture_slot(c, G_REC, key.h | 1ull, enqueue)) return rc;
@@ -1507,6 +1516,7 @@ LBM_API int lbm_run_record(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, void *
     } else {
         enqueue();
     }
+    c->couples = 0;  // the last recorded step consumed every spread force
     c->steps += nsteps;
     HIPCHK(hipGetLastError());
     return LBM_OK;

@@ -1,7 +1,7 @@
 """GPU parity of the coupled LBM + immersed-boundary step against the FP64
 oracle, through the C ABI: FP64 to rounding on small cases, FP32 deviation
-storage within 1e-5 relative velocity error after 1000 steps, and the
-posts-and-cells / throughput workloads at full size."""
+storage within 1e-5 relative velocity error after 1000 steps (the
+full-size workloads over long horizons are in test_gpu_long_parity.py)."""
 import time
 
 import numpy as np
@@ -148,43 +148,6 @@ def test_f32dev_1000_steps_small_posts_cells(orc, lbm):
           f"(oracle {time.time() - t:.1f}s)")
     assert err < 1e-5
     assert perr < 1e-4
-
-
-def test_posts_cells_full_size(orc, lbm):
-    """256x128x64 with 4x2 posts and 20 cells of 642 vertices (tau 0.8,
-    g 1e-5): FP32 deviation storage vs the oracle after 20 coupled steps."""
-    s = S.posts_and_cells()
-    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f32dev")
-    f = L.rest()
-    orc.run(L, M, f, X, V, nsteps=20)
-    lat.run(20, mesh)
-    fl = s.solid.reshape(-1) == 0
-    _, uo = orc.fluid_velocity(L, f)
-    _, ug = lat.fields()
-    err = rel_l2(ug.double().cpu().numpy(), uo, fl)
-    print(f"posts_cells full size, 20 steps: u rel L2 {err:.3e}")
-    assert err < 1e-5
-    assert np.abs(mesh.positions() - X).max() < 1e-5
-    mo = orc.mass_momentum(L, f)
-    mg = lat.sums()
-    assert abs(mg[0] - mo[0]) / mo[0] < 1e-10
-
-
-def test_throughput_workload_full_size(orc, lbm):
-    """512x256x128, 8x4 posts, 400 cells (the timed workload, in the launch
-    configuration the benchmark uses): 5 coupled steps vs the oracle."""
-    s = S.throughput()
-    lat, mesh, L, M, X, V = _pair(orc, lbm, s, "f32dev")
-    f = L.rest()
-    orc.run(L, M, f, X, V, nsteps=5)
-    lat.run(5, mesh)
-    fl = s.solid.reshape(-1) == 0
-    _, uo = orc.fluid_velocity(L, f)
-    _, ug = lat.fields()
-    err = rel_l2(ug.double().cpu().numpy(), uo, fl)
-    print(f"throughput full size, 5 steps: u rel L2 {err:.3e}")
-    assert err < 1e-5
-    assert np.abs(mesh.positions() - X).max() < 1e-5
 
 
 def test_two_meshes_in_one_step(orc, lbm):
@@ -414,3 +377,47 @@ def test_couple_requires_rest_shape(lbm):
     with pytest.raises(_lib.LbmError) as e:
         lat.couple(mesh)
     assert e.value.code == _lib.LBM_ESTATE
+
+
+def test_graphs_after_a_pending_couple_f64(lbm):
+    """ibm_couple(A) followed by a graph-replayed lbm_run(B) or a graphed
+    lbm_run_record(B): the first step adds B's spread force to A's at the
+    stencil nodes both share, exactly as the eager couple(A), couple(B),
+    step does, also when a graph for B alone was captured before."""
+    nx, ny, nz = 32, 24, 20
+    cen = np.array([[12.2, 11.7, 9.6], [14.9, 12.3, 10.1]])
+    mod = (0.01, 0.002, 0.005, 0.05, 0.2)
+    a, b = S.make_cells(cen[:1], 3.0, 2, moduli=mod), S.make_cells(cen[1:], 3.0, 2, moduli=mod)
+    s = S.Scenario("pending", nx, ny, nz, 0.8, (1e-4, 0, 0), S.channel_mask(nx, ny, nz), 10,
+                   cells=S.make_cells(cen, 3.0, 2, moduli=mod))
+
+    def go(graph):
+        lat = lbm.Lattice.from_scenario(s, prec="f64")
+        ma, mb = lbm.Mesh(lat, a), lbm.Mesh(lat, b)
+
+        def run_b(n):
+            if graph:
+                lat.run(n, mb, steps_per_graph=2)
+            else:
+                for _ in range(n):
+                    lat.couple(mb)
+                    lat.step(1)
+
+        run_b(4)            # captures B's graph with nothing pending
+        lat.couple(ma)
+        run_b(5)            # A pending before the first step
+        lat.couple(ma)
+        run_b(4)
+        run_b(4)            # nothing pending again
+        rec = lat.record_buffers(2, mb)
+        for pending in (False, True):
+            if pending:
+                lat.couple(ma)
+            lat.run_record(2, mb, rec, use_graph=graph)
+        out = (lat.populations_f64().cpu().numpy(), ma.positions(), mb.positions(), mb.velocities())
+        lat.close()
+        return out
+
+    eager, graphed = go(False), go(True)
+    for u, w in zip(eager, graphed):
+        assert np.array_equal(u, w)
