@@ -448,6 +448,8 @@ def main():
                     help="coupled steps of the staged filter run through frozen bead chains (0 skips the leg)")
     ap.add_argument("--red-cells-steps", type=int, default=100,
                     help="coupled steps of the red-cell suspension, neo-Hookean and linear (0 skips the leg)")
+    ap.add_argument("--node-records", type=int, default=0, choices=(0, 1),
+                    help="1: stencil-node velocities from the records of the collide-stream pass; 0: the lattice gather")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one 1 GiB device copy (reference kernel for HBM counter scaling)")
     args = ap.parse_args()
@@ -461,6 +463,7 @@ def main():
 
     s, prec = make_workload(args.workload)
     lat = lbm.Lattice.from_scenario(s, prec=prec)
+    lat.set_node_records(args.node_records)
     mesh = lbm.Mesh(lat, s.cells) if s.cells is not None else None
     stream = torch.cuda.current_stream()
 

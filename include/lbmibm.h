@@ -31,6 +31,13 @@
  *     (-1,-1,0); 9,10 = (1,-1,0),(-1,1,0); 11,12 = (1,0,1),(-1,0,-1);
  *     13,14 = (1,0,-1),(-1,0,1); 15,16 = (0,1,1),(0,-1,-1);
  *     17,18 = (0,1,-1),(0,-1,1).  Odd i and i+1 are opposite.
+ *     Population i of a fluid node n lies in slot (i, n), except when the
+ *     neighbour n - c_i is a solid node: then the population (the one n
+ *     sent towards that neighbour in the step before, returned by halfway
+ *     bounce-back) lies in slot (opp(i), n - c_i) of the solid node, where
+ *     the streaming put it.  Solid nodes hold no populations of their own
+ *     (their other slots carry rest values).  lbm_store_f64 / lbm_load_f64
+ *     convert to and from plain per-node populations.
  *   - Precision LBM_F64: double populations and arithmetic.  LBM_F32: float
  *     f_i.  LBM_F32_DEV: float deviations h_i = f_i - w_i from the rest
  *     weights, float arithmetic.  Global mass/momentum sums are double in
@@ -205,6 +212,27 @@ int lbm_set_launch(lbm_ctx *c, int32_t collide_waves_per_block, int32_t list_blo
 #define LBM_OVERLAP_MIN_POINTS 16384
 int lbm_set_ibm_overlap(lbm_ctx *c, int32_t mode);
 
+/* Where a coupled step takes the fluid velocity at the stencil nodes from
+ * (Sec. 2.2 step 1; results unchanged, bitwise).  mode = 1: every
+ * ibm_couple marks the stencils of the points' new positions, and the next
+ * collide-stream pass (lbm_step) copies the populations it streams into
+ * those nodes into a record, from which the next ibm_couple reads them; a
+ * stencil node the record lacks (for instance after the caller moved the
+ * points) sends that step through the lattice gather.  mode = 0 (the
+ * default): always the gather.  The records need every channel's nx to be a multiple of 64
+ * (otherwise the gather is always used); they take 19 reals and 4 bytes per
+ * slot, min(N, 8 x the IB points of the meshes given to ibm_rest_shape)
+ * slots, allocated by ibm_rest_shape.  Drops a captured graph; LBM_EINVAL
+ * for another mode. */
+int lbm_set_node_records(lbm_ctx *c, int32_t mode);
+
+/* How the last ibm_couple on c found the stencil velocities: *used = 1 if it
+ * read the records of the pass before it, *missed = 1 if a stencil node
+ * was not among them (that step then gathered from the lattice).  Valid
+ * until the next lbm_step; waits on the stream.  Either pointer may be
+ * NULL. */
+int lbm_node_records_used(lbm_ctx *c, int32_t *used, int32_t *missed);
+
 /* nsteps >= 0 coupled steps: for each, ibm_couple(c, m) (skipped when m is
  * NULL) then lbm_step(c, 1).  With steps_per_graph > 0 (even, at most
  * 4096) the steps are taken in groups of steps_per_graph, captured once into
@@ -258,7 +286,9 @@ int lbm_read_fields(lbm_ctx *c, void *rho, void *u, double *host_sums);
 int lbm_current(lbm_ctx *c, void **f_cur, int64_t *steps);
 
 /* Copy the current state to / from full FP64 populations f_i ([19][N]
- * double, device) -- adds / subtracts w_i in LBM_F32_DEV. */
+ * double, device, plain per-node layout) -- adds / subtracts w_i in
+ * LBM_F32_DEV.  Solid nodes read as their rest weights w_i and are ignored
+ * when loading. */
 int lbm_store_f64(lbm_ctx *c, double *f64);
 int lbm_load_f64(lbm_ctx *c, const double *f64);
 
@@ -304,8 +334,7 @@ int lbm_adjoint_step(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const doubl
  * v_rec [nsteps][3][nverts] real (ignored when m is NULL).  Step k reads its
  * populations from record k and writes record k+1 (the last step writes the
  * context's current state buffer, so lbm_current does not change), so
- * recording costs one copy of the state per call, not per step.  Only fluid
- * nodes' entries of records 1.. are written.  use_graph != 0 captures the
+ * recording costs one copy of the state per call, not per step.  use_graph != 0 captures the
  * whole call into a HIP graph (reused while the arguments, the mesh and the
  * state-buffer parity are the same) and replays it. */
 int lbm_run_record(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, void *f_rec, double *x_rec, void *v_rec,

@@ -38,7 +38,9 @@ def _restore(lat, mesh, snap):
 
 
 class CoupledRun(torch.autograd.Function):
-    """(f_T [19, N], x_T [3, nv], v_T [3, nv]) = run(G; initial state)."""
+    """(f_T [19, N], x_T [3, nv], v_T [3, nv]) = run(G; initial state), with
+    f_T the full FP64 populations of every node (per-node layout, as the
+    adjoint of the populations is kept)."""
 
     @staticmethod
     def forward(ctx, G, lat, mesh, nsteps: int, every: int = 20):
@@ -56,7 +58,7 @@ class CoupledRun(torch.autograd.Function):
         ctx.ckpts = ckpts
         ctx.final = _snapshot(lat, mesh)
         ctx.G_shape, ctx.G_dtype = G.shape, G.dtype
-        fT = lat.current().clone()
+        fT = lat.populations_f64()  # per-node populations (the storage keeps bounced ones in solid slots)
         if mesh is None:
             z = torch.zeros(3, 0, dtype=torch.float64, device=lat.device)
             return fT, z, z.clone()

@@ -109,6 +109,7 @@ struct AdjStepArgs {
     int64_t N;
     double g[3];
     double omega, kf;
+    int per[3];  // periodic axes (where f_n keeps its bounced populations, see pop_slot)
 };
 
 template <class S, class R, bool DEV, bool HAS_G>
@@ -165,9 +166,11 @@ __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
         return;
     }
     const S *f = static_cast<const S *>(a.f);
+    const int y = row % ch.ny, z = row / ch.ny;
+    const uint32_t links = a.cls[n] == CLS_WALL ? a.links[n] : 0u;
     R v[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) v[i] = R(f[i * st + n]);
+    for (int i = 0; i < Q; i++) v[i] = R(f[links ? pop_slot<int64_t>(i, n, links, x, y, z, ch, st, a.per) : i * st + n]);
     R s = R(0);
 #pragma unroll
     for (int i = 0; i < Q; i++) s += v[i];
@@ -179,12 +182,11 @@ __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
     const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
     const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
 
-    // lambda* pulled from where the forward pushed population i
-    const int y = row % ch.ny, z = row / ch.ny;
+    // lambda* pulled from where population i goes (lambda is kept per node
+    // and direction: a bounced population is population opp(i) of the node)
     const int xp = (x + 1 == ch.nx) ? 0 : x + 1, xm = (x == 0) ? ch.nx - 1 : x - 1;
     const int yp = (y + 1 == ch.ny) ? 0 : y + 1, ym = (y == 0) ? ch.ny - 1 : y - 1;
     const int zp = (z + 1 == ch.nz) ? 0 : z + 1, zm = (z == 0) ? ch.nz - 1 : z - 1;
-    const uint32_t links = a.cls[n] == CLS_WALL ? a.links[n] : 0u;
     const R *LN = static_cast<const R *>(a.lam_next);
     R ls[Q];
 #pragma unroll

@@ -26,9 +26,12 @@
 //   evaluated once however many IB points use it.
 //
 // k_couple (one thread per IB point): trilinear interpolation of that field
-//   (Sec. 2.2 step 1), coupling force (step 2), and the point update (step
-//   4).  The point also writes a spread record: its stencil's base node,
-//   fractional offsets and the force it exerts on the fluid (-F_c).
+//   (Sec. 2.2 step 1) and the coupling force (step 2), written into a spread
+//   record: the stencil's base node, fractional offsets and the force the
+//   point exerts on the fluid (-F_c).
+//
+// k_move (one thread per IB point, after the spread and the membrane
+//   kernel): the point update (step 4) with the membrane force and F_c.
 //
 // Spreading (step 3) avoids per-contribution float atomics, which run at a
 // small fraction of store throughput on this GPU:
@@ -102,6 +105,11 @@ struct MarkArgs {
     uint8_t *tneed;  // [ntiles] tile marks
     void *fibm;      // [N] Vec4 spread force: zeroed at newly marked nodes when `accumulate`
     int accumulate;  // 1: another membrane was coupled earlier in this step (its force stays)
+    // stencil nodes whose populations the last collide-stream pass recorded
+    // (bit x & 63 of word tile); a marked node outside them sets *miss.
+    // Null when the step does not use the records.
+    const uint4 *cover;  // RecTile entries (mask in x, y)
+    uint32_t *miss;
 };
 
 // Mark the 2x2x2 stencil of a point at offset (px, py, pz) from anchor
@@ -132,8 +140,13 @@ __device__ __forceinline__ void mark_stencil(const MarkArgs &a, const Chan &ch, 
             } else {
                 a.need[nn] = 1;
             }
+            const int64_t tile = ch.toff + (int64_t)row * ch.tpr + (xs[e] >> 6);
+            if (a.cover) {
+                const uint4 ce = a.cover[tile];
+                if (!((((uint64_t)ce.y << 32 | ce.x) >> (xs[e] & 63)) & 1ull)) *a.miss = 1u;
+            }
             // the two x of a row share a tile unless the pair crosses a tile edge
-            if (e == 0 || (xs[1] >> 6) != (xs[0] >> 6)) a.tneed[ch.toff + (int64_t)row * ch.tpr + (xs[e] >> 6)] = 1;
+            if (e == 0 || (xs[1] >> 6) != (xs[0] >> 6)) a.tneed[tile] = 1;
         }
     }
 }
@@ -398,10 +411,14 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
 // one 16-byte load; the block scans its counts and reserves its slots with a
 // single atomic, so the list length costs one atomic per 4096 tiles.
 constexpr int kCompactThreads = 256, kCompactPerThread = 16;
+// With `gate`, nothing is listed unless *gate is non-zero (a step whose
+// velocities come from records lists tiles only when a node was missed).
 __global__ __launch_bounds__(kCompactThreads) void k_compact(const uint8_t *__restrict__ tneed, int ntiles,
-                                                             uint32_t *__restrict__ tlist, uint32_t *tcount) {
+                                                             uint32_t *__restrict__ tlist, uint32_t *tcount,
+                                                             const uint32_t *gate) {
     __shared__ uint32_t wsum[kCompactThreads / 64];
     __shared__ uint32_t base_s;
+    if (gate && *gate == 0u) return;
     const int t0 = (blockIdx.x * kCompactThreads + threadIdx.x) * kCompactPerThread;
     uint32_t bits = 0;  // bit j: tile t0 + j is marked
     if (t0 + kCompactPerThread <= ntiles) {
@@ -445,6 +462,8 @@ struct NodeVelArgs {
     const void *f;
     int64_t stride;
     const uint8_t *cls;
+    const uint32_t *links;
+    int per[3];
     const void *gfield;
     void *ufield;  // [N] Vec4
     const uint8_t *need;
@@ -455,6 +474,30 @@ struct NodeVelArgs {
     int64_t N;
     double g[3];
 };
+
+// u_ext = (j + F_ext/2)/rho and rho of a fluid node from its 19
+// populations v (deviations in DEV), F_ext = g + G(n).  Both velocity passes
+// use this one sequence of operations, so they give the same bits.
+template <class R, bool DEV, bool HAS_G>
+__device__ __forceinline__ typename Vec4<R>::T node_u(const R (&v)[Q], const double (&g)[3], const void *gfield,
+                                                      int64_t N, int64_t n) {
+    R s = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; i++) s += v[i];
+    const R jx = (v[1] - v[2]) + (v[7] - v[8]) + (v[9] - v[10]) + (v[11] - v[12]) + (v[13] - v[14]);
+    const R jy = (v[3] - v[4]) + (v[7] - v[8]) + (v[10] - v[9]) + (v[15] - v[16]) + (v[17] - v[18]);
+    const R jz = (v[5] - v[6]) + (v[11] - v[12]) + (v[14] - v[13]) + (v[15] - v[16]) + (v[18] - v[17]);
+    R Fx = R(g[0]), Fy = R(g[1]), Fz = R(g[2]);
+    if (HAS_G) {
+        const R *G = static_cast<const R *>(gfield);
+        Fx += G[n];
+        Fy += G[N + n];
+        Fz += G[2 * N + n];
+    }
+    const R rho = DEV ? R(1) + s : s;
+    const R ir = R(1) / rho;
+    return typename Vec4<R>::T{(jx + R(0.5) * Fx) * ir, (jy + R(0.5) * Fy) * ir, (jz + R(0.5) * Fz) * ir, rho};
+}
 
 // u_ext of the marked nodes of every listed tile.  A fixed grid of waves
 // strides over the list (its length is only known on the device).
@@ -474,31 +517,148 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
         if (x >= ch.nx) continue;
         const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
         if (!a.need[n]) continue;
-        R ux = R(0), uy = R(0), uz = R(0), rho = R(0);
-        if (a.cls[n] != CLS_SOLID) {
+        R4 u = R4{R(0), R(0), R(0), R(0)};
+        const uint8_t cl = a.cls[n];
+        if (cl != CLS_SOLID) {
+            const uint32_t lk = cl == CLS_WALL ? a.links[n] : 0u;
+            const int y = row % ch.ny, z = row / ch.ny;
             R v[Q];
 #pragma unroll
-            for (int i = 0; i < Q; i++) v[i] = R(f[i * a.stride + n]);
-            R s = R(0);
-#pragma unroll
-            for (int i = 0; i < Q; i++) s += v[i];
-            const R jx = (v[1] - v[2]) + (v[7] - v[8]) + (v[9] - v[10]) + (v[11] - v[12]) + (v[13] - v[14]);
-            const R jy = (v[3] - v[4]) + (v[7] - v[8]) + (v[10] - v[9]) + (v[15] - v[16]) + (v[17] - v[18]);
-            const R jz = (v[5] - v[6]) + (v[11] - v[12]) + (v[14] - v[13]) + (v[15] - v[16]) + (v[18] - v[17]);
-            R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
-            if (HAS_G) {
-                const R *G = static_cast<const R *>(a.gfield);
-                Fx += G[n];
-                Fy += G[a.N + n];
-                Fz += G[2 * a.N + n];
-            }
-            rho = DEV ? R(1) + s : s;
-            const R ir = R(1) / rho;
-            ux = (jx + R(0.5) * Fx) * ir;
-            uy = (jy + R(0.5) * Fy) * ir;
-            uz = (jz + R(0.5) * Fz) * ir;
+            for (int i = 0; i < Q; i++)
+                v[i] = R(f[lk ? pop_slot<int64_t>(i, n, lk, x, y, z, ch, a.stride, a.per) : i * a.stride + n]);
+            u = node_u<R, DEV, HAS_G>(v, a.g, a.gfield, a.N, n);
         }
-        U[n] = R4{ux, uy, uz, rho};
+        U[n] = u;
+    }
+}
+
+// Records of the next step's stencil nodes.  The point update marks the
+// stencil of every point's new position (nx_need, nx_tneed); before the
+// collide-stream pass, k_next_list turns the marks into one entry per tile
+// (RecTile: a 64-bit mask, bit x & 63 set for a marked node, and the first
+// slot of the tile's range; slots are numbered in bit order)
+// and lists each slot's node; the pass then writes, beside every
+// population it streams into a marked node, a copy into the record
+// rec[i * cap + slot].  The next step's velocity pass reads a marked node's
+// 19 populations there, 64 consecutive slots per wave, instead of the 19
+// planes of the lattice (whole lines of every plane for the few marked
+// nodes of a tile).  Requires every channel's nx to be a multiple of 64.
+struct NextListArgs {
+    uint8_t *nx_need;     // [N] next-step marks, cleared here
+    uint8_t *nx_tneed;    // [ntiles] tile marks, cleared here
+    uint4 *ent;           // [ntiles] RecTile, written for every tile (mask 0 when unmarked or beyond the capacity)
+    uint32_t *node;       // [cap] node of each slot
+    uint32_t *count;      // slots handed out (zeroed by the point update before)
+    uint32_t *miss;       // zeroed here: set by the next step's marking when a marked node is not recorded
+    const Chan *chans;
+    const uint16_t *tile_chan;
+    int ntiles;
+    int64_t cap;
+};
+
+constexpr int kNextListThreads = 256, kNextListPer = 4;  // tiles per thread
+__global__ __launch_bounds__(kNextListThreads) void k_next_list(NextListArgs a) {
+    __shared__ uint32_t wsum[kNextListThreads / 64];
+    __shared__ uint32_t base_s;
+    const int t0 = (blockIdx.x * kNextListThreads + threadIdx.x) * kNextListPer;
+    if (t0 == 0) *a.miss = 0u;
+    uint64_t m[kNextListPer];
+    int64_t node0[kNextListPer];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int j = 0; j < kNextListPer; j++) {
+        const int t = t0 + j;
+        m[j] = 0;
+        node0[j] = 0;
+        if (t < a.ntiles && a.nx_tneed[t]) {
+            const Chan ch = a.chans[a.tile_chan ? (int)a.tile_chan[t] : 0];
+            const int lt = t - ch.toff, row = lt / ch.tpr;
+            node0[j] = ch.noff + (int64_t)row * ch.nx + (int64_t)(lt - row * ch.tpr) * 64;
+            uint4 *b = reinterpret_cast<uint4 *>(a.nx_need + node0[j]);  // 64 bytes, 64-byte aligned (nx % 64 == 0)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint4 v = b[q];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int k = 0; k < 4; k++)
+                        if ((w[i] >> (8 * k)) & 0xffu) m[j] |= 1ull << (16 * q + 4 * i + k);
+                b[q] = uint4{0u, 0u, 0u, 0u};
+            }
+            a.nx_tneed[t] = 0;
+        }
+        cnt += (uint32_t)__popcll(m[j]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int w = 0; w < kNextListThreads / 64; w++) tot += wsum[w];
+        base_s = tot ? atomicAdd(a.count, tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t pos = base_s + inc - cnt;
+    for (int w = 0; w < wave; w++) pos += wsum[w];
+#pragma unroll
+    for (int j = 0; j < kNextListPer; j++) {
+        const int t = t0 + j;
+        if (t >= a.ntiles) break;
+        uint64_t mj = m[j];
+        const uint32_t cj = (uint32_t)__popcll(mj);
+        // a tile whose range would pass the capacity is left out (its nodes
+        // are not recorded; the next step finds them uncovered and gathers them)
+        if ((int64_t)pos + cj > a.cap) mj = 0;
+        a.ent[t] = uint4{(uint32_t)mj, (uint32_t)(mj >> 32), pos, 0u};
+        uint32_t p = pos;
+        while (mj) {
+            const int b = __ffsll((unsigned long long)mj) - 1;
+            mj &= mj - 1;
+            a.node[p++] = (uint32_t)(node0[j] + b);
+        }
+        pos += cj;
+    }
+}
+
+struct VelRecArgs {
+    const void *rec;       // [19][cap] storage type
+    int64_t cap;
+    const uint32_t *node;  // [cap]
+    const uint32_t *count;
+    const uint8_t *cls;
+    const void *gfield;
+    void *ufield;          // [N] Vec4
+    int64_t N;
+    double g[3];
+};
+
+// u_ext of every recorded node from its record, one thread per slot (a
+// fixed grid strides over the slots, whose number is known on the device).
+// The 19 record loads of a slot go out together with its node's, before
+// the node's class is known (a solid node's record is never written and its
+// velocity is 0 whatever the loads return).
+template <class S, class R, bool DEV, bool HAS_G>
+__global__ __launch_bounds__(256) void k_velocity_records(VelRecArgs a) {
+    using R4 = typename Vec4<R>::T;
+    const uint32_t count = *a.count;
+    const __amdgpu_buffer_rsrc_t rr = buf_rsrc(a.rec, (uint64_t)Q * (uint64_t)a.cap * sizeof(S));
+    R4 *U = static_cast<R4 *>(a.ufield);
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < count; s += gridDim.x * blockDim.x) {
+        R v[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++)
+            v[i] = R(buf_load<S>(rr, s * (uint32_t)sizeof(S), (uint32_t)i * (uint32_t)a.cap * (uint32_t)sizeof(S)));
+        const uint32_t n = a.node[s];
+        R4 u = node_u<R, DEV, HAS_G>(v, a.g, a.gfield, a.N, n);
+        if (a.cls[n] == CLS_SOLID) u = R4{R(0), R(0), R(0), R(0)};
+        U[n] = u;
     }
 }
 
@@ -632,8 +792,15 @@ struct CoupleArgs {
     double xi, dt_over_m, dt;
     WallContact wall;  // nplanes = ncyl = 0: no wall contact forces
     int nb;            // point chunks of 128 per cell (workgroup mapping as for k_mark)
+    // marks of the next step's stencils (the new positions), or null
+    uint8_t *nx_need, *nx_tneed;
+    uint32_t *nx_count;  // zeroed here (read before by this step's velocity pass, counted next by k_next_list)
 };
 
+// Steps 1-2 of a point and the input of step 3: the interpolated velocity,
+// the coupling force F_c = xi A_k (u_k - V_k), and the spread record (base
+// node, fractional offsets, -F_c).  The membrane force is not needed here,
+// so this runs while the membrane kernel is still at work.
 template <class R>
 __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     using R4 = typename Vec4<R>::T;
@@ -644,9 +811,9 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const int k = vb + chunk * blockDim.x + threadIdx.x;
     if (k >= ve) return;
     const int NV = a.nverts;
-    double *X = a.x;
-    R *Vv = static_cast<R *>(a.v);
-    const R *FE = static_cast<const R *>(a.f_el);
+    if (a.nx_count && blockIdx.x == 0 && threadIdx.x == 0) *a.nx_count = 0u;
+    const double *X = a.x;
+    const R *Vv = static_cast<const R *>(a.v);
     const R4 *U = static_cast<const R4 *>(a.ufield);
     const double ox = X[k], oy = X[NV + k], oz = X[2 * NV + k];
     const double flx = floor(ox), fly = floor(oy), flz = floor(oz);
@@ -680,8 +847,31 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     // step 3 input: the spread record
     SRec<R> *SR = static_cast<SRec<R> *>(a.srec);
     SR[k] = SRec<R>{(uint32_t)(ch.noff + x0 + (int64_t)ch.nx * (y0 + (int64_t)ch.ny * z0)), dx, dy, dz, -fcx, -fcy, -fcz};
-    // step 4 (points): semi-implicit Euler with the vertex's mass; the
-    // membrane force carries the wall contact force when walls are given
+}
+
+// Step 4 of a point (semi-implicit Euler with the vertex's mass), once the
+// membrane force is there: the coupling force is read back from the spread
+// record (negated, exactly), the wall contact force added when walls are
+// given; then, with next-step marks, the stencil of the new position is
+// marked.  Workgroup mapping as for k_couple.
+template <class R>
+__global__ __launch_bounds__(128) void k_move(CoupleArgs a) {
+    int c, chunk;
+    xcd_cell_chunk(blockIdx.x, a.nb, c, chunk);
+    if (c >= a.ncells) return;
+    const int vb = a.vert_off[c], ve = a.vert_off[c + 1];
+    const int k = vb + chunk * blockDim.x + threadIdx.x;
+    if (k >= ve) return;
+    const int NV = a.nverts;
+    double *X = a.x;
+    R *Vv = static_cast<R *>(a.v);
+    const R *FE = static_cast<const R *>(a.f_el);
+    const SRec<R> r = static_cast<const SRec<R> *>(a.srec)[k];
+    const R fcx = -r.fx, fcy = -r.fy, fcz = -r.fz;
+    const double ox = X[k], oy = X[NV + k], oz = X[2 * NV + k];
+    const double ak = a.avert[k];
+    const R vx = Vv[k], vy = Vv[NV + k], vz = Vv[2 * NV + k];
+    const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
     R fex = FE[k], fey = FE[NV + k], fez = FE[2 * NV + k];
     if (a.wall.nplanes + a.wall.ncyl + a.wall.nsph > 0) {
         double wx_, wy_, wz_;
@@ -696,9 +886,27 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     Vv[k] = nvx;
     Vv[NV + k] = nvy;
     Vv[2 * NV + k] = nvz;
-    X[k] = ox + a.dt * (double)nvx;
-    X[NV + k] = oy + a.dt * (double)nvy;
-    X[2 * NV + k] = oz + a.dt * (double)nvz;
+    const double qx = ox + a.dt * (double)nvx, qy = oy + a.dt * (double)nvy, qz = oz + a.dt * (double)nvz;
+    X[k] = qx;
+    X[NV + k] = qy;
+    X[2 * NV + k] = qz;
+    if (a.nx_need) {  // the next step's stencil of the new position
+        const int x1 = pmod(a.anchor[c] + (int)floor(qx), ch.nx);
+        const int y1 = pmod(a.anchor[a.ncells + c] + (int)floor(qy), ch.ny);
+        const int z1 = pmod(a.anchor[2 * a.ncells + c] + (int)floor(qz), ch.nz);
+        const int xn[2] = {x1, x1 + 1 == ch.nx ? 0 : x1 + 1};
+        const int yn[2] = {y1, y1 + 1 == ch.ny ? 0 : y1 + 1};
+        const int zn[2] = {z1, z1 + 1 == ch.nz ? 0 : z1 + 1};
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int row = yn[q & 1] + ch.ny * zn[q >> 1];
+#pragma unroll
+            for (int e = 0; e < 2; e++) {
+                a.nx_need[ch.noff + (int64_t)row * ch.nx + xn[e]] = 1;
+                if (e == 0 || (xn[1] >> 6) != (xn[0] >> 6)) a.nx_tneed[ch.toff + (int64_t)row * ch.tpr + (xn[e] >> 6)] = 1;
+            }
+        }
+    }
 }
 
 constexpr int kSpreadThreads = 512;

@@ -3,6 +3,8 @@
 // bounce-back of Sec. 2.4), and the moments / FP64 global sums.
 #pragma once
 
+#include <type_traits>
+
 #include "d3q19.hpp"
 
 namespace lbm {
@@ -24,6 +26,81 @@ struct Chan {
 // Channel of a global tile, uniform across the wave.
 __device__ __forceinline__ int tile_channel(const uint16_t *tile_chan, int tile) {
     return tile_chan ? __builtin_amdgcn_readfirstlane((int)tile_chan[tile]) : 0;
+}
+
+// Where a state buffer keeps the populations.  Every pass writes each slot
+// (plane i, node m) exactly once, from the node m - c_i that streams into
+// it, so that every cache line is written whole:
+//  - a population streamed into a fluid node lies in that node's slot;
+//  - a population a fluid node sends towards a solid neighbour (halfway
+//    bounce-back: it returns to the node along the opposite direction) is
+//    streamed into the solid node's slot like any other, and the node reads
+//    it back from there: population i of fluid node n whose link opp(i)
+//    ends on a solid node s = n - c_i lies in slot opp(i) of s;
+//  - a solid node streams its rest value into its destinations, slots whose
+//    content nobody reads;
+//  - a population bounced at a non-periodic face of the lattice (no node
+//    beyond it) is written into the node's own slot opp(i), as the
+//    population i of the next step.
+// So population i of fluid node n is in slot (i, n) unless link opp(i) of n
+// ends on a solid node inside the lattice.
+
+// The link of (x, y, z) along c_i leaves the channel through a non-periodic face.
+__device__ __forceinline__ bool leaves_lattice(int i, int x, int y, int z, const Chan &ch, const int (&per)[3]) {
+    return (!per[0] && ((cx(i) > 0 && x + 1 == ch.nx) || (cx(i) < 0 && x == 0))) ||
+           (!per[1] && ((cy(i) > 0 && y + 1 == ch.ny) || (cy(i) < 0 && y == 0))) ||
+           (!per[2] && ((cz(i) > 0 && z + 1 == ch.nz) || (cz(i) < 0 && z == 0)));
+}
+
+// Element index of population i of fluid node n = (x, y, z) of channel ch
+// (links: its link mask).
+template <class IDX>
+__device__ __forceinline__ IDX pop_slot(int i, IDX n, uint32_t links, int x, int y, int z, const Chan &ch, IDX stride,
+                                        const int (&per)[3]) {
+    if (!((links >> opp(i)) & 1u) || leaves_lattice(opp(i), x, y, z, ch, per)) return (IDX)i * stride + n;
+    const int xs = x - cx(i) < 0 ? ch.nx - 1 : (x - cx(i) == ch.nx ? 0 : x - cx(i));
+    const int ys = y - cy(i) < 0 ? ch.ny - 1 : (y - cy(i) == ch.ny ? 0 : y - cy(i));
+    const int zs = z - cz(i) < 0 ? ch.nz - 1 : (z - cz(i) == ch.nz ? 0 : z - cz(i));
+    return (IDX)opp(i) * stride + (IDX)ch.noff + (IDX)xs + (IDX)ch.nx * ((IDX)ys + (IDX)ch.ny * (IDX)zs);
+}
+
+// Coordinates of node n (concatenated index) in its channel (nch channels,
+// ascending node offsets).
+__device__ __forceinline__ void node_coords(const Chan *chans, int nch, int64_t n, Chan &ch, int &x, int &y, int &z) {
+    int lo = 0, hi = nch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (chans[mid].noff <= n) lo = mid;
+        else hi = mid - 1;
+    }
+    ch = chans[lo];
+    const int64_t l = n - ch.noff;
+    x = (int)(l % ch.nx);
+    y = (int)((l / ch.nx) % ch.ny);
+    z = (int)(l / ((int64_t)ch.nx * ch.ny));
+}
+
+// Population i of node n as a per-node kernel reads it (a bulk node's own
+// slot; a wall node's through pop_slot).
+struct PopView {
+    const Chan *chans;
+    int nch;
+    int per[3];
+    const uint8_t *cls;
+    const uint32_t *links;
+};
+template <class S>
+__device__ __forceinline__ void load_node(const S *f, int64_t stride, int64_t n, const PopView &pv, S (&v)[Q]) {
+#pragma unroll
+    for (int i = 0; i < Q; i++) v[i] = f[i * stride + n];
+    if (pv.cls[n] != CLS_WALL) return;
+    const uint32_t lk = pv.links[n];
+    Chan ch;
+    int x, y, z;
+    node_coords(pv.chans, pv.nch, n, ch, x, y, z);
+#pragma unroll
+    for (int i = 0; i < Q; i++)
+        if ((lk >> opp(i)) & 1u) v[i] = f[pop_slot<int64_t>(i, n, lk, x, y, z, ch, stride, pv.per)];
 }
 
 // cls[n] and links[n] (bit i set = the link along c_i ends on a solid node
@@ -123,6 +200,35 @@ __device__ __forceinline__ const T &at(const T *base, IDX i) {
         return base[i];
 }
 
+// Raw buffer access (32-bit byte offsets from a resource descriptor, range
+// checked against the buffer's size: an access beyond it reads 0 and writes
+// nothing).  The plane offset of a population goes in the scalar offset, so
+// the 19 loads of a node share one per-lane offset register.
+constexpr int kBufFlags = 0x00020000;  // descriptor word 3: raw 32-bit data
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, uint64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0,
+                                             (int)(bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes), kBufFlags);
+}
+template <class T>
+__device__ __forceinline__ T buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    } else {
+        static_assert(sizeof(T) == 8, "4- or 8-byte elements");
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+    }
+}
+template <class T>
+__device__ __forceinline__ void buf_store(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+    } else {
+        static_assert(sizeof(T) == 8, "4- or 8-byte elements");
+        using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, (int)voff, (int)soff, 0);
+    }
+}
+
 struct StepArgs {
     const void *fa;
     void *fb;
@@ -144,7 +250,108 @@ struct StepArgs {
     int64_t N;
     double g[3];
     double omega, kf;
+    // records of the next step's stencil nodes (EMIT): per-tile entries
+    // (RecTile), the record [19][cap]
+    const uint4 *etile;
+    void *erec;
+    int64_t ecap;
+    int per[3];  // periodic axes (a link leaving a non-periodic face bounces in place)
 };
+
+// Number of set bits of m below this lane.
+__device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Per-tile entry of the next-step records (written by k_next_list): the
+// tile's marked nodes (bit x & 63) and the first slot of their range.
+struct RecTile {
+    uint32_t mlo, mhi, tbase, pad;
+};
+
+// The 27 tiles around a wave's tile, (dc, dy, dz) in {-1, 0, 1}^3 (tile
+// column, row y, row z; wrapped like the streaming), entry L = (dc + 1) +
+// 3 (dy + 1) + 9 (dz + 1) loaded by lane L into the wave's LDS slots `rt`
+// at the start of the pass (while every lane of the wave is active), so that
+// the entries arrive with the populations; the emission reads them back as
+// wave-uniform LDS loads.
+constexpr int kRecTiles = 27;
+__device__ __forceinline__ void stage_rec_tiles(const uint4 *ent, const Chan &ch, int col, int y, int z, int lane,
+                                                uint4 *rt) {
+    if (lane < kRecTiles) {
+        const int dc = lane % 3 - 1, dy = (lane / 3) % 3 - 1, dz = lane / 9 - 1;
+        const int c2 = col + dc < 0 ? ch.tpr - 1 : (col + dc == ch.tpr ? 0 : col + dc);
+        const int y2 = y + dy < 0 ? ch.ny - 1 : (y + dy == ch.ny ? 0 : y + dy);
+        const int z2 = z + dz < 0 ? ch.nz - 1 : (z + dz == ch.nz ? 0 : z + dz);
+        rt[lane] = ent[ch.toff + (int64_t)(y2 + ch.ny * z2) * ch.tpr + c2];
+    }
+    // the other lanes of the wave read these slots later
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Entry L of the wave's staged tiles as wave-uniform values: mask, first slot.
+// (readfirstlane returns a signed int: each word goes through uint32_t before
+// widening, or a mask with bit 31 set would sign-extend into the high word)
+__device__ __forceinline__ uint64_t rt_mask(const uint4 *rt, int L) {
+    const uint4 e = rt[L];
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane(e.x), hi = (uint32_t)__builtin_amdgcn_readfirstlane(e.y);
+    return (uint64_t)lo | (uint64_t)hi << 32;
+}
+__device__ __forceinline__ uint32_t rt_base(const uint4 *rt, int L) {
+    return (uint32_t)__builtin_amdgcn_readfirstlane(rt[L].z);
+}
+
+// Record of population i, just streamed, when it lands on a node marked for
+// the next step (see k_next_list): lane l's value goes to node (x + cx,
+// y + cy, z + cz) in tile column col + (l + cx) / 64, or, on a bounced link,
+// to slot opp(i) of its own node.  m0/b0: mask and first slot of the tile
+// of the destination row in the wave's own column; ms/bs: of the column
+// col + cx (cx != 0); mown/bown: of the wave's own tile.  The lane's bit and
+// slot come from the mask shifted by cx: for cx = +1 lane 63 lands on bit 0
+// of the next column, for cx = -1 lane 0 on bit 63 of the previous one.
+// Requires nx % 64 == 0, so tiles are whole.
+template <int I, class S>
+__device__ __forceinline__ void emit_record(const StepArgs &a, __amdgpu_buffer_rsrc_t rrec, int lane, uint32_t links,
+                                            uint64_t m0, uint32_t b0, uint64_t ms, uint32_t bs, uint64_t mown,
+                                            uint32_t bown, S val) {
+    constexpr int CX = cx(I);
+    if (!(m0 | ms | mown)) return;
+    const bool bounce = (links >> I) & 1u;
+    bool hit;
+    uint32_t slot;
+    if (bounce) {
+        hit = (mown >> lane) & 1ull;
+        slot = bown + bits_below_lane(mown);
+    } else if (CX == 0) {
+        hit = (m0 >> lane) & 1ull;
+        slot = b0 + bits_below_lane(m0);
+    } else if (CX > 0) {
+        if (lane == 63) {
+            hit = ms & 1ull;
+            slot = bs;
+        } else {
+            hit = (m0 >> (lane + 1)) & 1ull;
+            slot = b0 + (uint32_t)(m0 & 1ull) + bits_below_lane(m0 >> 1);
+        }
+    } else {
+        if (lane == 0) {
+            hit = ms >> 63;
+            slot = bs + (uint32_t)__popcll(ms) - 1u;
+        } else {
+            hit = (m0 >> (lane - 1)) & 1ull;
+            slot = b0 + bits_below_lane(m0 << 1);
+        }
+    }
+    if (hit) buf_store(val, rrec, (uint32_t)(((bounce ? opp(I) : I) * (uint32_t)a.ecap + slot) * sizeof(S)), 0u);
+}
+
+// The streaming order of the pass: by destination row (cy, cz), the
+// direction with cx = 0 first, then cx = +1, then cx = -1, so that the
+// record entries of a row are read once for its directions.
+constexpr int kRowDirs[9][3] = {{0, 1, 2},  {3, 7, 10},  {4, 9, 8},  {5, 11, 14}, {6, 13, 12},
+                                {15, -1, -1}, {16, -1, -1}, {17, -1, -1}, {18, -1, -1}};
 
 // One fused collide-and-stream pass (push): each wave owns one tile of 64
 // consecutive x of one (y,z) row, reads the 19 planes of its nodes
@@ -164,8 +371,8 @@ struct StepArgs {
 // (still held by the memory-side cache).  IDX is the index type of element offsets from the buffer
 // base: uint32_t when 19 planes fit in 4 GiB (single 64-bit base + 32-bit
 // lane offsets), int64_t otherwise.
-template <class S, class R, bool DEV, bool HAS_G, class IDX>
-__global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
+template <class S, class R, bool DEV, bool HAS_G, class IDX, bool EMIT = false>
+__global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int tile;
     if (a.wgtab) {
@@ -181,6 +388,10 @@ __global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
     const int lt = tile - ch.toff;
     const int row = lt / ch.tpr;
     const int x = (lt - row * ch.tpr) * 64 + lane;
+    __shared__ uint4 rec_tiles[EMIT ? 8 * kRecTiles : 1];
+    uint4 *rt = rec_tiles + (EMIT ? wave * kRecTiles : 0);
+    if constexpr (EMIT)  // every lane active here (whole waves only leave above)
+        stage_rec_tiles(a.etile, ch, lt - row * ch.tpr, row % ch.ny, row / ch.ny, lane, rt);
     if (x >= ch.nx) return;
     const IDX base = (IDX)ch.noff;
     const IDX n = base + (IDX)row * (IDX)ch.nx + (IDX)x;
@@ -219,52 +430,128 @@ __global__ __launch_bounds__(512) void k_collide_stream(StepArgs a) {
         }
     }
     const uint8_t cl = at(a.cls, n);
-    if (cl == CLS_SOLID) return;
+    const bool solid = cl == CLS_SOLID;  // streams its rest value (see pop_slot)
 
     const S *__restrict__ fa = static_cast<const S *>(a.fa);
     S *__restrict__ fb = static_cast<S *>(a.fb);
-    R f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) f[i] = R(at(fa, (IDX)i * stride + n));
-
-    collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
-
+    constexpr bool BUF = sizeof(IDX) == 4;  // every buffer below 4 GiB: raw buffer access
+    const uint64_t fbytes = (uint64_t)Q * (uint64_t)a.stride * sizeof(S);
+    __amdgpu_buffer_rsrc_t ra, rb;
+    if constexpr (BUF) {
+        ra = buf_rsrc(fa, fbytes);
+        rb = buf_rsrc(fb, fbytes);
+    }
     const int y = row % ch.ny, z = row / ch.ny;
+    const uint32_t links = (cl == CLS_WALL) ? at(a.links, n) : 0u;
+    R f[Q];
+    if (!solid) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            if constexpr (BUF)
+                f[i] = R(buf_load<S>(ra, (uint32_t)n * (uint32_t)sizeof(S), (uint32_t)i * (uint32_t)a.stride * (uint32_t)sizeof(S)));
+            else
+                f[i] = R(at(fa, (IDX)i * stride + n));
+        }
+        if (links) {  // populations bounced back from solid neighbours lie in their slots
+#pragma unroll
+            for (int i = 0; i < Q; i++) {
+                if (!((links >> opp(i)) & 1u)) continue;
+                const IDX src = pop_slot<IDX>(i, n, links, x, y, z, ch, stride, a.per);
+                if constexpr (BUF)
+                    f[i] = R(buf_load<S>(ra, (uint32_t)src * (uint32_t)sizeof(S), 0u));
+                else
+                    f[i] = R(at(fa, src));
+            }
+        }
+        collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; i++) f[i] = DEV ? R(0) : wgt<R>(i);
+    }
+
     const int xp = (x + 1 == ch.nx) ? 0 : x + 1;
     const int xm = (x == 0) ? ch.nx - 1 : x - 1;
     const int yp = (y + 1 == ch.ny) ? 0 : y + 1;
     const int ym = (y == 0) ? ch.ny - 1 : y - 1;
     const int zp = (z + 1 == ch.nz) ? 0 : z + 1;
     const int zm = (z == 0) ? ch.nz - 1 : z - 1;
-    const uint32_t links = (cl == CLS_WALL) ? at(a.links, n) : 0u;
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
+    __amdgpu_buffer_rsrc_t rrec;
+    uint64_t mown = 0;
+    uint32_t bown = 0;
+    if constexpr (EMIT) {
+        rrec = buf_rsrc(a.erec, (uint64_t)Q * (uint64_t)a.ecap * sizeof(S));
+        mown = rt_mask(rt, 13);
+        bown = rt_base(rt, 13);
+    }
+    auto stream = [&](auto ic, uint64_t m0, uint32_t b0, uint64_t ms, uint32_t bs) {
+        constexpr int i = decltype(ic)::value;
         const int xq = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
         const int yq = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
         const int zq = cz(i) > 0 ? zp : (cz(i) < 0 ? zm : z);
-        const IDX dst = ((links >> i) & 1u)
-                            ? (IDX)opp(i) * stride + n
-                            : (IDX)i * stride + base + (IDX)xq + (IDX)ch.nx * ((IDX)yq + (IDX)ch.ny * (IDX)zq);
-        at(fb, dst) = S(f[i]);
-    }
+        // streamed (into a solid node too: a bounced population waits there),
+        // except across a non-periodic face, where it bounces in place
+        const bool out = leaves_lattice(i, x, y, z, ch, a.per);
+        if (!(solid && out)) {
+            const IDX dst = out ? (IDX)opp(i) * stride + n
+                                : (IDX)i * stride + base + (IDX)xq + (IDX)ch.nx * ((IDX)yq + (IDX)ch.ny * (IDX)zq);
+            if constexpr (BUF)
+                buf_store(S(f[i]), rb, (uint32_t)dst * (uint32_t)sizeof(S), 0u);
+            else
+                at(fb, dst) = S(f[i]);
+        }
+        if constexpr (EMIT)
+            if (!solid) emit_record<i, S>(a, rrec, lane, links, m0, b0, ms, bs, mown, bown, S(f[i]));
+    };
+    auto stream_row = [&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int i0 = kRowDirs[r][0], ip = kRowDirs[r][1], im = kRowDirs[r][2];
+        constexpr int L0 = 1 + 3 * (cy(i0) + 1) + 9 * (cz(i0) + 1);  // entry of the row's tile in this column
+        uint64_t m0 = 0, mp = 0, mm = 0;
+        uint32_t b0 = 0, bp = 0, bm = 0;
+        if constexpr (EMIT) {
+            m0 = r == 0 ? mown : rt_mask(rt, L0);
+            b0 = r == 0 ? bown : rt_base(rt, L0);
+            if constexpr (ip >= 0) {
+                mp = rt_mask(rt, L0 + 1);
+                bp = rt_base(rt, L0 + 1);
+                mm = rt_mask(rt, L0 - 1);
+                bm = rt_base(rt, L0 - 1);
+            }
+        }
+        stream(std::integral_constant<int, i0>{}, m0, b0, 0ull, 0u);
+        if constexpr (ip >= 0) {
+            stream(std::integral_constant<int, ip>{}, m0, b0, mp, bp);
+            stream(std::integral_constant<int, im>{}, m0, b0, mm, bm);
+        }
+    };
+    stream_row(std::integral_constant<int, 0>{});
+    stream_row(std::integral_constant<int, 1>{});
+    stream_row(std::integral_constant<int, 2>{});
+    stream_row(std::integral_constant<int, 3>{});
+    stream_row(std::integral_constant<int, 4>{});
+    stream_row(std::integral_constant<int, 5>{});
+    stream_row(std::integral_constant<int, 6>{});
+    stream_row(std::integral_constant<int, 7>{});
+    stream_row(std::integral_constant<int, 8>{});
 }
 
 // rho and u = (j + F_ext/2)/rho per node (solid: 0), plus per-block FP64
 // partial sums of rho and j over fluid nodes.
 template <class S, class R, bool DEV, bool HAS_G>
-__global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, int64_t stride,
-                                                 const uint8_t *__restrict__ cls, const R *__restrict__ G,
-                                                 int64_t N, double gx, double gy, double gz, R *rho_out,
-                                                 R *u_out, double *partials) {
+__global__ __launch_bounds__(256) void k_moments(const S *__restrict__ f, int64_t stride, PopView pv,
+                                                 const R *__restrict__ G, int64_t N, double gx, double gy, double gz,
+                                                 R *rho_out, R *u_out, double *partials) {
     __shared__ double red[4 * 4];
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     if (n < N) {
-        if (cls[n] != CLS_SOLID) {
+        if (pv.cls[n] != CLS_SOLID) {
             double r = DEV ? 1.0 : 0.0, j[3] = {0.0, 0.0, 0.0};
+            S fv[Q];
+            load_node(f, stride, n, pv, fv);
 #pragma unroll
             for (int i = 0; i < Q; i++) {
-                const double v = (double)f[i * stride + n];
+                const double v = (double)fv[i];
                 r += v;
                 j[0] += cx(i) * v;
                 j[1] += cy(i) * v;
@@ -308,20 +595,40 @@ __global__ __launch_bounds__(256) void k_copy(const T *__restrict__ src, T *__re
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
 }
 
+// Full populations of every node (solid nodes carry none: their rest
+// weights are reported).
 template <class S, bool DEV>
-__global__ void k_store_f64(const S *__restrict__ f, int64_t stride, int64_t N, double *__restrict__ out) {
+__global__ void k_store_f64(const S *__restrict__ f, int64_t stride, int64_t N, PopView pv, double *__restrict__ out) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    if (pv.cls[n] == CLS_SOLID) {
 #pragma unroll
-    for (int i = 0; i < Q; i++) out[i * N + n] = (double)f[i * stride + n] + (DEV ? wgt<double>(i) : 0.0);
+        for (int i = 0; i < Q; i++) out[i * N + n] = wgt<double>(i);
+        return;
+    }
+    S v[Q];
+    load_node(f, stride, n, pv, v);
+#pragma unroll
+    for (int i = 0; i < Q; i++) out[i * N + n] = (double)v[i] + (DEV ? wgt<double>(i) : 0.0);
 }
 
+// Fluid nodes' populations into the slots that hold them (solid nodes'
+// values are ignored: those slots may hold a neighbour's population).
 template <class S, bool DEV>
-__global__ void k_load_f64(S *__restrict__ f, int64_t stride, int64_t N, const double *__restrict__ in) {
+__global__ void k_load_f64(S *__restrict__ f, int64_t stride, int64_t N, PopView pv, const double *__restrict__ in) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    const uint8_t cl = pv.cls[n];
+    if (cl == CLS_SOLID) return;
+    const uint32_t lk = cl == CLS_WALL ? pv.links[n] : 0u;
+    Chan ch{};
+    int x = 0, y = 0, z = 0;
+    if (lk) node_coords(pv.chans, pv.nch, n, ch, x, y, z);
 #pragma unroll
-    for (int i = 0; i < Q; i++) f[i * stride + n] = S(in[i * N + n] - (DEV ? wgt<double>(i) : 0.0));
+    for (int i = 0; i < Q; i++) {
+        const int64_t slot = lk ? pop_slot<int64_t>(i, n, lk, x, y, z, ch, stride, pv.per) : i * stride + n;
+        f[slot] = S(in[i * N + n] - (DEV ? wgt<double>(i) : 0.0));
+    }
 }
 
 }  // namespace lbm

@@ -178,10 +178,29 @@ struct lbm_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int ibm_overlap = -1;  // lbm_set_ibm_overlap mode
+    // records of the next step's stencil-node populations (see k_next_list):
+    // the point update marks the new positions' stencils, the collide-stream
+    // pass copies the populations it streams into them, and the next
+    // coupling takes the marked nodes' velocities from the copies
+    bool rec_capable = false;      // every channel's nx is a multiple of 64
+    int rec_mode = 0;              // lbm_set_node_records
+    bool rec_valid = false;        // the last pass recorded the nodes marked before it, from the current state
+    bool u_from_rec = false;       // this step's velocities already come from the records
+    bool last_rec = false;         // the last coupling took its velocities from the records
+    int64_t nx_pending = 0;        // IB points whose next stencils were marked since the last pass
+    int64_t nx_pts = 0;            // IB points of the meshes given to ibm_rest_shape (sizes the record)
+    int64_t nx_cap = 0;            // record slots
+    uint8_t *nx_need = nullptr;    // [N] next-step node marks
+    uint8_t *nx_tneed = nullptr;   // [ntiles] next-step tile marks
+    uint4 *nx_ent = nullptr;       // [ntiles] RecTile: recorded nodes of each tile, first slot
+    uint32_t *nx_flags = nullptr;  // [0] slots handed out, [1] a marked node was not recorded
+    uint32_t *nx_node = nullptr;   // [nx_cap] node of each slot
+    void *nx_rec = nullptr;        // [19][nx_cap] storage type
     // captured graphs: plain coupled steps, recorded steps, reverse sweep
     hipStream_t cap_s = nullptr;
     hipGraphExec_t gx[3] = {nullptr, nullptr, nullptr};
     uint64_t gk[3] = {0, 0, 0};
+    bool g_rec_end[3] = {false, false, false};  // rec_valid after each graph
 };
 
 enum { G_RUN = 0, G_REC = 1, G_ADJ = 2 };
@@ -319,7 +338,8 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
-                    c->sph_start, c->sph_items, c->wgtab};
+                    c->sph_start, c->sph_items, c->wgtab, c->nx_need, c->nx_tneed, c->nx_ent,
+                    c->nx_flags, c->nx_node, c->nx_rec};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
@@ -337,6 +357,8 @@ static int init_ctx(lbm_ctx *c) {
     c->nparts = cdiv(c->N, 256);
     c->off32 = 19 * c->stride * (int64_t)c->rsize < (int64_t(1) << 32);
     c->nch = (int)c->hchans.size();
+    c->rec_capable = true;
+    for (const Chan &ch : c->hchans) c->rec_capable = c->rec_capable && ch.nx % 64 == 0;
     const size_t tn = (size_t)c->ntiles;
     const size_t tpad = (size_t)cdiv((int64_t)tn, 16) * 16;
     if (hipMalloc(&c->chans, sizeof(Chan) * c->nch) != hipSuccess || hipMalloc(&c->cls, c->N) != hipSuccess ||
@@ -458,6 +480,30 @@ LBM_API int lbm_set_ibm_overlap(lbm_ctx *c, int32_t mode) {
     return LBM_OK;
 }
 
+LBM_API int lbm_set_node_records(lbm_ctx *c, int32_t mode) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (mode != 0 && mode != 1) return fail(LBM_EINVAL, "node-record mode must be 0 or 1 (got %d)", mode);
+    if (mode != c->rec_mode) {
+        drop_graph(c);
+        c->rec_valid = false;
+        c->u_from_rec = false;
+    }
+    c->rec_mode = mode;
+    return LBM_OK;
+}
+
+LBM_API int lbm_node_records_used(lbm_ctx *c, int32_t *used, int32_t *missed) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    uint32_t miss = 0;
+    if (c->last_rec && c->nx_flags) {
+        HIPCHK(hipStreamSynchronize(c->s));
+        HIPCHK(hipMemcpy(&miss, c->nx_flags + 1, 4, hipMemcpyDeviceToHost));
+    }
+    if (used) *used = c->last_rec ? 1 : 0;
+    if (missed) *missed = miss ? 1 : 0;
+    return LBM_OK;
+}
+
 static const void *cur_f(const lbm_ctx *c) { return c->cur ? c->p.f_b : c->p.f_a; }
 static void *nxt_f(const lbm_ctx *c) { return c->cur ? c->p.f_a : c->p.f_b; }
 
@@ -477,25 +523,31 @@ static CsShape cs_shape(const lbm_ctx *c) {
     return {c->cs_waves, (tpr >= 1 && c->cs_waves % tpr == 0) ? 0 : 1, (int)cdiv(c->ntiles, c->cs_waves), nullptr};
 }
 
+template <class S, class R, bool DEV, bool EMIT>
+static void launch_step_as(lbm_ctx *c, const StepArgs &a, int nb, int bs) {
+    if (c->off32) {
+        if (c->p.gfield)
+            k_collide_stream<S, R, DEV, true, uint32_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+        else
+            k_collide_stream<S, R, DEV, false, uint32_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+    } else {
+        if (c->p.gfield)
+            k_collide_stream<S, R, DEV, true, int64_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+        else
+            k_collide_stream<S, R, DEV, false, int64_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+    }
+}
+
 template <class S, class R, bool DEV>
 static void launch_step(lbm_ctx *c, StepArgs a) {
     const CsShape sh = cs_shape(c);
     a.remap = sh.remap;
     a.wgtab = sh.tab;
     a.reverse = (int)(c->steps & 1);  // every other pass walks the table backwards
-    const int nb = sh.nb;
-    const int bs = 64 * sh.waves;
-    if (c->off32) {
-        if (c->p.gfield)
-            k_collide_stream<S, R, DEV, true, uint32_t><<<nb, bs, 0, c->s>>>(a);
-        else
-            k_collide_stream<S, R, DEV, false, uint32_t><<<nb, bs, 0, c->s>>>(a);
-    } else {
-        if (c->p.gfield)
-            k_collide_stream<S, R, DEV, true, int64_t><<<nb, bs, 0, c->s>>>(a);
-        else
-            k_collide_stream<S, R, DEV, false, int64_t><<<nb, bs, 0, c->s>>>(a);
-    }
+    if (a.erec)
+        launch_step_as<S, R, DEV, true>(c, a, sh.nb, 64 * sh.waves);
+    else
+        launch_step_as<S, R, DEV, false>(c, a, sh.nb, 64 * sh.waves);
 }
 
 static void enqueue_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes) {
@@ -532,15 +584,50 @@ static StepArgs step_args(const lbm_ctx *c) {
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
     a.omega = 1.0 / c->p.tau;
     a.kf = 1.0 - 0.5 / c->p.tau;
+    for (int d = 0; d < 3; d++) a.per[d] = c->p.periodic[d];
     return a;
 }
 
+static PopView pop_view(const lbm_ctx *c) {
+    PopView v{};
+    v.chans = c->chans;
+    v.nch = c->nch;
+    for (int d = 0; d < 3; d++) v.per[d] = c->p.periodic[d];
+    v.cls = c->cls;
+    v.links = c->links;
+    return v;
+}
+
 // One collide-stream pass from fa into fb (the context's parity is untouched).
-static void enqueue_step_into(lbm_ctx *c, const void *fa, void *fb) {
+// With `plain` (a pass of the context's own state, fb becoming the current
+// buffer) the populations streamed into nodes marked for the next step are
+// recorded, when any were marked since the last pass.
+static void enqueue_step_into(lbm_ctx *c, const void *fa, void *fb, bool plain = false) {
     c->couples = 0;  // this pass consumes the spread force
     StepArgs a = step_args(c);
     a.fa = fa;
     a.fb = fb;
+    const bool emit = plain && c->nx_pending > 0 && c->nx_rec;
+    if (emit) {
+        NextListArgs l{};
+        l.nx_need = c->nx_need;
+        l.nx_tneed = c->nx_tneed;
+        l.ent = c->nx_ent;
+        l.node = c->nx_node;
+        l.count = c->nx_flags;
+        l.miss = c->nx_flags + 1;
+        l.chans = c->chans;
+        l.tile_chan = c->tile_chan;
+        l.ntiles = c->ntiles;
+        l.cap = c->nx_cap;
+        k_next_list<<<(int)cdiv(c->ntiles, kNextListThreads * kNextListPer), kNextListThreads, 0, c->s>>>(l);
+        a.etile = c->nx_ent;
+        a.erec = c->nx_rec;
+        a.ecap = c->nx_cap;
+    }
+    c->rec_valid = emit;
+    c->u_from_rec = false;
+    c->nx_pending = 0;
     switch (c->p.prec) {
         case LBM_F64: launch_step<double, double, false>(c, a); break;
         case LBM_F32: launch_step<float, float, false>(c, a); break;
@@ -550,7 +637,7 @@ static void enqueue_step_into(lbm_ctx *c, const void *fa, void *fb) {
 
 static void enqueue_steps(lbm_ctx *c, int32_t nsteps) {
     for (int s = 0; s < nsteps; s++) {
-        enqueue_step_into(c, cur_f(c), nxt_f(c));
+        enqueue_step_into(c, cur_f(c), nxt_f(c), true);
         c->cur ^= 1;
         c->steps++;
     }
@@ -577,10 +664,10 @@ static void launch_moments(lbm_ctx *c, void *rho, void *u) {
     const R *G = static_cast<const R *>(c->p.gfield);
     const double *g = c->p.body_force;
     if (G)
-        k_moments<S, R, DEV, true><<<nb, 256, 0, c->s>>>((const S *)cur_f(c), c->stride, c->cls, G, c->N, g[0], g[1],
-                                                          g[2], (R *)rho, (R *)u, c->partials);
+        k_moments<S, R, DEV, true><<<nb, 256, 0, c->s>>>((const S *)cur_f(c), c->stride, pop_view(c), G, c->N, g[0],
+                                                          g[1], g[2], (R *)rho, (R *)u, c->partials);
     else
-        k_moments<S, R, DEV, false><<<nb, 256, 0, c->s>>>((const S *)cur_f(c), c->stride, c->cls, G, c->N, g[0],
+        k_moments<S, R, DEV, false><<<nb, 256, 0, c->s>>>((const S *)cur_f(c), c->stride, pop_view(c), G, c->N, g[0],
                                                            g[1], g[2], (R *)rho, (R *)u, c->partials);
 }
 
@@ -611,9 +698,9 @@ LBM_API int lbm_store_f64(lbm_ctx *c, double *f64) {
     if ((uintptr_t)f64 % 8) return fail(LBM_EINVAL, "f64 misaligned");
     const int nb = (int)cdiv(c->N, 256);
     switch (c->p.prec) {
-        case LBM_F64: k_store_f64<double, false><<<nb, 256, 0, c->s>>>((const double *)cur_f(c), c->stride, c->N, f64); break;
-        case LBM_F32: k_store_f64<float, false><<<nb, 256, 0, c->s>>>((const float *)cur_f(c), c->stride, c->N, f64); break;
-        default: k_store_f64<float, true><<<nb, 256, 0, c->s>>>((const float *)cur_f(c), c->stride, c->N, f64); break;
+        case LBM_F64: k_store_f64<double, false><<<nb, 256, 0, c->s>>>((const double *)cur_f(c), c->stride, c->N, pop_view(c), f64); break;
+        case LBM_F32: k_store_f64<float, false><<<nb, 256, 0, c->s>>>((const float *)cur_f(c), c->stride, c->N, pop_view(c), f64); break;
+        default: k_store_f64<float, true><<<nb, 256, 0, c->s>>>((const float *)cur_f(c), c->stride, c->N, pop_view(c), f64); break;
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -622,12 +709,14 @@ LBM_API int lbm_store_f64(lbm_ctx *c, double *f64) {
 LBM_API int lbm_load_f64(lbm_ctx *c, const double *f64) {
     if (!c || !f64) return fail(LBM_EINVAL, "NULL argument");
     if ((uintptr_t)f64 % 8) return fail(LBM_EINVAL, "f64 misaligned");
+    c->rec_valid = false;  // the records hold the populations this replaces
+    c->u_from_rec = false;
     const int nb = (int)cdiv(c->N, 256);
     void *f = const_cast<void *>(cur_f(c));
     switch (c->p.prec) {
-        case LBM_F64: k_load_f64<double, false><<<nb, 256, 0, c->s>>>((double *)f, c->stride, c->N, f64); break;
-        case LBM_F32: k_load_f64<float, false><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N, f64); break;
-        default: k_load_f64<float, true><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N, f64); break;
+        case LBM_F64: k_load_f64<double, false><<<nb, 256, 0, c->s>>>((double *)f, c->stride, c->N, pop_view(c), f64); break;
+        case LBM_F32: k_load_f64<float, false><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N, pop_view(c), f64); break;
+        default: k_load_f64<float, true><<<nb, 256, 0, c->s>>>((float *)f, c->stride, c->N, pop_view(c), f64); break;
     }
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -683,8 +772,12 @@ static int waves_grid(const lbm_ctx *c) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->ntiles, 4 * 4), 16384));
 }
 
-static MarkArgs mark_args(const lbm_ctx *c, const ibm_mesh *m) {
+static MarkArgs mark_args(const lbm_ctx *c, const ibm_mesh *m, bool cover = false) {
     MarkArgs a{};
+    if (cover) {  // check the marks against the nodes the last pass recorded
+        a.cover = c->nx_ent;
+        a.miss = c->nx_flags + 1;
+    }
     a.tcount = c->tcount;
     a.epoch = c->epoch;
     a.chans = c->chans;
@@ -704,7 +797,7 @@ static MarkArgs mark_args(const lbm_ctx *c, const ibm_mesh *m) {
 // Membrane forces (rest: the rest shape); with `mark` the same kernel sets
 // the stencil marks.
 template <class R>
-static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest, bool mark = false) {
+static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest, bool mark = false, bool cover = false) {
     MembArgs a{};
     a.vtri_off = m->vtri_off;
     a.vtri = m->vtri;
@@ -736,7 +829,7 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest, bool mark 
     if (rest) {
         k_membrane<R, true, false><<<m->ncells, kMembThreads, sm, c->s>>>(a);
     } else if (mark) {
-        a.mark = mark_args(c, m);
+        a.mark = mark_args(c, m, cover);
         k_membrane<R, false, true><<<m->ncells, kMembThreads, sm, c->s>>>(a);
     } else {
         k_membrane<R, false, false><<<m->ncells, kMembThreads, sm, c->s>>>(a);
@@ -746,9 +839,9 @@ static void launch_membrane(lbm_ctx *c, const ibm_mesh *m, bool rest, bool mark 
 // Stencil marks of this step's positions on their own (with the list length
 // and claim epoch reset for the step).
 template <class R>
-static void launch_mark(lbm_ctx *c, const ibm_mesh *m) {
+static void launch_mark(lbm_ctx *c, const ibm_mesh *m, bool cover = false) {
     const int nb = (int)cdiv(m->max_cell_verts, 128);
-    k_mark<R><<<(unsigned)(nb * cdiv(m->ncells, 8) * 8), 128, 0, c->s>>>(mark_args(c, m), nb);
+    k_mark<R><<<(unsigned)(nb * cdiv(m->ncells, 8) * 8), 128, 0, c->s>>>(mark_args(c, m, cover), nb);
 }
 
 // Sort the fixed contact spheres into a uniform grid over the lattice (one
@@ -820,6 +913,44 @@ static int build_sphere_grid(lbm_ctx *c, const ibm_contact *k) {
     HIPCHK(hipMemcpy(c->sph_items, items.data(), 4 * (size_t)ns, hipMemcpyHostToDevice));
     c->sph_src = k->spheres;
     c->sph_n = ns;
+    return LBM_OK;
+}
+
+// Buffers of the next-step records (k_next_list), sized for every IB point
+// of the meshes seen so far (at most 8 stencil nodes each, and at most N).
+// Called from ibm_rest_shape, which waits on the stream anyway.
+static int ensure_records(lbm_ctx *c, int nverts) {
+    if (!c->rec_capable) return LBM_OK;
+    c->nx_pts += nverts;
+    const size_t tn = (size_t)c->ntiles, tpad = (size_t)cdiv((int64_t)tn, 16) * 16;
+    if (!c->nx_need) {
+        if (hipMalloc(&c->nx_need, c->N) != hipSuccess || hipMalloc(&c->nx_tneed, tpad) != hipSuccess ||
+            hipMalloc(&c->nx_ent, 16 * tn) != hipSuccess ||
+            hipMalloc(&c->nx_flags, 8) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "allocating the next-step marks failed");
+        }
+        HIPCHK(hipMemsetAsync(c->nx_need, 0, c->N, c->s));
+        HIPCHK(hipMemsetAsync(c->nx_tneed, 0, tpad, c->s));
+        HIPCHK(hipMemsetAsync(c->nx_ent, 0, 16 * tn, c->s));
+        HIPCHK(hipMemsetAsync(c->nx_flags, 0, 8, c->s));
+    }
+    const int64_t want = std::min<int64_t>(c->N, 8 * c->nx_pts);
+    if (want > c->nx_cap) {
+        drop_graph(c);  // captured steps name the old record
+        for (void *b : {(void *)c->nx_node, c->nx_rec})
+            if (b) HIPCHK(hipFree(b));
+        c->nx_node = nullptr;
+        c->nx_rec = nullptr;
+        c->nx_cap = 0;
+        c->rec_valid = false;
+        if (hipMalloc(&c->nx_node, 4 * (size_t)want) != hipSuccess ||
+            hipMalloc(&c->nx_rec, (size_t)Q * want * c->rsize) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(LBM_ENOMEM, "allocating the next-step record (%lld slots) failed", (long long)want);
+        }
+        c->nx_cap = want;
+    }
     return LBM_OK;
 }
 
@@ -910,6 +1041,7 @@ LBM_API int ibm_rest_shape(lbm_ctx *c, ibm_mesh *m) {
         }
         c->srec_cap = need_rec;
     }
+    if (int rc = ensure_records(c, m->nverts)) return rc;
     if (!c->owner) {
         if (hipMalloc(&c->owner, 4 * c->N) != hipSuccess) {
             (void)hipGetLastError();
@@ -1007,9 +1139,28 @@ static void launch_contact(lbm_ctx *c, const ibm_mesh *m) {
     k_contact_cells<R><<<grid, kContactThreads, 3 * (size_t)m->max_cell_verts * 8, c->s>>>(a);
 }
 
-static void launch_compact(lbm_ctx *c) {
+static void launch_compact(lbm_ctx *c, const uint32_t *gate = nullptr) {
     k_compact<<<(int)cdiv(c->ntiles, kCompactThreads * kCompactPerThread), kCompactThreads, 0, c->s>>>(
-        c->tneed, c->ntiles, c->tlist, c->tcount);
+        c->tneed, c->ntiles, c->tlist, c->tcount, gate);
+}
+
+template <class S, class R, bool DEV>
+static void launch_velocity_records(lbm_ctx *c) {
+    VelRecArgs a{};
+    a.rec = c->nx_rec;
+    a.cap = c->nx_cap;
+    a.node = c->nx_node;
+    a.count = c->nx_flags;
+    a.cls = c->cls;
+    a.gfield = c->p.gfield;
+    a.ufield = c->ufield;
+    a.N = c->N;
+    for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(c->nx_cap, 256), 16384));
+    if (c->p.gfield)
+        k_velocity_records<S, R, DEV, true><<<nb, 256, 0, c->s>>>(a);
+    else
+        k_velocity_records<S, R, DEV, false><<<nb, 256, 0, c->s>>>(a);
 }
 
 template <class S, class R, bool DEV>
@@ -1018,6 +1169,8 @@ static void launch_node_velocity(lbm_ctx *c, const void *f) {
     a.f = f;
     a.stride = c->stride;
     a.cls = c->cls;
+    a.links = c->links;
+    for (int d = 0; d < 3; d++) a.per[d] = c->p.periodic[d];
     a.gfield = c->p.gfield;
     a.ufield = c->ufield;
     a.need = c->need;
@@ -1033,9 +1186,13 @@ static void launch_node_velocity(lbm_ctx *c, const void *f) {
         k_node_velocity<S, R, DEV, false><<<waves_grid(c), 256, 0, c->s>>>(a);
 }
 
-template <class R>
-static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
+static CoupleArgs couple_args(lbm_ctx *c, const ibm_mesh *m, bool next, bool reset) {
     CoupleArgs a{};
+    if (next) {
+        a.nx_need = c->nx_need;
+        a.nx_tneed = c->nx_tneed;
+    }
+    if (reset) a.nx_count = c->nx_flags;
     a.ufield = c->ufield;
     a.srec = c->srec;
     a.chans = c->chans;
@@ -1071,6 +1228,14 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
         }
     }
     a.nb = (int)cdiv(m->max_cell_verts, 128);
+    return a;
+}
+
+// Steps 1-3 of the points: interpolation and coupling force (k_couple),
+// then the spread of -F_c.
+template <class R>
+static void launch_couple(lbm_ctx *c, const ibm_mesh *m, bool reset = false) {
+    const CoupleArgs a = couple_args(c, m, false, reset);
     k_couple<R><<<(unsigned)(a.nb * cdiv(m->ncells, 8) * 8), 128, 0, c->s>>>(a);
     SpreadArgs sp{};
     sp.vert_off = m->vert_off;
@@ -1088,52 +1253,84 @@ static void launch_couple(lbm_ctx *c, const ibm_mesh *m) {
     k_spread_cells<R><<<m->ncells, kSpreadThreads, spread_lds_bytes<R>(sp.pmax, sp.maxv), c->s>>>(sp);
 }
 
+// Step 4 of the points (needs the membrane force), and the next step's marks.
+template <class R>
+static void launch_move(lbm_ctx *c, const ibm_mesh *m, bool next) {
+    const CoupleArgs a = couple_args(c, m, next, false);
+    k_move<R><<<(unsigned)(a.nb * cdiv(m->ncells, 8) * 8), 128, 0, c->s>>>(a);
+}
+
 // The immersed-boundary half of a coupled step with the populations f.
 // With `overlap`, the membrane (and cell-cell contact) forces run on the
-// side stream while the stencil nodes are marked, the marked tiles listed
-// and their nodes' velocities evaluated; the point update waits for both.
+// side stream while the stencil nodes are marked, their velocities
+// evaluated, the points' coupling forces computed and spread; the point
+// update waits for both.
 // The membrane is launched first: its workgroups (a few per compute unit,
 // each holding its cell in LDS) then hold their slots before the velocity
 // pass fills the chip.  Without it (the adjoint's recomputed steps, small
 // and bound by launch latency) the membrane kernel also sets the marks and
 // everything runs in order on the caller's stream.  Everything is joined back into the caller's
 // stream before the call returns.
+//
+// `plain` marks a coupling of the context's own current state in a forward
+// run.  There, when the last collide-stream pass recorded the nodes marked
+// for this step, the stencil nodes' velocities come from those records
+// (once per step, for all meshes coupled in it); the marking checks every
+// stencil node against the recorded ones, and a node they miss (positions
+// changed by the caller, a mesh not marked in the step before) lists the
+// marked tiles for the gather pass, which recomputes every marked node from
+// the lattice with the same operations, so either way the bits are the same.
+// The point update then marks the stencils of the new positions for the
+// records of the coming pass, while the record has room for them.
 template <class S, class R, bool DEV>
-static void enqueue_couple_as(lbm_ctx *c, const ibm_mesh *m, const void *f, bool overlap) {
+static void enqueue_couple_as(lbm_ctx *c, const ibm_mesh *m, const void *f, bool overlap, bool plain) {
     c->acc = c->couples > 0;  // read by the mark and spread launches below
     c->couples++;
-    if (!overlap) {
-        launch_membrane<R>(c, m, false, true);
-        launch_contact<R>(c, m);
-        launch_compact(c);
+    const bool rec = plain && c->rec_valid;
+    const bool next = plain && c->rec_mode && c->rec_capable && c->nx_rec &&
+                      (c->nx_pending + m->nverts) * 8 <= c->nx_cap;
+    const bool reset = plain && c->nx_rec;
+    auto velocities = [&] {
+        if (rec && !c->u_from_rec) {
+            launch_velocity_records<S, R, DEV>(c);
+            c->u_from_rec = true;
+        }
+        launch_compact(c, rec ? c->nx_flags + 1 : nullptr);
         launch_node_velocity<S, R, DEV>(c, f);
-        launch_couple<R>(c, m);
-        return;
+    };
+    if (!overlap) {
+        launch_membrane<R>(c, m, false, true, rec);
+        launch_contact<R>(c, m);
+        velocities();
+        launch_couple<R>(c, m, reset);
+    } else {
+        const hipStream_t user = c->s;
+        (void)hipEventRecord(c->ev_fork, user);
+        (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+        c->s = c->side;
+        launch_membrane<R>(c, m, false);
+        launch_contact<R>(c, m);
+        (void)hipEventRecord(c->ev_join, c->side);
+        c->s = user;
+        launch_mark<R>(c, m, rec);
+        velocities();
+        launch_couple<R>(c, m, reset);
+        (void)hipStreamWaitEvent(user, c->ev_join, 0);
     }
-    const hipStream_t user = c->s;
-    (void)hipEventRecord(c->ev_fork, user);
-    (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
-    c->s = c->side;
-    launch_membrane<R>(c, m, false);
-    launch_contact<R>(c, m);
-    (void)hipEventRecord(c->ev_join, c->side);
-    c->s = user;
-    launch_mark<R>(c, m);
-    launch_compact(c);
-    launch_node_velocity<S, R, DEV>(c, f);
-    (void)hipStreamWaitEvent(user, c->ev_join, 0);
-    launch_couple<R>(c, m);
+    launch_move<R>(c, m, next);
+    if (next) c->nx_pending += m->nverts;
+    c->last_rec = rec;
 }
-static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f, bool may_overlap = true) {
+static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m, const void *f, bool may_overlap = true, bool plain = false) {
     const bool overlap =
         may_overlap && (c->ibm_overlap == 1 || (c->ibm_overlap == -1 && m->nverts >= LBM_OVERLAP_MIN_POINTS));
     switch (c->p.prec) {
-        case LBM_F64: enqueue_couple_as<double, double, false>(c, m, f, overlap); break;
-        case LBM_F32: enqueue_couple_as<float, float, false>(c, m, f, overlap); break;
-        default: enqueue_couple_as<float, float, true>(c, m, f, overlap); break;
+        case LBM_F64: enqueue_couple_as<double, double, false>(c, m, f, overlap, plain); break;
+        case LBM_F32: enqueue_couple_as<float, float, false>(c, m, f, overlap, plain); break;
+        default: enqueue_couple_as<float, float, true>(c, m, f, overlap, plain); break;
     }
 }
-static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m) { enqueue_couple(c, m, cur_f(c)); }
+static void enqueue_couple(lbm_ctx *c, const ibm_mesh *m) { enqueue_couple(c, m, cur_f(c), true, true); }
 
 // A mesh is ready for coupled steps when ibm_rest_shape has seen it in its
 // current form and the context's sphere grid is the one of its spheres.
@@ -1178,6 +1375,7 @@ static int capture_slot(lbm_ctx *c, int slot, uint64_t key, F &&enqueue) {
     c->s = user;
     c->cur = cur0;
     c->steps = steps0;
+    c->g_rec_end[slot] = c->rec_valid;  // every replay ends with the records as the capture left them
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(LBM_EHIP, "capturing a graph failed: %s", hipGetErrorString(e));
@@ -1203,10 +1401,12 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
         if (int rc = check_mesh_ready(c, m)) return rc;
     }
     int32_t left = nsteps;
-    if (c->couples > 0 && left > 0 && steps_per_graph > 0) {
-        // a mesh coupled before this call left its spread force pending: the
-        // first step adds to it (every captured step starts from none), so it
-        // runs as ordinary launches
+    // The first step runs as ordinary launches when a mesh coupled before
+    // this call left its spread force pending (the first step adds to it;
+    // every captured step starts from none), or when the next-step records
+    // are not there yet (the captured steps then all find them).
+    const bool first_records = m && c->rec_mode && c->rec_capable && c->nx_rec && !c->rec_valid;
+    if ((c->couples > 0 || first_records) && left > 0 && steps_per_graph > 0) {
         if (m) enqueue_couple(c, m);
         enqueue_steps(c, 1);
         left--;
@@ -1216,6 +1416,8 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
         key.mix(G_RUN);
         key.mix((uint64_t)steps_per_graph);
         key.mix((uint64_t)c->cur);
+        key.mix((uint64_t)c->rec_valid);
+        key.mix((uint64_t)(c->nx_rec != nullptr) | (uint64_t)c->rec_mode << 1);
         key.mix(mesh_launch_key(m));
         if (int rc = capture_slot(c, G_RUN, key.h | 1ull, [&] {
                 for (int k = 0; k < steps_per_graph; k++) {
@@ -1228,6 +1430,9 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
             HIPCHK(hipGraphLaunch(c->gx[G_RUN], c->s));
             c->steps += steps_per_graph;  // an even number of swaps: the parity is unchanged
         }
+        c->rec_valid = c->g_rec_end[G_RUN];
+        c->u_from_rec = false;
+        c->nx_pending = 0;
     }
     for (int32_t k = 0; k < left; k++) {
         if (m) enqueue_couple(c, m);
@@ -1381,6 +1586,7 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     for (int d = 0; d < 3; d++) a.g[d] = c->p.body_force[d];
     a.omega = 1.0 / c->p.tau;
     a.kf = 1.0 - 0.5 / c->p.tau;
+    for (int d = 0; d < 3; d++) a.per[d] = c->p.periodic[d];
     const CsShape sh = cs_shape(c);
     a.remap = sh.remap;
     a.wgtab = sh.tab;
@@ -1460,6 +1666,8 @@ LBM_API int lbm_adjoint_step(lbm_ctx *c, const ibm_mesh *m, const void *f_n, con
         if (!c->owner) return fail(LBM_ESTATE, "call ibm_rest_shape first");
     }
     if (int rc = ensure_adjoint(c, m)) return rc;
+    c->rec_valid = false;  // the recomputed step reuses the velocity field and the marks
+    c->u_from_rec = false;
     enqueue_adjoint(c, m, f_n, x_n, v_n, lam_next, lam, lam_x, lam_v, dgrad);
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -1517,6 +1725,9 @@ LBM_API int lbm_run_record(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, void *
         enqueue();
     }
     c->couples = 0;  // the last recorded step consumed every spread force
+    c->rec_valid = false;  // its passes record nothing
+    c->u_from_rec = false;
+    c->nx_pending = 0;
     c->steps += nsteps;
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -1533,6 +1744,8 @@ LBM_API int lbm_adjoint_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, const
         return fail(LBM_EINVAL, "lam_x and lam_v must be non-NULL and 8-byte aligned");
     if (nsteps == 0) return LBM_OK;
     if (int rc = ensure_adjoint(c, m)) return rc;
+    c->rec_valid = false;  // the recomputed steps reuse the velocity field and the marks
+    c->u_from_rec = false;
     const size_t fb = 19 * (size_t)c->stride * c->rsize;
     const size_t nv3 = m ? 3 * (size_t)m->nverts : 0;
     const char *F = static_cast<const char *>(f_rec);

@@ -95,6 +95,18 @@ class Lattice:
         """1: membrane forces beside the velocity pass, 0: in order, -1: by mesh size."""
         _lib.check(self.lib.lbm_set_ibm_overlap(self.ctx, int(mode)))
 
+    def set_node_records(self, mode: int = 1) -> None:
+        """1: stencil-node velocities from the populations the last collide-stream
+        pass recorded for them; 0: gathered from the lattice every step."""
+        _lib.check(self.lib.lbm_set_node_records(self.ctx, int(mode)))
+
+    def node_records_used(self):
+        """(used, missed) of the last coupling: velocities read from the
+        records, and whether a stencil node was missing from them."""
+        u, m = C.c_int32(), C.c_int32()
+        _lib.check(self.lib.lbm_node_records_used(self.ctx, C.byref(u), C.byref(m)))
+        return bool(u.value), bool(m.value)
+
     # -- the four calls of the path --------------------------------------
     def step(self, nsteps: int = 1) -> None:
         _lib.check(self.lib.lbm_step(self.ctx, int(nsteps)))
