@@ -9,8 +9,10 @@ tau 0.7, FP32 deviation storage.  A second leg times the batched form: the
 64-channel gap sweep as one batch against the same channels run one after
 another; a third the differentiation form: a checkpointed 300-step run and
 its backward pass against the plain forward run; a fourth the cost of the
-contact forces (collisions) on the main workload; a fifth the gap pass /
-no-pass sweep with those forces.  Prints ONE JSON line.
+contact forces (collisions) on the main workload; a fifth the minimum-gap
+experiment (gap ladders of tumour and red cells, run until each cell has
+passed or stalled); then the magnetic bead stage, the staged filter run
+through frozen bead chains and a red-cell suspension.  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -47,6 +49,17 @@ MEASURED_TRAFFIC = {"sha": "347e02d5cf2a226b", "bytes_per_launch": 2.6229e9}
 KERNEL_SOURCES = ["paper_1110_0995_amd/csrc/lattice_kernels.hpp", "paper_1110_0995_amd/csrc/d3q19.hpp"]
 
 
+def whole_step(lattice_bytes: float, ms_step: float) -> dict:
+    """The collide-stream's algorithmic bytes over the time of the whole
+    coupled step (membrane, IBM and lattice pass): the fraction of the HBM
+    peak the step as a whole runs at.  The immersed-boundary kernels' own
+    bytes are not added (a few per cent of the lattice's), so the figure is
+    a slight underestimate."""
+    gbs = lattice_bytes / (ms_step * 1e-3) / 1e9
+    return {"bytes": int(lattice_bytes), "ms": round(ms_step, 5), "achieved": round(gbs, 1),
+            "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def kernel_sha() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -76,9 +89,11 @@ def describe(s, prec):
     return d
 
 
-def cpu_baseline(s, prec, steps, lbm_mod):
-    """The FP64 oracle on the host cores for a bounded number of steps of the
-    same workload; also the GPU's error against it after those steps."""
+def cpu_baseline(s, prec, steps, err_steps, lbm_mod):
+    """The FP64 oracle on the host cores: its rate is timed over the first
+    ``steps`` coupled steps of the same workload; it then goes on to
+    ``err_steps`` steps, where the GPU's state (same start, same number of
+    steps) is compared with it."""
     import oracle
     oracle.build()
     L = oracle.Lattice.from_scenario(s)
@@ -91,29 +106,35 @@ def cpu_baseline(s, prec, steps, lbm_mod):
         V = np.zeros_like(X)
     f = L.rest()
     t0 = time.perf_counter()
-    oracle.run(L, M, f, X, V, nsteps=steps)
+    f = oracle.run(L, M, f, X, V, nsteps=steps)
     dt = time.perf_counter() - t0
+    if err_steps > steps:
+        f = oracle.run(L, M, f, X, V, nsteps=err_steps - steps)
+    n_err = max(steps, err_steps)
     # GPU from the same start
     lat = lbm_mod.Lattice.from_scenario(s, prec=prec)
     mesh = lbm_mod.Mesh(lat, s.cells) if s.cells is not None else None
-    lat.run(steps, mesh)
-    _, ug = lat.fields()
+    lat.run(n_err, mesh)
+    rho_g, ug = lat.fields()
     ug = ug.double().cpu().numpy()
-    _, uo = oracle.fluid_velocity(L, f)
+    rho_g = rho_g.double().cpu().numpy()
+    rho_o, uo = oracle.fluid_velocity(L, f)
     fl = s.solid.reshape(-1) == 0
     err = float(np.linalg.norm(ug[:, fl] - uo[:, fl]) / np.linalg.norm(uo[:, fl]))
+    merr = abs(float(rho_g[fl].sum()) - float(np.asarray(rho_o)[fl].sum())) / float(np.asarray(rho_o)[fl].sum())
     perr = float(np.abs(mesh.positions() - X).max()) if mesh is not None else None
     lat.close()
     return ({"value": s.n * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
-             "sample": f"{steps} full coupled steps of the same workload in FP64 ({dt:.1f} s)"},
-            {"u_rel_l2": err, "max_position_err": perr, "steps": steps})
+             "sample": f"the first {steps} full coupled steps of the same workload in FP64 ({dt:.1f} s)"},
+            {"u_rel_l2": err, "mass_rel_err": merr, "max_position_err": perr, "steps": n_err})
 
 
-def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool) -> dict:
+def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool, err_steps: int = 200) -> dict:
     """The 64-channel gap sweep stepped as one batch (one launch per kernel
     for all channels, graph-captured steps, autotuned launch shape) against
     the same 64 channels run one after another as plain single-channel
-    contexts with ordinary launches."""
+    contexts with ordinary launches.  The batch's collide-stream launch is
+    timed with HIP events over eager steps after the graph-timed run."""
     import torch
     from paper_1110_0995_amd import autotune
     from paper_1110_0995_amd import scenario as S
@@ -132,18 +153,18 @@ def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool) -> dict:
         import oracle
         k = min(range(len(scs)), key=lambda i: scs[i].n)
         s = scs[k]
-        lat.run(4, mesh)
+        lat.run(err_steps, mesh)
         _, ug = lat.fields()
         ug = ug[:, lat.channel(k)].double().cpu().numpy()
         L = oracle.Lattice.from_scenario(s)
         M = oracle.Mesh(s.cells)
         X = s.cells.positions()
         M.rest_shape(X)
-        f = oracle.run(L, M, L.rest(), X, np.zeros_like(X), nsteps=4)
+        f = oracle.run(L, M, L.rest(), X, np.zeros_like(X), nsteps=err_steps)
         _, uo = oracle.fluid_velocity(L, f)
         fl = s.solid.reshape(-1) == 0
         err = {"channel": k, "u_rel_l2": float(np.linalg.norm(ug[:, fl] - uo[:, fl]) / np.linalg.norm(uo[:, fl])),
-               "steps": 4}
+               "steps": err_steps}
     best = autotune.tune(lat, mesh)
     g = best["steps_per_graph"]
     K = max(g, steps - steps % g)
@@ -155,6 +176,16 @@ def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool) -> dict:
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / K
+    # the collide-stream launch alone: eager steps, events around lbm_step
+    cs = []
+    for _ in range(10):
+        lat.couple(mesh)
+        a.record(stream)
+        lat.step(1)
+        b.record(stream)
+        torch.cuda.synchronize()
+        cs.append(a.elapsed_time(b))
+    ms_cs = float(np.mean(cs))
     sums = lat.sums()
     lat.close()
     del lat, mesh
@@ -176,6 +207,12 @@ def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool) -> dict:
     for la, _ in runs:
         la.close()
     N = out["nodes"]
+    bpn = bytes_per_node(prec)
+    gbs = bpn * N / (ms_cs * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "kernel": "k_collide_stream", "bytes_per_node": bpn,
+                       "ms_per_launch": round(ms_cs, 5), "launches_timed": len(cs), "achieved": round(gbs, 1),
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out["whole_step"] = whole_step(bpn * N, ms)
     out.update(steps=K, ms_per_step=round(ms, 5), mlups=round(N / (ms * 1e-3) / 1e6, 1),
                sequential_ms_per_step=round(ms_seq, 5), sequential_mlups=round(N / (ms_seq * 1e-3) / 1e6, 1),
                speedup=round(ms_seq / ms, 3), launch=best, mass=sums[0])
@@ -285,28 +322,42 @@ def contact_leg(lbm_mod, steps: int) -> dict:
     return out
 
 
-def sweep_leg(lbm_mod, steps: int) -> dict:
-    """The gap pass / no-pass experiment on the 64-channel sweep: the batch
-    stepped with the contact forces of the collisions, every cell tracked
-    through its channel's post pair; reports the gaps passed, the smallest
-    one, and the wall-clock rate including the tracking."""
+LADDER_GAPS = {"tumour": range(2, 17), "red": range(1, 9)}
+
+
+def sweep_leg(lbm_mod, max_steps: int, drivings=(5e-5, 2.5e-5)) -> dict:
+    """The minimum-gap experiment of Sec. 3 as gap ladders: one channel per
+    gap (1 LU = 1 um steps; tumour cells 2..16, red cells 1..8), closed across
+    its width except for the opening, one Table 1 cell centred on the
+    opening; both ladders stepped as one batch with the contact forces
+    until every cell has passed the posts or stalled in front of them.
+    Reports per cell type the pass / stall curve and the smallest passing
+    gap, for each driving body force (the physical calibration of the
+    paper's 460 um/s is not available, so the result is given against the
+    driving)."""
     import torch
     from paper_1110_0995_amd import scenario as S
     from paper_1110_0995_amd import sweep
-    scs = S.gap_sweep()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    tr = sweep.run_sweep(lbm_mod, scs, steps, check_every=100)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    summ = tr.summary()
-    nodes = sum(s.n for s in scs)
-    return {"workload": "gap_sweep + contact", "channels": len(scs), "steps": steps, "check_every": 100,
-            "wall_s": round(dt, 3), "mlups_incl_setup_and_tracking": round(nodes * steps / dt / 1e6, 1),
-            "gaps": sorted({r["gap"] for r in summ}),
-            "passed_gaps": sorted({r["gap"] for r in summ if r["passed"]}),
-            "through": sum(r["through"] for r in summ), "around": sum(r["around"] for r in summ),
-            "min_passing_gap": tr.min_passing_gap()}
+    out = {"workload": "gap ladders 80x32x24 per channel, 1 cell per channel, contact, f32dev",
+           "gaps": {k: [min(v), max(v)] for k, v in LADDER_GAPS.items()}, "max_steps": max_steps,
+           "check_every": 250, "stall": "centroid advanced < 0.05 LU over 2000 steps, after 2000 steps",
+           "runs": []}
+    for gx in drivings:
+        scs = [s for cell, gaps in LADDER_GAPS.items() for s in S.gap_ladder(cell, gaps, gx=gx)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = sweep.run_ladder(lbm_mod, scs, max_steps, check_every=250)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        nodes = sum(s.n for s in scs)
+        summ = sweep.ladder_summary(tr.results())
+        out["runs"].append({"gx": gx, "channels": len(scs), "steps_run": tr.steps_run, "wall_s": round(dt, 3),
+                            "mlups_incl_setup_and_tracking": round(nodes * tr.steps_run / dt / 1e6, 1),
+                            "per_type": {cell: {k: d[k] for k in ("gaps", "outcome", "steps", "monotone",
+                                                                  "min_passing_gap", "max_stalling_gap",
+                                                                  "undecided", "non_finite")}
+                                         for cell, d in summ.items()}})
+    return out
 
 
 # FP64 operations of one dipole pair (Eq. interaction) plus the repulsion
@@ -315,6 +366,29 @@ def sweep_leg(lbm_mod, steps: int) -> dict:
 # the bracket and scale 19, accumulation 3, surface gap 1
 FLOPS_PER_PAIR = 53
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def magnet_executed_flops(n: int, periodic_axes: int) -> float:
+    """FP64 operations the pair kernel issues for n beads: it splits the
+    beads into blocks of 64 w (w waves per workgroup, the largest of 4, 2
+    giving at least 2048 block pairs, else 1); a diagonal block evaluates all
+    c^2 ordered pairs of its c beads (the bead with itself masked, not
+    skipped), an off-diagonal block pair each unordered pair once, adding
+    the reaction to the partner's sum (3 more).  Each evaluation also does the
+    minimum image on the periodic axes (a product and a fused multiply-add,
+    3 per axis)."""
+    w = 1
+    for cand in (4, 2):
+        nb = -(-n // (64 * cand))
+        if nb * (nb + 1) // 2 >= 2048:
+            w = cand
+            break
+    B = 64 * w
+    sizes = [min(B, n - i) for i in range(0, n, B)]
+    diag = sum(c * c for c in sizes)
+    off = (n * n - diag) // 2
+    per = 3 * periodic_axes
+    return float(off * (FLOPS_PER_PAIR + 3 + per) + diag * (FLOPS_PER_PAIR + per))
 
 
 def magnet_leg(steps: int) -> dict:
@@ -345,9 +419,16 @@ def magnet_leg(steps: int) -> dict:
     x = b.positions()
     pairs = st.n * (st.n - 1)
     tflops = pairs * FLOPS_PER_PAIR / (ms * 1e-3) / 1e12
+    exe = magnet_executed_flops(st.n, int(sum(st.periodic))) / (ms * 1e-3) / 1e12
     return {"workload": "bead_stage 512x256x128, 16384 beads a=1.5, 2 sheets + bias, f64", "steps": steps,
             "ms_per_step": round(ms, 5), "pair_interactions_per_s": round(pairs / (ms * 1e-3), 1),
-            "fp64_tflops_step": round(tflops, 2), "frac_of_fp64_vector_peak": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "definition_equivalent": {
+                "what": "n(n-1) ordered pairs x 53 FP64 ops over the whole step (the all-pairs sum as written)",
+                "tflops": round(tflops, 2), "frac_of_fp64_vector_peak": round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4)},
+            "executed": {
+                "what": "FP64 ops the pair kernel issues (each unordered pair once + reaction, diagonal blocks "
+                        "all c^2, minimum image) over the whole step",
+                "tflops": round(exe, 2), "frac_of_fp64_vector_peak": round(exe / FP64_VECTOR_PEAK_TFLOPS, 4)},
             "flops_per_pair": FLOPS_PER_PAIR, "freeze_ms": round(f0.elapsed_time(f1), 4),
             "solid_fraction_after_freeze": round(float(solid.float().mean().item()), 5),
             "finite": bool(np.isfinite(x).all())}
@@ -433,13 +514,16 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="throughput")
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="oracle steps timed for the CPU baseline")
+    ap.add_argument("--error-steps", type=int, default=100,
+                    help="coupled steps after which the GPU state is compared with the oracle's")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=200,
+    ap.add_argument("--batched-steps", type=int, default=2000,
                     help="steps of the 64-channel gap sweep, batched and sequential (0 skips the leg)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward leg")
-    ap.add_argument("--sweep-steps", type=int, default=2000,
-                    help="steps of the gap pass / no-pass sweep with contact forces (0 skips the leg)")
+    ap.add_argument("--sweep-steps", type=int, default=40000,
+                    help="most steps of the gap-ladder runs (0 skips the leg); they stop once every cell is decided")
     ap.add_argument("--contact-steps", type=int, default=100,
                     help="steps of the throughput workload with and without contact forces (0 skips the leg)")
     ap.add_argument("--magnet-steps", type=int, default=200,
@@ -530,6 +614,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if prec == "f64" else "f32",
+        "precision": ("FP64 throughout" if prec == "f64" else
+                      "lattice populations stored as FP32 deviations from the weights, collision in FP32; global "
+                      "sums FP64; IB point positions, velocities, membrane geometry and elastic forces FP64"),
         "data": "synthetic",
         "config": describe(s, prec),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -537,12 +624,13 @@ def main():
                      "kernel": "k_collide_stream", "bytes_per_node": bpn, "ms_per_launch": round(ms_cs, 5),
                      "launches_timed": len(ev),
                      "kernel_sha": sha},
+        "whole_step": whole_step(bpn * s.n, ms_step),
         "fluid_mlups": round(nfluid * args.steps / (ms_total * 1e-3) / 1e6, 1),
         "ibm_ms_per_step": round(ms_step - ms_cs, 5) if mesh is not None else 0.0,
         "mass": sums[0],
     }
     if not args.no_cpu_baseline:
-        cb, perr = cpu_baseline(s, prec, args.cpu_steps, lbm)
+        cb, perr = cpu_baseline(s, prec, args.cpu_steps, args.error_steps, lbm)
         out["cpu_baseline"] = cb
         out["error_vs_oracle"] = perr
     lat.close()

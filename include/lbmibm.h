@@ -72,7 +72,7 @@ extern "C" {
 #define LBM_EINVAL (-1)     /* bad argument (sizes, tau <= 1/2, null/misaligned pointer, bad mesh) */
 #define LBM_ENOMEM (-2)     /* device allocation failed */
 #define LBM_EHIP (-3)       /* HIP runtime or launch error */
-#define LBM_ENONFINITE (-4) /* a global sum came back NaN or Inf */
+#define LBM_ENONFINITE (-4) /* a global sum, or a node's populations, came out NaN or Inf */
 #define LBM_ESTATE (-5)     /* call out of order (e.g. ibm_couple before ibm_rest_shape) */
 
 #define LBM_F64 0
@@ -244,14 +244,31 @@ int lbm_node_records_used(lbm_ctx *c, int32_t *used, int32_t *missed);
  * the results are bitwise those of the eager loop.  When a mesh was
  * coupled (ibm_couple) before the call, its spread force is still pending:
  * the first step then runs as ordinary launches, adding m's force to it as
- * the eager loop does, and the graph groups follow. */
+ * the eager loop does, and the graph groups follow.
+ *
+ * Failure detection: every collide-stream pass flags, on the device, a node
+ * whose populations are not all finite; the flag stays set until
+ * lbm_load_f64.  lbm_run ends by queueing a copy of it to the host, and a
+ * later lbm_run or lbm_step call that finds the copy landed and set returns
+ * LBM_ENONFINITE without doing anything.  Nothing waits for that copy, so the
+ * report comes one or more calls after the pass that met the values; call
+ * lbm_check_finite to wait for it. */
 int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps_per_graph);
+
+/* Wait for the stream, then *nonfinite (host, may be NULL) = 1 if a
+ * collide-stream pass since the context was made (or since the last
+ * lbm_load_f64) met non-finite populations, else 0; returns LBM_ENONFINITE
+ * in the first case.  The state is then lost: reload it (lbm_load_f64) or
+ * destroy the context. */
+int lbm_check_finite(lbm_ctx *c, int32_t *nonfinite);
 
 /* Advance the lattice nsteps >= 0 times: fused BGK collision with Guo
  * forcing (force = g + G + the immersed-boundary force spread by the last
  * ibm_couple, which this call consumes and clears), then streaming with
  * halfway bounce-back (Sec. 2.1 LBM equation, Sec. 2.4).  With cells present
- * call ibm_couple before each single step. */
+ * call ibm_couple before each single step.  Returns LBM_ENONFINITE, without
+ * stepping, once an earlier pass is known to have met non-finite
+ * populations (see lbm_run). */
 int lbm_step(lbm_ctx *c, int32_t nsteps);
 
 /* Compute the rest shape (edge lengths, triangle areas, hinge angles, cell

@@ -154,8 +154,10 @@ __global__ void k_rest(S *__restrict__ f, int64_t stride, int64_t N) {
 // f_eq = w rho (1 + 3cu + 9/2 (cu)^2 - 3/2 u.u) (DEV: minus w),
 // S_i = (1 - 1/(2 tau)) w_i (3 (c_i - u).F + 9 (c_i.u)(c_i.F)),
 // f_i <- f_i - (f_i - f_eq_i)/tau + S_i.
+// Returns the sum of the populations before the collision (of the
+// deviations, with DEV): not finite iff some population is not.
 template <class R, bool DEV>
-__device__ __forceinline__ void collide(R (&f)[Q], R Fx, R Fy, R Fz, R omega, R kf) {
+__device__ __forceinline__ R collide(R (&f)[Q], R Fx, R Fy, R Fz, R omega, R kf) {
     R s = R(0);
 #pragma unroll
     for (int i = 0; i < Q; i++) s += f[i];
@@ -179,6 +181,7 @@ __device__ __forceinline__ void collide(R (&f)[Q], R Fx, R Fy, R Fz, R omega, R 
         const R src = kf * w * (R(3) * (cF - uF) + R(9) * cu * cF);
         f[i] = f[i] - omega * (f[i] - feq) + src;
     }
+    return s;
 }
 
 // Element i of an array addressed from its base: with a 32-bit IDX the byte
@@ -256,6 +259,7 @@ struct StepArgs {
     void *erec;
     int64_t ecap;
     int per[3];  // periodic axes (a link leaving a non-periodic face bounces in place)
+    uint32_t *nonfinite;  // set to 1 by a node whose populations are not all finite (never cleared here)
 };
 
 // Number of set bits of m below this lane.
@@ -444,6 +448,7 @@ __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(
     const int y = row % ch.ny, z = row / ch.ny;
     const uint32_t links = (cl == CLS_WALL) ? at(a.links, n) : 0u;
     R f[Q];
+    R sum = R(0);  // population sum before the collision (0 for solid nodes)
     if (!solid) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
@@ -463,11 +468,14 @@ __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(
                     f[i] = R(at(fa, src));
             }
         }
-        collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
+        sum = collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
     } else {
 #pragma unroll
         for (int i = 0; i < Q; i++) f[i] = DEV ? R(0) : wgt<R>(i);
     }
+    // failure detection: a wave with a non-finite node raises the flag (a
+    // wave-uniform branch; the active lanes store the same value)
+    if (__builtin_amdgcn_ballot_w64(!__builtin_isfinite(sum))) *a.nonfinite = 1u;
 
     const int xp = (x + 1 == ch.nx) ? 0 : x + 1;
     const int xm = (x == 0) ? ch.nx - 1 : x - 1;

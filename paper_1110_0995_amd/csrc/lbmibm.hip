@@ -145,6 +145,14 @@ struct lbm_ctx {
     int64_t nparts = 0;
     double *sums = nullptr;
     double *host_sums = nullptr;
+    // non-finite populations: the collide-stream pass sets *nf_dev (sticky);
+    // lbm_run ends by queueing its copy into pinned *nf_host (ev_nf after
+    // the last one), which later lbm_run / lbm_step calls read without
+    // waiting: a copy still in flight only delays the report
+    uint32_t *nf_dev = nullptr;
+    uint32_t *nf_host = nullptr;
+    hipEvent_t ev_nf = nullptr;
+    bool nf_pending = false;  // a copy may still be in flight
     int cur = 0;  // 0: state in f_a, 1: in f_b
     int64_t steps = 0;
     // launch shape
@@ -333,16 +341,17 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     drop_graph(c);
     if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
     if (c->side) (void)hipStreamDestroy(c->side);
-    for (hipEvent_t e : {c->ev_fork, c->ev_join})
+    for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_nf})
         if (e) (void)hipEventDestroy(e);
     void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
                     c->sph_start, c->sph_items, c->wgtab, c->nx_need, c->nx_tneed, c->nx_ent,
-                    c->nx_flags, c->nx_node, c->nx_rec};
+                    c->nx_flags, c->nx_node, c->nx_rec, c->nf_dev};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->host_sums) (void)hipHostFree(c->host_sums);
+    if (c->nf_host) (void)hipHostFree(c->nf_host);
     delete c;
 }
 
@@ -369,15 +378,18 @@ static int init_ctx(lbm_ctx *c) {
         hipMalloc(&c->tcount, 4) != hipSuccess || hipMalloc(&c->epoch, 4) != hipSuccess ||
         hipMalloc(&c->ftile, tpad) != hipSuccess ||
         hipMalloc(&c->partials, c->nparts * 4 * sizeof(double)) != hipSuccess ||
-        hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&c->sums, 4 * sizeof(double)) != hipSuccess || hipMalloc(&c->nf_dev, 4) != hipSuccess ||
         (c->nch > 1 && hipMalloc(&c->tile_chan, 2 * tn) != hipSuccess) ||
-        hipHostMalloc(&c->host_sums, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&c->host_sums, 4 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(&c->nf_host, 4, hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         return fail(LBM_ENOMEM, "device allocation of the context work buffers failed");
     }
     HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_nf, hipEventDisableTiming));
+    *c->nf_host = 0;
     HIPCHK(hipMemcpy(c->chans, c->hchans.data(), sizeof(Chan) * c->nch, hipMemcpyHostToDevice));
     {
         std::vector<uint32_t> tab;
@@ -408,6 +420,7 @@ static int init_ctx(lbm_ctx *c) {
     HIPCHK(hipMemsetAsync(c->ftile, 0, tpad, c->s));
     HIPCHK(hipMemsetAsync(c->tcount, 0, 4, c->s));
     HIPCHK(hipMemsetAsync(c->epoch, 0, 4, c->s));
+    HIPCHK(hipMemsetAsync(c->nf_dev, 0, 4, c->s));
     const int nb = (int)cdiv(c->N, 256);
     for (void *f : {p->f_a, p->f_b}) {
         switch (p->prec) {
@@ -585,7 +598,34 @@ static StepArgs step_args(const lbm_ctx *c) {
     a.omega = 1.0 / c->p.tau;
     a.kf = 1.0 - 0.5 / c->p.tau;
     for (int d = 0; d < 3; d++) a.per[d] = c->p.periodic[d];
+    a.nonfinite = c->nf_dev;
     return a;
+}
+
+// LBM_ENONFINITE once a copy of the flag queued by an earlier lbm_run has
+// landed with it set; never waits (the flag only goes from 0 to 1 between
+// resets, so a stale read just reports later).
+static int nonfinite_reported(lbm_ctx *c) {
+    if (__atomic_load_n(c->nf_host, __ATOMIC_ACQUIRE))
+        return fail(LBM_ENONFINITE, "a collide-stream pass met non-finite populations (state is lost)");
+    return LBM_OK;
+}
+
+// Queue the copy of the device flag that nonfinite_reported reads later.
+static int queue_nonfinite_copy(lbm_ctx *c) {
+    HIPCHK(hipMemcpyAsync(c->nf_host, c->nf_dev, 4, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipEventRecord(c->ev_nf, c->s));
+    c->nf_pending = true;
+    return LBM_OK;
+}
+
+// Clear the flag and its host copy (no copy left in flight to undo it).
+static int reset_nonfinite(lbm_ctx *c) {
+    if (c->nf_pending) HIPCHK(hipEventSynchronize(c->ev_nf));
+    c->nf_pending = false;
+    __atomic_store_n(c->nf_host, 0u, __ATOMIC_RELEASE);
+    HIPCHK(hipMemsetAsync(c->nf_dev, 0, 4, c->s));
+    return LBM_OK;
 }
 
 static PopView pop_view(const lbm_ctx *c) {
@@ -646,6 +686,7 @@ static void enqueue_steps(lbm_ctx *c, int32_t nsteps) {
 LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     if (!c) return fail(LBM_EINVAL, "context is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (int rc = nonfinite_reported(c)) return rc;
     enqueue_steps(c, nsteps);
     HIPCHK(hipGetLastError());
     return LBM_OK;
@@ -711,6 +752,7 @@ LBM_API int lbm_load_f64(lbm_ctx *c, const double *f64) {
     if ((uintptr_t)f64 % 8) return fail(LBM_EINVAL, "f64 misaligned");
     c->rec_valid = false;  // the records hold the populations this replaces
     c->u_from_rec = false;
+    if (int rc = reset_nonfinite(c)) return rc;  // a new state: forget earlier reports
     const int nb = (int)cdiv(c->N, 256);
     void *f = const_cast<void *>(cur_f(c));
     switch (c->p.prec) {
@@ -1400,6 +1442,7 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
         if (int rc = check_mesh_ptrs(c, m)) return rc;
         if (int rc = check_mesh_ready(c, m)) return rc;
     }
+    if (int rc = nonfinite_reported(c)) return rc;
     int32_t left = nsteps;
     // The first step runs as ordinary launches when a mesh coupled before
     // this call left its spread force pending (the first step adds to it;
@@ -1439,6 +1482,17 @@ LBM_API int lbm_run(lbm_ctx *c, const ibm_mesh *m, int32_t nsteps, int32_t steps
         enqueue_steps(c, 1);
     }
     HIPCHK(hipGetLastError());
+    return nsteps > 0 ? queue_nonfinite_copy(c) : LBM_OK;
+}
+
+LBM_API int lbm_check_finite(lbm_ctx *c, int32_t *nonfinite) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    HIPCHK(hipMemcpyAsync(c->nf_host, c->nf_dev, 4, hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    c->nf_pending = false;
+    const uint32_t bad = __atomic_load_n(c->nf_host, __ATOMIC_ACQUIRE);
+    if (nonfinite) *nonfinite = bad ? 1 : 0;
+    if (bad) return fail(LBM_ENONFINITE, "a collide-stream pass met non-finite populations (state is lost)");
     return LBM_OK;
 }
 

@@ -107,6 +107,15 @@ class Lattice:
         _lib.check(self.lib.lbm_node_records_used(self.ctx, C.byref(u), C.byref(m)))
         return bool(u.value), bool(m.value)
 
+    def check_finite(self) -> bool:
+        """Wait for the stream; False if a collide-stream pass met non-finite
+        populations (the state is then lost), True otherwise."""
+        bad = C.c_int32()
+        rc = self.lib.lbm_check_finite(self.ctx, C.byref(bad))
+        if rc not in (0, _lib.LBM_ENONFINITE):
+            _lib.check(rc)
+        return not bad.value
+
     # -- the four calls of the path --------------------------------------
     def step(self, nsteps: int = 1) -> None:
         _lib.check(self.lib.lbm_step(self.ctx, int(nsteps)))

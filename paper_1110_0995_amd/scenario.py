@@ -522,6 +522,80 @@ def gap_pair(nx: int = 64, ny: int = 32, nz: int = 24, *, gap: int = 8, post_rad
                     meta=dict(gap=gap, post_centres=centres, post_radius=post_radius))
 
 
+# Table 1 cell diameters in micrometres.  The gap ladder takes one lattice
+# spacing as one micrometre, so the paper's 1 um gap steps are 1 LU steps.
+DIAMETER_RBC = 8.0
+DIAMETER_CTC = 16.0
+# the disc's axis turned from z onto x: a red cell meets the opening face-on
+_AXIS_Z_TO_X = np.array([[0.0, 0.0, 1.0], [0.0, 1.0, 0.0], [-1.0, 0.0, 0.0]])
+
+
+def slit_posts(nx: int, ny: int, gap: int, post_radius: int, pitch: Optional[int] = None):
+    """Centres of a row of overlapping z-axis posts across the whole width of
+    a y-periodic channel at x = nx/2, leaving one opening.  At x = nx/2 the
+    fluid nodes of the opening are y0 .. y0 + gap - 1 (y0 = ny/2 - gap//2),
+    so its halfway bounce-back surfaces are exactly ``gap`` apart; posts
+    ``pitch`` apart (default the radius) overlap, so nothing else is open.
+    The two posts bounding the opening come first.  Returns (centres, the
+    y of the opening's midline)."""
+    if gap < 1:
+        raise ValueError("the opening needs at least one fluid node")
+    p = post_radius if pitch is None else pitch
+    xc = nx / 2.0
+    y0 = ny // 2 - gap // 2
+    lo, hi = y0 - 1 - post_radius, y0 + gap + post_radius
+    cen = [(xc, float(lo)), (xc, float(hi))]
+    y = hi + p
+    while y - p <= ny - 1:
+        cen.append((xc, float(y)))
+        y += p
+    y = lo - p
+    while y + p >= 0:
+        cen.append((xc, float(y)))
+        y -= p
+    return cen, y0 + (gap - 1) / 2.0
+
+
+def gap_ladder(cell: str, gaps: Sequence[int], *, nx: int = 80, ny: int = 32, nz: int = 24,
+               post_radius: int = 4, level: int = 3, tau: float = 0.8, gx: float = 5e-5,
+               clearance: float = 1.5, steps: int = 20000) -> List[Scenario]:
+    """The minimum-gap experiment of Sec. 3 for one cell type: one channel
+    per gap (gaps in lattice units = micrometres), each closed across its
+    width by a row of posts (slit_posts) except for the opening, and one cell
+    centred on the opening's midline and at mid-height, its front
+    ``clearance`` upstream of the posts' surface.  cell = "tumour": sphere
+    of diameter 16 with the tumour-cell moduli of Table 1; cell = "red":
+    biconcave disc of diameter 8 facing the opening, red-cell moduli.  Both
+    use neo-Hookean stretching and the red cells' membrane mass (so one
+    batch can hold both).  The channels share their shape, so a ladder of
+    each type can be stepped as one batch."""
+    if cell == "tumour":
+        radius, moduli, shape, rot = DIAMETER_CTC / 2.0, MODULI_CTC, "sphere", None
+    elif cell == "red":
+        radius, moduli, shape, rot = DIAMETER_RBC / 2.0, MODULI_RBC, "rbc", _AXIS_Z_TO_X
+    else:
+        raise ValueError(f"unknown cell type {cell}")
+    unit, _ = icosphere(level)
+    if shape == "rbc":
+        unit = biconcave(unit)
+    tmpl = radius * unit if rot is None else radius * unit @ rot.T
+    half_x = float(np.abs(tmpl[:, 0]).max())
+    out = []
+    for g in gaps:
+        g = int(g)
+        mask = channel_mask(nx, ny, nz)
+        cen, ymid = slit_posts(nx, ny, g, post_radius)
+        add_posts(mask, cen, post_radius)
+        face = nx / 2.0 - post_radius - 0.5  # upstream surface of the posts (halfway bounce-back)
+        c = np.array([[face - clearance - half_x, ymid, (nz - 1) / 2.0]])
+        cells = make_cells(c, radius, level, moduli, shape=shape, stretch_law=1, mass=MASS_RBC,
+                           rotations=None if rot is None else rot[None])
+        out.append(Scenario(f"{cell}_gap{g}", nx, ny, nz, tau, (gx, 0.0, 0.0), mask, steps, cells=cells,
+                            meta=dict(gap=g, cell=cell, post_centres=cen, post_radius=post_radius,
+                                      exit_x=nx / 2.0 + post_radius + 0.5, midline=ymid)))
+    return out
+
+
 def adjoint_channel(nx: int = 128, ny: int = 64, nz: int = 32, *, ncells: int = 3,
                     cell_radius: float = 4.0, level: int = 2, tau: float = 0.8, gx: float = 1e-5,
                     steps: int = 300, seed: int = 5, design_x=(32, 96)) -> Scenario:

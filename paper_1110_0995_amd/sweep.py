@@ -17,6 +17,7 @@ from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
+from . import _lib
 from . import scenario as S
 
 
@@ -89,4 +90,118 @@ def run_sweep(lbm, scenarios: Sequence[S.Scenario], nsteps: int, check_every: in
         done += n
         tr.update(mesh.positions(), done)
     lat.close()
+    return tr
+
+
+class LadderTracker:
+    """Outcome of each channel of a gap ladder (scenario.gap_ladder): its
+    cell has passed once every vertex is downstream of the posts' surface
+    (x > meta["exit_x"]); it has stalled once, after ``t_min`` steps, its
+    vertex centroid advanced less than ``stall_dist`` over the last
+    ``stall_window`` steps while still in front of that surface.  Positions
+    are unwrapped (anchor + offset), so a cell that passed cannot come back
+    into the opening through the periodic x boundary.  A channel whose
+    membrane positions stop being finite is recorded as "non-finite" (the
+    channels of a batch are independent, so the others go on)."""
+
+    def __init__(self, scenarios: Sequence[S.Scenario], vert_off: np.ndarray, chan: np.ndarray,
+                 stall_window: int = 2000, stall_dist: float = 0.05, t_min: int = 2000):
+        self.scs = list(scenarios)
+        self.vert_off = np.asarray(vert_off)
+        self.chan = np.asarray(chan, np.int64)
+        self.stall_window, self.stall_dist, self.t_min = stall_window, stall_dist, t_min
+        self.hist: List[tuple] = []  # (step, centroid x per channel)
+        self.outcome: List[Optional[str]] = [None] * len(self.scs)
+        self.at: List[Optional[int]] = [None] * len(self.scs)
+
+    def update(self, X: np.ndarray, step: int) -> None:
+        n = len(self.scs)
+        cx = np.zeros(n)
+        xmin = np.full(n, np.inf)
+        for c in range(len(self.vert_off) - 1):
+            k = int(self.chan[c])
+            v = X[self.vert_off[c]:self.vert_off[c + 1]]
+            if not np.isfinite(v).all():
+                cx[k] = np.nan
+                continue
+            cx[k] = v[:, 0].mean()
+            xmin[k] = min(xmin[k], v[:, 0].min())
+        self.hist.append((step, cx))
+        past = [h for h in self.hist if h[0] <= step - self.stall_window]
+        for k, s in enumerate(self.scs):
+            if self.outcome[k] is not None:
+                continue
+            if not np.isfinite(cx[k]):
+                self.outcome[k], self.at[k] = "non-finite", step
+            elif xmin[k] > s.meta["exit_x"]:
+                self.outcome[k], self.at[k] = "passed", step
+            elif step >= self.t_min and past and cx[k] - past[-1][1][k] < self.stall_dist:
+                self.outcome[k], self.at[k] = "stalled", step
+
+    def done(self) -> bool:
+        return all(o is not None for o in self.outcome)
+
+    def results(self) -> List[Dict]:
+        last = self.hist[-1][1] if self.hist else np.zeros(len(self.scs))
+        return [dict(channel=k, cell=s.meta["cell"], gap=s.meta["gap"], outcome=self.outcome[k] or "undecided",
+                     step=self.at[k], centroid_x=float(last[k])) for k, s in enumerate(self.scs)]
+
+
+def ladder_summary(results: Sequence[Dict]) -> Dict[str, Dict]:
+    """Per cell type: gaps in increasing order with their outcomes, whether
+    the decided outcomes are monotone in the gap (every passing gap above
+    every stalling one), the smallest passing gap (None if none passed;
+    with a non-monotone curve it is the smallest gap above every stall), and
+    the gaps whose run went non-finite."""
+    out: Dict[str, Dict] = {}
+    for cell in sorted({r["cell"] for r in results}):
+        rs = sorted((r for r in results if r["cell"] == cell), key=lambda r: r["gap"])
+        gaps = [r["gap"] for r in rs]
+        oc = [r["outcome"] for r in rs]
+        passed = [g for g, o in zip(gaps, oc) if o == "passed"]
+        nonfinite = [g for g, o in zip(gaps, oc) if o == "non-finite"]
+        stalled = [g for g, o in zip(gaps, oc) if o == "stalled"]
+        monotone = not passed or not stalled or min(passed) > max(stalled)
+        above = [g for g in passed if not stalled or g > max(stalled)]
+        out[cell] = dict(gaps=gaps, outcome=oc, steps=[r["step"] for r in rs], monotone=bool(monotone),
+                         min_passing_gap=(min(above) if above else None),
+                         max_stalling_gap=(max(stalled) if stalled else None),
+                         undecided=sum(o == "undecided" for o in oc), non_finite=nonfinite)
+    return out
+
+
+def run_ladder(lbm, scenarios: Sequence[S.Scenario], max_steps: int, check_every: int = 250,
+               prec: str = "f32dev", contact: bool = True, log=None, **track_kw) -> LadderTracker:
+    """Step the ladder channels as one batch (graph-captured groups of
+    check_every steps, contact forces of the collisions on) until every
+    channel is decided or max_steps have run.  When the library reports
+    non-finite populations the run stops there: the channels whose membranes
+    went non-finite are marked, the rest keep their outcome so far
+    (tracker.stopped says why)."""
+    lat = lbm.Lattice.batch(scenarios, prec=prec)
+    cells, chan = S.batch_cells(scenarios)
+    mesh = lbm.Mesh(lat, cells, chan, contact=S.contact_params_batch(scenarios) if contact else None)
+    tr = LadderTracker(scenarios, cells.vert_off, chan, **track_kw)
+    tr.update(mesh.positions(), 0)
+    spg = check_every if check_every % 2 == 0 else 0
+    done = 0
+    tr.stopped = None
+    try:
+        while done < max_steps and not tr.done():
+            n = min(check_every, max_steps - done)
+            try:
+                lat.run(n, mesh, steps_per_graph=spg if n == check_every else 0)
+            except _lib.LbmError as e:
+                if e.code != _lib.LBM_ENONFINITE:
+                    raise
+                tr.update(mesh.positions(), done)
+                tr.stopped = f"non-finite populations reported before step {done}"
+                break
+            done += n
+            tr.update(mesh.positions(), done)
+            if log is not None:
+                log(done, tr)
+    finally:
+        lat.close()
+    tr.steps_run = done
     return tr
