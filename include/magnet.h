@@ -94,6 +94,20 @@ int mag_forces(const mag_params *p, const double *x, double *m, double *F, void 
 /* nsteps >= 0 overdamped steps of the beads, x [3][n] advanced in place. */
 int mag_run(const mag_params *p, double *x, int32_t nsteps, void *work);
 
+/* mag_run without the work argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc): the same kernels, on the same inputs, give the
+ * same results, with their work in an array of 32 MiB that the library
+ * holds on each GPU it runs on (reserved when the library is loaded there,
+ * kept until the process ends).  The call allocates nothing.  The work of p
+ * (mag_workspace_bytes) must fit in 32 MiB -- every n up to 13184 does, and
+ * so does 16384 -- else LBM_EINVAL, before anything is enqueued.  Runs on
+ * the current device, whose stream p->stream must be.  Every call on one
+ * GPU shares its array: calls that overlap there (on two streams, or from
+ * two host threads) race and give wrong results; one call's contents
+ * survive into the next, and no part of the array needs to start at zero. */
+int mag_run_static(const mag_params *p, double *x, int32_t nsteps);
+
 /* Fix the chains: OR the bead spheres into solid [nx*ny*nz] (uint8, 1 =
  * solid); x [3][n].  Nodes are only set, never cleared. */
 int mag_freeze(const mag_params *p, const double *x, uint8_t *solid);

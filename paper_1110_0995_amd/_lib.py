@@ -21,7 +21,7 @@ EXPORTS = ("lbm_plane_stride", "lbm_workspace_bytes", "lbm_init", "lbm_init_chan
            "lbm_workspace_bytes_channels", "lbm_set_launch", "lbm_set_ibm_overlap", "lbm_set_node_records", "lbm_node_records_used", "lbm_run", "lbm_check_finite", "lbm_step",
            "ibm_rest_shape", "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp", "lbm_adjoint_step",
            "lbm_run_record", "lbm_adjoint_run", "lbm_destroy", "lbm_last_error",
-           "mag_workspace_bytes", "mag_field", "mag_forces", "mag_run", "mag_freeze")
+           "mag_workspace_bytes", "mag_field", "mag_forces", "mag_run", "mag_run_static", "mag_freeze")
 MAG_MAX_SHEETS = 8
 
 
@@ -110,13 +110,14 @@ def load() -> C.CDLL:
     L.mag_field.argtypes = [mp, vp, C.c_int32, vp, vp]
     L.mag_forces.argtypes = [mp, vp, vp, vp, vp]
     L.mag_run.argtypes = [mp, vp, C.c_int32, vp]
+    L.mag_run_static.argtypes = [mp, vp, C.c_int32]
     L.mag_freeze.argtypes = [mp, vp, vp]
     L.lbm_last_error.argtypes = []
     L.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_init", "lbm_init_channels", "lbm_set_launch", "lbm_set_ibm_overlap", "lbm_set_node_records",
                  "lbm_node_records_used", "lbm_run", "lbm_check_finite", "lbm_step",
                  "ibm_rest_shape", "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp",
-                 "lbm_adjoint_step", "lbm_run_record", "lbm_adjoint_run", "mag_field", "mag_forces", "mag_run",
+                 "lbm_adjoint_step", "lbm_run_record", "lbm_adjoint_run", "mag_field", "mag_forces", "mag_run", "mag_run_static",
                  "mag_freeze"):
         getattr(L, name).restype = C.c_int
     _lib = L

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "lbmibm.h"
 #include "magnet_kernels.hpp"
@@ -175,6 +176,47 @@ int check_work(const mag_params *p, const void *work) {
     return LBM_OK;
 }
 
+// step t: forces at x_t (moments, pairs), then x_(t+1) = x_t + mob F;
+// the move of step t is fused with the moments of step t + 1
+int run_steps(const mag_params *p, double *x, int32_t nsteps, void *work) {
+    const hipStream_t s = (hipStream_t)p->stream;
+    const MagArgs A = make_args(p, x, work);
+    if (int rc = launch_self(A, M_MOMENTS, s)) return rc;
+    for (int t = 0; t < nsteps; t++) {
+        if (int rc = launch_pairs(A, s)) return rc;
+        if (int rc = launch_self(A, t + 1 < nsteps ? (M_APPLY | M_MOMENTS) : M_APPLY, s)) return rc;
+    }
+    return LBM_OK;
+}
+
+// Work memory of mag_run_static: one array per GPU, in the code object's
+// device globals, reserved when the library is loaded on that GPU and held
+// until the process ends.  Host code reaches it only through the address
+// hipGetSymbolAddress gives for the current device (static_work); the
+// array's name is a host-side stand-in, not a device address.
+constexpr int64_t kStaticWorkBytes = int64_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+// Device address of the current device's array (looked up once per device).
+int static_work(void **out) {
+    int dev = -1;
+    MAGCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LBM_EINVAL, "device %d is beyond the %d this library tracks", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        MAGCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255) != 0) return fail(LBM_EHIP, "the static work array has no usable device address");
+        g_static_ptr[dev] = ptr;
+    }
+    *out = g_static_ptr[dev];
+    return LBM_OK;
+}
+
 }  // namespace
 
 #define MAG_API extern "C" __attribute__((visibility("default")))
@@ -227,16 +269,21 @@ MAG_API int mag_run(const mag_params *p, double *x, int32_t nsteps, void *work) 
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
     if (!x || !aligned8(x)) return fail(LBM_EINVAL, "x must be non-NULL and 8-byte aligned");
     if (nsteps == 0) return LBM_OK;
-    const hipStream_t s = (hipStream_t)p->stream;
-    const MagArgs A = make_args(p, x, work);
-    // step t: forces at x_t (moments, pairs), then x_(t+1) = x_t + mob F;
-    // the move of step t is fused with the moments of step t + 1
-    if (int rc = launch_self(A, M_MOMENTS, s)) return rc;
-    for (int t = 0; t < nsteps; t++) {
-        if (int rc = launch_pairs(A, s)) return rc;
-        if (int rc = launch_self(A, t + 1 < nsteps ? (M_APPLY | M_MOMENTS) : M_APPLY, s)) return rc;
-    }
-    return LBM_OK;
+    return run_steps(p, x, nsteps, work);
+}
+
+MAG_API int mag_run_static(const mag_params *p, double *x, int32_t nsteps) {
+    if (int rc = check_params(p)) return rc;
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
+    if (!x || !aligned8(x)) return fail(LBM_EINVAL, "x must be non-NULL and 8-byte aligned");
+    const int64_t need = work_bytes(p->n);
+    if (need > kStaticWorkBytes)
+        return fail(LBM_EINVAL, "%d beads need %lld bytes of work, more than the %lld of mag_run_static; use mag_run",
+                    p->n, (long long)need, (long long)kStaticWorkBytes);
+    void *work = nullptr;
+    if (int rc = static_work(&work)) return rc;
+    if (nsteps == 0) return LBM_OK;
+    return run_steps(p, x, nsteps, work);
 }
 
 MAG_API int mag_freeze(const mag_params *p, const double *x, uint8_t *solid) {
