@@ -45,7 +45,7 @@ def bytes_per_node(prec: str) -> int:
 # two rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE) scaled by the same
 # counters on a plain copy kernel; see profiles/.  Valid only while the
 # kernel source hashes to "sha".
-MEASURED_TRAFFIC = {"sha": "347e02d5cf2a226b", "bytes_per_launch": 2.6229e9}
+MEASURED_TRAFFIC = {"sha": "3ac8209d6b964527", "bytes_per_launch": 2.7125e9}
 KERNEL_SOURCES = ["paper_1110_0995_amd/csrc/lattice_kernels.hpp", "paper_1110_0995_amd/csrc/d3q19.hpp"]
 
 
@@ -69,9 +69,20 @@ def kernel_sha() -> str:
 
 
 def make_workload(name: str):
+    """throughput (the default), posts_cells, poiseuille; and two references
+    for the collide-stream pass alone: throughput_lattice (the throughput
+    lattice with its posts and walls, no cells, so no immersed-boundary
+    force) and periodic_box (the same 512x256x128 nodes, no solid node at
+    all, periodic on every axis: the pass's bare access pattern)."""
+    import dataclasses
     from paper_1110_0995_amd import scenario as S
     if name == "throughput":
         return S.throughput(), "f32dev"
+    if name == "throughput_lattice":
+        return dataclasses.replace(S.throughput(), name="throughput_lattice", cells=None), "f32dev"
+    if name == "periodic_box":
+        return S.Scenario("periodic_box", 512, 256, 128, 0.7, (1e-5, 0.0, 0.0), S.channel_mask(512, 256, 128, walls_z=False),
+                          1000, periodic=(1, 1, 1)), "f32dev"
     if name == "posts_cells":
         return S.posts_and_cells(), "f32dev"
     if name == "poiseuille":
