@@ -15,7 +15,7 @@
 //     repulsion of all of them, then adds it to its membrane force with
 //     three float atomics (only points in range do, so the order of these
 //     few adds is the one part of a step that is not fixed).
-// The wall part is evaluated per point inside k_couple (wall_force).
+// The wall part is evaluated per point inside the point update, k_move (wall_force).
 #pragma once
 
 #include "ibm_kernels.hpp"

@@ -25,17 +25,19 @@
 //   field (one 16-byte record per node: u_ext and rho); each node is
 //   evaluated once however many IB points use it.
 //
-// k_couple (one thread per IB point): trilinear interpolation of that field
-//   (Sec. 2.2 step 1) and the coupling force (step 2), written into a spread
-//   record: the stencil's base node, fractional offsets and the force the
-//   point exerts on the fluid (-F_c).
+// couple_record (per IB point, inside the spread's workgroup of its cell):
+//   trilinear interpolation of that field (Sec. 2.2 step 1) and the
+//   coupling force (step 2), as a spread record: the stencil's base node,
+//   fractional offsets and the force the point exerts on the fluid (-F_c).
 //
 // k_move (one thread per IB point, after the spread and the membrane
 //   kernel): the point update (step 4) with the membrane force and F_c.
 //
 // Spreading (step 3) avoids per-contribution float atomics, which run at a
 // small fraction of store throughput on this GPU:
-// k_spread_cells (one workgroup per cell) sorts the cell's records by base
+// k_spread_cells (one workgroup per cell) computes each point's record
+//   (interpolated velocity, coupling force: couple_record, also written out
+//   for the point update), sorts the records by base
 //   node in LDS, finds the cell's stencil nodes in a bitmap over the box of
 //   its base nodes and, one thread per node, sums the node's contributions
 //   in a fixed order, claims the node with one atomic exchange of the
@@ -797,28 +799,20 @@ struct CoupleArgs {
     uint32_t *nx_count;  // zeroed here (read before by this step's velocity pass, counted next by k_next_list)
 };
 
-// Steps 1-2 of a point and the input of step 3: the interpolated velocity,
-// the coupling force F_c = xi A_k (u_k - V_k), and the spread record (base
-// node, fractional offsets, -F_c).  The membrane force is not needed here,
-// so this runs while the membrane kernel is still at work.
+// Steps 1-2 of point k of cell c and the input of step 3: the interpolated
+// velocity, the coupling force F_c = xi A_k (u_k - V_k), and the spread
+// record (base node, fractional offsets, -F_c).  The membrane force is not
+// needed here, so this runs while the membrane kernel is still at work.
 template <class R>
-__global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
+__device__ __forceinline__ SRec<R> couple_record(const CoupleArgs &a, int c, int k, const Chan &ch) {
     using R4 = typename Vec4<R>::T;
-    int c, chunk;
-    xcd_cell_chunk(blockIdx.x, a.nb, c, chunk);
-    if (c >= a.ncells) return;
-    const int vb = a.vert_off[c], ve = a.vert_off[c + 1];
-    const int k = vb + chunk * blockDim.x + threadIdx.x;
-    if (k >= ve) return;
     const int NV = a.nverts;
-    if (a.nx_count && blockIdx.x == 0 && threadIdx.x == 0) *a.nx_count = 0u;
     const double *X = a.x;
     const R *Vv = static_cast<const R *>(a.v);
     const R4 *U = static_cast<const R4 *>(a.ufield);
     const double ox = X[k], oy = X[NV + k], oz = X[2 * NV + k];
     const double flx = floor(ox), fly = floor(oy), flz = floor(oz);
     const R dx = R(ox - flx), dy = R(oy - fly), dz = R(oz - flz);
-    const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
     const int x0 = pmod(a.anchor[c] + (int)flx, ch.nx);
     const int y0 = pmod(a.anchor[a.ncells + c] + (int)fly, ch.ny);
     const int z0 = pmod(a.anchor[2 * a.ncells + c] + (int)flz, ch.nz);
@@ -845,15 +839,14 @@ __global__ __launch_bounds__(128) void k_couple(CoupleArgs a) {
     const R xi = R(a.xi * ak);
     const R fcx = xi * (ux - vx), fcy = xi * (uy - vy), fcz = xi * (uz - vz);
     // step 3 input: the spread record
-    SRec<R> *SR = static_cast<SRec<R> *>(a.srec);
-    SR[k] = SRec<R>{(uint32_t)(ch.noff + x0 + (int64_t)ch.nx * (y0 + (int64_t)ch.ny * z0)), dx, dy, dz, -fcx, -fcy, -fcz};
+    return SRec<R>{(uint32_t)(ch.noff + x0 + (int64_t)ch.nx * (y0 + (int64_t)ch.ny * z0)), dx, dy, dz, -fcx, -fcy, -fcz};
 }
 
 // Step 4 of a point (semi-implicit Euler with the vertex's mass), once the
 // membrane force is there: the coupling force is read back from the spread
 // record (negated, exactly), the wall contact force added when walls are
 // given; then, with next-step marks, the stencil of the new position is
-// marked.  Workgroup mapping as for k_couple.
+// marked.  Workgroup index -> (cell, chunk) as for k_mark.
 template <class R>
 __global__ __launch_bounds__(128) void k_move(CoupleArgs a) {
     int c, chunk;
@@ -916,7 +909,7 @@ static_assert(kSpreadBox / 32 <= kSpreadThreads, "the spread scans one bitmap wo
 
 struct SpreadArgs {
     const int32_t *vert_off;
-    const void *srec;
+    void *srec;        // [nverts] SRec, written here for the point update
     uint32_t *owner;   // [N] epoch of the call that last claimed the node
     void *fibm;        // [N] Vec4: spread force, written (with `accumulate`, added) at the nodes a cell claims
     void *facc;        // [N] Vec4: accumulator of the fallback (zero between steps)
@@ -927,6 +920,7 @@ struct SpreadArgs {
     int accumulate;    // as in MarkArgs
     int pmax;          // power of two >= the largest cell's point count (>= 64)
     int maxv;          // the largest cell's point count
+    CoupleArgs cp;     // inputs of the points' interpolation and coupling force (couple_record)
 };
 
 // A point's offsets and force, staged in LDS by the spread.
@@ -936,13 +930,14 @@ struct SPoint {
 };
 
 // LDS of k_spread_cells: sort keys [pmax] (u32), staged points [maxv],
-// base-node and stencil-node bitmaps over the box [kSpreadBox/32] (u32 each),
-// prefix counts of the base bitmap's words [kSpreadBox/32] (u16), run starts
-// [maxv] and node list [8 maxv] (u16), and a few scalars.
+// their base nodes [maxv] (u32), base-node and stencil-node bitmaps over the
+// box [kSpreadBox/32] (u32 each), prefix counts of the base bitmap's words
+// [kSpreadBox/32] (u16), run starts [maxv] and node list [8 maxv] (u16), and
+// a few scalars.
 template <class R>
 __host__ __device__ inline size_t spread_lds_bytes(int pmax, int maxv) {
-    return 4 * (size_t)pmax + sizeof(SPoint<R>) * (size_t)maxv + 2 * (kSpreadBox / 32) * 4 + (kSpreadBox / 32) * 2 +
-           18 * (size_t)maxv + 256;
+    return 4 * (size_t)pmax + sizeof(SPoint<R>) * (size_t)maxv + 4 * (size_t)maxv + 2 * (kSpreadBox / 32) * 4 +
+           (kSpreadBox / 32) * 2 + 18 * (size_t)maxv + 256;
 }
 
 // Block-wide exclusive prefix sum of one int per thread (blockDim.x <= 1024);
@@ -992,7 +987,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     extern __shared__ uint32_t smem_u32[];
     uint32_t *key = smem_u32;                                          // [pmax]
     SPoint<R> *pts = reinterpret_cast<SPoint<R> *>(key + a.pmax);     // [maxv]
-    uint32_t *bbits = reinterpret_cast<uint32_t *>(pts + a.maxv);     // [kWords] base nodes of the cell
+    uint32_t *pbase = reinterpret_cast<uint32_t *>(pts + a.maxv);     // [maxv] the points' base nodes
+    uint32_t *bbits = pbase + a.maxv;                                  // [kWords] base nodes of the cell
     uint32_t *bits = bbits + kWords;                                   // [kWords] stencil nodes
     uint16_t *wpre = reinterpret_cast<uint16_t *>(bits + kWords);     // [kWords] base bits in earlier words
     uint16_t *rstart = wpre + kWords;                                  // [maxv] first sorted index of each run
@@ -1002,8 +998,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     const int v0 = a.vert_off[c], nv = a.vert_off[c + 1] - v0;
     if (nv <= 0) return;
     const Chan ch = a.chans[cell_channel(a.cell_chan, c)];
-    const SRec<R> *SR = static_cast<const SRec<R> *>(a.srec) + v0;
+    SRec<R> *SR = static_cast<SRec<R> *>(a.srec) + v0;
     const uint32_t epoch = *a.epoch;
+    if (a.cp.nx_count && c == 0 && threadIdx.x == 0) *a.cp.nx_count = 0u;
     R4 *FI = static_cast<R4 *>(a.fibm);
     R4 *FA = static_cast<R4 *>(a.facc);
     auto decode = [&](uint32_t b, int &x, int &y, int &z) {
@@ -1024,20 +1021,27 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         atomicAdd(rec + 2, fz);
         a.ftile[ch.toff + (int64_t)(gy + ch.ny * gz) * ch.tpr + (gx >> 6)] = 1;
     };
+    // steps 1-2 of every point of the cell (its record kept for the point
+    // update), staged in LDS
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        const SRec<R> r = couple_record<R>(a.cp, c, v0 + i, ch);
+        SR[i] = r;
+        pbase[i] = r.base;
+        pts[i] = SPoint<R>{r.dx, r.dy, r.dz, r.fx, r.fy, r.fz};
+    }
+    __syncthreads();
     // base nodes unwrapped around the first point's; their bounding box
     int rx, ry, rz;
-    decode(SR[0].base, rx, ry, rz);
+    decode(pbase[0], rx, ry, rz);
     int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, hi[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
     for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-        const SRec<R> r = SR[i];
         int x, y, z;
-        decode(r.base, x, y, z);
+        decode(pbase[i], x, y, z);
         const int u[3] = {unwrap(x - rx, ch.nx), unwrap(y - ry, ch.ny), unwrap(z - rz, ch.nz)};
         for (int d = 0; d < 3; d++) {
             lo[d] = min(lo[d], u[d]);
             hi[d] = max(hi[d], u[d]);
         }
-        pts[i] = SPoint<R>{r.dx, r.dy, r.dz, r.fx, r.fy, r.fz};
     }
     for (int d = 0; d < 3; d++) {
 #pragma unroll
@@ -1062,9 +1066,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         // a cell too large for the box: point by point through the fallback
         for (int t = threadIdx.x; t < 8 * nv; t += blockDim.x) {
             const int i = t >> 3, q = t & 7;
-            const SRec<R> r = SR[i];
+            const SPoint<R> r = pts[i];
             int x, y, z;
-            decode(r.base, x, y, z);
+            decode(pbase[i], x, y, z);
             const int gx = (q & 1) ? (x + 1 == ch.nx ? 0 : x + 1) : x;
             const int gy = ((q >> 1) & 1) ? (y + 1 == ch.ny ? 0 : y + 1) : y;
             const int gz = (q >> 2) ? (z + 1 == ch.nz ? 0 : z + 1) : z;
@@ -1093,7 +1097,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         lis[m] = 0;
         if (i < nv) {
             int x, y, z;
-            decode(SR[i].base, x, y, z);
+            decode(pbase[i], x, y, z);
             lis[m] = (uint32_t)((unwrap(x - rx, ch.nx) - mx) +
                                 bx_ * ((unwrap(y - ry, ch.ny) - my) + by_ * (unwrap(z - rz, ch.nz) - mz)));
         }

@@ -1273,13 +1273,12 @@ static CoupleArgs couple_args(lbm_ctx *c, const ibm_mesh *m, bool next, bool res
     return a;
 }
 
-// Steps 1-3 of the points: interpolation and coupling force (k_couple),
-// then the spread of -F_c.
+// Steps 1-3 of the points: interpolation, coupling force and the spread of
+// -F_c, one workgroup per cell (k_spread_cells).
 template <class R>
 static void launch_couple(lbm_ctx *c, const ibm_mesh *m, bool reset = false) {
-    const CoupleArgs a = couple_args(c, m, false, reset);
-    k_couple<R><<<(unsigned)(a.nb * cdiv(m->ncells, 8) * 8), 128, 0, c->s>>>(a);
     SpreadArgs sp{};
+    sp.cp = couple_args(c, m, false, reset);
     sp.vert_off = m->vert_off;
     sp.srec = c->srec;
     sp.owner = c->owner;
