@@ -362,7 +362,8 @@ def sweep_leg(lbm_mod, max_steps: int, drivings=(5e-5, 2.5e-5)) -> dict:
         dt = time.perf_counter() - t0
         nodes = sum(s.n for s in scs)
         summ = sweep.ladder_summary(tr.results())
-        out["runs"].append({"gx": gx, "channels": len(scs), "steps_run": tr.steps_run, "wall_s": round(dt, 3),
+        out["runs"].append({"gx": gx, "channels": len(scs), "steps_run": tr.steps_run, "stopped": tr.stopped,
+                            "wall_s": round(dt, 3),
                             "mlups_incl_setup_and_tracking": round(nodes * tr.steps_run / dt / 1e6, 1),
                             "per_type": {cell: {k: d[k] for k in ("gaps", "outcome", "steps", "monotone",
                                                                   "min_passing_gap", "max_stalling_gap",

@@ -101,8 +101,9 @@ class LadderTracker:
     ``stall_window`` steps while still in front of that surface.  Positions
     are unwrapped (anchor + offset), so a cell that passed cannot come back
     into the opening through the periodic x boundary.  A channel whose
-    membrane positions stop being finite is recorded as "non-finite" (the
-    channels of a batch are independent, so the others go on)."""
+    membrane positions stop being finite is recorded as "non-finite"; the
+    tracker keeps following the others (the channels of a batch are
+    independent)."""
 
     def __init__(self, scenarios: Sequence[S.Scenario], vert_off: np.ndarray, chan: np.ndarray,
                  stall_window: int = 2000, stall_dist: float = 0.05, t_min: int = 2000):
