@@ -33,12 +33,13 @@ LAUNCH_SAMPLE_EVERY = 5  # collide-stream launches bracketed by HIP events: ever
 
 # Algorithmic bytes per lattice node of one collide-stream launch: the 19
 # populations read and written once (4 B each in FP32 storage, 8 B in FP64)
-# plus the 1-byte node class.  The sparse immersed-boundary force (read and
-# cleared only on tiles that received spread force) is not counted, which
-# makes the achieved figure conservative.
-def bytes_per_node(prec: str) -> int:
+# plus the tile's solid and wall masks (16 B per 64-node tile, 0.25 B per
+# node).  The sparse immersed-boundary force (read and cleared only on tiles
+# that received spread force) is not counted, which makes the achieved
+# figure conservative.
+def bytes_per_node(prec: str) -> float:
     s = 8 if prec == "f64" else 4
-    return 2 * 19 * s + 1
+    return 2 * 19 * s + 16 / 64
 
 
 # HBM traffic of one collide-stream launch on the throughput workload, from

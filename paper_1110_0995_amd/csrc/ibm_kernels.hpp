@@ -469,6 +469,7 @@ struct NodeVelArgs {
     const void *gfield;
     void *ufield;  // [N] Vec4
     const uint8_t *need;
+    uint2 *tnmask;  // [ntiles] written for every listed tile: its marks as a 64-bit mask (bit x & 63)
     const uint32_t *tlist;
     const uint32_t *tcount;
     const Chan *chans;
@@ -501,8 +502,10 @@ __device__ __forceinline__ typename Vec4<R>::T node_u(const R (&v)[Q], const dou
     return typename Vec4<R>::T{(jx + R(0.5) * Fx) * ir, (jy + R(0.5) * Fy) * ir, (jz + R(0.5) * Fz) * ir, rho};
 }
 
-// u_ext of the marked nodes of every listed tile.  A fixed grid of waves
-// strides over the list (its length is only known on the device).
+// u_ext of the marked nodes of every listed tile, and the tile's marks as a
+// mask for the collide-stream pass (which then reads no node mark).  A fixed
+// grid of waves strides over the list (its length is only known on the
+// device).
 template <class S, class R, bool DEV, bool HAS_G>
 __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     using R4 = typename Vec4<R>::T;
@@ -516,9 +519,13 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
         const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
         const int lt = tile - ch.toff, row = lt / ch.tpr;
         const int x = (lt - row * ch.tpr) * 64 + lane;
-        if (x >= ch.nx) continue;
         const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
-        if (!a.need[n]) continue;
+        const bool marked = x < ch.nx && a.need[n];
+        if (a.tnmask) {  // every lane of the wave is at this tile here
+            const uint64_t m = __builtin_amdgcn_ballot_w64(marked);
+            if (lane == 0) a.tnmask[tile] = uint2{(uint32_t)m, (uint32_t)(m >> 32)};
+        }
+        if (!marked) continue;
         R4 u = R4{R(0), R(0), R(0), R(0)};
         const uint8_t cl = a.cls[n];
         if (cl != CLS_SOLID) {

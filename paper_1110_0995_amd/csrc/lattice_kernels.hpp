@@ -104,40 +104,47 @@ __device__ __forceinline__ void load_node(const S *f, int64_t stride, int64_t n,
 }
 
 // cls[n] and links[n] (bit i set = the link along c_i ends on a solid node
-// or leaves a non-periodic axis, so population i bounces back).  One wave
-// per tile.
+// or leaves a non-periodic axis, so population i bounces back), and per
+// tile the 64-bit masks of its solid and of its wall nodes (bit x & 63;
+// tmask[t] = {solid lo, solid hi, wall lo, wall hi}), which the
+// collide-stream pass reads with one scalar load per wave.  One wave per
+// tile.
 __global__ __launch_bounds__(256) void k_classify(const Chan *__restrict__ chans, const uint16_t *__restrict__ tile_chan,
                                                   int ntiles, int px, int py, int pz,
                                                   const uint8_t *__restrict__ solid, uint8_t *__restrict__ cls,
-                                                  uint32_t *__restrict__ links) {
+                                                  uint32_t *__restrict__ links, uint4 *__restrict__ tmask) {
     const int tile = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (tile >= ntiles) return;
     const Chan ch = chans[tile_channel(tile_chan, tile)];
     const int lt = tile - ch.toff, row = lt / ch.tpr;
     const int x = (lt - row * ch.tpr) * 64 + (threadIdx.x & 63);
-    if (x >= ch.nx) return;
-    const int y = row % ch.ny, z = row / ch.ny;
-    const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
-    if (solid[n]) {
-        cls[n] = CLS_SOLID;
-        links[n] = 0;
-        return;
-    }
-    const int per[3] = {px, py, pz}, d[3] = {ch.nx, ch.ny, ch.nz};
-    uint32_t m = 0;
-    for (int i = 1; i < Q; i++) {
-        int p[3] = {x + cx(i), y + cy(i), z + cz(i)};
-        bool out = false;
-        for (int k = 0; k < 3; k++) {
-            if (p[k] < 0 || p[k] >= d[k]) {
-                if (per[k]) p[k] = pmod(p[k], d[k]);
-                else out = true;
+    uint8_t c = CLS_BULK;
+    if (x < ch.nx) {
+        const int y = row % ch.ny, z = row / ch.ny;
+        const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
+        uint32_t m = 0;
+        if (solid[n]) {
+            c = CLS_SOLID;
+        } else {
+            const int per[3] = {px, py, pz}, d[3] = {ch.nx, ch.ny, ch.nz};
+            for (int i = 1; i < Q; i++) {
+                int p[3] = {x + cx(i), y + cy(i), z + cz(i)};
+                bool out = false;
+                for (int k = 0; k < 3; k++) {
+                    if (p[k] < 0 || p[k] >= d[k]) {
+                        if (per[k]) p[k] = pmod(p[k], d[k]);
+                        else out = true;
+                    }
+                }
+                if (out || solid[ch.noff + p[0] + (int64_t)ch.nx * (p[1] + (int64_t)ch.ny * p[2])]) m |= 1u << i;
             }
+            c = m ? CLS_WALL : CLS_BULK;
         }
-        if (out || solid[ch.noff + p[0] + (int64_t)ch.nx * (p[1] + (int64_t)ch.ny * p[2])]) m |= 1u << i;
+        cls[n] = c;
+        links[n] = m;
     }
-    cls[n] = m ? CLS_WALL : CLS_BULK;
-    links[n] = m;
+    const uint64_t sm = __builtin_amdgcn_ballot_w64(c == CLS_SOLID), wm = __builtin_amdgcn_ballot_w64(c == CLS_WALL);
+    if ((threadIdx.x & 63) == 0) tmask[tile] = uint4{(uint32_t)sm, (uint32_t)(sm >> 32), (uint32_t)wm, (uint32_t)(wm >> 32)};
 }
 
 // Fluid at rest: f_i = w_i (or h_i = 0 for the deviation storage).
@@ -236,13 +243,16 @@ struct StepArgs {
     const void *fa;
     void *fb;
     int64_t stride;
-    const uint8_t *cls;
+    const uint4 *tmask;   // [ntiles] solid and wall masks of each tile (k_classify)
     const uint32_t *links;
     const void *fibm;     // [N] x 4 immersed-boundary force (x, y, z, unused), valid at marked nodes
     void *facc;           // [N] x 4 the spread's fallback accumulator: added and cleared in flagged tiles
     uint8_t *ftile;       // [ntiles] 1: the tile holds fallback sums (cleared here)
     uint8_t *need;        // [N] 1: the node received spread force this step
     uint8_t *tneed;       // [ntiles] 1: the tile holds such a node
+    const uint2 *tnmask;  // [ntiles] the marks of each marked tile as a 64-bit mask (bit x & 63), written by
+                          // the velocity pass of the step
+    int use_tnmask;       // 0: the masks are not all current (velocities from records); read the node marks
     const void *gfield;   // [3][N] or null
     const Chan *chans;
     const uint16_t *tile_chan;  // null for a single channel
@@ -261,6 +271,13 @@ struct StepArgs {
     int per[3];  // periodic axes (a link leaving a non-periodic face bounces in place)
     uint32_t *nonfinite;  // set to 1 by a node whose populations are not all finite (never cleared here)
 };
+
+// Byte t of a byte array allocated in whole 16-byte units, for a
+// wave-uniform t: one scalar load of the aligned word that holds it.
+__device__ __forceinline__ uint32_t uniform_byte(const uint8_t *p, int t) {
+    const uint32_t w = *reinterpret_cast<const uint32_t *>(p + (t & ~3));
+    return (w >> (8 * (t & 3))) & 0xffu;
+}
 
 // Number of set bits of m below this lane.
 __device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
@@ -378,63 +395,40 @@ constexpr int kRowDirs[9][3] = {{0, 1, 2},  {3, 7, 10},  {4, 9, 8},  {5, 11, 14}
 template <class S, class R, bool DEV, bool HAS_G, class IDX, bool EMIT = false>
 __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // Every wave of the workgroup reaches the barrier below, so none leaves
+    // early: a wave without a tile (a shorter table entry, the end of the
+    // tile range) and the lanes past the end of a row only skip the work.
     int tile;
+    bool wlive;  // wave-uniform: the wave owns a tile
     if (a.wgtab) {
         const uint32_t e = a.wgtab[a.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
-        if (wave > (int)(e & 7u)) return;
         tile = (int)(e >> 3) + wave;
+        wlive = wave <= (int)(e & 7u);
     } else {
         const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
         tile = blk * (blockDim.x >> 6) + wave;
+        wlive = true;
     }
-    if (tile >= a.ntiles) return;
-    const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
-    const int lt = tile - ch.toff;
-    const int row = lt / ch.tpr;
-    const int x = (lt - row * ch.tpr) * 64 + lane;
+    wlive = wlive && tile < a.ntiles;
     __shared__ uint4 rec_tiles[EMIT ? 8 * kRecTiles : 1];
     uint4 *rt = rec_tiles + (EMIT ? wave * kRecTiles : 0);
-    if constexpr (EMIT)  // every lane active here (whole waves only leave above)
-        stage_rec_tiles(a.etile, ch, lt - row * ch.tpr, row % ch.ny, row / ch.ny, lane, rt);
-    if (x >= ch.nx) return;
+    Chan ch{};
+    int row = 0, x = 0;
+    bool live = false;
+    if (wlive) {
+        ch = a.chans[tile_channel(a.tile_chan, tile)];
+        const int lt = tile - ch.toff;
+        row = lt / ch.tpr;
+        x = (lt - row * ch.tpr) * 64 + lane;
+        if constexpr (EMIT)  // every lane of the wave is active here
+            stage_rec_tiles(a.etile, ch, lt - row * ch.tpr, row % ch.ny, row / ch.ny, lane, rt);
+        live = x < ch.nx;
+    }
     const IDX base = (IDX)ch.noff;
     const IDX n = base + (IDX)row * (IDX)ch.nx + (IDX)x;
     const IDX N = (IDX)a.N;
     const IDX stride = (IDX)a.stride;
-
-    R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
-    if (HAS_G) {
-        const R *G = static_cast<const R *>(a.gfield);
-        Fx += at(G, n);
-        Fy += at(G, N + n);
-        Fz += at(G, 2 * N + n);
-    }
-    if (a.tneed[tile]) {
-        const bool fl = a.ftile[tile] != 0;
-        if (at(a.need, n)) {
-            const R *fi = static_cast<const R *>(a.fibm);
-            R fx = at(fi, 4 * n), fy = at(fi, 4 * n + 1), fz = at(fi, 4 * n + 2);
-            if (fl) {  // the spread's fallback sums, taken once
-                R *fa = static_cast<R *>(a.facc);
-                fx = fx + at(fa, 4 * n);
-                fy = fy + at(fa, 4 * n + 1);
-                fz = fz + at(fa, 4 * n + 2);
-                at(fa, 4 * n) = R(0);
-                at(fa, 4 * n + 1) = R(0);
-                at(fa, 4 * n + 2) = R(0);
-            }
-            Fx += fx;
-            Fy += fy;
-            Fz += fz;
-            at(a.need, n) = 0;
-        }
-        if (lane == 0) {
-            a.tneed[tile] = 0;
-            if (fl) a.ftile[tile] = 0;
-        }
-    }
-    const uint8_t cl = at(a.cls, n);
-    const bool solid = cl == CLS_SOLID;  // streams its rest value (see pop_slot)
+    const int y = ch.ny ? row % ch.ny : 0, z = ch.ny ? row / ch.ny : 0;
 
     const S *__restrict__ fa = static_cast<const S *>(a.fa);
     S *__restrict__ fb = static_cast<S *>(a.fb);
@@ -445,34 +439,109 @@ __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(
         ra = buf_rsrc(fa, fbytes);
         rb = buf_rsrc(fb, fbytes);
     }
-    const int y = row % ch.ny, z = row / ch.ny;
-    const uint32_t links = (cl == CLS_WALL) ? at(a.links, n) : 0u;
     R f[Q];
+    bool solid = false;  // streams its rest value (see pop_slot)
+    uint32_t links = 0u;
     R sum = R(0);  // population sum before the collision (0 for solid nodes)
-    if (!solid) {
-#pragma unroll
-        for (int i = 0; i < Q; i++) {
-            if constexpr (BUF)
-                f[i] = R(buf_load<S>(ra, (uint32_t)n * (uint32_t)sizeof(S), (uint32_t)i * (uint32_t)a.stride * (uint32_t)sizeof(S)));
+    if (live) {
+        // What the wave needs to know about its tile comes in scalar loads:
+        // the tile's solid and wall masks, its stencil and fallback marks and
+        // the mask of its stencil nodes.  So every vector load of the node
+        // (its links, its immersed-boundary force, its 19 slots) is issued
+        // before any has to be waited for, the populations last: waiting for
+        // the links then does not wait for the populations.
+        const int utile = __builtin_amdgcn_readfirstlane(tile);
+        const uint4 tm = a.tmask[utile];
+        const uint32_t tmark = uniform_byte(a.tneed, utile), tfall = uniform_byte(a.ftile, utile);
+        const uint2 nm = a.tnmask[utile];  // meaningful only where tmark and use_tnmask are set
+        solid = (((uint64_t)tm.y << 32 | tm.x) >> lane) & 1u;
+        const bool wall = (((uint64_t)tm.w << 32 | tm.z) >> lane) & 1u;
+        bool nmark = false;
+        if (tmark) {
+            if (a.use_tnmask)
+                nmark = (((uint64_t)nm.y << 32 | nm.x) >> lane) & 1u;
             else
-                f[i] = R(at(fa, (IDX)i * stride + n));
+                nmark = at(a.need, n) != 0;
         }
-        if (links) {  // populations bounced back from solid neighbours lie in their slots
-#pragma unroll
-            for (int i = 0; i < Q; i++) {
-                if (!((links >> opp(i)) & 1u)) continue;
-                const IDX src = pop_slot<IDX>(i, n, links, x, y, z, ch, stride, a.per);
-                if constexpr (BUF)
-                    f[i] = R(buf_load<S>(ra, (uint32_t)src * (uint32_t)sizeof(S), 0u));
-                else
-                    f[i] = R(at(fa, src));
+        links = wall ? at(a.links, n) : 0u;
+        // the spread force (and its fallback sums), used once the populations are requested
+        R ibx = R(0), iby = R(0), ibz = R(0), acx = R(0), acy = R(0), acz = R(0);
+        if (nmark) {
+            const R *fi = static_cast<const R *>(a.fibm);
+            ibx = at(fi, 4 * n);
+            iby = at(fi, 4 * n + 1);
+            ibz = at(fi, 4 * n + 2);
+            if (tfall) {
+                const R *acc = static_cast<const R *>(a.facc);
+                acx = at(acc, 4 * n);
+                acy = at(acc, 4 * n + 1);
+                acz = at(acc, 4 * n + 2);
             }
         }
-        sum = collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
-    } else {
+        if (!solid) {
 #pragma unroll
-        for (int i = 0; i < Q; i++) f[i] = DEV ? R(0) : wgt<R>(i);
+            for (int i = 0; i < Q; i++) {
+                if constexpr (BUF)
+                    f[i] = R(buf_load<S>(ra, (uint32_t)n * (uint32_t)sizeof(S), (uint32_t)i * (uint32_t)a.stride * (uint32_t)sizeof(S)));
+                else
+                    f[i] = R(at(fa, (IDX)i * stride + n));
+            }
+        }
+
+        R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
+        if (HAS_G) {
+            const R *G = static_cast<const R *>(a.gfield);
+            Fx += at(G, n);
+            Fy += at(G, N + n);
+            Fz += at(G, 2 * N + n);
+        }
+        if (nmark) {
+            if (tfall) {  // the spread's fallback sums, taken once
+                ibx = ibx + acx;
+                iby = iby + acy;
+                ibz = ibz + acz;
+                R *acc = static_cast<R *>(a.facc);
+                at(acc, 4 * n) = R(0);
+                at(acc, 4 * n + 1) = R(0);
+                at(acc, 4 * n + 2) = R(0);
+            }
+            Fx += ibx;
+            Fy += iby;
+            Fz += ibz;
+            at(a.need, n) = 0;
+        }
+        if (tmark && lane == 0) {
+            a.tneed[tile] = 0;
+            if (tfall) a.ftile[tile] = 0;
+        }
+        if (!solid) {
+            if (links) {  // populations bounced back from solid neighbours lie in their slots
+#pragma unroll
+                for (int i = 0; i < Q; i++) {
+                    if (!((links >> opp(i)) & 1u)) continue;
+                    const IDX src = pop_slot<IDX>(i, n, links, x, y, z, ch, stride, a.per);
+                    if constexpr (BUF)
+                        f[i] = R(buf_load<S>(ra, (uint32_t)src * (uint32_t)sizeof(S), 0u));
+                    else
+                        f[i] = R(at(fa, src));
+                }
+            }
+            sum = collide<R, DEV>(f, Fx, Fy, Fz, R(a.omega), R(a.kf));
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; i++) f[i] = DEV ? R(0) : wgt<R>(i);
+        }
     }
+    // The workgroup's waves store together.  Most slots of a line are written
+    // by one wave, but an x-shifted store also covers the first or last
+    // element of the neighbouring tile's line, which the neighbouring wave
+    // (the same workgroup when it holds whole rows) completes: issued at the
+    // same time, the two halves meet in L2 and the line goes to HBM once,
+    // whole.  Waves left free to drift apart (one waiting on the spread
+    // force, a neighbour not) leave the partial lines in L2 long enough to be
+    // written back in pieces.
+    __syncthreads();
+    if (!live) return;
     // failure detection: a wave with a non-finite node raises the flag (a
     // wave-uniform branch; the active lanes store the same value)
     if (__builtin_amdgcn_ballot_w64(!__builtin_isfinite(sum))) *a.nonfinite = 1u;

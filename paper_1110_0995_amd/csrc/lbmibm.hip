@@ -126,6 +126,8 @@ struct lbm_ctx {
     int ntiles = 0;
     size_t rsize = 4;  // sizeof(real)
     uint8_t *cls = nullptr;
+    uint4 *tmask = nullptr;      // [ntiles] solid and wall masks of each tile
+    uint2 *tnmask = nullptr;     // [ntiles] marks of each marked tile as a mask, from the velocity pass
     uint32_t *links = nullptr;
     void *fibm = nullptr;        // [N] x 4 real: spread force of the step, valid at the nodes marked this step
     void *facc = nullptr;        // [N] x 4 real: accumulator of the atomic fallback spread, zero between steps
@@ -343,7 +345,7 @@ LBM_API void lbm_destroy(lbm_ctx *c) {
     if (c->side) (void)hipStreamDestroy(c->side);
     for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_nf})
         if (e) (void)hipEventDestroy(e);
-    void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
+    void *bufs[] = {c->chans, c->tile_chan, c->cls,  c->tmask, c->tnmask, c->links, c->fibm, c->facc, c->ufield, c->need, c->tneed, c->tlist,
                     c->tcount, c->epoch,    c->srec, c->owner, c->partials, c->sums, c->ftile,
                     c->lamF,  c->lamU,      c->xs,   c->vs,    c->fels,  c->hv, c->bounds, c->pairs, c->npairs,
                     c->sph_start, c->sph_items, c->wgtab, c->nx_need, c->nx_tneed, c->nx_ent,
@@ -371,6 +373,7 @@ static int init_ctx(lbm_ctx *c) {
     const size_t tn = (size_t)c->ntiles;
     const size_t tpad = (size_t)cdiv((int64_t)tn, 16) * 16;
     if (hipMalloc(&c->chans, sizeof(Chan) * c->nch) != hipSuccess || hipMalloc(&c->cls, c->N) != hipSuccess ||
+        hipMalloc(&c->tmask, sizeof(uint4) * tn) != hipSuccess || hipMalloc(&c->tnmask, sizeof(uint2) * tn) != hipSuccess ||
         hipMalloc(&c->links, 4 * c->N) != hipSuccess || hipMalloc(&c->fibm, 4 * c->N * c->rsize) != hipSuccess ||
         hipMalloc(&c->facc, 4 * c->N * c->rsize) != hipSuccess ||
         hipMalloc(&c->ufield, 4 * c->N * c->rsize) != hipSuccess || hipMalloc(&c->need, c->N) != hipSuccess ||
@@ -411,12 +414,13 @@ static int init_ctx(lbm_ctx *c) {
         HIPCHK(hipMemcpy(c->tile_chan, tc.data(), 2 * tn, hipMemcpyHostToDevice));
     }
     k_classify<<<(int)cdiv(c->ntiles, 4), 256, 0, c->s>>>(c->chans, c->tile_chan, c->ntiles, p->periodic[0],
-                                                           p->periodic[1], p->periodic[2], p->solid, c->cls, c->links);
+                                                           p->periodic[1], p->periodic[2], p->solid, c->cls, c->links, c->tmask);
     HIPCHK(hipMemsetAsync(c->fibm, 0, 4 * c->N * c->rsize, c->s));
     HIPCHK(hipMemsetAsync(c->facc, 0, 4 * c->N * c->rsize, c->s));
     HIPCHK(hipMemsetAsync(c->ufield, 0, 4 * c->N * c->rsize, c->s));
     HIPCHK(hipMemsetAsync(c->need, 0, c->N, c->s));
     HIPCHK(hipMemsetAsync(c->tneed, 0, tpad, c->s));
+    HIPCHK(hipMemsetAsync(c->tnmask, 0, sizeof(uint2) * tn, c->s));
     HIPCHK(hipMemsetAsync(c->ftile, 0, tpad, c->s));
     HIPCHK(hipMemsetAsync(c->tcount, 0, 4, c->s));
     HIPCHK(hipMemsetAsync(c->epoch, 0, 4, c->s));
@@ -582,7 +586,7 @@ static void enqueue_copy(lbm_ctx *c, void *dst, const void *src, size_t bytes) {
 static StepArgs step_args(const lbm_ctx *c) {
     StepArgs a{};
     a.stride = c->stride;
-    a.cls = c->cls;
+    a.tmask = c->tmask;
     a.links = c->links;
     a.fibm = c->fibm;
     a.facc = c->facc;
@@ -665,6 +669,10 @@ static void enqueue_step_into(lbm_ctx *c, const void *fa, void *fb, bool plain =
         a.erec = c->nx_rec;
         a.ecap = c->nx_cap;
     }
+    // the velocity pass left the marks of every marked tile as masks unless
+    // a coupling of this step took its velocities from the records
+    a.tnmask = c->tnmask;
+    a.use_tnmask = c->u_from_rec ? 0 : 1;
     c->rec_valid = emit;
     c->u_from_rec = false;
     c->nx_pending = 0;
@@ -1216,6 +1224,7 @@ static void launch_node_velocity(lbm_ctx *c, const void *f) {
     a.gfield = c->p.gfield;
     a.ufield = c->ufield;
     a.need = c->need;
+    a.tnmask = c->tnmask;
     a.tlist = c->tlist;
     a.tcount = c->tcount;
     a.chans = c->chans;

@@ -19,9 +19,10 @@ def test_more_than_one_gpu_is_refused():
 def test_reported_unit_counts():
     sys.path.insert(0, ROOT)
     import bench
-    # FP32 deviation storage: 19 populations read and written, 1-byte node class
-    assert bench.bytes_per_node("f32dev") == 19 * 4 * 2 + 1
-    assert bench.bytes_per_node("f64") == 19 * 8 * 2 + 1
+    # FP32 deviation storage: 19 populations read and written, the 16-byte
+    # solid and wall masks of each 64-node tile
+    assert bench.bytes_per_node("f32dev") == 19 * 4 * 2 + 16 / 64
+    assert bench.bytes_per_node("f64") == 19 * 8 * 2 + 16 / 64
     # dipole pair: separation 3, |r|^2 5, |r| 1, 3/(4 pi |r|^5) 3, three dot
     # products 15, 5 (m1.r)(m2.r)/|r|^2 3, bracket and scale 19, accumulate 3,
     # surface gap 1
