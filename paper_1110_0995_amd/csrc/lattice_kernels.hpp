@@ -508,8 +508,10 @@ __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(
             Fx += ibx;
             Fy += iby;
             Fz += ibz;
-            at(a.need, n) = 0;
         }
+        // the marks are cleared for the next step: every lane of a marked
+        // tile stores, so the tile's 64 mark bytes go out as one whole write
+        if (tmark) at(a.need, n) = 0;
         if (tmark && lane == 0) {
             a.tneed[tile] = 0;
             if (tfall) a.ftile[tile] = 0;
