@@ -279,6 +279,23 @@ __device__ __forceinline__ uint32_t uniform_byte(const uint8_t *p, int t) {
     return (w >> (8 * (t & 3))) & 0xffu;
 }
 
+// Element i of an array that nothing writes while the kernel runs, read at a
+// wave-uniform index through the constant address space, so that it is one
+// scalar load even where the compiler cannot prove that no store of the
+// kernel reaches it.
+template <class T>
+__device__ __forceinline__ T uniform_load(const T *p, int64_t i) {
+    static_assert(sizeof(T) % 4 == 0, "whole dwords");
+    using CU = const __attribute__((address_space(4))) uint32_t;
+    CU *q = (CU *)(p + i);
+    struct W {
+        uint32_t w[sizeof(T) / 4];
+    } v;
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); k++) v.w[k] = q[k];
+    return __builtin_bit_cast(T, v);
+}
+
 // Number of set bits of m below this lane.
 __device__ __forceinline__ uint32_t bits_below_lane(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
