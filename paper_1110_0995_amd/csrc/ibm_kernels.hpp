@@ -18,8 +18,7 @@
 //   positions, so their small departures from the (FP64) rest shape keep
 //   full accuracy in every storage precision.
 //
-// k_compact: the marked tiles become a dense list, with each listed tile's
-//   node marks as a 64-bit mask.
+// k_compact: the marked tiles become a dense list.
 //
 // k_node_velocity (one wave per listed tile): u_ext = (j + F_ext/2)/rho of
 //   the marked nodes only, from their current populations, into an AoS
@@ -410,73 +409,55 @@ __global__ __launch_bounds__(kMembThreads) void k_membrane(MembArgs a) {
     }
 }
 
-// Marked tiles -> dense list, and each listed tile's node marks as a 64-bit
-// mask (bit x & 63), which the velocity pass and the collide-stream pass
-// read with one scalar load instead of a vector load per node.  One thread
-// per tile: a marked tile's 64 mark bytes come in four 16-byte loads (one
-// byte per node, in a tile that starts on a 16-byte boundary and is whole;
-// byte by byte otherwise).  The block scans its counts and reserves its
-// slots with a single atomic, so the list costs one atomic per 256 tiles.
+// Marked tiles -> dense list.  Each thread reads the flags of 16 tiles with
+// one 16-byte load; the block scans its counts and reserves its slots with a
+// single atomic, so the list length costs one atomic per 4096 tiles.
+constexpr int kCompactThreads = 256, kCompactPerThread = 16;
 // With `gate`, nothing is listed unless *gate is non-zero (a step whose
 // velocities come from records lists tiles only when a node was missed).
-constexpr int kCompactThreads = 256;
-struct CompactArgs {
-    const uint8_t *tneed;   // [ntiles] tile marks
-    const uint8_t *need;    // [N] node marks (0 or 1)
-    const Chan *chans;
-    const uint16_t *tile_chan;  // null for a single channel
-    int ntiles;
-    uint32_t *tlist;        // [ntiles] the list
-    uint32_t *tcount;       // its length
-    uint2 *tnmask;          // [ntiles] written for every listed tile
-    const uint32_t *gate;
-};
-
-// Four mark bytes (each 0 or 1) -> four bits.
-__device__ __forceinline__ uint32_t mark_nibble(uint32_t w) { return (w | w >> 7 | w >> 14 | w >> 21) & 0xfu; }
-
-__global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
+__global__ __launch_bounds__(kCompactThreads) void k_compact(const uint8_t *__restrict__ tneed, int ntiles,
+                                                             uint32_t *__restrict__ tlist, uint32_t *tcount,
+                                                             const uint32_t *gate) {
     __shared__ uint32_t wsum[kCompactThreads / 64];
     __shared__ uint32_t base_s;
-    if (a.gate && *a.gate == 0u) return;  // the same for the whole block
-    const int t = blockIdx.x * kCompactThreads + threadIdx.x;
-    const bool marked = t < a.ntiles && a.tneed[t] != 0;
-    if (marked) {
-        const Chan ch = a.chans[a.tile_chan ? (int)a.tile_chan[t] : 0];
-        const int lt = t - ch.toff, row = lt / ch.tpr, x0 = (lt - row * ch.tpr) * 64;
-        const int64_t n0 = ch.noff + (int64_t)row * ch.nx + x0;
-        const int cnt = min(64, ch.nx - x0);
-        uint64_t m = 0;
-        if (cnt == 64 && (n0 & 15) == 0) {
-            const uint4 *q = reinterpret_cast<const uint4 *>(a.need + n0);
-            const uint4 b0 = q[0], b1 = q[1], b2 = q[2], b3 = q[3];
-            const uint4 bb[4] = {b0, b1, b2, b3};
+    if (gate && *gate == 0u) return;
+    const int t0 = (blockIdx.x * kCompactThreads + threadIdx.x) * kCompactPerThread;
+    uint32_t bits = 0;  // bit j: tile t0 + j is marked
+    if (t0 + kCompactPerThread <= ntiles) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(tneed + t0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const uint64_t h = (uint64_t)(mark_nibble(bb[k].x) | mark_nibble(bb[k].y) << 4 |
-                                              mark_nibble(bb[k].z) << 8 | mark_nibble(bb[k].w) << 12);
-                m |= h << (16 * k);
-            }
-        } else {
-            for (int j = 0; j < cnt; j++)
-                if (a.need[n0 + j]) m |= 1ull << j;
-        }
-        a.tnmask[t] = uint2{(uint32_t)m, (uint32_t)(m >> 32)};
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int k = 0; k < 4; k++)
+                if ((w[i] >> (8 * k)) & 0xffu) bits |= 1u << (4 * i + k);
+    } else {
+        for (int j = 0; j < kCompactPerThread; j++)
+            if (t0 + j < ntiles && tneed[t0 + j]) bits |= 1u << j;
     }
+    const uint32_t cnt = __popc(bits);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t bal = __builtin_amdgcn_ballot_w64(marked);
-    if (lane == 0) wsum[wave] = (uint32_t)__popcll(bal);
+    uint32_t inc = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wave] = inc;
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t tot = 0;
         for (int w = 0; w < kCompactThreads / 64; w++) tot += wsum[w];
-        base_s = tot ? atomicAdd(a.tcount, tot) : 0u;
+        base_s = tot ? atomicAdd(tcount, tot) : 0u;
     }
     __syncthreads();
-    if (!marked) return;
-    uint32_t pos = base_s + bits_below_lane(bal);
+    uint32_t pos = base_s + inc - cnt;
     for (int w = 0; w < wave; w++) pos += wsum[w];
-    a.tlist[pos] = (uint32_t)t;
+    while (bits) {
+        const int j = __ffs(bits) - 1;
+        bits &= bits - 1;
+        tlist[pos++] = (uint32_t)(t0 + j);
+    }
 }
 
 struct NodeVelArgs {
@@ -486,8 +467,9 @@ struct NodeVelArgs {
     int per[3];
     const void *gfield;
     void *ufield;  // [N] Vec4
+    const uint8_t *need;  // [N] node marks (0 or 1)
     const uint4 *tmask;   // [ntiles] solid and wall masks of each tile
-    const uint2 *tnmask;  // [ntiles] node marks of each listed tile (k_compact)
+    uint2 *tnmask;        // [ntiles] written for every listed tile: its node marks as a 64-bit mask
     const uint32_t *tlist;
     const uint32_t *tcount;
     const Chan *chans;
@@ -520,13 +502,22 @@ __device__ __forceinline__ typename Vec4<R>::T node_u(const R (&v)[Q], const dou
     return typename Vec4<R>::T{(jx + R(0.5) * Fx) * ir, (jy + R(0.5) * Fy) * ir, (jz + R(0.5) * Fz) * ir, rho};
 }
 
-// u_ext of the marked nodes of every listed tile.  What a wave needs to know
-// of its tile (its node marks, solid and wall nodes) comes in scalar loads,
-// so the 19 loads of its marked nodes are issued at once.  A fixed grid of
-// waves strides over the list (its length is only known on the device).
+// Four mark bytes (each 0 or 1) -> four bits.
+__device__ __forceinline__ uint32_t mark_nibble(uint32_t w) { return (w | w >> 7 | w >> 14 | w >> 21) & 0xfu; }
+
+// u_ext of the marked nodes of every listed tile, and the tile's marks as a
+// 64-bit mask (bit x & 63) for the collide-stream pass.  What a wave needs to
+// know of its tile comes in scalar loads (the list entry, the channel, the
+// solid and wall masks, and the 64 mark bytes of a whole tile that starts on
+// a 4-byte boundary; a vector load and a ballot otherwise), so the 19 loads
+// of its marked nodes are issued at once.  A fixed grid of waves strides
+// over the list (its length is only known on the device).
 template <class S, class R, bool DEV, bool HAS_G>
 __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     using R4 = typename Vec4<R>::T;
+    struct Marks {
+        uint32_t w[16];
+    };
     const int lane = threadIdx.x & 63;
     const uint32_t nwaves = gridDim.x * (blockDim.x >> 6);
     const uint32_t count = *a.tcount;
@@ -535,12 +526,21 @@ __global__ __launch_bounds__(256) void k_node_velocity(NodeVelArgs a) {
     for (uint32_t w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < count; w += nwaves) {
         const int tile = (int)uniform_load(a.tlist, __builtin_amdgcn_readfirstlane((int)w));
         const Chan ch = uniform_load(a.chans, tile_channel(a.tile_chan, tile));
-        const uint2 nm = uniform_load(a.tnmask, tile);
         const uint4 tm = uniform_load(a.tmask, tile);
-        const int lt = tile - ch.toff, row = lt / ch.tpr;
-        const int x = (lt - row * ch.tpr) * 64 + lane;
-        const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
-        if (!((((uint64_t)nm.y << 32 | nm.x) >> lane) & 1u)) continue;  // unmarked (or past the row's end)
+        const int lt = tile - ch.toff, row = lt / ch.tpr, x0 = (lt - row * ch.tpr) * 64;
+        const int x = x0 + lane;
+        const int64_t n0 = ch.noff + (int64_t)row * ch.nx + x0, n = n0 + lane;
+        uint64_t mk;
+        if (x0 + 64 <= ch.nx && (n0 & 3) == 0) {
+            const Marks b = uniform_load(reinterpret_cast<const Marks *>(a.need + n0), 0);
+            mk = 0;
+#pragma unroll
+            for (int k = 0; k < 16; k++) mk |= (uint64_t)mark_nibble(b.w[k]) << (4 * k);
+        } else {
+            mk = __builtin_amdgcn_ballot_w64(x < ch.nx && a.need[n]);
+        }
+        if (lane == 0) a.tnmask[tile] = uint2{(uint32_t)mk, (uint32_t)(mk >> 32)};
+        if (!((mk >> lane) & 1u)) continue;  // unmarked (or past the row's end)
         R4 u = R4{R(0), R(0), R(0), R(0)};
         if (!((((uint64_t)tm.y << 32 | tm.x) >> lane) & 1u)) {  // fluid
             const bool wall = (((uint64_t)tm.w << 32 | tm.z) >> lane) & 1u;

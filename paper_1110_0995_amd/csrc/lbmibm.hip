@@ -1190,17 +1190,8 @@ static void launch_contact(lbm_ctx *c, const ibm_mesh *m) {
 }
 
 static void launch_compact(lbm_ctx *c, const uint32_t *gate = nullptr) {
-    CompactArgs a{};
-    a.tneed = c->tneed;
-    a.need = c->need;
-    a.chans = c->chans;
-    a.tile_chan = c->tile_chan;
-    a.ntiles = c->ntiles;
-    a.tlist = c->tlist;
-    a.tcount = c->tcount;
-    a.tnmask = c->tnmask;
-    a.gate = gate;
-    k_compact<<<(int)cdiv(c->ntiles, kCompactThreads), kCompactThreads, 0, c->s>>>(a);
+    k_compact<<<(int)cdiv(c->ntiles, kCompactThreads * kCompactPerThread), kCompactThreads, 0, c->s>>>(
+        c->tneed, c->ntiles, c->tlist, c->tcount, gate);
 }
 
 template <class S, class R, bool DEV>
@@ -1231,6 +1222,7 @@ static void launch_node_velocity(lbm_ctx *c, const void *f) {
     for (int d = 0; d < 3; d++) a.per[d] = c->p.periodic[d];
     a.gfield = c->p.gfield;
     a.ufield = c->ufield;
+    a.need = c->need;
     a.tmask = c->tmask;
     a.tnmask = c->tnmask;
     a.tlist = c->tlist;
