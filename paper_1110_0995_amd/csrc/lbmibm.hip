@@ -313,8 +313,11 @@ static void build_row_groups(const std::vector<Chan> &chs, std::vector<uint32_t>
 }
 
 static int64_t workspace(int64_t N, int64_t tiles, int64_t es, int nch, int64_t nwg) {
-    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 4 + 4 + cdiv(N, 256) * 32 + 32 +
-           (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
+    // workgroup table, classes, links, three 4-vector fields, node marks, tile
+    // marks and fallback tile flags, tile list, solid/wall and stencil-node
+    // masks per tile, counters, partial sums, channels
+    return 4 * nwg + N + 4 * N + 12 * N * es + N + 2 * cdiv(tiles, 16) * 16 + 4 * tiles + 16 * tiles + 8 * tiles + 4 +
+           4 + cdiv(N, 256) * 32 + 32 + (int64_t)nch * (int64_t)sizeof(Chan) + (nch > 1 ? 2 * tiles : 0);
 }
 
 LBM_API int64_t lbm_workspace_bytes(const lbm_params *p) {

@@ -104,11 +104,13 @@ def test_workspace_bytes(L):
     n = 512
     tiles = 8 * 8  # one 64-wide tile per x-row
     # node class + link mask + spread force, fallback accumulator and velocity
-    # field (4 floats each) + node marks + tile marks and tile fallback flags (each padded to
-    # 16) and tile list (4 bytes each) + list length + claim epoch +
-    # reduction partials + sums + the channel record + the collide-stream
-    # workgroup table (4 bytes per workgroup of 8 one-tile rows: 8 of them)
-    one = n + 4 * n + 12 * n * 4 + n + 2 * tiles + 4 * tiles + 4 + 4 + 2 * 32 + 32 + CHAN_BYTES + 4 * 8
+    # field (4 floats each) + node marks + tile marks and tile fallback flags
+    # (each padded to 16) and tile list (4 bytes each) + the solid/wall masks
+    # (16 bytes) and stencil-node mask (8 bytes) of each tile + list length +
+    # claim epoch + reduction partials + sums + the channel record + the
+    # collide-stream workgroup table (4 bytes per workgroup of 8 one-tile
+    # rows: 8 of them)
+    one = n + 4 * n + 12 * n * 4 + n + 2 * tiles + 4 * tiles + 24 * tiles + 4 + 4 + 2 * 32 + 32 + CHAN_BYTES + 4 * 8
     assert L.lbm_workspace_bytes(C.byref(p)) == one
     dims = (C.c_int32 * 3)(8, 8, 8)
     assert L.lbm_workspace_bytes_channels(C.byref(p), 1, dims) == one
@@ -121,8 +123,8 @@ def test_workspace_bytes_channels(L):
     tiles = 2 * 3 * 2 + 8 * 8
     # as for one channel, plus a 2-byte channel id per tile; workgroups: the
     # 6 two-tile rows of channel 0 in groups of 4 rows (2), 8 of channel 1
-    expect = (n + 4 * n + 12 * n * 4 + n + 2 * 80 + 4 * tiles + 4 + 4 + 5 * 32 + 32 + 2 * CHAN_BYTES + 2 * tiles
-              + 4 * (2 + 8))
+    expect = (n + 4 * n + 12 * n * 4 + n + 2 * 80 + 4 * tiles + 24 * tiles + 4 + 4 + 5 * 32 + 32 + 2 * CHAN_BYTES
+              + 2 * tiles + 4 * (2 + 8))
     assert L.lbm_workspace_bytes_channels(C.byref(p), 2, dims) == expect
 
 
