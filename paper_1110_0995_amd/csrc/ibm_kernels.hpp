@@ -1049,11 +1049,21 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     };
     // steps 1-2 of every point of the cell (its record kept for the point
     // update), staged in LDS
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+    // two points per thread at a time (the second clamped to the last point
+    // and kept only when it exists), so that both points' loads are in flight
+    // together
+    for (int i = threadIdx.x; i < nv; i += 2 * blockDim.x) {
+        const int i2 = i + blockDim.x;
         const SRec<R> r = couple_record<R>(a.cp, c, v0 + i, ch);
+        const SRec<R> r2 = couple_record<R>(a.cp, c, v0 + min(i2, nv - 1), ch);
         SR[i] = r;
         pbase[i] = r.base;
         pts[i] = SPoint<R>{r.dx, r.dy, r.dz, r.fx, r.fy, r.fz};
+        if (i2 < nv) {
+            SR[i2] = r2;
+            pbase[i2] = r2.base;
+            pts[i2] = SPoint<R>{r2.dx, r2.dy, r2.dz, r2.fx, r2.fy, r2.fz};
+        }
     }
     __syncthreads();
     // base nodes unwrapped around the first point's; their bounding box
@@ -1222,7 +1232,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         // the claim goes out first, so that its round trip overlaps the sum
         const uint32_t prev = atomicExch(&a.owner[n], epoch);
         R Fx = R(0), Fy = R(0), Fz = R(0);
-#pragma unroll 1
+#pragma unroll
         for (int q = 0; q < 8; q++) {
             const int ex = lx - (q & 1), ey = ly - ((q >> 1) & 1), ez = lz - (q >> 2);
             if (ex < 0 || ey < 0 || ez < 0) continue;
