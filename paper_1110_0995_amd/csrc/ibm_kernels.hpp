@@ -955,6 +955,45 @@ struct SPoint {
     R dx, dy, dz, fx, fy, fz;
 };
 
+// q = a / b and r = a % b (a >= 0, b >= 1, a < 2^50) from the reciprocal rb
+// = 1/b: the estimate is within one of q, and one correction step makes both
+// exact.
+__device__ __forceinline__ void divmod_est(int64_t a, int b, double rb, int64_t &q, int64_t &r) {
+    q = (int64_t)((double)a * rb);
+    r = a - q * b;
+    if (r < 0) {
+        q--;
+        r += b;
+    } else if (r >= b) {
+        q++;
+        r -= b;
+    }
+}
+// The same for a, b below 2^24 with a float reciprocal.
+__device__ __forceinline__ void divmod_est(int a, int b, float rb, int &q, int &r) {
+    q = (int)((float)a * rb);
+    r = a - q * b;
+    if (r < 0) {
+        q--;
+        r += b;
+    } else if (r >= b) {
+        q++;
+        r -= b;
+    }
+}
+// Box index li = lx + bx (ly + by lz) -> (lx, ly, lz).
+__device__ __forceinline__ void box_coords(int li, int bx, int by, float rbx, float rby, int &lx, int &ly, int &lz) {
+    int row;
+    divmod_est(li, bx, rbx, row, lx);
+    divmod_est(row, by, rby, lz, ly);
+}
+// v mod n for any v (one step in the usual case of v in [-n, 2n)).
+__device__ __forceinline__ int wrap_to(int v, int n) {
+    while (v >= n) v -= n;
+    while (v < 0) v += n;
+    return v;
+}
+
 // LDS of k_spread_cells: sort keys [pmax] (u32), staged points [maxv],
 // their base nodes [maxv] (u32), base-node and stencil-node bitmaps over the
 // box [kSpreadBox/32] (u32 each), prefix counts of the base bitmap's words
@@ -1029,14 +1068,20 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     if (a.cp.nx_count && c == 0 && threadIdx.x == 0) *a.cp.nx_count = 0u;
     R4 *FI = static_cast<R4 *>(a.fibm);
     R4 *FA = static_cast<R4 *>(a.facc);
+    // node index -> coordinates in the channel (quotients from a reciprocal,
+    // corrected to the exact integer ones)
+    const double rnx = 1.0 / ch.nx, rny = 1.0 / ch.ny;
     auto decode = [&](uint32_t b, int &x, int &y, int &z) {
-        const int64_t lb = (int64_t)b - ch.noff;
-        x = (int)(lb % ch.nx);
-        y = (int)((lb / ch.nx) % ch.ny);
-        z = (int)(lb / ((int64_t)ch.nx * ch.ny));
+        int64_t row;
+        int64_t r;
+        divmod_est((int64_t)b - ch.noff, ch.nx, rnx, row, r);
+        x = (int)r;
+        int64_t zz;
+        divmod_est(row, ch.ny, rny, zz, r);
+        y = (int)r;
+        z = (int)zz;
     };
-    auto unwrap = [](int d, int L) {  // d mod L in (-L/2, L/2]
-        d %= L;
+    auto unwrap = [](int d, int L) {  // d mod L in (-L/2, L/2], for d in (-L, L)
         if (d < 0) d += L;
         return 2 * d > L ? d - L : d;
     };
@@ -1118,6 +1163,7 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         return;
     }
     const int bx_ = (int)Bx, by_ = (int)By, V = (int)(Bx * By * Bz);
+    const float rbx = 1.0f / (float)bx_, rby = 1.0f / (float)by_;
     const int nwords = (V + 31) / 32;
     // Counting sort of the points by (box index of the base node, point).  A
     // run of points with one base node is numbered by that node's rank among
@@ -1147,7 +1193,8 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         if (threadIdx.x + m * kSpreadThreads >= nv) continue;
         const uint32_t li = lis[m];
         atomicOr(&bbits[li >> 5], 1u << (li & 31));
-        const int lx = (int)(li % bx_), ly = (int)((li / bx_) % by_), lz = (int)(li / (bx_ * by_));
+        int lx, ly, lz;
+        box_coords((int)li, bx_, by_, rbx, rby, lx, ly, lz);
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             const int nn = (lx + (q & 1)) + bx_ * ((ly + ((q >> 1) & 1)) + by_ * (lz + (q >> 2)));
@@ -1223,11 +1270,9 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
     // one thread per stencil node
     for (int k = threadIdx.x; k < total; k += blockDim.x) {
         const int li = nodes[k];
-        const int lx = li % bx_, ly = (li / bx_) % by_, lz = li / (bx_ * by_);
-        int gx = (rx + mx + lx) % ch.nx, gy = (ry + my + ly) % ch.ny, gz = (rz + mz + lz) % ch.nz;
-        gx += gx < 0 ? ch.nx : 0;
-        gy += gy < 0 ? ch.ny : 0;
-        gz += gz < 0 ? ch.nz : 0;
+        int lx, ly, lz;
+        box_coords(li, bx_, by_, rbx, rby, lx, ly, lz);
+        const int gx = wrap_to(rx + mx + lx, ch.nx), gy = wrap_to(ry + my + ly, ch.ny), gz = wrap_to(rz + mz + lz, ch.nz);
         const uint32_t n = (uint32_t)(ch.noff + gx + (int64_t)ch.nx * (gy + (int64_t)ch.ny * gz));
         // the claim goes out first, so that its round trip overlaps the sum
         const uint32_t prev = atomicExch(&a.owner[n], epoch);
