@@ -412,9 +412,10 @@ constexpr int kRowDirs[9][3] = {{0, 1, 2},  {3, 7, 10},  {4, 9, 8},  {5, 11, 14}
 template <class S, class R, bool DEV, bool HAS_G, class IDX, bool EMIT = false>
 __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(StepArgs a) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    // Every wave of the workgroup reaches the barrier below, so none leaves
-    // early: a wave without a tile (a shorter table entry, the end of the
-    // tile range) and the lanes past the end of a row only skip the work.
+    // A wave without a tile (a shorter table entry, the end of the tile
+    // range) ends at once: the barrier below waits only for the waves of the
+    // workgroup that have not ended.  Every other wave reaches it, the lanes
+    // past the end of a row only skipping the work.
     int tile;
     bool wlive;  // wave-uniform: the wave owns a tile
     if (a.wgtab) {
@@ -427,6 +428,7 @@ __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(
         wlive = true;
     }
     wlive = wlive && tile < a.ntiles;
+    if (!wlive) return;
     __shared__ uint4 rec_tiles[EMIT ? 8 * kRecTiles : 1];
     uint4 *rt = rec_tiles + (EMIT ? wave * kRecTiles : 0);
     Chan ch{};
