@@ -98,6 +98,8 @@ struct AdjStepArgs {
     uint8_t *ftile;        // tiles holding fallback sums (cleared here)
     const uint8_t *need;   // stencil-node marks (left set for k_adj_nodes)
     const uint8_t *tneed;  // tile marks
+    const uint4 *tmask;    // [ntiles] solid and wall masks of each tile
+    const uint2 *tnmask;   // [ntiles] node marks of each marked tile (the recomputed velocity pass)
     void *lamF;            // [N] Vec4: lambda_F at marked nodes (written)
     void *dgrad;           // [3][N] real, dJ/dG accumulated, or null
     const void *gfield;    // [3][N] real, or null
@@ -132,7 +134,50 @@ __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
     if (x >= ch.nx) return;
     const int64_t n = ch.noff + (int64_t)row * ch.nx + x;
     const int64_t N = a.N, st = a.stride;
-
+    // What the wave needs to know about its tile comes in scalar loads (solid
+    // and wall masks, marks, fallback flag), so that the loads of f_n and of
+    // lambda* go out before any vector load has to be waited for; a wall
+    // node's bounced entries are loaded again once its links are in.
+    const int utile = __builtin_amdgcn_readfirstlane(tile);
+    const uint4 tm = uniform_load(a.tmask, utile);
+    const uint2 nm = uniform_load(a.tnmask, utile);
+    const uint32_t tmark = uniform_byte(a.tneed, utile), tfall = uniform_byte(a.ftile, utile);
+    const bool solid = (((uint64_t)tm.y << 32 | tm.x) >> lane) & 1u;
+    const bool wall = (((uint64_t)tm.w << 32 | tm.z) >> lane) & 1u;
+    const bool marked = tmark && ((((uint64_t)nm.y << 32 | nm.x) >> lane) & 1u);
+    const bool fl = tmark && tfall;
+    R *L = static_cast<R *>(a.lam);
+    R4 *LF = static_cast<R4 *>(a.lamF);
+    if (fl && lane == 0) a.ftile[tile] = 0;
+    if (solid) {
+        if (fl && marked) {  // the fallback sums are taken (and cleared) at every marked node
+            R4 *FA = static_cast<R4 *>(a.facc);
+            FA[n] = R4{R(0), R(0), R(0), R(0)};
+        }
+#pragma unroll
+        for (int i = 0; i < Q; i++) L[i * st + n] = R(0);
+        if (marked) LF[n] = R4{R(0), R(0), R(0), R(0)};
+        return;
+    }
+    const S *f = static_cast<const S *>(a.f);
+    const int y = row % ch.ny, z = row / ch.ny;
+    const uint32_t links = wall ? a.links[n] : 0u;
+    // lambda* pulled from where population i goes (lambda is kept per node
+    // and direction: a bounced population is population opp(i) of the node)
+    const int xp = (x + 1 == ch.nx) ? 0 : x + 1, xm = (x == 0) ? ch.nx - 1 : x - 1;
+    const int yp = (y + 1 == ch.ny) ? 0 : y + 1, ym = (y == 0) ? ch.ny - 1 : y - 1;
+    const int zp = (z + 1 == ch.nz) ? 0 : z + 1, zm = (z == 0) ? ch.nz - 1 : z - 1;
+    const R *LN = static_cast<const R *>(a.lam_next);
+    R ls[Q], v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const int xq = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
+        const int yq = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
+        const int zq = cz(i) > 0 ? zp : (cz(i) < 0 ? zm : z);
+        ls[i] = LN[i * st + ch.noff + xq + (int64_t)ch.nx * (yq + (int64_t)ch.ny * zq)];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) v[i] = R(f[i * st + n]);
     R Fx = R(a.g[0]), Fy = R(a.g[1]), Fz = R(a.g[2]);
     if (HAS_G) {
         const R *G = static_cast<const R *>(a.gfield);
@@ -140,9 +185,6 @@ __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
         Fy += G[N + n];
         Fz += G[2 * N + n];
     }
-    const bool tmark = a.tneed[tile] != 0;
-    const bool marked = tmark && a.need[n];
-    const bool fl = tmark && a.ftile[tile] != 0;
     const R4 *FI = static_cast<const R4 *>(a.fibm);
     if (marked) {
         R4 fi = FI[n];
@@ -156,21 +198,13 @@ __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
         Fy += fi.y;
         Fz += fi.z;
     }
-    if (fl && lane == 0) a.ftile[tile] = 0;
-    R *L = static_cast<R *>(a.lam);
-    R4 *LF = static_cast<R4 *>(a.lamF);
-    if (a.cls[n] == CLS_SOLID) {
+    if (links) {  // bounced entries: f_n in the solid neighbour's slot, lambda* in the node's own opposite slot
 #pragma unroll
-        for (int i = 0; i < Q; i++) L[i * st + n] = R(0);
-        if (marked) LF[n] = R4{R(0), R(0), R(0), R(0)};
-        return;
+        for (int i = 0; i < Q; i++) {
+            if ((links >> opp(i)) & 1u) v[i] = R(f[pop_slot<int64_t>(i, n, links, x, y, z, ch, st, a.per)]);
+            if ((links >> i) & 1u) ls[i] = LN[opp(i) * st + n];
+        }
     }
-    const S *f = static_cast<const S *>(a.f);
-    const int y = row % ch.ny, z = row / ch.ny;
-    const uint32_t links = a.cls[n] == CLS_WALL ? a.links[n] : 0u;
-    R v[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) v[i] = R(f[links ? pop_slot<int64_t>(i, n, links, x, y, z, ch, st, a.per) : i * st + n]);
     R s = R(0);
 #pragma unroll
     for (int i = 0; i < Q; i++) s += v[i];
@@ -182,22 +216,6 @@ __global__ __launch_bounds__(512) void k_adj_collide_stream(AdjStepArgs a) {
     const R ux = (jx + R(0.5) * Fx) * ir, uy = (jy + R(0.5) * Fy) * ir, uz = (jz + R(0.5) * Fz) * ir;
     const R usq = R(1.5) * (ux * ux + uy * uy + uz * uz);
 
-    // lambda* pulled from where population i goes (lambda is kept per node
-    // and direction: a bounced population is population opp(i) of the node)
-    const int xp = (x + 1 == ch.nx) ? 0 : x + 1, xm = (x == 0) ? ch.nx - 1 : x - 1;
-    const int yp = (y + 1 == ch.ny) ? 0 : y + 1, ym = (y == 0) ? ch.ny - 1 : y - 1;
-    const int zp = (z + 1 == ch.nz) ? 0 : z + 1, zm = (z == 0) ? ch.nz - 1 : z - 1;
-    const R *LN = static_cast<const R *>(a.lam_next);
-    R ls[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        const int xq = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
-        const int yq = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-        const int zq = cz(i) > 0 ? zp : (cz(i) < 0 ? zm : z);
-        const int64_t src = ((links >> i) & 1u) ? opp(i) * st + n
-                                                : i * st + ch.noff + xq + (int64_t)ch.nx * (yq + (int64_t)ch.ny * zq);
-        ls[i] = LN[src];
-    }
 
     // derivatives of Phi = sum_i ls_i (omega f_eq_i(rho, u) + S_i(u, F))
     const R omega = R(a.omega), kf = R(a.kf);

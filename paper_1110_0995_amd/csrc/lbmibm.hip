@@ -1641,6 +1641,8 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     a.ftile = c->ftile;
     a.need = c->need;
     a.tneed = c->tneed;
+    a.tmask = c->tmask;
+    a.tnmask = c->tnmask;
     a.lamF = c->lamF;
     a.dgrad = dgrad;
     a.gfield = c->p.gfield;
