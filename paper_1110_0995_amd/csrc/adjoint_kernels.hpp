@@ -91,13 +91,11 @@ struct AdjStepArgs {
     const void *lam_next;  // lambda of f_{n+1} [19][stride], real
     void *lam;             // lambda of f_n [19][stride], real (written)
     int64_t stride;
-    const uint8_t *cls;
     const uint32_t *links;
     const void *fibm;      // spread force of step n, valid at the marked nodes
     void *facc;            // the spread's fallback accumulator: added and cleared in flagged tiles
     uint8_t *ftile;        // tiles holding fallback sums (cleared here)
-    const uint8_t *need;   // stencil-node marks (left set for k_adj_nodes)
-    const uint8_t *tneed;  // tile marks
+    const uint8_t *tneed;  // tile marks (the node marks stay set for k_adj_nodes)
     const uint4 *tmask;    // [ntiles] solid and wall masks of each tile
     const uint2 *tnmask;   // [ntiles] node marks of each marked tile (the recomputed velocity pass)
     void *lamF;            // [N] Vec4: lambda_F at marked nodes (written)

@@ -1634,12 +1634,10 @@ static void launch_adjoint(lbm_ctx *c, const ibm_mesh *m, const void *f_n, const
     a.lam_next = lam_next;
     a.lam = lam;
     a.stride = c->stride;
-    a.cls = c->cls;
     a.links = c->links;
     a.fibm = c->fibm;
     a.facc = c->facc;
     a.ftile = c->ftile;
-    a.need = c->need;
     a.tneed = c->tneed;
     a.tmask = c->tmask;
     a.tnmask = c->tnmask;
