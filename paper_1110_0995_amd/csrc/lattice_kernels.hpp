@@ -417,7 +417,7 @@ __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(
     // workgroup that have not ended.  Every other wave reaches it, the lanes
     // past the end of a row only skipping the work.
     int tile;
-    bool wlive;  // wave-uniform: the wave owns a tile
+    bool wlive = true;  // wave-uniform: the wave owns a tile
     if (a.wgtab) {
         const uint32_t e = a.wgtab[a.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x];
         tile = (int)(e >> 3) + wave;
@@ -425,29 +425,22 @@ __global__ __launch_bounds__(512, sizeof(S) == 4 ? 8 : 1) void k_collide_stream(
     } else {
         const int blk = a.remap ? xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
         tile = blk * (blockDim.x >> 6) + wave;
-        wlive = true;
     }
-    wlive = wlive && tile < a.ntiles;
-    if (!wlive) return;
+    if (!wlive || tile >= a.ntiles) return;
+    const Chan ch = a.chans[tile_channel(a.tile_chan, tile)];
+    const int lt = tile - ch.toff;
+    const int row = lt / ch.tpr;
+    const int x = (lt - row * ch.tpr) * 64 + lane;
     __shared__ uint4 rec_tiles[EMIT ? 8 * kRecTiles : 1];
     uint4 *rt = rec_tiles + (EMIT ? wave * kRecTiles : 0);
-    Chan ch{};
-    int row = 0, x = 0;
-    bool live = false;
-    if (wlive) {
-        ch = a.chans[tile_channel(a.tile_chan, tile)];
-        const int lt = tile - ch.toff;
-        row = lt / ch.tpr;
-        x = (lt - row * ch.tpr) * 64 + lane;
-        if constexpr (EMIT)  // every lane of the wave is active here
-            stage_rec_tiles(a.etile, ch, lt - row * ch.tpr, row % ch.ny, row / ch.ny, lane, rt);
-        live = x < ch.nx;
-    }
+    if constexpr (EMIT)  // every lane of the wave is active here
+        stage_rec_tiles(a.etile, ch, lt - row * ch.tpr, row % ch.ny, row / ch.ny, lane, rt);
+    const bool live = x < ch.nx;
     const IDX base = (IDX)ch.noff;
     const IDX n = base + (IDX)row * (IDX)ch.nx + (IDX)x;
     const IDX N = (IDX)a.N;
     const IDX stride = (IDX)a.stride;
-    const int y = ch.ny ? row % ch.ny : 0, z = ch.ny ? row / ch.ny : 0;
+    const int y = row % ch.ny, z = row / ch.ny;
 
     const S *__restrict__ fa = static_cast<const S *>(a.fa);
     S *__restrict__ fb = static_cast<S *>(a.fb);
