@@ -188,15 +188,20 @@ def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool, err_steps: int = 20
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / K
-    # the collide-stream launch alone: eager steps, events around lbm_step
-    cs = []
+    # the collide-stream launch alone: eager steps, its kernel's own start
+    # and end (lbm_step_timed), and events recorded around the call
+    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ka.record(stream)  # torch creates an event at its first record
+    kb.record(stream)
+    cs, cs_dispatch = [], []
     for _ in range(10):
         lat.couple(mesh)
         a.record(stream)
-        lat.step(1)
+        lat.step_timed(ka.cuda_event, kb.cuda_event)
         b.record(stream)
         torch.cuda.synchronize()
-        cs.append(a.elapsed_time(b))
+        cs.append(ka.elapsed_time(kb))
+        cs_dispatch.append(a.elapsed_time(b))
     ms_cs = float(np.mean(cs))
     sums = lat.sums()
     lat.close()
@@ -222,7 +227,9 @@ def batched_leg(lbm_mod, steps: int, warmup: int, cpu: bool, err_steps: int = 20
     bpn = bytes_per_node(prec)
     gbs = bpn * N / (ms_cs * 1e-3) / 1e9
     out["roofline"] = {"bound": "hbm", "kernel": "k_collide_stream", "bytes_per_node": bpn,
-                       "ms_per_launch": round(ms_cs, 5), "launches_timed": len(cs), "achieved": round(gbs, 1),
+                       "ms_per_launch": round(ms_cs, 5),
+                       "ms_per_launch_with_dispatch": round(float(np.mean(cs_dispatch)), 5),
+                       "launches_timed": len(cs), "achieved": round(gbs, 1),
                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}
     out["whole_step"] = whole_step(bpn * N, ms)
     out.update(steps=K, ms_per_step=round(ms, 5), mlups=round(N / (ms * 1e-3) / 1e6, 1),
@@ -580,14 +587,22 @@ def main():
         one_step()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps; events bracket every LAUNCH_SAMPLE_EVERY-th
-    # collide-stream launch on the stream the library enqueues on (torch's
-    # current stream).  Each event record opens a gap of a few microseconds
-    # between the kernels around it, which the other steps are spared; the
-    # stride is odd, so launches of both workgroup orders are sampled.
+    # timed region: K whole steps.  Every LAUNCH_SAMPLE_EVERY-th
+    # collide-stream launch goes through lbm_step_timed, which hands the
+    # kernel a pair of HIP events that the runtime sets to the kernel's own
+    # start and end (its duration, as the kernel trace has it); events
+    # recorded around the same call on the stream the library enqueues on
+    # (torch's current stream) also take in the dispatch gaps.  Each record
+    # opens a gap of a few microseconds between the kernels around it, which
+    # the other steps are spared; the stride is odd, so launches of both
+    # workgroup orders are sampled.
     every = LAUNCH_SAMPLE_EVERY if args.steps >= 2 * LAUNCH_SAMPLE_EVERY else 1
-    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for k in range(0, args.steps, every)}
+    sampled = range(0, args.steps, every)
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
+    kev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
+    for pair in kev.values():  # torch creates an event at its first record
+        for e in pair:
+            e.record(stream)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -598,14 +613,16 @@ def main():
         e = ev.get(k)
         if e:
             e[0].record(stream)
-        lat.step(1)
-        if e:
+            lat.step_timed(kev[k][0].cuda_event, kev[k][1].cuda_event)
             e[1].record(stream)
+        else:
+            lat.step(1)
     t_end.record(stream)
     torch.cuda.synchronize()
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
-    ms_cs = float(np.mean([a.elapsed_time(b) for a, b in ev.values()]))
+    ms_cs = float(np.mean([a.elapsed_time(b) for a, b in kev.values()]))
+    ms_bracket = float(np.mean([a.elapsed_time(b) for a, b in ev.values()]))
     sums = lat.sums()
 
     mlups = s.n * args.steps / (ms_total * 1e-3) / 1e6
@@ -635,7 +652,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_unit": "B/launch",
                      "kernel": "k_collide_stream", "bytes_per_node": bpn, "ms_per_launch": round(ms_cs, 5),
-                     "launches_timed": len(ev),
+                     "ms_per_launch_with_dispatch": round(ms_bracket, 5), "launches_timed": len(ev),
                      "kernel_sha": sha},
         "whole_step": whole_step(bpn * s.n, ms_step),
         "fluid_mlups": round(nfluid * args.steps / (ms_total * 1e-3) / 1e6, 1),

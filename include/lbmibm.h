@@ -271,6 +271,15 @@ int lbm_check_finite(lbm_ctx *c, int32_t *nonfinite);
  * populations (see lbm_run). */
 int lbm_step(lbm_ctx *c, int32_t nsteps);
 
+/* lbm_step(c, 1) whose collide-stream kernel is launched with two HIP
+ * events (hipEvent_t, created by the caller with timing enabled and not
+ * recorded on another stream meanwhile): the runtime sets them to that
+ * kernel's own start and end, so hipEventElapsedTime(start, stop) is the
+ * kernel's duration, without the dispatch gaps that events recorded around
+ * the call include.  For measurement; not for graph capture.  LBM_EINVAL if
+ * either event is NULL. */
+int lbm_step_timed(lbm_ctx *c, void *start_event, void *stop_event);
+
 /* Compute the rest shape (edge lengths, triangle areas, hinge angles, cell
  * area and volume, vertex areas; all in FP64) of the mesh at its current
  * positions into m->l0, a0, th0, a0c, v0c, avert, and the per-vertex

@@ -19,7 +19,7 @@ ERRORS = {LBM_EINVAL: "EINVAL", LBM_ENOMEM: "ENOMEM", LBM_EHIP: "EHIP", LBM_ENON
 # every symbol include/*.h declares
 EXPORTS = ("lbm_plane_stride", "lbm_workspace_bytes", "lbm_init", "lbm_init_channels",
            "lbm_workspace_bytes_channels", "lbm_set_launch", "lbm_set_ibm_overlap", "lbm_set_node_records", "lbm_node_records_used", "lbm_run", "lbm_check_finite", "lbm_step",
-           "ibm_rest_shape", "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp", "lbm_adjoint_step",
+           "lbm_step_timed", "ibm_rest_shape", "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp", "lbm_adjoint_step",
            "lbm_run_record", "lbm_adjoint_run", "lbm_destroy", "lbm_last_error",
            "mag_workspace_bytes", "mag_field", "mag_forces", "mag_run", "mag_run_static", "mag_freeze")
 MAG_MAX_SHEETS = 8
@@ -92,6 +92,7 @@ def load() -> C.CDLL:
     L.lbm_check_finite.argtypes = [vp, C.POINTER(C.c_int32)]
     L.lbm_run.argtypes = [vp, C.POINTER(IbmMesh), C.c_int32, C.c_int32]
     L.lbm_step.argtypes = [vp, C.c_int32]
+    L.lbm_step_timed.argtypes = [vp, vp, vp]
     L.ibm_rest_shape.argtypes = [vp, C.POINTER(IbmMesh)]
     L.ibm_couple.argtypes = [vp, C.POINTER(IbmMesh)]
     L.lbm_read_fields.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
@@ -116,7 +117,7 @@ def load() -> C.CDLL:
     L.lbm_last_error.restype = C.c_char_p
     for name in ("lbm_init", "lbm_init_channels", "lbm_set_launch", "lbm_set_ibm_overlap", "lbm_set_node_records",
                  "lbm_node_records_used", "lbm_run", "lbm_check_finite", "lbm_step",
-                 "ibm_rest_shape", "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp",
+                 "lbm_step_timed", "ibm_rest_shape", "ibm_couple", "lbm_read_fields", "lbm_current", "lbm_store_f64", "lbm_load_f64", "ibm_force_jvp",
                  "lbm_adjoint_step", "lbm_run_record", "lbm_adjoint_run", "mag_field", "mag_forces", "mag_run", "mag_run_static",
                  "mag_freeze"):
         getattr(L, name).restype = C.c_int

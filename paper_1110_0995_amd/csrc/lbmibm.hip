@@ -3,6 +3,7 @@
 // dispatch by precision, and hipGraph capture of coupled steps.
 #include "lbmibm.h"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -187,6 +188,9 @@ struct lbm_ctx {
     // the compaction and velocity passes; ev_fork / ev_join order the two
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // lbm_step_timed: events the next collide-stream launch binds to its own
+    // start and end (null otherwise)
+    hipEvent_t t_start = nullptr, t_stop = nullptr;
     int ibm_overlap = -1;  // lbm_set_ibm_overlap mode
     // records of the next step's stencil-node populations (see k_next_list):
     // the point update marks the new positions' stencils, the collide-stream
@@ -543,18 +547,27 @@ static CsShape cs_shape(const lbm_ctx *c) {
     return {c->cs_waves, (tpr >= 1 && c->cs_waves % tpr == 0) ? 0 : 1, (int)cdiv(c->ntiles, c->cs_waves), nullptr};
 }
 
+template <class S, class R, bool DEV, bool HAS_G, class IDX, bool EMIT>
+static void launch_cs(lbm_ctx *c, const StepArgs &a, int nb, int bs) {
+    if (c->t_start)  // the events take the kernel's own start and end
+        hipExtLaunchKernelGGL(k_collide_stream<S, R, DEV, HAS_G, IDX, EMIT>, dim3(nb), dim3(bs), 0, c->s, c->t_start,
+                              c->t_stop, 0u, a);
+    else
+        k_collide_stream<S, R, DEV, HAS_G, IDX, EMIT><<<nb, bs, 0, c->s>>>(a);
+}
+
 template <class S, class R, bool DEV, bool EMIT>
 static void launch_step_as(lbm_ctx *c, const StepArgs &a, int nb, int bs) {
     if (c->off32) {
         if (c->p.gfield)
-            k_collide_stream<S, R, DEV, true, uint32_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+            launch_cs<S, R, DEV, true, uint32_t, EMIT>(c, a, nb, bs);
         else
-            k_collide_stream<S, R, DEV, false, uint32_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+            launch_cs<S, R, DEV, false, uint32_t, EMIT>(c, a, nb, bs);
     } else {
         if (c->p.gfield)
-            k_collide_stream<S, R, DEV, true, int64_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+            launch_cs<S, R, DEV, true, int64_t, EMIT>(c, a, nb, bs);
         else
-            k_collide_stream<S, R, DEV, false, int64_t, EMIT><<<nb, bs, 0, c->s>>>(a);
+            launch_cs<S, R, DEV, false, int64_t, EMIT>(c, a, nb, bs);
     }
 }
 
@@ -699,6 +712,18 @@ LBM_API int lbm_step(lbm_ctx *c, int32_t nsteps) {
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps must be >= 0");
     if (int rc = nonfinite_reported(c)) return rc;
     enqueue_steps(c, nsteps);
+    HIPCHK(hipGetLastError());
+    return LBM_OK;
+}
+
+LBM_API int lbm_step_timed(lbm_ctx *c, void *start_event, void *stop_event) {
+    if (!c) return fail(LBM_EINVAL, "context is NULL");
+    if (!start_event || !stop_event) return fail(LBM_EINVAL, "start_event and stop_event must be HIP events");
+    if (int rc = nonfinite_reported(c)) return rc;
+    c->t_start = static_cast<hipEvent_t>(start_event);
+    c->t_stop = static_cast<hipEvent_t>(stop_event);
+    enqueue_steps(c, 1);
+    c->t_start = c->t_stop = nullptr;
     HIPCHK(hipGetLastError());
     return LBM_OK;
 }

@@ -120,6 +120,12 @@ class Lattice:
     def step(self, nsteps: int = 1) -> None:
         _lib.check(self.lib.lbm_step(self.ctx, int(nsteps)))
 
+    def step_timed(self, start_event: int, stop_event: int) -> None:
+        """One step whose collide-stream kernel sets the two HIP events (raw
+        hipEvent_t handles, e.g. torch.cuda.Event(enable_timing=True).cuda_event
+        after one record) to its own start and end."""
+        _lib.check(self.lib.lbm_step_timed(self.ctx, C.c_void_p(int(start_event)), C.c_void_p(int(stop_event))))
+
     def couple(self, mesh: "Mesh") -> None:
         _lib.check(self.lib.ibm_couple(self.ctx, C.byref(mesh.s)))
 

@@ -82,6 +82,7 @@ def test_init_rejects_bad_params(L, kw, msg):
 def test_null_context_calls(L):
     from paper_1110_0995_amd import _lib
     assert L.lbm_step(None, 1) == _lib.LBM_EINVAL
+    assert L.lbm_step_timed(None, None, None) == _lib.LBM_EINVAL
     assert L.ibm_couple(None, None) == _lib.LBM_EINVAL
     assert L.ibm_rest_shape(None, None) == _lib.LBM_EINVAL
     assert L.lbm_read_fields(None, None, None, None) == _lib.LBM_EINVAL

@@ -196,3 +196,37 @@ def test_row_workgroups_match_other_shapes(lbm, nx):
         lat.close()
     for f, x in out[1:]:
         assert np.array_equal(f, out[0][0]) and np.array_equal(x, out[0][1])
+
+
+def test_step_timed_is_step(lbm):
+    """lbm_step_timed takes the same step as lbm_step (bitwise, with cells,
+    posts and a ragged last tile) and sets its two events to the pass
+    kernel's own start and end (a positive duration no longer than events
+    recorded around the call)."""
+    import torch
+    s = S.posts_and_cells(150, 24, 16, posts_x=1, posts_y=1, post_radius=3, gap=6, ncells=2, cell_radius=3.0,
+                          level=2, gx=1e-4, seed=5)
+    stream = torch.cuda.current_stream()
+    ka, kb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ka.record(stream)
+    kb.record(stream)
+    out = []
+    for timed in (False, True):
+        lat = lbm.Lattice.from_scenario(s, prec="f32dev")
+        mesh = lbm.Mesh(lat, s.cells)
+        for _ in range(6):
+            lat.couple(mesh)
+            if timed:
+                a.record(stream)
+                lat.step_timed(ka.cuda_event, kb.cuda_event)
+                b.record(stream)
+                torch.cuda.synchronize()
+                t_kernel, t_call = ka.elapsed_time(kb), a.elapsed_time(b)
+                assert 0.0 < t_kernel <= t_call
+            else:
+                lat.step(1)
+        torch.cuda.synchronize()
+        out.append((lat.current().cpu().numpy(), mesh.positions()))
+        lat.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
