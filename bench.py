@@ -29,7 +29,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-LAUNCH_SAMPLE_EVERY = 5  # collide-stream launches bracketed by HIP events: every 5th step
+LAUNCH_SAMPLES = 40  # collide-stream launches timed by events inside the timed region (about)
+
+
+def sample_stride(steps: int) -> int:
+    """Odd stride between timed collide-stream launches, so that launches of
+    both workgroup orders are sampled, giving about LAUNCH_SAMPLES of them (a
+    sampled step runs ~25 us longer: the event records and the timed launch's
+    own marker)."""
+    return max(1, steps // LAUNCH_SAMPLES) | 1
 
 # Algorithmic bytes per lattice node of one collide-stream launch: the 19
 # populations read and written once (4 B each in FP32 storage, 8 B in FP64)
@@ -587,16 +595,15 @@ def main():
         one_step()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps.  Every LAUNCH_SAMPLE_EVERY-th
+    # timed region: K whole steps.  Every sample_stride(K)-th
     # collide-stream launch goes through lbm_step_timed, which hands the
     # kernel a pair of HIP events that the runtime sets to the kernel's own
     # start and end (its duration, as the kernel trace has it); events
     # recorded around the same call on the stream the library enqueues on
     # (torch's current stream) also take in the dispatch gaps.  Each record
     # opens a gap of a few microseconds between the kernels around it, which
-    # the other steps are spared; the stride is odd, so launches of both
-    # workgroup orders are sampled.
-    every = LAUNCH_SAMPLE_EVERY if args.steps >= 2 * LAUNCH_SAMPLE_EVERY else 1
+    # the other steps are spared.
+    every = sample_stride(args.steps)
     sampled = range(0, args.steps, every)
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}
     kev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for k in sampled}

@@ -28,3 +28,18 @@ def test_reported_unit_counts():
     # surface gap 1
     assert bench.FLOPS_PER_PAIR == 3 + 5 + 1 + 3 + 15 + 3 + 19 + 3 + 1
     assert len(bench.kernel_sha()) == 16
+
+
+def test_launch_sample_stride():
+    sys.path.insert(0, ROOT)
+    import bench
+    # odd strides (the pass alternates its workgroup order every step, so both
+    # orders are sampled), about LAUNCH_SAMPLES launches per run
+    for steps in (1, 5, 50, 100, 400, 1000, 2001):
+        k = bench.sample_stride(steps)
+        assert k % 2 == 1
+        n = len(range(0, steps, k))
+        assert 1 <= n <= steps
+        if steps >= 2 * bench.LAUNCH_SAMPLES:
+            assert bench.LAUNCH_SAMPLES // 2 <= n <= 2 * bench.LAUNCH_SAMPLES
+    assert bench.sample_stride(1000) == 25
