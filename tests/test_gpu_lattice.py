@@ -228,5 +228,10 @@ def test_step_timed_is_step(lbm):
                 lat.step(1)
         torch.cuda.synchronize()
         out.append((lat.current().cpu().numpy(), mesh.positions()))
+        if timed:  # a missing event is refused without stepping
+            from paper_1110_0995_amd import _lib
+            with pytest.raises(_lib.LbmError) as e:
+                lat.step_timed(0, kb.cuda_event)
+            assert e.value.code == _lib.LBM_EINVAL and lat.steps_taken() == 6
         lat.close()
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
