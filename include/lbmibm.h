@@ -271,9 +271,10 @@ int lbm_check_finite(lbm_ctx *c, int32_t *nonfinite);
  * populations (see lbm_run). */
 int lbm_step(lbm_ctx *c, int32_t nsteps);
 
-/* lbm_step(c, 1) whose collide-stream kernel is launched with two HIP
- * events (hipEvent_t, created by the caller with timing enabled and not
- * recorded on another stream meanwhile): the runtime sets them to that
+/* lbm_step(c, 1) (the same step: Sec. 2.1 LBM equation, Sec. 2.4) whose
+ * collide-stream kernel is launched with two HIP events (hipEvent_t, created
+ * by the caller with timing enabled and not recorded on another stream
+ * meanwhile): the runtime sets them to that
  * kernel's own start and end, so hipEventElapsedTime(start, stop) is the
  * kernel's duration, without the dispatch gaps that events recorded around
  * the call include.  For measurement; not for graph capture.  LBM_EINVAL if
