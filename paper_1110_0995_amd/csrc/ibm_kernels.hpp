@@ -1276,25 +1276,50 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         const uint32_t n = (uint32_t)(ch.noff + gx + (int64_t)ch.nx * (gy + (int64_t)ch.ny * gz));
         // the claim goes out first, so that its round trip overlaps the sum
         const uint32_t prev = atomicExch(&a.owner[n], epoch);
-        R Fx = R(0), Fy = R(0), Fz = R(0);
+        // The eight base nodes whose stencils could hold this node (q: its
+        // offset from them).  Their LDS lookups (base bit, run start, first
+        // point) are independent, so all eight go out before any is used;
+        // the sums then take the runs in the same order as before.
+        uint32_t bq[8], mq[8], kq[8];
+        bool in[8];
+        int sq[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             const int ex = lx - (q & 1), ey = ly - ((q >> 1) & 1), ez = lz - (q >> 2);
-            if (ex < 0 || ey < 0 || ez < 0) continue;
-            const uint32_t bi = (uint32_t)(ex + bx_ * (ey + by_ * ez));
-            const uint32_t m = bbits[bi >> 5], bit = 1u << (bi & 31);
-            if (!(m & bit)) continue;
-            const int s0 = rstart[wpre[bi >> 5] + __popc(m & (bit - 1u))];
+            in[q] = ex >= 0 && ey >= 0 && ez >= 0;
+            bq[q] = in[q] ? (uint32_t)(ex + bx_ * (ey + by_ * ez)) : 0u;
+            mq[q] = bbits[bq[q] >> 5];
+        }
+        // (every read is made, at index 0 where the corner is out, and masked
+        // arithmetically, so none waits behind a branch)
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const uint32_t bit = 1u << (bq[q] & 31);
+            in[q] = in[q] && (mq[q] & bit);
+            sq[q] = ((int)wpre[bq[q] >> 5] + __popc(mq[q] & (bit - 1u))) * (int)in[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q++) sq[q] = (int)rstart[sq[q]] * (int)in[q];
+#pragma unroll
+        for (int q = 0; q < 8; q++) kq[q] = key[sq[q]];  // the run's first point (a set base bit has one)
+        R Fx = R(0), Fy = R(0), Fz = R(0);
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            if (!in[q]) continue;
             R Sx = R(0), Sy = R(0), Sz = R(0);
-            for (int j = s0; j < nv && (key[j] >> 11) == bi; j++) {
-                const SPoint<R> r = pts[key[j] & 0x7ffu];
+            uint32_t kk = kq[q];
+            int j = sq[q];
+            do {
+                const SPoint<R> r = pts[kk & 0x7ffu];
                 const R wx = (q & 1) ? r.dx : R(1) - r.dx, wy = ((q >> 1) & 1) ? r.dy : R(1) - r.dy;
                 const R wz = (q >> 2) ? r.dz : R(1) - r.dz;
                 const R wt = wx * wy * wz;
                 Sx += wt * r.fx;
                 Sy += wt * r.fy;
                 Sz += wt * r.fz;
-            }
+                ++j;
+                kk = j < nv ? key[j] : ~0u;
+            } while ((kk >> 11) == bq[q]);
             Fx += Sx;
             Fy += Sy;
             Fz += Sz;
