@@ -1277,9 +1277,10 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_cells(SpreadArgs a) {
         // the claim goes out first, so that its round trip overlaps the sum
         const uint32_t prev = atomicExch(&a.owner[n], epoch);
         // The eight base nodes whose stencils could hold this node (q: its
-        // offset from them).  Their LDS lookups (base bit, run start, first
-        // point) are independent, so all eight go out before any is used;
-        // the sums then take the runs in the same order as before.
+        // offset from them).  Their LDS lookups (base bit, word prefix, run
+        // start, the run's first key) are independent across the eight, so
+        // each level goes out for all eight before any is used; the sums
+        // then take the runs in the order of a plain loop over q.
         uint32_t bq[8], mq[8], kq[8];
         bool in[8];
         int sq[8];
